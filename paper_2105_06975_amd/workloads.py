@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs for the weak-constraint 4D-Var saddle-point solve.
+
+This module only *draws problem data*: covariance matrices, observation
+operators, model coefficients and right-hand sides.  It holds none of the
+solver's arithmetic (no saddle-point operator, no preconditioner, no Krylov
+step), so both the HIP path and the CPU oracle can take their inputs from it.
+
+Problem statement (Tabeart & Pearson, §2.1, eq. saddlepointsystem and
+eq. saddlepointA): a window has time blocks i = 0..N, a state of size s per
+block, p_i observations at time i, covariances D = blkdiag(B, Q_1..Q_N),
+R = blkdiag(R_0..R_N), H = blkdiag(H_i) and the model maps M_i (x_{i-1} -> x_i).
+
+Covariance recipe (paper §6.1 and eq. SOAR, with the readings recorded in the
+design notes): second-order auto-regressive correlations sigma^2 (1 + r/l) e^{-r/l}
+with the chordal distance r = sin(pi |dx|)/pi on the unit periodic domain (the
+arc distance makes SOAR indefinite).  As in §6.1, R_i is kept well conditioned:
+when its condition number exceeds KAPPA_R_MAX it is shifted by a multiple of the
+identity so that it equals KAPPA_R_MAX (the paper floors lambda_min(R_i) so that
+kappa(R_i) stays below about 707/0.41 ~ 1724, Table 2).
+
+Model (advection-diffusion): backward-Euler upwind advection with Courant number
+C plus centred diffusion nu on a periodic grid, i.e. T x = x_new with
+(T x)_j = -(C+nu) x_{j-1} + (1+C+2 nu) x_j - nu x_{j+1}; M = T^{-1}.  The
+generator only reports (a, b, c) = (-(C+nu), 1+C+2nu, -nu).
+
+Right-hand side: the first outer loop of incremental 4D-Var started from a
+free model run has b = 0 and d_i = y_i - H_i x_i.  Innovations are drawn
+directly as d_i = H_i e_i + R_i^{1/2} eps_i with a smooth signal e_i = B^{1/2} xi_i;
+no nature run of the model is made for the linear workloads.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+KAPPA_R_MAX = 1724.0
+
+# Workload descriptions (sizes as in the five configurations this library is
+# measured on).  C1 is the small case, C2 the single-window headline shape.
+CONFIGS = {
+    "c1": dict(s=100, N=10, obs="every", obs_stride=2, r_kind="soar", r_len=0.05, r_var=0.5,
+               b_len=0.1, b_var=1.0, q_scale=0.1, courant=0.5, nu=0.1),
+    "c2": dict(s=4096, N=64, obs="random", p=2048, r_kind="soar", r_len=0.05, r_var=0.5,
+               b_len=0.1, b_var=1.0, q_scale=0.1, courant=0.5, nu=0.1),
+    "c5": dict(s=4096, N=32, obs="random", p=2048, r_kind="soar", r_len=0.05, r_var=0.5,
+               b_len=0.1, b_var=1.0, q_scale=0.1, courant=0.5, nu=0.1),
+}
+
+
+@dataclass
+class Window:
+    """One assimilation window, all arrays float64 / int32, row-major."""
+    s: int
+    N: int
+    p: np.ndarray                       # [N+1] observations per block
+    dmats: list                         # distinct s x s covariance matrices
+    d_index: np.ndarray                 # [N+1] D_i = d_scale[i] * dmats[d_index[i]]
+    d_scale: np.ndarray                 # [N+1]
+    rmats: list                         # distinct p_i x p_i observation covariances
+    r_index: np.ndarray                 # [N+1] R_i = rmats[r_index[i]]
+    h_width: int                        # ELL width of each H_i row
+    h_cols: list                        # [N+1] int32 arrays (p_i, w), state index per entry
+    h_vals: list                        # [N+1] float64 arrays (p_i, w)
+    model: dict                         # see module docstring
+    rhs: Optional[np.ndarray] = None    # [nrhs, n] saddle right-hand sides (b; d; 0)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nb(self) -> int:
+        return self.N + 1
+
+    @property
+    def P(self) -> int:
+        return int(np.sum(self.p))
+
+    @property
+    def n(self) -> int:
+        return 2 * self.nb * self.s + self.P
+
+
+# ---------------------------------------------------------------- covariances
+def chordal_distance(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Chordal distance between points x, y of the unit periodic domain."""
+    d = np.abs(x[:, None] - y[None, :])
+    return np.sin(np.pi * d) / np.pi
+
+
+def soar_matrix(pos: np.ndarray, length: float, var: float) -> np.ndarray:
+    r = chordal_distance(pos, pos) / length
+    return var * (1.0 + r) * np.exp(-r)
+
+
+def gaussian_grid_matrix(idx: np.ndarray, s: int, length_cells: float, var: float) -> np.ndarray:
+    """exp(-d^2 / (2 l^2)) with d the periodic grid distance in cells."""
+    d = np.abs(idx[:, None] - idx[None, :]).astype(np.float64)
+    d = np.minimum(d, s - d)
+    return var * np.exp(-d * d / (2.0 * length_cells ** 2))
+
+
+def recondition(R: np.ndarray, kappa_max: float = KAPPA_R_MAX) -> tuple[np.ndarray, float]:
+    """Shift R by a multiple of I so that its condition number is at most kappa_max.
+
+    Returns (R_shifted, shift).  A no-op when R is already that well conditioned.
+    """
+    lam = np.linalg.eigvalsh(R)
+    lmin, lmax = lam[0], lam[-1]
+    if lmin > 0 and lmax / lmin <= kappa_max:
+        return R, 0.0
+    shift = (lmax - kappa_max * lmin) / (kappa_max - 1.0)
+    return R + shift * np.eye(R.shape[0]), float(shift)
+
+
+def _spd_sqrt_factor(C: np.ndarray) -> np.ndarray:
+    """A factor F with F F^T = C for drawing correlated samples."""
+    try:
+        return np.linalg.cholesky(C)
+    except np.linalg.LinAlgError:
+        lam, V = np.linalg.eigh(C)
+        return V * np.sqrt(np.clip(lam, 0.0, None))
+
+
+# ---------------------------------------------------------------- windows
+def advdiff_coeffs(courant: float, nu: float) -> tuple[float, float, float]:
+    return (-(courant + nu), 1.0 + courant + 2.0 * nu, -nu)
+
+
+def obs_indices(s: int, mode: str, rng: np.random.Generator, stride: int = 2,
+                p: Optional[int] = None) -> np.ndarray:
+    if mode == "every":
+        return np.arange(0, s, stride, dtype=np.int32)
+    if mode == "random":
+        return np.sort(rng.choice(s, size=p, replace=False)).astype(np.int32)
+    raise ValueError(mode)
+
+
+def make_advdiff_window(s: int, N: int, obs_idx: np.ndarray, *, r_kind: str = "soar",
+                        r_len: float = 0.05, r_var: float = 0.5, b_len: float = 0.1,
+                        b_var: float = 1.0, q_scale: float = 0.1, courant: float = 0.5,
+                        nu: float = 0.1, nrhs: int = 1, seed: int = 0,
+                        rhs_kind: str = "innovation", model_kind: str = "tridiag_inv",
+                        kappa_r_max: float = KAPPA_R_MAX) -> Window:
+    """A linear advection-diffusion window with SOAR B, Q = q B and a shared R_i."""
+    ss = np.random.SeedSequence(seed)
+    rng_sig, rng_obs = [np.random.default_rng(c) for c in ss.spawn(2)]
+    grid = np.arange(s, dtype=np.float64) / s
+    B = soar_matrix(grid, b_len, b_var)
+    obs_idx = np.asarray(obs_idx, dtype=np.int32)
+    p = len(obs_idx)
+    if r_kind == "soar":
+        R = soar_matrix(grid[obs_idx], r_len, r_var)
+    elif r_kind == "gaussian":
+        R = gaussian_grid_matrix(obs_idx, s, r_len, r_var)
+    else:
+        raise ValueError(r_kind)
+    R, shift = recondition(R, kappa_r_max)
+    nb = N + 1
+    a, b, c = advdiff_coeffs(courant, nu)
+    if model_kind == "tridiag_inv":
+        model = dict(kind="tridiag_inv", a=a, b=b, c=c)
+    else:
+        raise ValueError(model_kind)
+    win = Window(
+        s=s, N=N, p=np.full(nb, p, dtype=np.int32),
+        dmats=[B], d_index=np.zeros(nb, dtype=np.int32),
+        d_scale=np.array([1.0] + [q_scale] * N, dtype=np.float64),
+        rmats=[R], r_index=np.zeros(nb, dtype=np.int32), h_width=1,
+        h_cols=[obs_idx.reshape(p, 1).copy() for _ in range(nb)],
+        h_vals=[np.ones((p, 1)) for _ in range(nb)],
+        model=model,
+        meta=dict(r_shift=shift, seed=seed, r_len=r_len, b_len=b_len, q_scale=q_scale),
+    )
+    win.rhs = draw_rhs(win, nrhs, rng_sig, rng_obs, kind=rhs_kind)
+    return win
+
+
+def draw_rhs(win: Window, nrhs: int, rng_sig: np.random.Generator,
+             rng_obs: np.random.Generator, kind: str = "innovation") -> np.ndarray:
+    """Right-hand sides (b; d; 0) of the saddle system, one row per RHS.
+
+    kind="innovation": b = 0, d_i = H_i B^{1/2} xi_i + R_i^{1/2} eps_i, with the
+    smooth signal shared by all RHS and the observation noise redrawn per RHS
+    (perturbed observations).  kind="random": every component of (b; d; 0)
+    standard normal except the last, which is zero (used for parity tests).
+    """
+    s, nb = win.s, win.nb
+    out = np.zeros((nrhs, win.n))
+    if kind == "random":
+        out[:, : nb * s + win.P] = rng_obs.standard_normal((nrhs, nb * s + win.P))
+        return out
+    FB = _spd_sqrt_factor(win.dmats[0])
+    FR = [_spd_sqrt_factor(R) for R in win.rmats]
+    sig = FB @ rng_sig.standard_normal((s, nb))          # smooth signal per block
+    off = nb * s
+    for i in range(nb):
+        pi = int(win.p[i])
+        cols, vals = win.h_cols[i], win.h_vals[i]
+        hx = np.sum(vals * sig[cols, i], axis=1)
+        F = FR[int(win.r_index[i])]
+        noise = F @ rng_obs.standard_normal((pi, nrhs))
+        out[:, off: off + pi] = hx[None, :] + noise.T
+        off += pi
+    return out
+
+
+def make_config_window(name: str, *, seed: int = 0, nrhs: int = 1, r_len: Optional[float] = None,
+                       rhs_kind: str = "innovation") -> Window:
+    cfg = dict(CONFIGS[name])
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 7]))
+    idx = obs_indices(cfg["s"], cfg["obs"], rng, stride=cfg.get("obs_stride", 2), p=cfg.get("p"))
+    if r_len is not None:
+        cfg["r_len"] = r_len
+    win = make_advdiff_window(cfg["s"], cfg["N"], idx, r_kind=cfg["r_kind"], r_len=cfg["r_len"],
+                              r_var=cfg["r_var"], b_len=cfg["b_len"], b_var=cfg["b_var"],
+                              q_scale=cfg["q_scale"], courant=cfg["courant"], nu=cfg["nu"],
+                              nrhs=nrhs, seed=seed, rhs_kind=rhs_kind)
+    win.meta["config"] = name
+    return win
+
+
+def make_small_window(s: int = 16, N: int = 4, p: int = 6, *, seed: int = 0, nrhs: int = 1,
+                      r_len: float = 0.1, b_len: float = 0.2, q_scale: float = 0.5,
+                      rhs_kind: str = "random", h_width: int = 1,
+                      kappa_r_max: float = KAPPA_R_MAX) -> Window:
+    """Tiny windows for dense cross-checks (random obs positions, optional ELL width > 1)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 11]))
+    idx = obs_indices(s, "random", rng, p=p)
+    win = make_advdiff_window(s, N, idx, r_len=r_len, b_len=b_len, q_scale=q_scale, nrhs=nrhs,
+                              seed=seed, rhs_kind=rhs_kind, kappa_r_max=kappa_r_max)
+    if h_width > 1:
+        # smoothed observations: each row averages h_width neighbouring state points
+        offs = np.arange(h_width) - h_width // 2
+        cols = (idx[:, None] + offs[None, :]) % s
+        for i in range(win.nb):
+            win.h_cols[i] = cols.astype(np.int32)
+            win.h_vals[i] = np.full((p, h_width), 1.0 / h_width)
+        win.h_width = h_width
+        rng2 = np.random.default_rng(seed + 99)
+        win.rhs = draw_rhs(win, nrhs, rng2, rng2, kind=rhs_kind)
+    return win
+
+
+def random_vectors(win: Window, nrhs: int, seed: int = 0) -> np.ndarray:
+    """Standard normal saddle vectors, shape (nrhs, n)."""
+    return np.random.default_rng(seed).standard_normal((nrhs, win.n))
+
+
+def pack(windows: list, arrays: list) -> np.ndarray:
+    """Concatenate per-window arrays of shape (nrhs, n_w) into one packed vector."""
+    return np.concatenate([a.reshape(-1) for a in arrays])
+
+
+def with_dense_model(win: Window, *, seed: int = 0, norm: float = 0.9) -> Window:
+    """Replace the model by N distinct random dense maps M_1..M_N with ||M_i||_2 = norm.
+
+    Distinct M_i make every block index visible in cross-checks (the advection-diffusion
+    map is the same at every time)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 23]))
+    mats = []
+    for _ in range(win.N):
+        G = rng.standard_normal((win.s, win.s))
+        mats.append(norm * G / np.linalg.norm(G, 2))
+    win.model = dict(kind="dense", mats=mats)
+    return win

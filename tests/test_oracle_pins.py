@@ -1,0 +1,311 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: a dense direct solve,
+the primal normal equations, Lemma 1's explicit block products, Propositions 1-4,
+Theorem 1, a circulant closed form, or values printed in the paper (tests/golden).
+Tiny instances use distinct random dense model maps M_i so that a wrong block index,
+sign or transpose anywhere in the oracle changes at least one result.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import svar_oracle as so
+from oracle import theory as th
+from paper_2105_06975_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(seed=0, s=10, N=4, p=5, dense=True, h_width=1, norm=0.9):
+    win = wl.make_small_window(s=s, N=N, p=p, seed=seed, h_width=h_width)
+    if dense:
+        wl.with_dense_model(win, seed=seed, norm=norm)
+    return win
+
+
+def ms_list(orc):
+    return [None] + [orc.model.dense(i) for i in range(1, orc.N + 1)]
+
+
+# ------------------------------------------------------------------ operator structure
+@pytest.mark.parametrize("h_width", [1, 3])
+def test_apply_A_matches_assembled_definition(h_width):
+    win = tiny(seed=1, h_width=h_width)
+    orc = so.SaddleOracle(win, k=2)
+    A = orc.A_dense()
+    v = np.random.default_rng(0).standard_normal(orc.n)
+    assert np.allclose(orc.apply_A(v), A @ v, rtol=1e-13, atol=1e-13)
+    # P3: A is symmetric (eq. saddlepointA)
+    assert np.abs(A - A.T).max() == 0.0
+
+
+def test_L_is_definition1_with_k_Nplus1_and_paper_indexing():
+    """eq. def:L equals Definition 1 with k = N+1, built with the paper's 1-based indices."""
+    win = tiny(seed=2)
+    orc = so.SaddleOracle(win)
+    Ms = ms_list(orc)
+    s, nb = orc.s, orc.nb
+    for k in range(1, nb + 1):
+        Lk = np.block([[th.definition1_block(Ms, k, i, j, s) for j in range(1, nb + 1)]
+                       for i in range(1, nb + 1)])
+        assert np.array_equal(orc.L_dense(k), Lk)
+    x = np.random.default_rng(1).standard_normal((nb, s))
+    L = orc.L_dense()
+    assert np.allclose(orc.L_apply(x).ravel(), L @ x.ravel(), atol=1e-14)
+    assert np.allclose(orc.LT_apply(x).ravel(), L.T @ x.ravel(), atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_lemma1_explicit_inverse(k):
+    """P5: the sweeps equal Lemma 1's block products; k=1 is I; k=N+1 inverts L."""
+    win = tiny(seed=3, N=4)
+    orc = so.SaddleOracle(win, k=k)
+    Ms = ms_list(orc)
+    s, nb = orc.s, orc.nb
+    lem = np.block([[th.lemma1_block(Ms, k, i, j, s) for j in range(1, nb + 1)]
+                    for i in range(1, nb + 1)])
+    sweep = orc.xspace_dense(lambda x: orc.LM_inv(x))
+    sweepT = orc.xspace_dense(lambda x: orc.LM_invT(x))
+    assert np.allclose(sweep, lem, rtol=1e-12, atol=1e-13)
+    assert np.allclose(sweepT, lem.T, rtol=1e-12, atol=1e-13)
+    assert np.allclose(orc.L_dense(k) @ lem, np.eye(nb * s), atol=1e-12)
+    if k == 1:
+        assert np.array_equal(sweep, np.eye(nb * s))
+    if k == nb:
+        assert np.allclose(orc.L_dense() @ sweep, np.eye(nb * s), atol=1e-12)
+
+
+# ------------------------------------------------------------------ solutions
+@pytest.mark.parametrize("prec,k,rhat", [("PI", 1, "DIAG"), ("PI", 3, "RR"), ("PI", 5, "ME"),
+                                         ("PD", 2, "EXACT"), ("PD", 3, "RR"), ("NONE", 1, "DIAG")])
+def test_fgmres_matches_dense_lu(prec, k, rhat):
+    """P1: FGMRES at rtol 1e-13 reaches the dense LU solution of the assembled A."""
+    win = tiny(seed=4)
+    orc = so.SaddleOracle(win, k=k, rhat=rhat)
+    rhs = win.rhs[0]
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    out = so.solve(orc, rhs, prec=prec, rtol=1e-13, maxit=orc.n)
+    assert np.linalg.norm(out["x"] - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+    # P4: the Givens estimate never increases and matches the true residual at the end
+    h = np.array(out["hist"])
+    assert np.all(np.diff(h) <= 1e-15)
+    assert abs(h[-1] - out["relres_true"]) <= 1e-11
+
+
+def test_primal_normal_equations_equivalence():
+    """P2: the saddle solution equals the primal weak-constraint solution."""
+    win = tiny(seed=5)
+    orc = so.SaddleOracle(win)
+    rhs = win.rhs[0]
+    v1, v2, _ = orc.split(rhs)
+    ref = so.primal_solution(orc, v1.ravel(), v2)
+    x = np.linalg.solve(orc.A_dense(), rhs)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_minres_pd_matches_dense():
+    win = tiny(seed=6)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    rhs = win.rhs[0]
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    out = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-14, maxit=4 * orc.n)
+    assert np.linalg.norm(out["x"] - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    assert np.all(np.diff(np.array(out["hist"])) <= 1e-12)
+
+
+# ------------------------------------------------------------------ preconditioners
+@pytest.mark.parametrize("rhat", so.RHAT_KINDS)
+@pytest.mark.parametrize("k", [1, 3])
+def test_preconditioner_inverses_match_definitions(rhat, k):
+    """P3: P_D^{-1}, P_I^{-1} are the inverses of eq. prec assembled from their blocks,
+    and both are symmetric; P_D^{-1} is positive definite."""
+    win = tiny(seed=7, h_width=2)
+    orc = so.SaddleOracle(win, k=k, rhat=rhat)
+    s, nb, P = orc.s, orc.nb, orc.P
+    D, R, H, L = orc.blocks_dense()
+    Lh = orc.L_dense(k)
+    Dhat = np.zeros((nb * s, nb * s))
+    for i in range(nb):
+        Dhat[i * s:(i + 1) * s, i * s:(i + 1) * s] = orc.D_block(i) + 0.01 * np.eye(s)
+    Rhat = np.zeros((P, P))
+    for i in range(nb):
+        a, b = orc.poff[i], orc.poff[i + 1]
+        Rhat[a:b, a:b] = orc.Rhat_dense(i)
+    Shat = Lh.T @ np.linalg.solve(D, Lh)
+    Z = np.zeros
+    PD = np.block([[Dhat, Z((nb * s, P)), Z((nb * s, nb * s))],
+                   [Z((P, nb * s)), Rhat, Z((P, nb * s))],
+                   [Z((nb * s, nb * s)), Z((nb * s, P)), Shat]])
+    PI = np.block([[D, Z((nb * s, P)), Lh],
+                   [Z((P, nb * s)), Rhat, Z((P, nb * s))],
+                   [Lh.T, Z((nb * s, P)), Z((nb * s, nb * s))]])
+    PDi = orc.operator_dense(orc.apply_PD_inv)
+    PIi = orc.operator_dense(orc.apply_PI_inv)
+    n = orc.n
+    assert np.allclose(PD @ PDi, np.eye(n), atol=1e-8)
+    assert np.allclose(PI @ PIi, np.eye(n), atol=1e-8)
+    assert np.abs(PDi - PDi.T).max() <= 1e-9 * np.abs(PDi).max()
+    assert np.abs(PIi - PIi.T).max() <= 1e-9 * np.abs(PIi).max()
+    assert np.linalg.eigvalsh(0.5 * (PDi + PDi.T)).min() > 0
+
+
+def test_rhat_spectra_props_3_and_4():
+    """P7: eig(R_RR^{-1} R) = lam/(lam+gamma); eig(R_ME^{-1} R) = lam/max(T, lam)."""
+    win = wl.make_small_window(s=40, N=1, p=20, seed=8, r_len=0.1)
+    R = win.rmats[0]
+    lam = np.linalg.eigvalsh(R)
+    for kind, expect in [("RR", th.prop3_spectrum(lam, lam[0])),
+                         ("ME", th.prop4_spectrum(lam, lam[1])),
+                         ("RR_g", th.prop3_spectrum(lam, 0.37)),
+                         ("ME_T", th.prop4_spectrum(lam, lam[5]))]:
+        if kind == "RR_g":
+            orc = so.SaddleOracle(win, rhat="RR", rr_gamma=0.37)
+        elif kind == "ME_T":
+            orc = so.SaddleOracle(win, rhat="ME", me_T=lam[5])
+        else:
+            orc = so.SaddleOracle(win, rhat=kind)
+        Rhi = np.column_stack([orc.Rhat_inv(np.concatenate([e, np.zeros(orc.P - len(e))]))[: len(e)]
+                               for e in np.eye(len(lam))])
+        got = np.sort(np.linalg.eigvals(Rhi @ R).real)
+        assert np.allclose(got, np.sort(expect), rtol=1e-9, atol=1e-12), kind
+    # with T = lambda_2 all eigenvalues but one equal 1 (§6.1)
+    me = th.prop4_spectrum(lam, lam[1])
+    assert np.sum(np.abs(me - 1) < 1e-14) == len(lam) - 1
+
+
+# ------------------------------------------------------------------ L_M theory
+@pytest.mark.parametrize("N,k", [(4, 2), (6, 3), (7, 3), (6, 4), (5, 6)])
+def test_prop1_unit_eigenvalues_and_prop2_bound(N, k):
+    """P6: at least (N+1-2 floor(N/k)) s unit eigenvalues; lambda_max <= Prop. 2 bound
+    for contractive M_i (norm 0.9 dense maps and the advection-diffusion map)."""
+    for dense in (True, False):
+        win = tiny(seed=9 + N + k, N=N, s=6, p=3, dense=dense)
+        orc = so.SaddleOracle(win, k=k)
+        L = orc.L_dense()
+        LMi = orc.xspace_dense(lambda x: orc.LM_inv(x))
+        Msym = LMi.T @ L.T @ L @ LMi
+        ev = np.linalg.eigvalsh(0.5 * (Msym + Msym.T))
+        assert np.sum(np.abs(ev - 1.0) < 1e-9) >= th.prop1_unit_eigs(N, k, orc.s)
+        assert ev.max() <= th.prop2_bound(k, N) + 1e-10
+
+
+def test_theorem1_interval_inclusion():
+    """P8: eig(P_D^{-1} A) lies in Theorem 1's intervals (tiny instance, D and Dhat SPD)."""
+    win = tiny(seed=12, s=8, N=3, p=4)
+    k = 2
+    orc = so.SaddleOracle(win, k=k, rhat="RR")
+    D, R, H, L = orc.blocks_dense()
+    nb, s = orc.nb, orc.s
+    Dhat = sla_block(orc, lambda i: orc.D_block(i) + 0.01 * np.eye(s))
+    Rhat = np.zeros_like(R)
+    for i in range(nb):
+        a, b = orc.poff[i], orc.poff[i + 1]
+        Rhat[a:b, a:b] = orc.Rhat_dense(i)
+    Lh = orc.L_dense(k)
+
+    def gen_range(X, Y):  # eigenvalues of Y^{-1} X (X, Y SPD)
+        ev = np.linalg.eigvals(np.linalg.solve(Y, X)).real
+        return ev.min(), ev.max()
+
+    lD, LD = gen_range(D, Dhat)
+    lR, LR = gen_range(R, Rhat)
+    Di = np.linalg.inv(D)
+    S = L.T @ Di @ L + H.T @ np.linalg.inv(R) @ H
+    St = L.T @ Di @ L
+    lS, LS = gen_range(S, St)
+    lL, LL = gen_range(L.T @ L, Lh.T @ Lh)
+    evD = np.linalg.eigvalsh(D)
+    neg, mid, pos = th.theorem1_intervals(lD, LD, lR, LR, lS, LS, lL, LL, evD[-1] / evD[0])
+    PDi = orc.operator_dense(orc.apply_PD_inv)
+    ev = np.linalg.eigvals(PDi @ orc.A_dense())
+    assert np.abs(ev.imag).max() < 1e-6
+    tol = 1e-8
+    for e in ev.real:
+        inside = any(lo - tol * abs(lo) - tol <= e <= hi + tol * abs(hi) + tol
+                     for lo, hi in (neg, mid, pos))
+        assert inside, e
+
+
+def sla_block(orc, fn):
+    import scipy.linalg as sla
+    return sla.block_diag(*[fn(i) for i in range(orc.nb)])
+
+
+def test_remark1_minres_rate():
+    """Remark 1: the MINRES P^{-1}-norm residual obeys the two-interval bound."""
+    win = tiny(seed=13, s=8, N=3, p=4)
+    orc = so.SaddleOracle(win, k=2, rhat="EXACT")
+    PDi = orc.operator_dense(orc.apply_PD_inv)
+    ev = np.sort(np.linalg.eigvals(PDi @ orc.A_dense()).real)
+    negs, poss = ev[ev < 0], ev[ev > 0]
+    mu1, mu2, mu3, mu4 = th.stretch_intervals((negs.min(), negs.max()), (poss.min(), poss.max()))
+    out = so.solve(orc, win.rhs[0], prec="PD", method="MINRES", rtol=1e-14, maxit=60)
+    h = out["hist"]
+    for ell in range(1, len(h) // 2):
+        assert h[2 * ell] <= th.remark1_minres_bound(mu1, mu2, mu3, mu4, ell, 1.0) * (1 + 1e-6) + 1e-12
+
+
+# ------------------------------------------------------------------ model
+def test_advection_diffusion_model_matches_circulant_closed_form():
+    """P13: M = T^{-1}; its eigenvalues are 1/(b + a e^{-i th} + c e^{i th}); ||M||_2 = 1."""
+    s = 32
+    win = wl.make_small_window(s=s, N=2, p=4, seed=14)
+    orc = so.SaddleOracle(win)
+    Md = orc.model.dense(1)
+    m = win.model
+    ev = np.linalg.eigvals(Md)
+    ref = th.circulant_tridiag_inverse_eigs(m["a"], m["b"], m["c"], s)
+    assert np.allclose(np.sort_complex(np.round(ev, 12)), np.sort_complex(np.round(ref, 12)), atol=1e-10)
+    assert abs(np.linalg.norm(Md, 2) - 1.0) < 1e-12
+    # M^T applied by the oracle is the transpose of M
+    x = np.random.default_rng(2).standard_normal(s)
+    assert np.allclose(orc.model.MT(1, x), Md.T @ x, atol=1e-14)
+    # the upwind stencil of the configurations: (a, b, c) = (-0.6, 1.7, -0.1)
+    assert np.allclose(wl.advdiff_coeffs(0.5, 0.1), (-0.6, 1.7, -0.1))
+
+
+# ------------------------------------------------------------------ golden values printed in the paper
+def test_golden_table3_theorem1_bounds():
+    """Table 3 (§7.1): the printed Theorem 1 bounds follow from the printed extreme
+    eigenvalues of Rhat^{-1} R (Table 2, p = 250) and one pair (phi, Phi) shared by the
+    L_M rows; fitting (phi, Phi) on the 'L_M, R' row must reproduce the other rows."""
+    with open(os.path.join(GOLDEN, "table3_theorem1_bounds.json")) as f:
+        g = json.load(f)
+    fit = g["rows"]["LM_R"]
+    # l = U = 1 for Rhat = R and D = Dhat = I: solve the bound equations for phi, Phi
+    Phi = ((1 - 2 * fit["neg_lo"]) ** 2 - 1) / 4
+    phi = ((1 - 2 * fit["neg_hi"]) ** 2 - 1) / 4
+    for name, row in g["rows"].items():
+        if not name.startswith("LM_"):
+            continue
+        l, U = row["lam_phi"], row["Lam_phi"]
+        neg, mid, pos = th.intervals_from(l, U, phi, Phi)
+        got = [neg[0], neg[1], min(mid[0], pos[0]), pos[1]]
+        want = [row["neg_lo"], row["neg_hi"], row["pos_lo"], row["pos_hi"]]
+        assert np.allclose(got, want, atol=6e-4), (name, got, want)
+
+
+def test_golden_table2_ridge_regression():
+    """Table 2 prints lambda_min(R_RR^{-1} R_i) = 0.2908 for lambda_min(R_i) = 0.41 at every p;
+    by Proposition 3 that is 0.41/(0.41 + gamma) with gamma = 1 (the reading recorded for
+    the table).  Its printed lambda_max of 1.0000 is only bounded (Prop. 3 gives < 1)."""
+    with open(os.path.join(GOLDEN, "table2_rhat_eigs.json")) as f:
+        g = json.load(f)
+    gamma = g["gamma_reading"]
+    for row in g["rows"]:
+        lo = th.prop3_spectrum([row["lam_min"]], gamma)[0]
+        hi = th.prop3_spectrum([row["lam_max"]], gamma)[0]
+        assert round(lo, 4) == row["rr_min"]
+        assert hi < 1.0 and row["rr_max"] <= 1.0
+        assert row["me_min"] < 1.0  # Prop. 4: only the smallest eigenvalue moves below 1
+
+
+def test_golden_prop1_counts_table_sizes():
+    """Proposition 1 at the sizes of Table 3 (s=500, N=5, k=3): r = N+1-2 floor(N/k) = 4."""
+    assert th.prop1_unit_eigs(5, 3, 500) == 4 * 500
+    assert th.prop1_unit_eigs(15, 16, 2500) == 16 * 2500  # k = N+1: L_M = L
+    assert th.prop2_bound(3, 5) == pytest.approx(1 + 3 + math.sqrt(3))
