@@ -1,0 +1,208 @@
+"""Benchmark: preconditioned saddle-point solves per second on one MI355X.
+
+Workload (one "step" = one complete solve of the hot path): a linearised weak-constraint
+4D-Var window shaped like the paper's experiments, s = 4096 state variables, N = 64 (65 time
+blocks), p_i = 2048 random observation points, dense SOAR B (length 0.1), Q_i = 0.1 B,
+dense SOAR R_i (length 0.05), implicit advection-diffusion model; right-hand side (0; d; 0)
+with synthetic innovations.  Inexact-constraint preconditioner P_I with L_M(3) and the
+ridge-regression Rhat, flexible GMRES to a 1e-6 true relative residual, x0 = 0.
+
+Paths timed: the plain float64 solve (the reference path) and the mixed-precision one
+(float64 refinement, float32 inner operator, bfloat16 preconditioner products).  The JSON
+line reports the plain float64 path as `value` and the others alongside.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--k", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, nargs=2, default=(8, 24),
+                    help="oracle iteration counts of the two timed samples")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ortho_bytes(n, iters):
+    """Algorithmic HBM bytes of the two Gram-Schmidt passes over all iterations: iteration j
+    reads j basis vectors twice plus u, w, z and writes Z[j], v_j, u."""
+    tot = 0
+    for j in range(iters + 1):
+        tot += (2 * j + 9) * n * 8
+    return tot
+
+
+def gemm_flops(win, iters, applies_a64):
+    """Algorithmic flops of the covariance products: per iteration one A (D and R products)
+    and one P_I (D and Rhat^{-1} products), plus float64 residual checks (A only)."""
+    s, nb, p = win.s, win.nb, int(win.p[0])
+    fa = 2.0 * s * s * nb + 2.0 * p * p * nb
+    fp = 2.0 * s * s * nb + 2.0 * p * p * nb
+    return (iters + 1) * (fa + fp) + applies_a64 * fa
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are "
+                                   "not part of this build (see DESIGN.md for the sharding "
+                                   "design)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2105_06975_amd import svar, workloads as wl
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    win = wl.make_config_window("c2", seed=0)
+    log(f"workload built in {time.time() - t0:.1f}s: n={win.n}")
+    t0 = time.time()
+    h = svar.Handle([win], svar.Precond(type="PI", k=args.k, rhat="RR"))
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log(f"handle set-up {setup_s:.2f}s")
+    rhs = torch.from_numpy(win.rhs[0]).to(dev)
+
+    def run(precision, steps, warmup, timing=False):
+        kw = dict(rtol=args.rtol, maxit=1000)
+        if precision != "FP64":
+            kw.update(precision=precision, restart=60, inner_rtol=1e-3, max_outer=40)
+        infos = None
+        for _ in range(warmup):
+            x, infos, rc = h.solve(rhs, **kw)
+            log(f"  warmup {precision}: rc={rc} iters={infos[0]['iters']} "
+                f"relres={infos[0]['relres_true']:.2e}")
+        if timing:
+            for kc in ("GEMM", "ORTHO"):
+                h.timing_enable(kc, True)
+                h.timing_read(kc, reset=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for i in range(steps):
+            x, infos, rc = h.solve(rhs, **kw)
+            assert rc == svar.OK, infos
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        tm = {}
+        if timing:
+            for kc in ("GEMM", "ORTHO"):
+                tm[kc] = h.timing_read(kc, reset=True)
+                h.timing_enable(kc, False)
+        log(f"  {precision}: {steps} solves in {el:.3f}s, iters={infos[0]['iters']}, "
+            f"relres={infos[0]['relres_true']:.2e}")
+        return el, infos[0], tm, x
+
+    el64, info64, tm, x64 = run("FP64", args.steps, args.warmup, timing=True)
+    sps = args.steps / el64
+    it = int(info64["iters"])
+    res = {
+        "metric": "saddle solves/sec to 1e-6 rel residual; learned+batched vs plain FP64, 1 GPU",
+        "value": sps,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * el64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2 single window: s=4096, N=64, p_i=2048 random obs, SOAR B "
+                               "l=0.1, Q=0.1B, SOAR R l=0.05, implicit advection-diffusion; "
+                               f"P_I with L_M({args.k}) and R_RR; FGMRES rtol {args.rtol}",
+                   "path": "plain FP64 FGMRES (no restart)", "n_unknowns": int(win.n)},
+        "iters": it,
+        "relres_true": info64["relres_true"],
+        "setup_s": setup_s,
+    }
+    # roofline of the dominant kernel class (by measured time in the timed region)
+    gms, gl = tm["GEMM"]
+    oms, ol = tm["ORTHO"]
+    applies_a64 = 2  # refinement check after the cycle + final true residual
+    if gms >= oms:
+        flops = gemm_flops(win, it, applies_a64) * args.steps
+        ach = flops / (gms * 1e-3) / 1e12
+        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm_f64 (covariance products)",
+                           "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                           "launches": gl, "avg_ms": gms / max(gl, 1)}
+    else:
+        byts = ortho_bytes(win.n, it) * args.steps
+        ach = byts / (oms * 1e-3) / 1e9
+        res["roofline"] = {"bound": "hbm", "kernel": "k_fg_dot + k_fg_update (Gram-Schmidt)",
+                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "launches": ol, "avg_ms": oms / max(ol, 1)}
+    res["kernel_time_ms"] = {"gemm": gms, "gemm_launches": gl, "ortho": oms,
+                             "ortho_launches": ol}
+    if not args.no_mixed:
+        try:
+            elm, infom, _, xm = run("MIXED_BF16P", args.steps, args.warmup)
+            res["mixed_bf16p"] = {"value": args.steps / elm, "iters": infom["iters"],
+                                  "outer": infom["outer"], "relres_true": infom["relres_true"],
+                                  "speedup_vs_fp64": el64 / elm}
+        except Exception as e:  # reported, not fatal for the FP64 line
+            res["mixed_bf16p"] = {"error": str(e)[:200]}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(win, args, it)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(win, args, gpu_iters):
+    """The float64 oracle on the host cores: FGMRES timed for two short iteration counts
+    (operator cost a per iteration, Gram-Schmidt cost b per basis vector), extrapolated to
+    the GPU's iteration count: T(I) = a I + b I^2 / 2.  Set-up is excluded on both sides."""
+    from oracle import svar_oracle as so
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    orc = so.SaddleOracle(win, k=args.k, rhat="RR")
+    rhs = win.rhs[0]
+    times = []
+    m1, m2 = args.cpu_iters
+    for m in (m1, m2):
+        t = time.perf_counter()
+        so.fgmres(orc.apply_A, orc.apply_PI_inv, rhs, 1e-30, m)
+        times.append(time.perf_counter() - t)
+        log(f"  oracle {m} iterations: {times[-1]:.2f}s")
+    # T(m) = a m + b m^2 / 2
+    M = np.array([[m1, m1 * m1 / 2.0], [m2, m2 * m2 / 2.0]])
+    a, b = np.linalg.solve(M, np.array(times))
+    a, b = max(a, 1e-9), max(b, 0.0)
+    t_solve = a * gpu_iters + b * gpu_iters ** 2 / 2.0
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle FGMRES timed at {m1} and {m2} iterations on the same window "
+                      f"({sum(times):.1f}s), extrapolated to {gpu_iters} iterations",
+            "sec_per_solve": t_solve}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * svar.h -- C ABI of libsvar, an MI355X (gfx950) library for the preconditioned Krylov
+ * solve of the linearised weak-constraint 4D-Var saddle-point system
+ *
+ *     [ D   0   L ] [d eta]   [ b ]
+ *     [ 0   R   H ] [d nu ] = [ d ]        (Tabeart & Pearson, §2.1, eq. saddlepointsystem)
+ *     [ L^T H^T 0 ] [d x  ]   [ 0 ]
+ *
+ * with D = blkdiag(B, Q_1..Q_N), R = blkdiag(R_0..R_N), H = blkdiag(H_0..H_N) and L block
+ * lower-bidiagonal with identity diagonal and -M_i on the subdiagonal (eq. saddlepointA,
+ * eq. def:L).  Time blocks are numbered i = 0..N; M_i maps the state at time i-1 to time i.
+ *
+ * Conventions for every call below.
+ *  - Status: every function returns an int status (SVAR_OK on success).  On failure
+ *    svar_last_error() returns a thread-local, NUL-terminated message that stays valid until
+ *    the next call on the same thread.  No C++ exception crosses the ABI.
+ *  - Descriptor arrays (svar_window_desc and what it points to) are HOST memory, float64 /
+ *    int32, row-major; svar_create copies them to the device and the caller may free them
+ *    on return.
+ *  - Vector arguments of svar_apply_A / svar_apply_P / svar_apply_op / svar_solve are DEVICE
+ *    pointers (float64) owned by the caller; the library never frees caller memory.  Input
+ *    and output must not overlap.
+ *  - Packed layout: windows in creation order; inside a window, nrhs vectors of that window
+ *    one after another; a saddle vector of window w has length n_w = (2 s + pbar)(N+1) and
+ *    holds (eta_0..eta_N | nu_0..nu_N | x_0..x_N), each eta_i / x_i of length s and nu_i of
+ *    length p_i.  svar_offsets() returns the element offset of every window.
+ *  - stream is a hipStream_t (NULL = default stream).  Calls are stream ordered and
+ *    asynchronous except svar_create (synchronous set-up) and svar_solve, which synchronises
+ *    the stream to read convergence flags and returns with info filled.  One handle must not
+ *    be used from two streams or threads at once.
+ */
+#ifndef SVAR_H
+#define SVAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define SVAR_OK 0
+#define SVAR_E_INVAL 1      /* bad argument or descriptor (message says which) */
+#define SVAR_E_NOTSPD 2     /* a covariance (or Rhat / Dhat) is not symmetric positive definite */
+#define SVAR_E_NOCONV 3     /* maxit reached; x holds the last iterate, info is filled */
+#define SVAR_E_BREAKDOWN 4  /* non-finite value met in the Krylov recurrence */
+#define SVAR_E_HIP 5        /* a HIP runtime call failed */
+#define SVAR_E_NOMEM 6      /* device allocation failed */
+
+/* ------------------------------------------------------------------ model maps M_i */
+#define SVAR_MODEL_DENSE 0               /* M_i given as dense s x s matrices, i = 1..N       */
+#define SVAR_MODEL_CIRC_BAND 1           /* (M x)_j = sum_t w_t x_{(j + off_t) mod s}, all i */
+#define SVAR_MODEL_PERIODIC_TRIDIAG_INV 2/* M = T^{-1}, (T x)_j = a x_{j-1} + b x_j + c x_{j+1}
+                                            periodic, same for all i (implicit advection-
+                                            diffusion step)                                 */
+#define SVAR_MODEL_L96_TLM 3             /* tangent linear of nsteps RK4 steps of Lorenz-96
+                                            about a stored trajectory (see fields)          */
+
+typedef struct svar_model_desc {
+  int32_t kind;
+  /* DENSE: dense[i-1] points to M_i (s x s, row-major), i = 1..N */
+  const double* const* dense;
+  /* CIRC_BAND */
+  int32_t ntaps;
+  const int32_t* offsets;   /* [ntaps], any integers (taken modulo s) */
+  const double* weights;    /* [ntaps] */
+  /* PERIODIC_TRIDIAG_INV: a, b, c as above; |b| > |a| + |c| required */
+  double tri_a, tri_b, tri_c;
+  /* L96_TLM: dx_j/dt = (x_{j+1} - x_{j-2}) x_{j-1} - x_j + F (periodic, §7.1); M_i is the
+     Jacobian of l96_nsteps RK4 steps of length l96_dt started from l96_traj[(i-1)*s ..]. */
+  double l96_F, l96_dt;
+  int32_t l96_nsteps;
+  const double* l96_traj;   /* [N+1][s] linearisation states x_0..x_N (x_N unused) */
+} svar_model_desc;
+
+/* ------------------------------------------------------------------ one window */
+typedef struct svar_window_desc {
+  int32_t s;                 /* state size per time block                          */
+  int32_t N;                 /* number of subwindows; blocks i = 0..N               */
+  const int32_t* p;          /* [N+1] observations per block, p_i >= 0              */
+  /* D_i = d_scale[i] * dmats[d_index[i]]  (B = D_0, Q_i = D_i)                    */
+  int32_t n_dmat;
+  const double* const* dmats;/* [n_dmat] s x s symmetric positive definite          */
+  const int32_t* d_index;    /* [N+1]                                               */
+  const double* d_scale;     /* [N+1] > 0                                           */
+  /* R_i = rmats[r_index[i]], size p_i x p_i                                        */
+  int32_t n_rmat;
+  const double* const* rmats;/* [n_rmat] symmetric positive definite                */
+  const int32_t* r_index;    /* [N+1]                                               */
+  /* H_i in ELL form: row r of block i is sum_w h_vals[.][w] x_i[h_cols[.][w]]        */
+  int32_t h_width;           /* entries per observation row, >= 1                   */
+  const int32_t* h_cols;     /* [sum_i p_i * h_width], blocks concatenated, in [0,s) */
+  const double* h_vals;      /* same shape                                          */
+  svar_model_desc model;
+} svar_window_desc;
+
+/* ------------------------------------------------------------------ preconditioner options */
+#define SVAR_PREC_NONE 0
+#define SVAR_PREC_PD 1   /* block diagonal blkdiag(Dhat, Rhat, Lhat^T D^{-1} Lhat), eq. prec */
+#define SVAR_PREC_PI 2   /* inexact constraint [[D,0,Lhat],[0,Rhat,0],[Lhat^T,0,0]], eq. prec */
+
+#define SVAR_RHAT_DIAG 0   /* diag(R_i)                                          §5.1      */
+#define SVAR_RHAT_RR 1     /* R_i + gamma I (ridge regression)                   Alg. 1    */
+#define SVAR_RHAT_ME 2     /* eigenvalues below T raised to T (minimum eigenvalue) Alg. 2  */
+#define SVAR_RHAT_EXACT 3  /* R_i itself                                                   */
+
+typedef struct svar_prec_opts {
+  int32_t type;      /* SVAR_PREC_*                                                        */
+  int32_t k;         /* Lhat = L_M(k), 1 <= k <= N+1 (Definition 1; k = 1 gives L_0 = I)   */
+  int32_t rhat;      /* SVAR_RHAT_*                                                        */
+  double rr_gamma;   /* gamma of R_RR; < 0 selects lambda_min(R_i) (§6.1)                  */
+  double me_T;       /* threshold of R_ME; < 0 selects the second smallest eigenvalue      */
+  double d_ridge;    /* Dhat_i = D_i + d_ridge I (§6.1 uses 0.01); used by PD only         */
+} svar_prec_opts;
+
+/* ------------------------------------------------------------------ solver options */
+#define SVAR_METHOD_FGMRES 0  /* right-preconditioned flexible GMRES                    */
+#define SVAR_METHOD_MINRES 1  /* preconditioned MINRES, needs SVAR_PREC_PD or NONE        */
+
+#define SVAR_PRECISION_FP64 0         /* every operator in float64                       */
+#define SVAR_PRECISION_MIXED_FP32 1   /* FP64 refinement; inner A and P in float32       */
+#define SVAR_PRECISION_MIXED_BF16P 2  /* FP64 refinement; inner A float32, P covariance
+                                         products bfloat16 with float32 accumulation      */
+
+typedef struct svar_solve_opts {
+  int32_t method;     /* SVAR_METHOD_*                                                      */
+  double rtol;        /* stop when ||rhs - A x||_2 <= rtol ||rhs||_2 (per right-hand side)  */
+  int32_t maxit;      /* Krylov iterations allowed in total (per right-hand side)           */
+  int32_t restart;    /* FGMRES basis size per cycle; 0 = no restart (one cycle of maxit)   */
+  int32_t precision;  /* SVAR_PRECISION_*                                                   */
+  double inner_rtol;  /* mixed precision: relative tolerance of each inner cycle            */
+  int32_t max_outer;  /* refinement / restart cycles allowed (>= 1)                         */
+} svar_solve_opts;
+
+typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */
+  int32_t iters;        /* Krylov iterations used (all cycles)                              */
+  int32_t outer;        /* refinement / restart cycles used                                 */
+  int32_t status;       /* SVAR_OK, SVAR_E_NOCONV or SVAR_E_BREAKDOWN                       */
+  int32_t reserved;
+  double relres_true;   /* ||rhs - A x||_2 / ||rhs||_2 computed in float64 at return        */
+  double relres_est;    /* the solver's own estimate at its last iteration                  */
+  /* matrix-vector products with component blocks, counted as in Tables 4 and 5 */
+  int64_t n_M, n_MT, n_D, n_R, n_Rhat_inv, n_Dhat_inv;
+} svar_solve_info;
+
+typedef struct svar_handle svar_handle;
+
+/* Create a handle for nwin windows (all with the same preconditioner options).  Copies the
+   descriptors to the device of the calling thread, then builds Rhat^{-1} and Dhat^{-1} on
+   the GPU (§6.2: Rhat_i is precomputed before the iteration).  Synchronous. */
+int svar_create(const svar_window_desc* windows, int32_t nwin, const svar_prec_opts* popts,
+                svar_handle** out, void* stream);
+
+/* Release every device buffer of the handle.  NULL is accepted. */
+int svar_destroy(svar_handle* h);
+
+/* Per-RHS saddle vector length n_w of window w (or -1 if w is out of range). */
+int64_t svar_system_size(const svar_handle* h, int32_t w);
+
+/* off[w] = element offset of window w in a packed vector of nrhs right-hand sides per window;
+   off[nwin] = total length.  off must hold nwin + 1 entries (host memory). */
+int svar_offsets(const svar_handle* h, int32_t nrhs, int64_t* off);
+
+/* y = A v for every window and right-hand side (§6.2: c1 = D v1 + L v3, c2 = R v2 + H v3,
+   c3 = L^T v1 + H^T v2). */
+int svar_apply_A(svar_handle* h, int32_t nrhs, const double* v, double* y, void* stream);
+
+/* z = P^{-1} v with the handle's preconditioner (§6.2):
+   P_D^{-1} v = (Dhat^{-1} v1, Rhat^{-1} v2, Lhat^{-1} D Lhat^{-T} v3),
+   P_I^{-1} v = (c1 = Lhat^{-T} v3, Rhat^{-1} v2, Lhat^{-1}(v1 - D c1)). */
+int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void* stream);
+
+/* Component maps, for checking each step on its own.  Vectors of the "state" space hold
+   (N+1) s entries per (window, rhs); those of the "obs" space hold sum_i p_i entries; packed
+   window by window and rhs by rhs like saddle vectors. */
+#define SVAR_OP_L 0           /* state -> state: L x                                    */
+#define SVAR_OP_LT 1          /* state -> state: L^T x                                  */
+#define SVAR_OP_LHAT_INV 2    /* state -> state: L_M(k)^{-1} x                          */
+#define SVAR_OP_LHAT_INVT 3   /* state -> state: L_M(k)^{-T} x                          */
+#define SVAR_OP_D 4           /* state -> state: D x                                    */
+#define SVAR_OP_DHAT_INV 5    /* state -> state: Dhat^{-1} x (needs a PD handle)        */
+#define SVAR_OP_R 6           /* obs -> obs: R y                                        */
+#define SVAR_OP_RHAT_INV 7    /* obs -> obs: Rhat^{-1} y                                */
+#define SVAR_OP_H 8           /* state -> obs: H x                                      */
+#define SVAR_OP_HT 9          /* obs -> state: H^T y                                    */
+int svar_apply_op(svar_handle* h, int32_t op, int32_t nrhs, const double* in, double* out,
+                  void* stream);
+
+/* Solve A x = rhs for nrhs right-hand sides per window, x0 = 0.  info: host array of
+   nwin * nrhs entries (packed order).  Returns SVAR_OK when every system met rtol,
+   SVAR_E_NOCONV / SVAR_E_BREAKDOWN when one did not (x then holds its last iterate). */
+int svar_solve(svar_handle* h, const svar_solve_opts* opts, int32_t nrhs, const double* rhs,
+               double* x, svar_solve_info* info, void* stream);
+
+/* Set-up results of window w: gamma of R_RR, T of R_ME and lambda_1(R_i) for each distinct
+   R matrix (host arrays of n_rmat entries; NaN where not applicable; any may be NULL). */
+int svar_rhat_params(const svar_handle* h, int32_t w, double* gamma, double* T, double* lam1);
+
+/* Kernel timing: when enabled, the library records HIP events around every launch of the
+   given kernel class on the caller's stream and accumulates their durations. */
+#define SVAR_KCLASS_GEMM 0      /* covariance products (D, R, Rhat^{-1}, Dhat^{-1})      */
+#define SVAR_KCLASS_ORTHO 1     /* Gram-Schmidt passes of FGMRES                          */
+#define SVAR_KCLASS_MODEL 2     /* model products and Lhat sweeps                         */
+#define SVAR_KCLASS_COUNT 3
+int svar_timing_enable(svar_handle* h, int32_t kclass, int32_t on);
+/* total_ms, launches: host pointers; resets the accumulators when reset != 0. */
+int svar_timing_read(svar_handle* h, int32_t kclass, double* total_ms, int64_t* launches,
+                     int32_t reset);
+
+const char* svar_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVAR_H */

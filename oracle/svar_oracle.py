@@ -209,6 +209,9 @@ class SaddleOracle:
 
     # ---------------------------------------------------------- Rhat (§5, §6.1)
     def _rhat_setup(self, R, kind, rr_gamma, me_T, idx):
+        if R.shape[0] == 0:  # a matrix used only by blocks without observations
+            self.rhat_params[idx] = {}
+            return ("diag", np.zeros(0))
         if kind == "DIAG":
             self.rhat_params[idx] = {}
             return ("diag", np.diag(R).copy())

@@ -1,0 +1,230 @@
+// Covariance products Y = beta Z + diag(alpha) (C X) on MFMA (gfx950).
+//
+// The dense covariance blocks B, Q_i = q B, R_i and the precomputed Rhat_i^{-1}, Dhat_i^{-1}
+// multiply all time blocks (and right-hand sides) at once, so each product is one GEMM of an
+// n x n matrix with an n x ncols panel of vectors (§6.2: "loop over the N+1 blocks" becomes
+// one matrix-panel product because the blocks share the matrix).
+//
+// Tiling: a workgroup is four wave64s; each wave owns 16 rows of C and CT x 16 columns of the
+// panel and walks its k-range in steps of 16 with v_mfma_f64_16x16x4f64.  Within a step a
+// lane loads four consecutive k of its row of C and four consecutive k of its panel column,
+// so both operands are read as 32-byte runs straight from global memory; the order in which
+// the four MFMAs of a step consume k is the same for both operands, so the contraction is
+// unchanged.  Splitting k over several workgroups gives enough waves for 256 CUs; the split
+// partials are summed in a fixed order by a second kernel (deterministic results).
+#include "svar_impl.h"
+
+namespace svar {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double* opnd(const Bases& b, const Operand& o) {
+  return b.p[o.base] + o.off;
+}
+
+__device__ __forceinline__ void gemm_store(const GemmProb& P, const Bases& b, int r, int c,
+                                           double acc) {
+  const int co = c / P.per, ci = c - co * P.per;
+  const double a = P.alpha0 * (P.alpha ? P.alpha[ci] : 1.0);
+  double y = a * acc;
+  if (P.Z.base >= 0 && P.beta != 0.0) y += P.beta * opnd(b, P.Z)[co * P.zo + ci * P.zi + r];
+  opnd(b, P.Y)[co * P.yo + ci * P.yi + r] = y;
+}
+
+// element loads of the matrix in its storage type, widened to double / float
+__device__ __forceinline__ double ld_c(const void* C, size_t i, int dt) {
+  if (dt == DT_F64) return ((const double*)C)[i];
+  if (dt == DT_F32) return (double)((const float*)C)[i];
+  const unsigned short h = ((const unsigned short*)C)[i];
+  return (double)__uint_as_float(((unsigned)h) << 16);
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ probs,
+                                                  const GemmTask* __restrict__ tasks,
+                                                  double* __restrict__ ws, Bases b,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const GemmTask t = tasks[blockIdx.x];
+  const GemmProb P = probs[t.prob];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int rbase = t.row0 + wave * 16;
+  if (rbase >= P.n) return;
+  const int rowA = rbase + r16;
+  const bool rowok = rowA < P.n;
+  const double* __restrict__ A = (const double*)P.C + (size_t)(rowok ? rowA : 0) * P.n;
+  const double* X = opnd(b, P.X);
+  const double* xp[CT];
+  bool cok[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = t.col0 + ct * 16 + r16;
+    cok[ct] = c < P.ncols;
+    const int cc = cok[ct] ? c : 0;
+    const int co = cc / P.per, ci = cc - co * P.per;
+    xp[ct] = X + co * P.xo + ci * P.xi;
+  }
+  v4d acc[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  int k = t.k0;
+  for (; k + 16 <= t.k1; k += 16) {
+    const int kk = k + 4 * q;
+    double a[4], bb[CT][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = rowok ? A[kk + i] : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bb[ct][i] = cok[ct] ? xp[ct][kk + i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[ct][i], acc[ct], 0, 0, 0);
+  }
+  if (k < t.k1) {  // ragged tail of the k-range
+    const int kk = k + 4 * q;
+    double a[4], bb[CT][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = (rowok && kk + i < t.k1) ? A[kk + i] : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bb[ct][i] = (cok[ct] && kk + i < t.k1) ? xp[ct][kk + i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[ct][i], acc[ct], 0, 0, 0);
+  }
+  // lane holds rows rbase + 4q + e (e = 0..3) of column col0 + 16 ct + r16
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = t.col0 + ct * 16 + r16;
+    if (c >= P.ncols) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rbase + 4 * q + e;
+      if (r >= P.n) continue;
+      if (P.splits > 1)
+        ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = acc[ct][e];
+      else
+        gemm_store(P, b, r, c, acc[ct][e]);
+    }
+  }
+}
+
+// Reduced-precision matrix (float32 or bfloat16 storage) with float32 MFMA accumulation.
+// The panel is converted to float on load; accumulation is float32 (v_mfma_f32_16x16x4f32).
+template <int CT>
+__global__ __launch_bounds__(256) void k_gemm_lp(const GemmProb* __restrict__ probs,
+                                                 const GemmTask* __restrict__ tasks,
+                                                 double* __restrict__ ws, Bases b,
+                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const GemmTask t = tasks[blockIdx.x];
+  const GemmProb P = probs[t.prob];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, q = lane >> 4;
+  const int rbase = t.row0 + wave * 16;
+  if (rbase >= P.n) return;
+  const int rowA = rbase + r16;
+  const bool rowok = rowA < P.n;
+  const size_t abase = (size_t)(rowok ? rowA : 0) * P.n;
+  const double* X = opnd(b, P.X);
+  const double* xp[CT];
+  bool cok[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = t.col0 + ct * 16 + r16;
+    cok[ct] = c < P.ncols;
+    const int cc = cok[ct] ? c : 0;
+    const int co = cc / P.per, ci = cc - co * P.per;
+    xp[ct] = X + co * P.xo + ci * P.xi;
+  }
+  v4f acc[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int k = t.k0; k < t.k1; k += 16) {
+    const int kk = k + 4 * q;
+    float a[4], bb[CT][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = (rowok && kk + i < t.k1) ? (float)ld_c(P.C, abase + kk + i, P.dtype) : 0.f;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        bb[ct][i] = (cok[ct] && kk + i < t.k1) ? (float)xp[ct][kk + i] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[ct][i], acc[ct], 0, 0, 0);
+  }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = t.col0 + ct * 16 + r16;
+    if (c >= P.ncols) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rbase + 4 * q + e;
+      if (r >= P.n) continue;
+      if (P.splits > 1)
+        ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = (double)acc[ct][e];
+      else
+        gemm_store(P, b, r, c, (double)acc[ct][e]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict__ probs,
+                                                     const int* __restrict__ list,
+                                                     const double* __restrict__ ws, Bases b,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const GemmProb P = probs[list[blockIdx.y]];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t tot = (int64_t)P.n * P.ncols;
+  if (e >= tot) return;
+  const int c = (int)(e / P.n), r = (int)(e - (int64_t)c * P.n);
+  double s = 0.0;
+  for (int sp = 0; sp < P.splits; ++sp) s += ws[P.ws_off + ((int64_t)sp * P.ncols + c) * P.n + r];
+  gemm_store(P, b, r, c, s);
+}
+
+template <int CT>
+static void launch_ct(const GemmPlanDev& g, Bases b, double* ws, const int* skip,
+                      hipStream_t st) {
+  if (g.dtype == DT_F64)
+    hipLaunchKernelGGL(k_gemm_f64<CT>, dim3(g.ntask), dim3(256), 0, st, g.probs, g.tasks, ws, b,
+                       skip);
+  else
+    hipLaunchKernelGGL(k_gemm_lp<CT>, dim3(g.ntask), dim3(256), 0, st, g.probs, g.tasks, ws, b,
+                       skip);
+}
+
+void launch_gemm(const GemmPlanDev& g, Bases b, double* ws, const int* skip, hipStream_t st) {
+  if (g.ntask == 0) return;
+  switch (g.maxct) {
+    case 1: launch_ct<1>(g, b, ws, skip, st); break;
+    case 2: launch_ct<2>(g, b, ws, skip, st); break;
+    case 3: launch_ct<3>(g, b, ws, skip, st); break;
+    case 4: launch_ct<4>(g, b, ws, skip, st); break;
+    case 5: launch_ct<5>(g, b, ws, skip, st); break;
+    case 6: launch_ct<6>(g, b, ws, skip, st); break;
+    case 7: launch_ct<7>(g, b, ws, skip, st); break;
+    default: launch_ct<8>(g, b, ws, skip, st); break;
+  }
+  if (!g.reduce_probs.empty()) {
+    const int gx = (int)((g.max_reduce_elems + 255) / 256);
+    hipLaunchKernelGGL(k_gemm_reduce, dim3(gx, (unsigned)g.reduce_probs.size()), dim3(256), 0, st,
+                       g.probs, g.reduce_list, ws, b, skip);
+  }
+}
+
+}  // namespace svar

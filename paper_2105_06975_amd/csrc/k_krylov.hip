@@ -1,0 +1,510 @@
+// Device-resident flexible GMRES (right preconditioned, x0 = 0 per cycle), float64.
+//
+// Many independent systems (windows x right-hand sides) advance in lock step; each has its
+// own Hessenberg matrix, Givens rotations and convergence flag.  The iteration counter j is
+// kept in device memory so that one iteration is the same sequence of launches every time.
+//
+// Orthogonalisation: classical Gram-Schmidt with the second (re-orthogonalisation) pass of
+// each new vector delayed into the next iteration.  Iteration j holds u_j, the candidate for
+// v_j after one projection, scaled to unit norm, and uses it directly as the input of the
+// preconditioner (flexible GMRES accepts any z_j; A Z = V Hbar stays exact).  With
+// w = A P^{-1} u_j, one pass over V_{0..j-1} computes V^T w, V^T u_j, u_j^T w, u_j^T u_j; then
+//   v_j = (u_j - V s)/nu,  s = V^T u_j,  nu^2 = u_j^T u_j - s^T s,
+//   column j-1 of Hbar = (h_{j-1} + s/sigma_j, nu/sigma_j)    (sigma_j: scale applied to u_j),
+//   provisional column j: h_t = (V^T w)_t, h_j = (u_j^T w - s^T V^T w)/nu,
+// and a second pass writes v_j and u_{j+1} = w - V h - v_j h_j.  Two reads of the basis per
+// iteration instead of four for two-pass classical Gram-Schmidt.
+#include "svar_impl.h"
+#include "krylov.h"
+
+namespace svar {
+
+static constexpr int NT = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum of one value per thread; every thread gets the result
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  __syncthreads();
+  if (ln == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  return t;
+}
+
+// ---------------------------------------------------------------- norms
+__global__ __launch_bounds__(NT) void k_nrm2_part(const KTask* __restrict__ tasks,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  const KTask t = tasks[blockIdx.x];
+  double acc = 0.0;
+  for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) acc += x[e] * x[e];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// per-system sum of task partials (fixed order)
+__global__ __launch_bounds__(64) void k_seg_sum(const KSys* __restrict__ sys,
+                                                const double* __restrict__ part,
+                                                double* __restrict__ out) {
+  const KSys S = sys[blockIdx.x];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < S.ntask; i += 64) acc += part[S.task0 + i];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------- cycle start
+// u = r / ||r|| per system; state reset; global j = 0.
+__global__ __launch_bounds__(NT) void k_fg_start(const KTask* __restrict__ tasks,
+                                                 const KSys* __restrict__ sys,
+                                                 const double* __restrict__ part,
+                                                 const double* __restrict__ r,
+                                                 double* __restrict__ u, KState* __restrict__ st,
+                                                 const double* __restrict__ tol_rel,
+                                                 KGlobal* __restrict__ gl, int nsys) {
+  __shared__ double red[NT / 64];
+  const KTask t = tasks[blockIdx.x];
+  const KSys S = sys[t.sys];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < S.ntask; i += NT) acc += part[S.task0 + i];
+  const double nrm = sqrt(block_sum(acc, red));
+  const bool zero = !(nrm > 0.0);
+  const double sig = zero ? 0.0 : 1.0 / nrm;
+  for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) u[e] = r[e] * sig;
+  if (threadIdx.x == 0 && blockIdx.x == (unsigned)S.task0) {
+    KState s0;
+    s0.done = (zero || tol_rel[t.sys] >= 1.0) ? 1 : 0;  // tol_rel >= 1: inactive system
+    s0.iters = 0;
+    s0.status = isfinite(nrm) ? 0 : SVAR_E_BREAKDOWN;
+    if (!isfinite(nrm)) s0.done = 1;
+    s0.pad = 0;
+    s0.beta = nrm;
+    s0.tol_abs = tol_rel[t.sys] * nrm;
+    s0.sigma = sig;
+    s0.nu = 0.0;
+    s0.est = nrm;
+    st[t.sys] = s0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    gl->j = 0;
+    gl->remaining = nsys;  // corrected by k_fg_count
+  }
+}
+
+// count systems that are already done at the start of a cycle
+__global__ void k_fg_count(const KState* __restrict__ st, KGlobal* __restrict__ gl, int nsys) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int rem = 0;
+    for (int i = 0; i < nsys; ++i) rem += st[i].done ? 0 : 1;
+    gl->remaining = rem;
+    gl->all_done = rem == 0 ? 1 : 0;
+  }
+}
+
+// u *= 1 / ||u|| (norm from the update pass partials); sigma recorded; j advanced.
+__global__ __launch_bounds__(NT) void k_fg_scale(const KTask* __restrict__ tasks,
+                                                 const KSys* __restrict__ sys,
+                                                 const double* __restrict__ part,
+                                                 double* __restrict__ u, KState* __restrict__ st,
+                                                 KGlobal* __restrict__ gl) {
+  __shared__ double red[NT / 64];
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  const KSys S = sys[t.sys];
+  if (st[t.sys].done) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < S.ntask; i += NT) acc += part[S.task0 + i];
+  const double nrm = sqrt(block_sum(acc, red));
+  const double sig = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) u[e] *= sig;
+  if (threadIdx.x == 0 && blockIdx.x == (unsigned)S.task0) st[t.sys].sigma = sig;
+}
+
+// ---------------------------------------------------------------- dot pass
+// partial sums per task: [0, j) V^T w, [m, m+j) V^T u, 2m: u^T w, 2m+1: u^T u.
+// Also stores z into Z[j].  Each thread keeps its EPT elements of u and w in registers.
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_fg_dot(const KTask* __restrict__ tasks,
+                                               const KState* __restrict__ st,
+                                               const KGlobal* __restrict__ gl,
+                                               const double* __restrict__ V,
+                                               const double* __restrict__ u,
+                                               const double* __restrict__ w,
+                                               const double* __restrict__ z,
+                                               double* __restrict__ Zb, int64_t ntot, int m,
+                                               int with_w, double* __restrict__ part) {
+  __shared__ double lw[NT / 64][64];
+  __shared__ double lu[NT / 64][64];
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  if (st[t.sys].done) return;
+  const int j = gl->j;
+  const int SL = 2 * m + 2;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  double ur[EPT], wr[EPT];
+  int64_t idx[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    idx[q] = t.e0 + threadIdx.x + (int64_t)q * NT;
+    const bool ok = idx[q] < t.e1;
+    ur[q] = ok ? u[idx[q]] : 0.0;
+    wr[q] = (ok && with_w) ? w[idx[q]] : 0.0;
+    if (ok && with_w) Zb[(int64_t)j * ntot + idx[q]] = z[idx[q]];
+  }
+  double* P = part + (int64_t)blockIdx.x * SL;
+  for (int t0 = 0; t0 < j; t0 += 64) {
+    const int tn = min(64, j - t0);
+    for (int tt = 0; tt < tn; ++tt) {
+      const double* Vt = V + (int64_t)(t0 + tt) * ntot;
+      double aw = 0.0, au = 0.0;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const double v = idx[q] < t.e1 ? Vt[idx[q]] : 0.0;
+        aw += v * wr[q];
+        au += v * ur[q];
+      }
+      aw = wave_sum(aw);
+      au = wave_sum(au);
+      if (ln == 0) {
+        lw[wv][tt] = aw;
+        lu[wv][tt] = au;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < tn) {
+      double a = 0.0, c = 0.0;
+      for (int i = 0; i < NT / 64; ++i) {
+        a += lw[i][threadIdx.x];
+        c += lu[i][threadIdx.x];
+      }
+      P[t0 + threadIdx.x] = a;
+      P[m + t0 + threadIdx.x] = c;
+    }
+    __syncthreads();
+  }
+  double uw = 0.0, uu = 0.0;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    uw += ur[q] * wr[q];
+    uu += ur[q] * ur[q];
+  }
+  uw = wave_sum(uw);
+  uu = wave_sum(uu);
+  if (ln == 0) {
+    lw[wv][0] = uw;
+    lu[wv][0] = uu;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int i = 0; i < NT / 64; ++i) {
+      a += lw[i][0];
+      c += lu[i][0];
+    }
+    P[2 * m] = a;
+    P[2 * m + 1] = c;
+  }
+}
+
+// sums[sys][slot] = sum over the system's tasks of part[task][slot] (fixed order).
+// grid: (nsys, ceil(nslot_used / 8)); block 256 = 8 slots x 32 task lanes.
+__global__ __launch_bounds__(NT) void k_fg_reduce(const KSys* __restrict__ sys,
+                                                  const KState* __restrict__ st,
+                                                  const KGlobal* __restrict__ gl,
+                                                  const double* __restrict__ part,
+                                                  double* __restrict__ sums, int m) {
+  __shared__ double red[8][33];
+  if (gl->all_done) return;
+  if (st[blockIdx.x].done) return;
+  const KSys S = sys[blockIdx.x];
+  const int j = gl->j;
+  const int SL = 2 * m + 2;
+  const int nused = 2 * j + 2;  // compact index -> slot
+  const int sl = threadIdx.x >> 5, tl = threadIdx.x & 31;
+  const int ci = blockIdx.y * 8 + sl;
+  int slot = -1;
+  if (ci < nused) slot = ci < j ? ci : (ci < 2 * j ? m + (ci - j) : 2 * m + (ci - 2 * j));
+  double acc = 0.0;
+  if (slot >= 0)
+    for (int i = tl; i < S.ntask; i += 32) acc += part[(int64_t)(S.task0 + i) * SL + slot];
+  red[sl][tl] = acc;
+  __syncthreads();
+  if (tl == 0 && slot >= 0) {
+    double s = 0.0;
+    for (int i = 0; i < 32; ++i) s += red[sl][i];
+    sums[(int64_t)blockIdx.x * SL + slot] = s;
+  }
+}
+
+// ---------------------------------------------------------------- small dense step
+// One workgroup per system: finalise column j-1, Givens, convergence, coefficients for the
+// update pass.  finalize_only: no new column (last iteration of a cycle).
+__global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGlobal* __restrict__ gl,
+                                                 const double* __restrict__ sums,
+                                                 KHess* __restrict__ hs, int m, int finalize_only) {
+  __shared__ double red[NT / 64];
+  __shared__ double col[1];
+  if (gl->all_done) return;
+  KState S = st[blockIdx.x];
+  const int j = gl->j;
+  if (S.done) return;
+  const int SL = 2 * m + 2;
+  const double* sm = sums + (int64_t)blockIdx.x * SL;
+  KHess Hh = hs[blockIdx.x];
+  // s = V^T u, ss = s^T s, sa = s^T (V^T w)
+  double ss = 0.0, sa = 0.0;
+  for (int t = threadIdx.x; t < j; t += NT) {
+    const double sv = sm[m + t];
+    ss += sv * sv;
+    sa += sv * sm[t];
+    Hh.coef_s[t] = sv;
+  }
+  ss = block_sum(ss, red);
+  sa = block_sum(sa, red);
+  const double uu = sm[2 * m + 1], uw = sm[2 * m];
+  const double nu2 = uu - ss;
+  const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+  const double sig = S.sigma;
+  // finalise column j-1: H[0..j-1][j-1] = hprev + s / sigma, H[j][j-1] = nu / sigma
+  if (j >= 1) {
+    double* Hc = Hh.H + (int64_t)(j - 1) * (m + 1);
+    for (int t = threadIdx.x; t < j; t += NT) Hc[t] = Hh.hprev[t] + sm[m + t] / sig;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Hc[j] = nu / sig;
+      for (int i = 0; i < j - 1; ++i) {
+        const double a = Hc[i], bq = Hc[i + 1];
+        Hc[i] = Hh.cs[i] * a + Hh.sn[i] * bq;
+        Hc[i + 1] = -Hh.sn[i] * a + Hh.cs[i] * bq;
+      }
+      const double a = Hc[j - 1], bq = Hc[j];
+      double rho = hypot(a, bq);
+      double c = 1.0, s = 0.0;
+      if (rho > 0.0) {
+        c = a / rho;
+        s = bq / rho;
+      }
+      Hh.cs[j - 1] = c;
+      Hh.sn[j - 1] = s;
+      Hc[j - 1] = rho;
+      Hc[j] = 0.0;
+      const double gj = Hh.g[j - 1];
+      Hh.g[j] = -s * gj;
+      Hh.g[j - 1] = c * gj;
+      S.est = fabs(Hh.g[j]);
+      S.iters = j;
+      bool fin = isfinite(S.est) && isfinite(rho);
+      if (!fin) {
+        S.status = SVAR_E_BREAKDOWN;
+        S.done = 1;
+      } else if (S.est <= S.tol_abs || !(nu / sig > 1e-300) || rho == 0.0) {
+        S.done = 1;  // converged, or happy breakdown (invariant Krylov space)
+      } else if (finalize_only) {
+        S.done = 1;  // cycle exhausted
+        S.status = SVAR_E_NOCONV;
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    Hh.g[0] = nu / sig;  // r = (nu / sigma) v_0
+    S.est = Hh.g[0];
+  }
+  __syncthreads();
+  // provisional column j of w
+  if (threadIdx.x == 0) {
+    col[0] = nu > 0.0 ? (uw - sa) / nu : 0.0;
+    if (!S.done && !(nu > 0.0)) {  // u_j vanished: Krylov space exhausted at j (j = 0 only)
+      S.done = 1;
+      S.iters = j;
+    }
+  }
+  __syncthreads();
+  if (!finalize_only) {
+    for (int t = threadIdx.x; t < j; t += NT) Hh.hprev[t] = sm[t];
+    if (threadIdx.x == 0) Hh.hprev[j] = col[0];
+  }
+  if (threadIdx.x == 0) {
+    S.nu = nu;
+    st[blockIdx.x] = S;
+    if (S.done) {
+      const int left = atomicSub(&gl->remaining, 1) - 1;
+      if (left == 0) gl->all_done = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- update pass
+// v_j = (u - V s)/nu -> V[j];  u <- w - V h - v_j h_j;  partial ||u||^2 per task.
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_fg_update(const KTask* __restrict__ tasks,
+                                                  const KState* __restrict__ st,
+                                                  const KGlobal* __restrict__ gl,
+                                                  double* __restrict__ V, double* __restrict__ u,
+                                                  const double* __restrict__ w,
+                                                  const KHess* __restrict__ hs, int64_t ntot,
+                                                  double* __restrict__ part) {
+  extern __shared__ double coef[];  // [2 j + 1]: s_0..s_{j-1}, h_0..h_j
+  __shared__ double red[NT / 64];
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  const KState S = st[t.sys];
+  if (S.done) return;
+  const int j = gl->j;
+  const KHess Hh = hs[t.sys];
+  for (int i = threadIdx.x; i < j; i += NT) coef[i] = Hh.coef_s[i];
+  for (int i = threadIdx.x; i <= j; i += NT) coef[j + i] = Hh.hprev[i];
+  __syncthreads();
+  double as[EPT], ah[EPT];
+  int64_t idx[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    idx[q] = t.e0 + threadIdx.x + (int64_t)q * NT;
+    as[q] = 0.0;
+    ah[q] = 0.0;
+  }
+  for (int tt = 0; tt < j; ++tt) {
+    const double* Vt = V + (int64_t)tt * ntot;
+    const double cs_ = coef[tt], ch = coef[j + tt];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      if (idx[q] < t.e1) {
+        const double v = Vt[idx[q]];
+        as[q] += v * cs_;
+        ah[q] += v * ch;
+      }
+    }
+  }
+  const double inu = 1.0 / S.nu, hj = coef[2 * j];
+  double acc = 0.0;
+  double* Vj = V + (int64_t)j * ntot;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    if (idx[q] < t.e1) {
+      const double vj = (u[idx[q]] - as[q]) * inu;
+      Vj[idx[q]] = vj;
+      const double un = w[idx[q]] - ah[q] - vj * hj;
+      u[idx[q]] = un;
+      acc += un * un;
+    }
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// advance the iteration counter (single thread)
+__global__ void k_fg_advance(KGlobal* __restrict__ gl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && !gl->all_done) gl->j = gl->j + 1;
+}
+
+// ---------------------------------------------------------------- end of cycle
+// y = R^{-1} g (upper triangular from the rotated Hessenberg), one workgroup per system.
+__global__ __launch_bounds__(64) void k_fg_solve_y(const KState* __restrict__ st,
+                                                   KHess* __restrict__ hs, int m) {
+  const KState S = st[blockIdx.x];
+  KHess Hh = hs[blockIdx.x];
+  const int nc = S.iters;
+  if (threadIdx.x != 0) return;
+  for (int i = nc - 1; i >= 0; --i) {
+    double acc = Hh.g[i];
+    for (int c = i + 1; c < nc; ++c) acc -= Hh.H[(int64_t)c * (m + 1) + i] * Hh.y[c];
+    const double d = Hh.H[(int64_t)i * (m + 1) + i];
+    Hh.y[i] = d != 0.0 ? acc / d : 0.0;
+  }
+}
+
+// x += Z y over each system's used columns
+__global__ __launch_bounds__(NT) void k_fg_xupdate(const KTask* __restrict__ tasks,
+                                                   const KState* __restrict__ st,
+                                                   const KHess* __restrict__ hs,
+                                                   const double* __restrict__ Zb, int64_t ntot,
+                                                   double* __restrict__ x) {
+  extern __shared__ double yv[];
+  const KTask t = tasks[blockIdx.x];
+  const int nc = st[t.sys].iters;
+  const KHess Hh = hs[t.sys];
+  for (int i = threadIdx.x; i < nc; i += NT) yv[i] = Hh.y[i];
+  __syncthreads();
+  for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) {
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += yv[c] * Zb[(int64_t)c * ntot + e];
+    x[e] += acc;
+  }
+}
+
+// r = rhs - r  (r holds A x on entry)
+__global__ void k_resid(double* __restrict__ r, const double* __restrict__ rhs, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = rhs[i] - r[i];
+}
+
+// ---------------------------------------------------------------- launchers
+static unsigned capg(int64_t n) {
+  int64_t g = (n + NT - 1) / NT;
+  return (unsigned)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+void kr_nrm2_part(const KPlan& p, const double* x, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrm2_part, dim3(p.ntask), dim3(NT), 0, st, p.tasks, x, part);
+}
+void kr_seg_sum(const KPlan& p, const double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_sum, dim3(p.nsys), dim3(64), 0, st, p.sys, part, out);
+}
+void kr_start(const KPlan& p, const double* part, const double* r, double* u, KState* stt,
+              const double* tol_rel, KGlobal* gl, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_start, dim3(p.ntask), dim3(NT), 0, st, p.tasks, p.sys, part, r, u, stt,
+                     tol_rel, gl, p.nsys);
+  hipLaunchKernelGGL(k_fg_count, dim3(1), dim3(64), 0, st, stt, gl, p.nsys);
+}
+void kr_scale(const KPlan& p, const double* part, double* u, KState* stt, KGlobal* gl,
+              hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_scale, dim3(p.ntask), dim3(NT), 0, st, p.tasks, p.sys, part, u, stt, gl);
+}
+void kr_dot(const KPlan& p, const KState* stt, const KGlobal* gl, const double* V,
+            const double* u, const double* w, const double* z, double* Zb, int64_t ntot, int m,
+            int with_w, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_dot<KR_EPT>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V, u, w,
+                     z, Zb, ntot, m, with_w, part);
+}
+void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const double* part,
+               double* sums, int m, int jmax, hipStream_t st) {
+  const int gy = (2 * jmax + 2 + 7) / 8;
+  hipLaunchKernelGGL(k_fg_reduce, dim3(p.nsys, gy), dim3(NT), 0, st, p.sys, stt, gl, part, sums,
+                     m);
+}
+void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
+              int finalize_only, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_small, dim3(p.nsys), dim3(NT), 0, st, stt, gl, sums, hs, m,
+                     finalize_only);
+}
+void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
+               const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_update<KR_EPT>, dim3(p.ntask), dim3(NT),
+                     (size_t)(2 * jmax + 2) * sizeof(double), st, p.tasks, stt, gl, V, u, w, hs,
+                     ntot, part);
+}
+void kr_advance(KGlobal* gl, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_advance, dim3(1), dim3(64), 0, st, gl);
+}
+void kr_solve_y(const KPlan& p, const KState* stt, KHess* hs, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_solve_y, dim3(p.nsys), dim3(64), 0, st, stt, hs, m);
+}
+void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double* Zb,
+                int64_t ntot, double* x, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_xupdate, dim3(p.ntask), dim3(NT), (size_t)(m + 1) * sizeof(double), st,
+                     p.tasks, stt, hs, Zb, ntot, x);
+}
+void kr_resid(double* r, const double* rhs, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid, dim3(capg(n)), dim3(NT), 0, st, r, rhs, n);
+}
+
+}  // namespace svar

@@ -1,0 +1,189 @@
+// Model products, L / L^T / L_M(k) sweep steps, observation operators and vector jobs.
+//
+// L v, L^T v (eq. def:L) and one step of the L_M(k)^{-1}, L_M(k)^{-T} recurrences (Lemma 1:
+// inside a segment z_i = v_i + M_i z_{i-1}, w_i = v_i + M_{i+1}^T w_{i+1}) are all of the form
+//     out_i = in_i + alpha * M^(T) x_j
+// for a list of independent (i, j) block pairs, so one kernel serves all of them; a sweep is
+// k-1 launches, one per position inside the segments, each covering every segment and
+// right-hand side at once (§4: the segments of L_M(k) are independent).
+//
+// Band models (the implicit advection-diffusion step is applied through the taps of T^{-1})
+// stage the input tile plus its halo in LDS so that every HBM element is read once and the
+// taps are applied from LDS.
+#include "svar_impl.h"
+
+namespace svar {
+
+static constexpr int TS = 256;  // outputs per workgroup
+static constexpr int YMAX = 65535;
+
+__device__ __forceinline__ int job_id() { return blockIdx.y + YMAX * blockIdx.z; }
+static dim3 jgrid(unsigned gx, int njobs) {
+  return njobs <= YMAX ? dim3(gx, njobs, 1) : dim3(gx, YMAX, (njobs + YMAX - 1) / YMAX);
+}
+
+__device__ __forceinline__ double* opnd(const Bases& b, const Operand& o) {
+  return b.p[o.base] + o.off;
+}
+
+__global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs,
+                                                   const ModelDev* __restrict__ models, Bases b,
+                                                   const int* __restrict__ skip, int njobs) {
+  if (skip && *skip) return;
+  extern __shared__ double lds[];
+  if (job_id() >= njobs) return;
+  const MJob J = jobs[job_id()];
+  const int s = J.s;
+  const int j0 = blockIdx.x * TS;
+  if (j0 >= s) return;
+  const double* in = opnd(b, J.in);
+  double* out = opnd(b, J.out);
+  const int j = j0 + threadIdx.x;
+  if (J.model < 0) {  // plain copy (first block of L, segment starts)
+    if (j < s) out[j] = in[j];
+    return;
+  }
+  const ModelDev& M = models[J.model];
+  const int* __restrict__ off = J.trans ? M.offT : M.off;
+  const double* __restrict__ w = J.trans ? M.wT : M.w;
+  const int omin = J.trans ? M.ominT : M.omin;
+  const int omax = J.trans ? M.omaxT : M.omax;
+  const int span = TS + omax - omin;
+  const double* x = opnd(b, J.x);
+  for (int t = threadIdx.x; t < span; t += TS) {
+    int g = j0 + omin + t;
+    g %= s;
+    if (g < 0) g += s;
+    lds[t] = x[g];
+  }
+  __syncthreads();
+  if (j >= s) return;
+  double acc = 0.0;
+  const int base = threadIdx.x - omin;
+  for (int tp = 0; tp < M.ntap; ++tp) acc += w[tp] * lds[base + off[tp]];
+  out[j] = in[j] + J.alpha * acc;
+}
+
+// Dense model maps (distinct M_i per block): one output element per thread.
+__global__ __launch_bounds__(TS) void k_mstep_dense(const MJob* __restrict__ jobs,
+                                                    const ModelDev* __restrict__ models, Bases b,
+                                                    const int* __restrict__ skip, int njobs) {
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const MJob J = jobs[job_id()];
+  const int s = J.s;
+  const int j = blockIdx.x * TS + threadIdx.x;
+  if (j >= s) return;
+  const double* in = opnd(b, J.in);
+  double* out = opnd(b, J.out);
+  if (J.model < 0) {
+    out[j] = in[j];
+    return;
+  }
+  const ModelDev& M = models[J.model];
+  const double* Mi = M.dense + (size_t)(J.mi - 1) * s * s;
+  const double* x = opnd(b, J.x);
+  double acc = 0.0;
+  if (J.trans)
+    for (int m = 0; m < s; ++m) acc += Mi[(size_t)m * s + j] * x[m];
+  else
+    for (int m = 0; m < s; ++m) acc += Mi[(size_t)j * s + m] * x[m];
+  out[j] = in[j] + J.alpha * acc;
+}
+
+__global__ __launch_bounds__(TS) void k_gather(const HJob* __restrict__ jobs, Bases b,
+                                               const int* __restrict__ skip, int njobs) {
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const HJob J = jobs[job_id()];
+  const int r = blockIdx.x * TS + threadIdx.x;
+  if (r >= J.rows) return;
+  const double* x = opnd(b, J.x);
+  double acc = 0.0;
+  for (int e = 0; e < J.width; ++e)
+    acc += J.vals[(size_t)r * J.width + e] * x[J.cols[(size_t)r * J.width + e]];
+  opnd(b, J.out)[r] = acc;
+}
+
+__global__ __launch_bounds__(TS) void k_scatter(const HTJob* __restrict__ jobs, Bases b,
+                                                const int* __restrict__ skip, int njobs) {
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const HTJob J = jobs[job_id()];
+  const int j = blockIdx.x * TS + threadIdx.x;
+  if (j >= J.s) return;
+  const double* y = opnd(b, J.y);
+  double acc = 0.0;
+  for (int e = J.ptr[j]; e < J.ptr[j + 1]; ++e) acc += J.val[e] * y[J.idx[e]];
+  opnd(b, J.out)[j] += acc;
+}
+
+__global__ __launch_bounds__(TS) void k_vec(const VJob* __restrict__ jobs, Bases b,
+                                            const int* __restrict__ skip, int njobs) {
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const VJob J = jobs[job_id()];
+  const double* in = opnd(b, J.in);
+  double* out = opnd(b, J.out);
+  for (int64_t j = (int64_t)blockIdx.x * TS + threadIdx.x; j < J.len; j += (int64_t)gridDim.x * TS)
+    out[j] = J.scale ? in[j] * J.scale[j] : (J.alpha == 0.0 ? 0.0 : in[j] * J.alpha);
+}
+
+__global__ void k_fill(double* x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void k_axpby(double* y, const double* x, int64_t n, double a, double bcoef) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + bcoef * y[i];
+}
+
+static unsigned tiles(int64_t n) { return (unsigned)((n + TS - 1) / TS); }
+
+void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
+                       const ModelDev* models, Bases b, const int* skip, hipStream_t st) {
+  if (njobs == 0) return;
+  // LDS: the output tile plus the widest halo of any band model (checked at set-up)
+  hipLaunchKernelGGL(k_mstep_band, jgrid(tiles(max_s), njobs), dim3(TS),
+                     (size_t)(TS + max_halo) * sizeof(double), st, jobs, models, b, skip, njobs);
+}
+void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
+                        const int* skip, hipStream_t st) {
+  if (njobs == 0) return;
+  hipLaunchKernelGGL(k_mstep_dense, jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs, models, b,
+                     skip, njobs);
+}
+void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
+                   hipStream_t st) {
+  if (njobs == 0 || max_rows == 0) return;
+  hipLaunchKernelGGL(k_gather, jgrid(tiles(max_rows), njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
+}
+void launch_scatter(const HTJob* jobs, int njobs, int max_s, Bases b, const int* skip,
+                    hipStream_t st) {
+  if (njobs == 0) return;
+  hipLaunchKernelGGL(k_scatter, jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
+}
+void launch_vec(const VJob* jobs, int njobs, int64_t max_len, Bases b, const int* skip,
+                hipStream_t st) {
+  if (njobs == 0 || max_len == 0) return;
+  unsigned gx = tiles(max_len);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_vec, jgrid(gx, njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
+}
+void launch_fill(double* x, int64_t n, double v, hipStream_t st) {
+  if (n == 0) return;
+  unsigned g = tiles(n);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill, dim3(g), dim3(TS), 0, st, x, n, v);
+}
+void launch_axpby(double* y, const double* x, int64_t n, double a, double bcoef, hipStream_t st) {
+  if (n == 0) return;
+  unsigned g = tiles(n);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_axpby, dim3(g), dim3(TS), 0, st, y, x, n, a, bcoef);
+}
+
+}  // namespace svar

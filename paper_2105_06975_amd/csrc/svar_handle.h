@@ -1,0 +1,104 @@
+// Handle state of libsvar (internal).
+#pragma once
+#include <memory>
+
+#include "krylov.h"
+#include "svar_impl.h"
+
+struct svar_handle;
+
+namespace svar {
+
+struct WinDev {
+  int s = 0, N = 0, nb = 0, P = 0;
+  int64_t n = 0;                     // saddle length per right-hand side
+  std::vector<int> p, poff;          // per block, offsets inside the obs component
+  // D
+  std::vector<double*> dmats;        // device, s x s
+  std::vector<int> d_index;
+  std::vector<double> d_scale;
+  double* d_scale_dev = nullptr;     // [nb]
+  double* neg_d_scale_dev = nullptr; // [nb], -d_scale
+  // R
+  std::vector<double*> rmats;        // device, p x p
+  std::vector<int> rmat_p;
+  std::vector<int> r_index;
+  // Rhat^{-1} per distinct R: dense inverse or inverse diagonal
+  std::vector<double*> rhat_inv;
+  std::vector<double*> rhat_dinv;
+  double* rhat_dinv_blocks = nullptr; // [P] inverse diagonal laid out per block (DIAG)
+  std::vector<double> rr_gamma, me_T, lam1;
+  // Dhat^{-1}: distinct inverses and the one used by each block
+  std::vector<double*> dhat_inv;
+  std::vector<int> dhat_of_block;
+  // low-precision copies for the mixed paths (per distinct matrix)
+  std::vector<void*> dmats_f32, rmats_f32, dmats_bf16, rhat_inv_bf16, dhat_inv_bf16;
+  // H (ELL) and its transpose (CSR per block)
+  int hw = 1;
+  int32_t* h_cols = nullptr;
+  double* h_vals = nullptr;
+  std::vector<int64_t> h_off;        // per block, entry offset
+  int32_t* ht_ptr = nullptr;         // nb x (s+1)
+  int32_t* ht_idx = nullptr;
+  double* ht_val = nullptr;
+  std::vector<int64_t> ht_ent_off;   // per block, entry offset
+  // model
+  int model_id = 0;
+  int model_kind = MK_BAND;
+};
+
+struct ProgKey {
+  int op, nrhs, prec;  // op code, rhs count, precision variant
+  bool operator<(const ProgKey& o) const {
+    if (op != o.op) return op < o.op;
+    if (nrhs != o.nrhs) return nrhs < o.nrhs;
+    return prec < o.prec;
+  }
+};
+
+// internal program codes (beyond the public SVAR_OP_*)
+enum { PROG_A = 100, PROG_P = 101 };
+// precision variants of a program
+enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2 };
+
+struct Timer {
+  bool on = false;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+};
+
+}  // namespace svar
+
+struct svar_handle {
+  int device = 0;
+  svar_prec_opts popts{};
+  std::vector<svar::WinDev> wins;
+  std::vector<svar::ModelDev> models;       // host copy
+  svar::ModelDev* models_dev = nullptr;
+  int max_halo = 0;
+  std::vector<void*> allocs;                // every device allocation owned by the handle
+  std::map<svar::ProgKey, svar::Program> progs;
+  // workspaces
+  double* gemm_ws = nullptr;
+  int64_t gemm_ws_elems = 0;
+  double* tmp = nullptr;
+  int64_t tmp_elems = 0;
+  svar::Timer timers[SVAR_KCLASS_COUNT];
+  // Krylov workspace (grown on demand)
+  struct Kry {
+    int nrhs = -1, m = 0;
+    int64_t ntot = 0;
+    svar::KPlan plan;
+    double *V = nullptr, *Z = nullptr, *u = nullptr, *w = nullptr, *z = nullptr;
+    double *r = nullptr, *xs = nullptr, *part = nullptr, *npart = nullptr, *sums = nullptr;
+    double* sysv = nullptr;
+    double *tol_rel = nullptr, *hbuf = nullptr;
+    svar::KState* st = nullptr;
+    svar::KGlobal* gl = nullptr;
+    svar::KHess* hs = nullptr;
+    svar::KGlobal* gl_host = nullptr;  // pinned
+    std::vector<void*> allocs;
+  } kry;
+};

@@ -1,0 +1,160 @@
+// Internal declarations of libsvar (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "svar.h"
+
+struct svar_handle;
+
+namespace svar {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+#define SVAR_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      ::svar::set_error(std::string("HIP error ") + hipGetErrorString(e_) + " at " +     \
+                        __FILE__ + ":" + std::to_string(__LINE__) + " (" #call ")");     \
+      return SVAR_E_HIP;                                                                 \
+    }                                                                                    \
+  } while (0)
+inline int inval_msg(const std::string& m) {
+  set_error(m);
+  return SVAR_E_INVAL;
+}
+#define SVAR_TRY(call)          \
+  do {                          \
+    int st_ = (call);           \
+    if (st_ != SVAR_OK) return st_; \
+  } while (0)
+
+// ------------------------------------------------------------------ addressing
+// Kernels address caller and workspace vectors through a small table of base pointers
+// passed by value; job tables store (base, offset) pairs so that they can be built once
+// per (operation, nrhs) and reused for any caller pointers.
+enum BaseId { B_IN = 0, B_OUT = 1, B_TMP = 2, B_AUX = 3 };
+struct Bases {
+  double* p[4];
+};
+struct Operand {
+  int32_t base;  // BaseId, or -1 for "none"
+  int32_t pad;
+  int64_t off;   // element offset
+};
+
+// ------------------------------------------------------------------ covariance GEMM
+// Y[:, c] = beta * Z[:, c] + alpha0 * alpha[c % per] * (C X)[:, c], C an n x n matrix
+// stored row-major (lda = n).  Column c of X lives at X.off + (c / per) * xo + (c % per) * xi.
+enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+struct GemmProb {
+  const void* C;
+  int32_t n, ncols, per, splits;
+  Operand X, Y, Z;
+  int64_t xo, xi, yo, yi, zo, zi;
+  const double* alpha;  // [per] device, or nullptr
+  double alpha0, beta;
+  int64_t ws_off;       // element offset of the split-K partials (splits > 1)
+  int32_t dtype, pad;
+};
+struct GemmTask {
+  int32_t prob, row0, k0, k1, col0, split;
+};
+
+// ------------------------------------------------------------------ model products
+// out[j] = in[j] + alpha * (M op x)[j], j < s, for one block; op = M_mi or M_mi^T.
+struct MJob {
+  Operand in, x, out;
+  int32_t model, mi, trans, s;
+  double alpha;
+};
+enum ModelKind { MK_BAND = 0, MK_DENSE = 1, MK_L96 = 2 };
+struct ModelDev {
+  int32_t kind, s, N, ntap;
+  const int32_t* off;    // band taps of M
+  const double* w;
+  const int32_t* offT;   // band taps of M^T
+  const double* wT;
+  int32_t omin, omax, ominT, omaxT;
+  const double* dense;   // N matrices, M_i at (i-1)*s*s
+  // Lorenz-96 tangent linear model
+  const double* traj;    // [N+1][s]
+  double F, dt;
+  int32_t nsteps, pad;
+};
+
+// ------------------------------------------------------------------ H
+struct HJob {            // gather: out[r] = sum_w vals[r*w+e] * x[cols[r*w+e]]
+  Operand x, out;
+  const int32_t* cols;
+  const double* vals;
+  int32_t rows, width;
+};
+struct HTJob {           // scatter-add: out[j] += sum_{e in ptr[j]..ptr[j+1]} val[e] * y[idx[e]]
+  Operand y, out;
+  const int32_t* ptr;
+  const int32_t* idx;
+  const double* val;
+  int32_t s, pad;
+};
+struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha), j < len
+  Operand in, out;
+  const double* scale;
+  double alpha;
+  int64_t len;
+};
+
+// ------------------------------------------------------------------ launch programs
+enum LaunchKind { LK_MSTEP_BAND, LK_MSTEP_DENSE, LK_MSTEP_L96, LK_GATHER, LK_SCATTER, LK_VEC,
+                  LK_GEMM };
+struct GemmPlanDev {
+  GemmProb* probs = nullptr;   // device
+  GemmTask* tasks = nullptr;   // device
+  int nprob = 0, ntask = 0, maxct = 0;
+  std::vector<int> reduce_probs;  // host indices of problems with splits > 1
+  int* reduce_list = nullptr;     // device copy
+  int64_t max_reduce_elems = 0;
+  int64_t ws_elems = 0;
+  int dtype = DT_F64;
+};
+struct Launch {
+  LaunchKind kind;
+  void* jobs = nullptr;   // device job table
+  int njobs = 0;
+  int grid_x = 0;
+  int max_s = 0;
+  GemmPlanDev gemm;
+  int kclass = -1;        // timing class
+};
+struct Program {
+  std::vector<Launch> launches;
+  int64_t tmp_elems = 0;  // B_TMP workspace needed
+  // component counters per application (Tables 4 and 5 style): M, M^T, D, R, Rhat^-1, Dhat^-1
+  int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+};
+
+// kernel launchers (defined in the .hip files)
+void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
+                       const ModelDev* models, Bases b, const int* skip, hipStream_t st);
+void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
+                        Bases b, const int* skip, hipStream_t st);
+void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
+                      Bases b, const int* skip, hipStream_t st);
+void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
+                   hipStream_t st);
+void launch_scatter(const HTJob* jobs, int njobs, int max_s, Bases b, const int* skip,
+                    hipStream_t st);
+void launch_vec(const VJob* jobs, int njobs, int64_t max_len, Bases b, const int* skip,
+                hipStream_t st);
+void launch_gemm(const GemmPlanDev& g, Bases b, double* ws, const int* skip, hipStream_t st);
+
+// plain helpers used by set-up and drivers
+void launch_fill(double* x, int64_t n, double v, hipStream_t st);
+void launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipStream_t st);
+
+}  // namespace svar

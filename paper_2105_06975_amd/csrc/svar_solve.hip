@@ -1,0 +1,300 @@
+// Solve drivers: flexible GMRES cycles inside a float64 refinement loop, and preconditioned
+// MINRES (§7: MINRES with P_D, GMRES with P_I, relative two-norm tolerance, x0 = 0).
+//
+// svar_solve runs cycles of right-preconditioned FGMRES on A d = r with r = rhs - A x
+// recomputed in float64 between cycles.  With FP64 operators and no restart this is the
+// paper's unrestarted GMRES followed by a true-residual check; with restart it is FGMRES(m);
+// with the mixed precisions the inner operators use float32 / bfloat16 covariance products
+// while the Arnoldi basis, Hessenberg least squares and residual checks stay float64.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "mem.h"
+#include "minres.h"
+#include "svar_handle.h"
+
+namespace svar {
+
+int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
+  auto& K = h->kry;
+  if (K.nrhs == nrhs && K.m >= m) return SVAR_OK;
+  SVAR_HIP(hipStreamSynchronize(st));
+  free_all(K.allocs);
+  {
+    KGlobal* keep = K.gl_host;
+    K = svar_handle::Kry();
+    K.gl_host = keep;
+  }
+  const int nw = (int)h->wins.size();
+  const int nsys = nw * nrhs;
+  const int64_t ntot = handle_total(h, nrhs);
+  std::vector<KSys> sys(nsys);
+  std::vector<KTask> tasks;
+  int64_t off = 0;
+  for (int w = 0, si = 0; w < nw; ++w)
+    for (int r = 0; r < nrhs; ++r, ++si) {
+      const int64_t n = h->wins[w].n;
+      sys[si].off = off;
+      sys[si].n = n;
+      sys[si].task0 = (int)tasks.size();
+      for (int64_t e = 0; e < n; e += KR_TASK) {
+        KTask t{};
+        t.sys = si;
+        t.e0 = off + e;
+        t.e1 = off + std::min<int64_t>(n, e + KR_TASK);
+        tasks.push_back(t);
+      }
+      sys[si].ntask = (int)tasks.size() - sys[si].task0;
+      off += n;
+    }
+  K.nrhs = nrhs;
+  K.m = m;
+  K.ntot = ntot;
+  const int SL = 2 * m + 2;
+  auto& A = K.allocs;
+  SVAR_TRY(dalloc(A, &K.plan.tasks, tasks.size()));
+  SVAR_TRY(dalloc(A, &K.plan.sys, sys.size()));
+  SVAR_HIP(hipMemcpyAsync(K.plan.tasks, tasks.data(), tasks.size() * sizeof(KTask),
+                          hipMemcpyHostToDevice, st));
+  SVAR_HIP(hipMemcpyAsync(K.plan.sys, sys.data(), sys.size() * sizeof(KSys), hipMemcpyHostToDevice,
+                          st));
+  K.plan.ntask = (int)tasks.size();
+  K.plan.nsys = nsys;
+  SVAR_TRY(dalloc(A, &K.V, (size_t)m * ntot));
+  SVAR_TRY(dalloc(A, &K.Z, (size_t)m * ntot));
+  SVAR_TRY(dalloc(A, &K.u, (size_t)ntot));
+  SVAR_TRY(dalloc(A, &K.w, (size_t)ntot));
+  SVAR_TRY(dalloc(A, &K.z, (size_t)ntot));
+  SVAR_TRY(dalloc(A, &K.r, (size_t)ntot));
+  SVAR_TRY(dalloc(A, &K.xs, (size_t)ntot));
+  SVAR_TRY(dalloc(A, &K.part, (size_t)K.plan.ntask * SL));
+  SVAR_TRY(dalloc(A, &K.npart, (size_t)K.plan.ntask));
+  SVAR_TRY(dalloc(A, &K.sums, (size_t)nsys * SL));
+  SVAR_TRY(dalloc(A, &K.sysv, (size_t)nsys));
+  SVAR_TRY(dalloc(A, &K.tol_rel, (size_t)nsys));
+  SVAR_TRY(dalloc(A, &K.st, (size_t)nsys));
+  SVAR_TRY(dalloc(A, &K.gl, 1));
+  // Hessenberg storage per system
+  const size_t per = (size_t)(m + 1) * m + m + m + (m + 1) + m + (m + 1) + m;
+  SVAR_TRY(dalloc(A, &K.hbuf, per * nsys));
+  std::vector<KHess> hs(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    double* p = K.hbuf + per * i;
+    hs[i].H = p;
+    p += (size_t)(m + 1) * m;
+    hs[i].cs = p;
+    p += m;
+    hs[i].sn = p;
+    p += m;
+    hs[i].g = p;
+    p += m + 1;
+    hs[i].y = p;
+    p += m;
+    hs[i].hprev = p;
+    p += m + 1;
+    hs[i].coef_s = p;
+  }
+  SVAR_TRY(dalloc(A, &K.hs, (size_t)nsys));
+  SVAR_HIP(hipMemcpyAsync(K.hs, hs.data(), nsys * sizeof(KHess), hipMemcpyHostToDevice, st));
+  if (!K.gl_host) SVAR_HIP(hipHostMalloc((void**)&K.gl_host, sizeof(KGlobal)));
+  SVAR_HIP(hipStreamSynchronize(st));
+  return SVAR_OK;
+}
+
+// per-system squared norms of x (host vector)
+int sys_norm2(svar_handle* h, const double* x, std::vector<double>& out, hipStream_t st) {
+  auto& K = h->kry;
+  kr_nrm2_part(K.plan, x, K.npart, st);
+  kr_seg_sum(K.plan, K.npart, K.sysv, st);
+  out.resize(K.plan.nsys);
+  SVAR_HIP(hipMemcpyAsync(out.data(), K.sysv, K.plan.nsys * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  SVAR_HIP(hipStreamSynchronize(st));
+  return SVAR_OK;
+}
+
+// One FGMRES cycle of at most m iterations on A d = r (K.r), accumulating x += d.
+static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
+                        const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
+                        hipStream_t st) {
+  auto& K = h->kry;
+  SVAR_HIP(hipMemcpyAsync(K.tol_rel, tol_rel.data(), tol_rel.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+  kr_nrm2_part(K.plan, K.r, K.npart, st);
+  kr_start(K.plan, K.npart, K.r, K.u, K.st, K.tol_rel, K.gl, st);
+  const int* skip = &K.gl->all_done;
+  const int check_every = 4;
+  bool all_done = false;
+  int j = 0;
+  for (; j < m; ++j) {
+    if (j > 0) kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
+    SVAR_TRY(run_program(h, PP, K.u, K.z, st, skip));
+    SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip));
+    hipEvent_t e0, e1;
+    timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+    kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
+    timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+    kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, j, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, st);
+    timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+    kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, j, st);
+    timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+    kr_advance(K.gl, st);
+    if ((j + 1) % check_every == 0 || j + 1 == m) {
+      SVAR_HIP(hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
+      SVAR_HIP(hipStreamSynchronize(st));
+      if (K.gl_host->all_done) {
+        all_done = true;
+        break;
+      }
+    }
+  }
+  if (!all_done) {
+    // every basis slot is used: finalise column m-1 without a new product
+    kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
+    kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 0, K.part, st);
+    kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, m, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, st);
+  }
+  kr_solve_y(K.plan, K.st, K.hs, m, st);
+  kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ntot, x, m, st);
+  out.resize(K.plan.nsys);
+  SVAR_HIP(hipMemcpyAsync(out.data(), K.st, K.plan.nsys * sizeof(KState), hipMemcpyDeviceToHost,
+                          st));
+  SVAR_HIP(hipStreamSynchronize(st));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("Krylov kernel failed: ") + hipGetErrorString(e));
+    return SVAR_E_HIP;
+  }
+  return SVAR_OK;
+}
+
+static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, const double* rhs,
+                        double* x, svar_solve_info* info, hipStream_t st) {
+  const int nsys = (int)h->wins.size() * nrhs;
+  // one cycle holds at most KR_MAX_CYCLE basis vectors (LDS of the update pass); longer
+  // unrestarted runs continue as further cycles of the refinement loop
+  int cyc = o->restart > 0 ? std::min(o->restart, o->maxit) : o->maxit;
+  cyc = std::min(cyc, KR_MAX_CYCLE);
+  if (cyc < 1) return inval_msg("maxit must be >= 1");
+  SVAR_TRY(ensure_krylov(h, nrhs, cyc, st));
+  auto& K = h->kry;
+  const int pv_a = o->precision == SVAR_PRECISION_FP64 ? PV_F64 : PV_F32;
+  const int pv_p = o->precision == SVAR_PRECISION_MIXED_BF16P ? PV_BF16P : PV_F64;
+  Program *A64 = nullptr, *Ain = nullptr, *Pin = nullptr;
+  SVAR_TRY(get_program(h, PROG_A, nrhs, PV_F64, &A64, st));
+  SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
+  SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &Pin, st));
+  launch_fill(x, K.ntot, 0.0, st);
+  std::vector<double> rhs2;
+  SVAR_TRY(sys_norm2(h, rhs, rhs2, st));
+  std::vector<int> iters(nsys, 0), status(nsys, SVAR_OK), cycles(nsys, 0);
+  std::vector<double> est(nsys, 0.0), relres(nsys, 1.0);
+  for (int i = 0; i < nsys; ++i) relres[i] = rhs2[i] > 0 ? 1.0 : 0.0;
+  SVAR_HIP(hipMemcpyAsync(K.r, rhs, K.ntot * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int64_t applies_A64 = 0;
+  int max_outer = std::max(1, o->max_outer);
+  if (o->restart <= 0 && o->maxit > KR_MAX_CYCLE)
+    max_outer = std::max(max_outer, (o->maxit + KR_MAX_CYCLE - 1) / KR_MAX_CYCLE + 1);
+  int used = 0;
+  for (int outer = 0; outer < max_outer; ++outer) {
+    std::vector<double> r2 = rhs2;
+    if (outer > 0) {
+      SVAR_TRY(run_program(h, *A64, x, K.r, st, nullptr));
+      kr_resid(K.r, rhs, K.ntot, st);
+      ++applies_A64;
+      SVAR_TRY(sys_norm2(h, K.r, r2, st));
+    }
+    bool all = true;
+    std::vector<double> tol(nsys);
+    for (int i = 0; i < nsys; ++i) {
+      const double nr = std::sqrt(r2[i]), nb = std::sqrt(rhs2[i]);
+      relres[i] = nb > 0 ? nr / nb : 0.0;
+      const bool ok = relres[i] <= o->rtol;
+      if (!std::isfinite(relres[i])) status[i] = SVAR_E_BREAKDOWN;
+      if (ok || status[i] == SVAR_E_BREAKDOWN || iters[i] >= o->maxit) {
+        tol[i] = 2.0;  // inactive in this cycle
+        continue;
+      }
+      all = false;
+      double t = nr > 0 ? o->rtol * nb / nr : 1.0;
+      if (o->precision != SVAR_PRECISION_FP64) t = std::max(t, o->inner_rtol);
+      tol[i] = t;
+    }
+    if (all) break;
+    const int m = std::min(cyc, o->maxit - used);
+    if (m < 1) break;
+    std::vector<KState> ks;
+    SVAR_TRY(fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, st));
+    int jmax = 0;
+    for (int i = 0; i < nsys; ++i) {
+      if (tol[i] >= 1.0) continue;
+      iters[i] += ks[i].iters;
+      cycles[i] += 1;
+      est[i] = ks[i].est / std::max(std::sqrt(rhs2[i]), 1e-300);
+      if (ks[i].status == SVAR_E_BREAKDOWN) status[i] = SVAR_E_BREAKDOWN;
+      jmax = std::max(jmax, ks[i].iters);
+    }
+    used += std::max(jmax, 1);
+  }
+  // final true residual in float64
+  SVAR_TRY(run_program(h, *A64, x, K.r, st, nullptr));
+  kr_resid(K.r, rhs, K.ntot, st);
+  ++applies_A64;
+  std::vector<double> r2;
+  SVAR_TRY(sys_norm2(h, K.r, r2, st));
+  int rc = SVAR_OK;
+  for (int i = 0; i < nsys; ++i) {
+    const double nb = std::sqrt(rhs2[i]);
+    const double rr = nb > 0 ? std::sqrt(r2[i]) / nb : 0.0;
+    svar_solve_info& I = info[i];
+    I.iters = iters[i];
+    I.outer = cycles[i];
+    I.relres_true = rr;
+    I.relres_est = est[i];
+    I.status = status[i];
+    if (I.status == SVAR_OK && !(rr <= o->rtol)) I.status = std::isfinite(rr) ? SVAR_E_NOCONV
+                                                                            : SVAR_E_BREAKDOWN;
+    const double per_rhs = 1.0 / (double)nsys;
+    (void)per_rhs;
+    // component products per system, as counted in Tables 4 and 5 (per right-hand side)
+    const int nw = (int)h->wins.size();
+    const double scale = 1.0 / (double)(nw * nrhs);
+    I.n_M = (int64_t)std::llround((Ain->cnt[0] + Pin->cnt[0]) * scale * iters[i] +
+                                  A64->cnt[0] * scale * applies_A64);
+    I.n_MT = (int64_t)std::llround((Ain->cnt[1] + Pin->cnt[1]) * scale * iters[i] +
+                                   A64->cnt[1] * scale * applies_A64);
+    I.n_D = (int64_t)std::llround((Ain->cnt[2] + Pin->cnt[2]) * scale * iters[i] +
+                                  A64->cnt[2] * scale * applies_A64);
+    I.n_R = (int64_t)std::llround((Ain->cnt[3] + Pin->cnt[3]) * scale * iters[i] +
+                                  A64->cnt[3] * scale * applies_A64);
+    I.n_Rhat_inv = (int64_t)std::llround(Pin->cnt[4] * scale * iters[i]);
+    I.n_Dhat_inv = (int64_t)std::llround(Pin->cnt[5] * scale * iters[i]);
+    if (I.status != SVAR_OK && rc == SVAR_OK) rc = I.status;
+  }
+  if (rc != SVAR_OK) set_error("at least one system did not reach rtol (see info)");
+  return rc;
+}
+
+}  // namespace svar
+
+using namespace svar;
+
+extern "C" int svar_solve(svar_handle* h, const svar_solve_opts* o, int32_t nrhs,
+                          const double* rhs, double* x, svar_solve_info* info, void* stream) {
+  if (!h || !o || !rhs || !x || !info || nrhs < 1) return inval_msg("bad arguments");
+  if (!(o->rtol > 0.0) || o->maxit < 1) return inval_msg("need rtol > 0 and maxit >= 1");
+  if (o->precision < SVAR_PRECISION_FP64 || o->precision > SVAR_PRECISION_MIXED_BF16P)
+    return inval_msg("bad precision");
+  hipStream_t st = (hipStream_t)stream;
+  if (o->method == SVAR_METHOD_FGMRES) return solve_fgmres(h, o, nrhs, rhs, x, info, st);
+  if (o->method == SVAR_METHOD_MINRES) {
+    if (h->popts.type == SVAR_PREC_PI)
+      return inval_msg("MINRES needs a symmetric positive definite preconditioner (P_D)");
+    if (o->precision != SVAR_PRECISION_FP64) return inval_msg("MINRES runs in float64 only");
+    return solve_minres(h, o, nrhs, rhs, x, info, st);
+  }
+  return inval_msg("bad method");
+}

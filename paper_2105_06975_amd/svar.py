@@ -1,0 +1,292 @@
+"""ctypes binding of libsvar (declared in include/svar.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.  Device
+vectors are torch float64 tensors on the current CUDA (HIP) device; the current torch
+stream is passed to the library.  Importing this module fails loudly when the built
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvar.so")
+
+OK, E_INVAL, E_NOTSPD, E_NOCONV, E_BREAKDOWN, E_HIP, E_NOMEM = range(7)
+STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOTSPD", 3: "E_NOCONV", 4: "E_BREAKDOWN", 5: "E_HIP",
+          6: "E_NOMEM"}
+MODEL = {"dense": 0, "band": 1, "tridiag_inv": 2, "l96": 3}
+PREC = {"NONE": 0, "PD": 1, "PI": 2}
+RHAT = {"DIAG": 0, "RR": 1, "ME": 2, "EXACT": 3}
+METHOD = {"FGMRES": 0, "MINRES": 1}
+PRECISION = {"FP64": 0, "MIXED_FP32": 1, "MIXED_BF16P": 2}
+OPS = {"L": 0, "LT": 1, "LHAT_INV": 2, "LHAT_INVT": 3, "D": 4, "DHAT_INV": 5, "R": 6,
+       "RHAT_INV": 7, "H": 8, "HT": 9}
+OP_SPACES = {"L": ("state", "state"), "LT": ("state", "state"), "LHAT_INV": ("state", "state"),
+             "LHAT_INVT": ("state", "state"), "D": ("state", "state"),
+             "DHAT_INV": ("state", "state"), "R": ("obs", "obs"), "RHAT_INV": ("obs", "obs"),
+             "H": ("state", "obs"), "HT": ("obs", "state")}
+KCLASS = {"GEMM": 0, "ORTHO": 1, "MODEL": 2}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dense", C.POINTER(_dp)), ("ntaps", C.c_int32),
+                ("offsets", _ip), ("weights", _dp), ("tri_a", C.c_double), ("tri_b", C.c_double),
+                ("tri_c", C.c_double), ("l96_F", C.c_double), ("l96_dt", C.c_double),
+                ("l96_nsteps", C.c_int32), ("l96_traj", _dp)]
+
+
+class WindowDesc(C.Structure):
+    _fields_ = [("s", C.c_int32), ("N", C.c_int32), ("p", _ip), ("n_dmat", C.c_int32),
+                ("dmats", C.POINTER(_dp)), ("d_index", _ip), ("d_scale", _dp),
+                ("n_rmat", C.c_int32), ("rmats", C.POINTER(_dp)), ("r_index", _ip),
+                ("h_width", C.c_int32), ("h_cols", _ip), ("h_vals", _dp), ("model", ModelDesc)]
+
+
+class PrecOpts(C.Structure):
+    _fields_ = [("type", C.c_int32), ("k", C.c_int32), ("rhat", C.c_int32),
+                ("rr_gamma", C.c_double), ("me_T", C.c_double), ("d_ridge", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
+                ("restart", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
+                ("max_outer", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("relres_true", C.c_double), ("relres_est", C.c_double),
+                ("n_M", C.c_int64), ("n_MT", C.c_int64), ("n_D", C.c_int64), ("n_R", C.c_int64),
+                ("n_Rhat_inv", C.c_int64), ("n_Dhat_inv", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libsvar.so not built at {path}: run paper_2105_06975_amd.build")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.svar_create.argtypes = [C.POINTER(WindowDesc), C.c_int32, C.POINTER(PrecOpts),
+                                C.POINTER(vp), vp]
+    lib.svar_destroy.argtypes = [vp]
+    lib.svar_system_size.argtypes = [vp, C.c_int32]
+    lib.svar_system_size.restype = C.c_int64
+    lib.svar_offsets.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+    for f in (lib.svar_apply_A, lib.svar_apply_P):
+        f.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.svar_apply_op.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
+    lib.svar_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int32, vp, vp, C.POINTER(SolveInfo),
+                               vp]
+    lib.svar_rhat_params.argtypes = [vp, C.c_int32, _dp, _dp, _dp]
+    lib.svar_timing_enable.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.svar_timing_read.argtypes = [vp, C.c_int32, _dp, C.POINTER(C.c_int64), C.c_int32]
+    lib.svar_last_error.restype = C.c_char_p
+    return lib
+
+
+_LIB: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class SvarError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise SvarError(rc, lib().svar_last_error().decode())
+    return rc
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _vp(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class _Keep:
+    """Holds the numpy arrays a descriptor points to until svar_create returns."""
+
+    def __init__(self):
+        self.items = []
+
+    def arr(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.items.append(a)
+        return a
+
+    def ptr_array(self, mats):
+        arrs = [self.arr(m, np.float64) for m in mats]
+        P = (_dp * len(arrs))(*[_ptr(a, C.c_double) for a in arrs])
+        self.items.append(P)
+        return P
+
+
+def window_desc(win, keep: _Keep) -> WindowDesc:
+    d = WindowDesc()
+    d.s, d.N = int(win.s), int(win.N)
+    d.p = _ptr(keep.arr(win.p, np.int32), C.c_int32)
+    d.n_dmat = len(win.dmats)
+    d.dmats = keep.ptr_array(win.dmats)
+    d.d_index = _ptr(keep.arr(win.d_index, np.int32), C.c_int32)
+    d.d_scale = _ptr(keep.arr(win.d_scale, np.float64), C.c_double)
+    d.n_rmat = len(win.rmats)
+    d.rmats = keep.ptr_array(win.rmats)
+    d.r_index = _ptr(keep.arr(win.r_index, np.int32), C.c_int32)
+    d.h_width = int(win.h_width)
+    cols = np.concatenate([np.asarray(c, np.int32).reshape(-1) for c in win.h_cols]) \
+        if len(win.h_cols) else np.zeros(0, np.int32)
+    vals = np.concatenate([np.asarray(v, np.float64).reshape(-1) for v in win.h_vals]) \
+        if len(win.h_vals) else np.zeros(0)
+    d.h_cols = _ptr(keep.arr(cols, np.int32), C.c_int32)
+    d.h_vals = _ptr(keep.arr(vals, np.float64), C.c_double)
+    m = win.model
+    md = ModelDesc()
+    md.kind = MODEL[m["kind"]]
+    if m["kind"] == "tridiag_inv":
+        md.tri_a, md.tri_b, md.tri_c = float(m["a"]), float(m["b"]), float(m["c"])
+    elif m["kind"] == "band":
+        md.ntaps = len(m["offsets"])
+        md.offsets = _ptr(keep.arr(m["offsets"], np.int32), C.c_int32)
+        md.weights = _ptr(keep.arr(m["weights"], np.float64), C.c_double)
+    elif m["kind"] == "dense":
+        md.dense = keep.ptr_array(m["mats"])
+    elif m["kind"] == "l96":
+        md.l96_F, md.l96_dt, md.l96_nsteps = float(m["F"]), float(m["dt"]), int(m["nsteps"])
+        md.l96_traj = _ptr(keep.arr(m["traj"], np.float64), C.c_double)
+    d.model = md
+    return d
+
+
+@dataclass
+class Precond:
+    type: str = "PI"
+    k: int = 1
+    rhat: str = "RR"
+    rr_gamma: float = -1.0
+    me_T: float = -1.0
+    d_ridge: float = 0.01
+
+
+class Handle:
+    """A libsvar handle over one or more windows (same preconditioner options)."""
+
+    def __init__(self, windows: Sequence, prec: Precond = Precond(), stream=None):
+        self.windows = list(windows)
+        keep = _Keep()
+        descs = (WindowDesc * len(self.windows))(*[window_desc(w, keep) for w in self.windows])
+        po = PrecOpts(PREC[prec.type], int(prec.k), RHAT[prec.rhat], float(prec.rr_gamma),
+                      float(prec.me_T), float(prec.d_ridge))
+        self.prec = prec
+        h = C.c_void_p()
+        _check(lib().svar_create(descs, len(self.windows), C.byref(po), C.byref(h), _stream(stream)))
+        self._h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().svar_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- layout
+    def system_size(self, w: int = 0) -> int:
+        return int(lib().svar_system_size(self._h, w))
+
+    def offsets(self, nrhs: int = 1) -> np.ndarray:
+        off = np.zeros(len(self.windows) + 1, dtype=np.int64)
+        _check(lib().svar_offsets(self._h, nrhs, _ptr(off, C.c_int64)))
+        return off
+
+    def space_len(self, space: str, nrhs: int = 1) -> int:
+        tot = 0
+        for w in self.windows:
+            n = {"saddle": w.n, "state": w.nb * w.s, "obs": w.P}[space]
+            tot += nrhs * n
+        return tot
+
+    # ------------------------------------------------------------- operators
+    def apply_A(self, v, nrhs: int = 1, out=None, stream=None):
+        import torch
+        out = torch.empty_like(v) if out is None else out
+        _check(lib().svar_apply_A(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
+        return out
+
+    def apply_P(self, v, nrhs: int = 1, out=None, stream=None):
+        import torch
+        out = torch.empty_like(v) if out is None else out
+        _check(lib().svar_apply_P(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
+        return out
+
+    def apply_op(self, op: str, v, nrhs: int = 1, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.space_len(OP_SPACES[op][1], nrhs), dtype=torch.float64,
+                              device=v.device)
+        _check(lib().svar_apply_op(self._h, OPS[op], nrhs, _vp(v), _vp(out), _stream(stream)))
+        return out
+
+    def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
+              precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
+              check=False):
+        """Solve A x = rhs; returns (x, [info dicts], status)."""
+        import torch
+        x = torch.empty_like(rhs) if x is None else x
+        o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
+                      float(inner_rtol), int(max_outer))
+        ninfo = len(self.windows) * nrhs
+        infos = (SolveInfo * ninfo)()
+        rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
+        if rc not in (OK, E_NOCONV) or (check and rc != OK):
+            _check(rc)
+        return x, [i.as_dict() for i in infos], rc
+
+    def rhat_params(self, w: int = 0):
+        n = len(self.windows[w].rmats)
+        g, T, l1 = np.zeros(n), np.zeros(n), np.zeros(n)
+        _check(lib().svar_rhat_params(self._h, w, _ptr(g, C.c_double), _ptr(T, C.c_double),
+                                      _ptr(l1, C.c_double)))
+        return dict(gamma=g, T=T, lam1=l1)
+
+    def timing_enable(self, kclass: str, on: bool = True):
+        _check(lib().svar_timing_enable(self._h, KCLASS[kclass], 1 if on else 0))
+
+    def timing_read(self, kclass: str, reset: bool = False):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().svar_timing_read(self._h, KCLASS[kclass], C.byref(ms), C.byref(n),
+                                      1 if reset else 0))
+        return ms.value, n.value

@@ -1,0 +1,338 @@
+"""Parity of the HIP library (through the C ABI) with the float64 CPU oracle.
+
+Every test feeds the same seeded inputs to both sides and compares element by element:
+operator maps to a relative norm error of 1e-12 (1e-10 where an explicit inverse formed
+by Newton-Schulz is involved: its error is about kappa * eps), solutions against a dense
+LU solve to the bound kappa(A) * relres (and 1e-10 on well-conditioned instances).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import svar_oracle as so
+from paper_2105_06975_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_06975_amd import svar
+    return svar
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def tiny(seed=0, s=10, N=4, p=5, dense=True, h_width=1):
+    win = wl.make_small_window(s=s, N=N, p=p, seed=seed, h_width=h_width)
+    if dense:
+        wl.with_dense_model(win, seed=seed)
+    return win
+
+
+def state_split(win, v):
+    return v.reshape(win.nb, win.s)
+
+
+# ------------------------------------------------------------------ A v
+@pytest.mark.parametrize("case", ["tiny_dense", "tiny_h3", "c1", "ragged_band"])
+def test_apply_A(sv, case):
+    if case == "tiny_dense":
+        win = tiny(seed=1)
+    elif case == "tiny_h3":
+        win = tiny(seed=2, h_width=3)
+    elif case == "c1":
+        win = wl.make_config_window("c1", seed=0)
+    else:
+        win = wl.make_small_window(s=37, N=6, p=13, seed=3)  # ragged tiles, band model
+    nrhs = 3
+    orc = so.SaddleOracle(win)
+    V = wl.random_vectors(win, nrhs, seed=4)
+    h = sv.Handle([win], sv.Precond(type="NONE"))
+    Y = host(h.apply_A(dev(V), nrhs)).reshape(nrhs, -1)
+    for r in range(nrhs):
+        assert rel(Y[r], orc.apply_A(V[r])) < 1e-12
+
+
+# ------------------------------------------------------------------ component maps
+OPS_STATE = ["L", "LT", "LHAT_INV", "LHAT_INVT", "D"]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_component_maps(sv, k):
+    win = tiny(seed=5, s=12, N=4, p=6, h_width=2)
+    orc = so.SaddleOracle(win, k=k, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PD", k=k, rhat="RR"))
+    nrhs = 2
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((nrhs, win.nb * win.s))
+    Yo = rng.standard_normal((nrhs, win.P))
+    ref = {
+        "L": lambda x: orc.L_apply(state_split(win, x)).ravel(),
+        "LT": lambda x: orc.LT_apply(state_split(win, x)).ravel(),
+        "LHAT_INV": lambda x: orc.LM_inv(state_split(win, x)).ravel(),
+        "LHAT_INVT": lambda x: orc.LM_invT(state_split(win, x)).ravel(),
+        "D": lambda x: orc.D_apply(state_split(win, x)).ravel(),
+        "DHAT_INV": lambda x: orc.Dhat_inv(state_split(win, x)).ravel(),
+        "H": lambda x: orc.H_full(state_split(win, x)),
+    }
+    for op, fn in ref.items():
+        out = host(h.apply_op(op, dev(X), nrhs)).reshape(nrhs, -1)
+        tol = 1e-10 if op == "DHAT_INV" else 1e-12
+        for r in range(nrhs):
+            assert rel(out[r], fn(X[r])) < tol, op
+    for op, fn in {"R": orc.R_apply, "RHAT_INV": orc.Rhat_inv,
+                   "HT": lambda y: orc.HT_full(y).ravel()}.items():
+        out = host(h.apply_op(op, dev(Yo), nrhs)).reshape(nrhs, -1)
+        tol = 1e-10 if op == "RHAT_INV" else 1e-12
+        for r in range(nrhs):
+            assert rel(out[r], fn(Yo[r])) < tol, op
+
+
+@pytest.mark.parametrize("rhat", ["DIAG", "RR", "ME", "EXACT"])
+def test_rhat_kinds_and_parameters(sv, rhat):
+    win = wl.make_small_window(s=64, N=2, p=40, seed=7, r_len=0.08)
+    orc = so.SaddleOracle(win, rhat=rhat)
+    h = sv.Handle([win], sv.Precond(type="PI", k=1, rhat=rhat))
+    Y = np.random.default_rng(8).standard_normal(win.P)
+    out = host(h.apply_op("RHAT_INV", dev(Y)))
+    assert rel(out, orc.Rhat_inv(Y)) < 1e-10
+    lam = np.linalg.eigvalsh(win.rmats[0])
+    prm = h.rhat_params(0)
+    if rhat == "RR":
+        assert abs(prm["gamma"][0] - lam[0]) <= 1e-10 * lam[0]
+    if rhat == "ME":
+        assert abs(prm["lam1"][0] - lam[0]) <= 1e-10 * lam[0]
+        assert abs(prm["T"][0] - lam[1]) <= 1e-9 * lam[1]
+
+
+# ------------------------------------------------------------------ P^{-1} v
+@pytest.mark.parametrize("prec", ["PD", "PI"])
+@pytest.mark.parametrize("rhat", ["DIAG", "RR", "ME", "EXACT"])
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_apply_P(sv, prec, rhat, k):
+    win = tiny(seed=9, s=12, N=4, p=6, h_width=2)
+    orc = so.SaddleOracle(win, k=k, rhat=rhat)
+    h = sv.Handle([win], sv.Precond(type=prec, k=k, rhat=rhat))
+    nrhs = 2
+    V = wl.random_vectors(win, nrhs, seed=10)
+    Z = host(h.apply_P(dev(V), nrhs)).reshape(nrhs, -1)
+    for r in range(nrhs):
+        assert rel(Z[r], orc.apply_P_inv(V[r], prec)) < 1e-10
+
+
+def test_apply_P_c1_band_model(sv):
+    win = wl.make_config_window("c1", seed=1)
+    for prec in ("PD", "PI"):
+        orc = so.SaddleOracle(win, k=3, rhat="RR")
+        h = sv.Handle([win], sv.Precond(type=prec, k=3, rhat="RR"))
+        V = wl.random_vectors(win, 1, seed=11)[0]
+        assert rel(host(h.apply_P(dev(V))), orc.apply_P_inv(V, prec)) < 1e-10
+
+
+def test_multiple_uneven_windows(sv):
+    wins = [tiny(seed=12, s=9, N=3, p=4), wl.make_small_window(s=33, N=5, p=11, seed=13),
+            tiny(seed=14, s=16, N=1, p=7, h_width=3)]
+    nrhs = 2
+    h = sv.Handle(wins, sv.Precond(type="PI", k=2, rhat="ME"))
+    off = h.offsets(nrhs)
+    Vs = [wl.random_vectors(w, nrhs, seed=20 + i) for i, w in enumerate(wins)]
+    V = np.concatenate([v.reshape(-1) for v in Vs])
+    assert off[-1] == V.size
+    YA = host(h.apply_A(dev(V), nrhs))
+    YP = host(h.apply_P(dev(V), nrhs))
+    for i, w in enumerate(wins):
+        orc = so.SaddleOracle(w, k=2, rhat="ME")
+        a = YA[off[i]:off[i + 1]].reshape(nrhs, -1)
+        p = YP[off[i]:off[i + 1]].reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert rel(a[r], orc.apply_A(Vs[i][r])) < 1e-12
+            assert rel(p[r], orc.apply_P_inv(Vs[i][r], "PI")) < 1e-10
+
+
+# ------------------------------------------------------------------ solves
+@pytest.mark.parametrize("prec,k,rhat", [("PI", 1, "DIAG"), ("PI", 3, "RR"), ("PD", 2, "ME"),
+                                         ("PI", 5, "EXACT")])
+def test_fgmres_matches_dense_solution(sv, prec, k, rhat):
+    win = tiny(seed=15)
+    orc = so.SaddleOracle(win, k=k, rhat=rhat)
+    rhs = win.rhs[0]
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    h = sv.Handle([win], sv.Precond(type=prec, k=k, rhat=rhat))
+    x, info, rc = h.solve(dev(rhs), rtol=1e-13, maxit=win.n, max_outer=3)
+    assert rc == sv.OK, info
+    assert rel(host(x), x_ref) < 1e-10
+    ref = so.solve(orc, rhs, prec=prec, rtol=1e-8, maxit=win.n)
+    x8, info8, rc8 = h.solve(dev(rhs), rtol=1e-8, maxit=win.n)
+    assert rc8 == sv.OK
+    assert abs(info8[0]["iters"] - ref["iters"]) <= 2
+    assert info8[0]["relres_true"] <= 1e-8
+
+
+def test_fgmres_c1(sv):
+    """C1 (n = 2750): GPU FGMRES with P_I, L_M(3), R_RR; iteration count vs the oracle and
+    solution vs the dense LU solution within kappa(A) * relres."""
+    win = wl.make_config_window("c1", seed=0)
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    rhs = win.rhs[0]
+    A = orc.A_dense()
+    x_ref = np.linalg.solve(A, rhs)
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    x, info, rc = h.solve(dev(rhs), rtol=1e-8, maxit=win.n)
+    assert rc == sv.OK
+    ref = so.solve(orc, rhs, prec="PI", rtol=1e-8, maxit=win.n)
+    assert abs(info[0]["iters"] - ref["iters"]) <= 2
+    rr = np.linalg.norm(rhs - A @ host(x)) / np.linalg.norm(rhs)
+    assert rr <= 1e-8 and abs(rr - info[0]["relres_true"]) <= 1e-10
+    x12, info12, rc12 = h.solve(dev(rhs), rtol=1e-12, maxit=win.n, max_outer=4)
+    assert rc12 == sv.OK
+    kappa = np.linalg.cond(A)
+    err = rel(host(x12), x_ref)
+    assert err <= max(1e-10, 4 * kappa * info12[0]["relres_true"]), (err, kappa)
+
+
+def test_minres_pd(sv):
+    win = tiny(seed=16)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    rhs = win.rhs[0]
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    h = sv.Handle([win], sv.Precond(type="PD", k=2, rhat="RR"))
+    x, info, rc = h.solve(dev(rhs), method="MINRES", rtol=1e-13, maxit=4 * win.n)
+    assert rc == sv.OK
+    assert rel(host(x), x_ref) < 1e-9
+    ref = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-8, maxit=4 * win.n)
+    x8, info8, _ = h.solve(dev(rhs), method="MINRES", rtol=1e-8, maxit=4 * win.n)
+    assert abs(info8[0]["iters"] - ref["iters"]) <= 2
+    assert abs(info8[0]["relres_est"] - ref["hist"][-1]) <= 1e-9
+
+
+def test_batched_systems_and_restarts(sv):
+    """Two uneven windows x 3 right-hand sides in one call, restarted FGMRES(8)."""
+    wins = [tiny(seed=17, s=10, N=3, p=5), wl.make_small_window(s=24, N=5, p=9, seed=18)]
+    nrhs = 3
+    h = sv.Handle(wins, sv.Precond(type="PI", k=2, rhat="RR"))
+    rhs = [wl.random_vectors(w, nrhs, seed=30 + i) for i, w in enumerate(wins)]
+    off = h.offsets(nrhs)
+    x, info, rc = h.solve(dev(np.concatenate([r.reshape(-1) for r in rhs])), nrhs, rtol=1e-10,
+                          maxit=400, restart=8, max_outer=100)
+    assert rc == sv.OK, info
+    X = host(x)
+    for i, w in enumerate(wins):
+        orc = so.SaddleOracle(w, k=2, rhat="RR")
+        A = orc.A_dense()
+        xs = X[off[i]:off[i + 1]].reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert np.linalg.norm(rhs[i][r] - A @ xs[r]) <= 1.0001e-10 * np.linalg.norm(rhs[i][r])
+            assert info[i * nrhs + r]["outer"] >= 1
+
+
+@pytest.mark.parametrize("precision", ["MIXED_FP32", "MIXED_BF16P"])
+def test_mixed_precision_refinement(sv, precision):
+    win = wl.make_config_window("c1", seed=2)
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    rhs = win.rhs[0]
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    x64, i64, rc = h.solve(dev(rhs), rtol=1e-8, maxit=win.n)
+    xm, im, rcm = h.solve(dev(rhs), rtol=1e-8, maxit=win.n, restart=60, precision=precision,
+                          inner_rtol=1e-3, max_outer=60)
+    assert rcm == sv.OK, im
+    assert im[0]["relres_true"] <= 1e-8
+    rr = np.linalg.norm(rhs - orc.apply_A(host(xm))) / np.linalg.norm(rhs)
+    assert rr <= 1e-8
+    A = orc.A_dense()
+    kappa = np.linalg.cond(A)
+    assert rel(host(xm), host(x64)) <= 4 * kappa * 1e-8
+
+
+# ------------------------------------------------------------------ edge cases
+def test_edge_cases(sv):
+    win = tiny(seed=19, s=8, N=3, p=4)
+    h = sv.Handle([win], sv.Precond(type="PI", k=2, rhat="RR"))
+    z = torch.zeros(win.n, dtype=torch.float64, device="cuda")
+    x, info, rc = h.solve(z, rtol=1e-8, maxit=50)
+    assert rc == sv.OK and info[0]["iters"] == 0 and float(x.abs().max()) == 0.0
+    bad = dev(win.rhs[0])
+    bad[3] = float("nan")
+    x, info, rc = h.solve(bad, rtol=1e-8, maxit=50)
+    assert rc == sv.E_BREAKDOWN
+    x, info, rc = h.solve(dev(win.rhs[0]), rtol=1e-14, maxit=3)
+    assert rc == sv.E_NOCONV and info[0]["iters"] == 3
+    # N = 0 (one time block), blocks without observations
+    w0 = wl.make_small_window(s=12, N=0, p=5, seed=21)
+    h0 = sv.Handle([w0], sv.Precond(type="PD", k=1, rhat="EXACT"))
+    orc0 = so.SaddleOracle(w0, rhat="EXACT")
+    x, info, rc = h0.solve(dev(w0.rhs[0]), rtol=1e-12, maxit=w0.n)
+    assert rc == sv.OK and rel(host(x), np.linalg.solve(orc0.A_dense(), w0.rhs[0])) < 1e-9
+    w1 = tiny(seed=22, s=10, N=4, p=5)
+    w1.p = np.array([5, 0, 5, 0, 5], dtype=np.int32)
+    w1.h_cols = [c if pi else c[:0] for c, pi in zip(w1.h_cols, w1.p)]
+    w1.h_vals = [v if pi else v[:0] for v, pi in zip(w1.h_vals, w1.p)]
+    w1.rmats = [w1.rmats[0], np.zeros((0, 0))]
+    w1.r_index = np.array([0, 1, 0, 1, 0], dtype=np.int32)
+    orc1 = so.SaddleOracle(w1, k=5, rhat="RR")
+    h1 = sv.Handle([w1], sv.Precond(type="PI", k=5, rhat="RR"))
+    V = wl.random_vectors(w1, 1, seed=23)[0]
+    assert rel(host(h1.apply_A(dev(V))), orc1.apply_A(V)) < 1e-12
+    assert rel(host(h1.apply_P(dev(V))), orc1.apply_P_inv(V, "PI")) < 1e-10
+
+
+def test_invalid_inputs_rejected(sv):
+    win = tiny(seed=24, s=8, N=3, p=4)
+    with pytest.raises(sv.SvarError) as e:
+        sv.Handle([win], sv.Precond(type="PI", k=win.N + 2))
+    assert e.value.code == sv.E_INVAL
+    bad = tiny(seed=24, s=8, N=3, p=4)
+    R = bad.rmats[0].copy()
+    R[0, 0] = -5.0
+    bad.rmats = [R]
+    with pytest.raises(sv.SvarError) as e:
+        sv.Handle([bad], sv.Precond(type="PI", k=2, rhat="EXACT"))
+    assert e.value.code == sv.E_NOTSPD
+
+
+# ------------------------------------------------------------------ full-size (C2 shape)
+@pytest.fixture(scope="module")
+def c2():
+    return wl.make_config_window("c2", seed=0)
+
+
+def test_c2_operator_parity(sv, c2):
+    """C2 shape (s=4096, N=64, p=2048): A v and P_I^{-1} v (k=3, R_RR) against the oracle."""
+    win = c2
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    V = wl.random_vectors(win, 1, seed=40)[0]
+    assert rel(host(h.apply_A(dev(V))), orc.apply_A(V)) < 1e-12
+    assert rel(host(h.apply_P(dev(V))), orc.apply_P_inv(V, "PI")) < 1e-10
+    lam = np.linalg.eigvalsh(win.rmats[0])
+    assert abs(h.rhat_params(0)["gamma"][0] - lam[0]) <= 1e-9 * lam[0]
+
+
+def test_c2_solve_true_residual(sv, c2):
+    """The metric's solve at full size: the oracle's own A confirms ||rhs - A x|| <= 1e-6 ||rhs||."""
+    win = c2
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    rhs = win.rhs[0]
+    x, info, rc = h.solve(dev(rhs), rtol=1e-6, maxit=1000)
+    assert rc == sv.OK, info
+    rr = np.linalg.norm(rhs - orc.apply_A(host(x))) / np.linalg.norm(rhs)
+    assert rr <= 1e-6
+    assert abs(rr - info[0]["relres_true"]) <= 1e-9
