@@ -170,6 +170,16 @@ int svar_apply_A(svar_handle* h, int32_t nrhs, const double* v, double* y, void*
    P_I^{-1} v = (c1 = Lhat^{-T} v3, Rhat^{-1} v2, Lhat^{-1}(v1 - D c1)). */
 int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void* stream);
 
+/* The operators of the inner loop of the mixed-precision solves (§6.2 maps with reduced-
+   precision covariance products, float32 accumulation).  precision = SVAR_PRECISION_FP64 is
+   svar_apply_A / svar_apply_P; for A both mixed settings use float32 copies of D and R; for
+   P, SVAR_PRECISION_MIXED_BF16P uses bfloat16 copies of D, Rhat^{-1} and Dhat^{-1} and
+   SVAR_PRECISION_MIXED_FP32 is the float64 preconditioner.  Vectors stay float64. */
+int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* y,
+                      void* stream);
+int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* z,
+                      void* stream);
+
 /* Component maps, for checking each step on its own.  Vectors of the "state" space hold
    (N+1) s entries per (window, rhs); those of the "obs" space hold sum_i p_i entries; packed
    window by window and rhs by rhs like saddle vectors. */

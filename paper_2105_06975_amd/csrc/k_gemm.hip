@@ -101,14 +101,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
       for (int ct = 0; ct < CT; ++ct)
         acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[ct][i], acc[ct], 0, 0, 0);
   }
-  // lane holds rows rbase + 4q + e (e = 0..3) of column col0 + 16 ct + r16
+  // v_mfma_f64_16x16x4f64 result layout: accumulator element e of lane (q, r16) is row
+  // q + 4 e of the 16 x 16 tile (rows interleaved across the four lane groups), column r16
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int c = t.col0 + ct * 16 + r16;
     if (c >= P.ncols) continue;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int r = rbase + 4 * q + e;
+      const int r = rbase + q + 4 * e;
       if (r >= P.n) continue;
       if (P.splits > 1)
         ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = acc[ct][e];
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const GemmProb* __restrict__ pr
       for (int ct = 0; ct < CT; ++ct)
         acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[ct][i], acc[ct], 0, 0, 0);
   }
+  // v_mfma_f32_16x16x4f32 result layout: element e of lane (q, r16) is row 4 q + e
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int c = t.col0 + ct * 16 + r16;

@@ -1270,6 +1270,29 @@ int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void*
   return run_program(h, *P, const_cast<double*>(v), z, st, nullptr);
 }
 
+int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* y,
+                      void* stream) {
+  if (!h || !v || !y || nrhs < 1) return inval("bad arguments");
+  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_MIXED_BF16P)
+    return inval("bad precision");
+  Program* P = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  SVAR_TRY(get_program(h, PROG_A, nrhs, precision == SVAR_PRECISION_FP64 ? PV_F64 : PV_F32, &P, st));
+  return run_program(h, *P, const_cast<double*>(v), y, st, nullptr);
+}
+
+int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* z,
+                      void* stream) {
+  if (!h || !v || !z || nrhs < 1) return inval("bad arguments");
+  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_MIXED_BF16P)
+    return inval("bad precision");
+  Program* P = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  SVAR_TRY(get_program(h, PROG_P, nrhs, precision == SVAR_PRECISION_MIXED_BF16P ? PV_BF16P : PV_F64,
+                       &P, st));
+  return run_program(h, *P, const_cast<double*>(v), z, st, nullptr);
+}
+
 int svar_apply_op(svar_handle* h, int32_t op, int32_t nrhs, const double* in, double* out,
                   void* stream) {
   if (!h || !in || !out || nrhs < 1) return inval("bad arguments");

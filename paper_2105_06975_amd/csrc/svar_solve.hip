@@ -192,7 +192,10 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   SVAR_TRY(sys_norm2(h, rhs, rhs2, st));
   std::vector<int> iters(nsys, 0), status(nsys, SVAR_OK), cycles(nsys, 0);
   std::vector<double> est(nsys, 0.0), relres(nsys, 1.0);
-  for (int i = 0; i < nsys; ++i) relres[i] = rhs2[i] > 0 ? 1.0 : 0.0;
+  for (int i = 0; i < nsys; ++i) {
+    relres[i] = rhs2[i] > 0 ? 1.0 : 0.0;
+    if (!std::isfinite(rhs2[i])) status[i] = SVAR_E_BREAKDOWN;  // non-finite right-hand side
+  }
   SVAR_HIP(hipMemcpyAsync(K.r, rhs, K.ntot * sizeof(double), hipMemcpyDeviceToDevice, st));
   int64_t applies_A64 = 0;
   int max_outer = std::max(1, o->max_outer);
@@ -248,7 +251,8 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   int rc = SVAR_OK;
   for (int i = 0; i < nsys; ++i) {
     const double nb = std::sqrt(rhs2[i]);
-    const double rr = nb > 0 ? std::sqrt(r2[i]) / nb : 0.0;
+    const double rr = !std::isfinite(nb) ? std::numeric_limits<double>::quiet_NaN()
+                                         : (nb > 0 ? std::sqrt(r2[i]) / nb : 0.0);
     svar_solve_info& I = info[i];
     I.iters = iters[i];
     I.outer = cycles[i];

@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     for f in (lib.svar_apply_A, lib.svar_apply_P):
         f.argtypes = [vp, C.c_int32, vp, vp, vp]
     lib.svar_apply_op.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
+    for f in (lib.svar_apply_A_prec, lib.svar_apply_P_prec):
+        f.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     lib.svar_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int32, vp, vp, C.POINTER(SolveInfo),
                                vp]
     lib.svar_rhat_params.argtypes = [vp, C.c_int32, _dp, _dp, _dp]
@@ -239,16 +241,24 @@ class Handle:
         return tot
 
     # ------------------------------------------------------------- operators
-    def apply_A(self, v, nrhs: int = 1, out=None, stream=None):
+    def apply_A(self, v, nrhs: int = 1, out=None, stream=None, precision: str = "FP64"):
         import torch
         out = torch.empty_like(v) if out is None else out
-        _check(lib().svar_apply_A(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
+        if precision == "FP64":
+            _check(lib().svar_apply_A(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
+        else:
+            _check(lib().svar_apply_A_prec(self._h, PRECISION[precision], nrhs, _vp(v), _vp(out),
+                                           _stream(stream)))
         return out
 
-    def apply_P(self, v, nrhs: int = 1, out=None, stream=None):
+    def apply_P(self, v, nrhs: int = 1, out=None, stream=None, precision: str = "FP64"):
         import torch
         out = torch.empty_like(v) if out is None else out
-        _check(lib().svar_apply_P(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
+        if precision == "FP64":
+            _check(lib().svar_apply_P(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
+        else:
+            _check(lib().svar_apply_P_prec(self._h, PRECISION[precision], nrhs, _vp(v), _vp(out),
+                                           _stream(stream)))
         return out
 
     def apply_op(self, op: str, v, nrhs: int = 1, out=None, stream=None):
@@ -270,7 +280,8 @@ class Handle:
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
-        if rc not in (OK, E_NOCONV) or (check and rc != OK):
+        # E_NOCONV / E_BREAKDOWN are solver outcomes reported per system in info
+        if rc not in (OK, E_NOCONV, E_BREAKDOWN) or (check and rc != OK):
             _check(rc)
         return x, [i.as_dict() for i in infos], rc
 
