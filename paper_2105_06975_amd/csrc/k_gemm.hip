@@ -40,21 +40,63 @@ __device__ __forceinline__ double ld_c(const void* C, size_t i, int dt) {
   return (double)__uint_as_float(((unsigned)h) << 16);
 }
 
-template <int CT>
+// FP64 product.  Workgroup = 4 waves sharing one (RT x 16)-row tile and its k-range: wave w
+// takes the w-th quarter of the k-range, so the workgroup's partial sums are combined in LDS
+// (two rounds, fixed order) and only the split-K over workgroups goes through global memory.
+// Each wave keeps RT x CT accumulator tiles; the operand fragments of step s+1 are loaded
+// while the MFMAs of step s run (two register buffers), which hides global-load latency.
+template <int CT, int RT>
+__device__ __forceinline__ void gemm_load(const double* const (&A)[RT], const bool (&rok)[RT],
+                                          const double* const (&xp)[CT], const bool (&cok)[CT],
+                                          int kk, int ke, double (&a)[RT][4],
+                                          double (&bb)[CT][4]) {
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[rt][i] = (rok[rt] && kk + i < ke) ? A[rt][kk + i] : 0.0;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bb[ct][i] = (cok[ct] && kk + i < ke) ? xp[ct][kk + i] : 0.0;
+}
+
+template <int CT, int RT>
+__device__ __forceinline__ void gemm_mfma(v4d (&acc)[RT][CT], const double (&a)[RT][4],
+                                          const double (&bb)[CT][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][i], bb[ct][i], acc[rt][ct], 0, 0, 0);
+}
+
+template <int CT, int RT>
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ probs,
-                                                  const GemmTask* __restrict__ tasks,
-                                                  double* __restrict__ ws, Bases b,
-                                                  const int* __restrict__ skip) {
+                                                     const GemmTask* __restrict__ tasks,
+                                                     double* __restrict__ ws, Bases b,
+                                                     const int* __restrict__ skip) {
+  __shared__ double red[2][RT * CT * 4][64];
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, q = lane >> 4;
-  const int rbase = t.row0 + wave * 16;
+  const int rbase = t.row0;
   if (rbase >= P.n) return;
-  const int rowA = rbase + r16;
-  const bool rowok = rowA < P.n;
-  const double* __restrict__ A = (const double*)P.C + (size_t)(rowok ? rowA : 0) * P.n;
+  // this wave's quarter of the workgroup k-range (multiple of 16)
+  const int wlen = ((t.k1 - t.k0 + 63) / 64) * 16;
+  const int kb = t.k0 + wave * wlen;
+  const int ke = min(t.k1, kb + wlen);
+  const double* A[RT];
+  bool rok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int row = rbase + rt * 16 + r16;
+    rok[rt] = row < P.n;
+    A[rt] = (const double*)P.C + (size_t)(rok[rt] ? row : 0) * P.n;
+  }
   const double* X = opnd(b, P.X);
   const double* xp[CT];
   bool cok[CT];
@@ -66,41 +108,44 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
     const int co = cc / P.per, ci = cc - co * P.per;
     xp[ct] = X + co * P.xo + ci * P.xi;
   }
-  v4d acc[CT];
+  v4d acc[RT][CT];
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) acc[ct] = (v4d){0.0, 0.0, 0.0, 0.0};
-
-  int k = t.k0;
-  for (; k + 16 <= t.k1; k += 16) {
-    const int kk = k + 4 * q;
-    double a[4], bb[CT][4];
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = rowok ? A[kk + i] : 0.0;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) bb[ct][i] = cok[ct] ? xp[ct][kk + i] : 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[ct][i], acc[ct], 0, 0, 0);
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = (v4d){0.0, 0.0, 0.0, 0.0};
+  double a0[RT][4], b0[CT][4], a1[RT][4], b1[CT][4];
+  // two steps of 16 per trip; loads past ke are masked off (they contribute zeros)
+  gemm_load<CT, RT>(A, rok, xp, cok, kb + 4 * q, ke, a0, b0);
+  for (int k = kb; k < ke; k += 32) {
+    gemm_load<CT, RT>(A, rok, xp, cok, k + 16 + 4 * q, ke, a1, b1);
+    gemm_mfma<CT, RT>(acc, a0, b0);
+    gemm_load<CT, RT>(A, rok, xp, cok, k + 32 + 4 * q, ke, a0, b0);
+    gemm_mfma<CT, RT>(acc, a1, b1);
   }
-  if (k < t.k1) {  // ragged tail of the k-range
-    const int kk = k + 4 * q;
-    double a[4], bb[CT][4];
+  // combine the four waves: (2,3) -> (0,1), then 1 -> 0
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = (rowok && kk + i < t.k1) ? A[kk + i] : 0.0;
+  for (int round = 0; round < 2; ++round) {
+    const int half = round == 0 ? 2 : 1;
+    if (wave >= half && wave < 2 * half) {
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) bb[ct][i] = (cok[ct] && kk + i < t.k1) ? xp[ct][kk + i] : 0.0;
+        for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+          for (int e = 0; e < 4; ++e) red[wave - half][(rt * CT + ct) * 4 + e][lane] = acc[rt][ct][e];
+    }
+    __syncthreads();
+    if (wave < half) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[ct][i], acc[ct], 0, 0, 0);
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[rt][ct][e] += red[wave][(rt * CT + ct) * 4 + e][lane];
+    }
+    __syncthreads();
   }
+  if (wave != 0) return;
   // v_mfma_f64_16x16x4f64 result layout: accumulator element e of lane (q, r16) is row
   // q + 4 e of the 16 x 16 tile (rows interleaved across the four lane groups), column r16
 #pragma unroll
@@ -108,14 +153,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
     const int c = t.col0 + ct * 16 + r16;
     if (c >= P.ncols) continue;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = rbase + q + 4 * e;
-      if (r >= P.n) continue;
-      if (P.splits > 1)
-        ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = acc[ct][e];
-      else
-        gemm_store(P, b, r, c, acc[ct][e]);
-    }
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rbase + rt * 16 + q + 4 * e;
+        if (r >= P.n) continue;
+        if (P.splits > 1)
+          ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = acc[rt][ct][e];
+        else
+          gemm_store(P, b, r, c, acc[rt][ct][e]);
+      }
   }
 }
 
@@ -203,8 +250,8 @@ template <int CT>
 static void launch_ct(const GemmPlanDev& g, Bases b, double* ws, const int* skip,
                       hipStream_t st) {
   if (g.dtype == DT_F64)
-    hipLaunchKernelGGL(k_gemm_f64<CT>, dim3(g.ntask), dim3(256), 0, st, g.probs, g.tasks, ws, b,
-                       skip);
+    hipLaunchKernelGGL((k_gemm_f64<CT, gemm_rt(CT)>), dim3(g.ntask), dim3(256), 0, st, g.probs,
+                       g.tasks, ws, b, skip);
   else
     hipLaunchKernelGGL(k_gemm_lp<CT>, dim3(g.ntask), dim3(256), 0, st, g.probs, g.tasks, ws, b,
                        skip);

@@ -27,6 +27,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums 16 values per lane over the 64 lanes of a wave with a halving exchange: at each of
+// four steps a lane keeps half of its values and adds its partner's copy of that half, then
+// two plain butterfly steps finish.  On return lane l holds the wave total of value
+// index (l >> 2) & 15.  17 double shuffles instead of 16 x 6.
+__device__ __forceinline__ double wave_sum16(double (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int o = 32 >> step;          // partner distance
+    const int K = 16 >> step;          // live values
+    const bool up = (lane & o) != 0;   // keeps the upper half
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+      const double send = up ? v[i] : v[i + K / 2];
+      const double keep = up ? v[i + K / 2] : v[i];
+      v[i] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  double r = v[0];
+  r += __shfl_xor(r, 2, 64);
+  r += __shfl_xor(r, 1, 64);
+  return r;
+}
+
 // block-wide sum of one value per thread; every thread gets the result
 __device__ double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -161,22 +185,34 @@ __global__ __launch_bounds__(NT) void k_fg_dot(const KTask* __restrict__ tasks,
     if (ok && with_w) Zb[(int64_t)j * ntot + idx[q]] = z[idx[q]];
   }
   double* P = part + (int64_t)blockIdx.x * SL;
+  int64_t cidx[EPT];  // clamped indices: loads stay in range, the weights are zero outside
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) cidx[q] = idx[q] < t.e1 ? idx[q] : t.e1 - 1;
   for (int t0 = 0; t0 < j; t0 += 64) {
     const int tn = min(64, j - t0);
-    for (int tt = 0; tt < tn; ++tt) {
-      const double* Vt = V + (int64_t)(t0 + tt) * ntot;
-      double aw = 0.0, au = 0.0;
+    for (int tt = 0; tt < tn; tt += 8) {
+      double acc[16];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const double v = idx[q] < t.e1 ? Vt[idx[q]] : 0.0;
-        aw += v * wr[q];
-        au += v * ur[q];
+      for (int v8 = 0; v8 < 8; ++v8) {
+        const int tv = min(t0 + tt + v8, j - 1);
+        const double* Vt = V + (int64_t)tv * ntot;
+        double aw = 0.0, au = 0.0;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const double v = Vt[cidx[q]];
+          aw += v * wr[q];
+          au += v * ur[q];
+        }
+        acc[2 * v8] = aw;
+        acc[2 * v8 + 1] = au;
       }
-      aw = wave_sum(aw);
-      au = wave_sum(au);
-      if (ln == 0) {
-        lw[wv][tt] = aw;
-        lu[wv][tt] = au;
+      const double s = wave_sum16(acc);
+      const int id = (ln >> 2) & 15;
+      if ((ln & 3) == 0 && tt + (id >> 1) < tn) {
+        if (id & 1)
+          lu[wv][tt + (id >> 1)] = s;
+        else
+          lw[wv][tt + (id >> 1)] = s;
       }
     }
     __syncthreads();
@@ -253,6 +289,7 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
                                                  KHess* __restrict__ hs, int m, int finalize_only) {
   __shared__ double red[NT / 64];
   __shared__ double col[1];
+  extern __shared__ double dyn[];  // 3 j + 1 doubles
   if (gl->all_done) return;
   KState S = st[blockIdx.x];
   const int j = gl->j;
@@ -277,16 +314,27 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
   // finalise column j-1: H[0..j-1][j-1] = hprev + s / sigma, H[j][j-1] = nu / sigma
   if (j >= 1) {
     double* Hc = Hh.H + (int64_t)(j - 1) * (m + 1);
-    for (int t = threadIdx.x; t < j; t += NT) Hc[t] = Hh.hprev[t] + sm[m + t] / sig;
+    // stage the new column and the rotations in LDS; the rotation chain runs on one thread
+    // with the running entry in a register
+    double* lc = dyn;           // j + 1
+    double* lcs = dyn + (j + 1);  // j
+    double* lsn = lcs + j;        // j
+    for (int t = threadIdx.x; t < j; t += NT) {
+      lc[t] = Hh.hprev[t] + sm[m + t] / sig;
+      lcs[t] = Hh.cs[t];
+      lsn[t] = Hh.sn[t];
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      Hc[j] = nu / sig;
+      lc[j] = nu / sig;
+      double carry = lc[0];
       for (int i = 0; i < j - 1; ++i) {
-        const double a = Hc[i], bq = Hc[i + 1];
-        Hc[i] = Hh.cs[i] * a + Hh.sn[i] * bq;
-        Hc[i + 1] = -Hh.sn[i] * a + Hh.cs[i] * bq;
+        const double bq = lc[i + 1];
+        lc[i] = lcs[i] * carry + lsn[i] * bq;
+        carry = -lsn[i] * carry + lcs[i] * bq;
       }
-      const double a = Hc[j - 1], bq = Hc[j];
+      lc[j - 1] = carry;
+      const double a = lc[j - 1], bq = lc[j];
       double rho = hypot(a, bq);
       double c = 1.0, s = 0.0;
       if (rho > 0.0) {
@@ -295,8 +343,8 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
       }
       Hh.cs[j - 1] = c;
       Hh.sn[j - 1] = s;
-      Hc[j - 1] = rho;
-      Hc[j] = 0.0;
+      lc[j - 1] = rho;
+      lc[j] = 0.0;
       const double gj = Hh.g[j - 1];
       Hh.g[j] = -s * gj;
       Hh.g[j - 1] = c * gj;
@@ -313,6 +361,8 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
         S.status = SVAR_E_NOCONV;
       }
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= j; t += NT) Hc[t] = lc[t];
   } else if (threadIdx.x == 0) {
     Hh.g[0] = nu / sig;  // r = (nu / sigma) v_0
     S.est = Hh.g[0];
@@ -370,16 +420,33 @@ __global__ __launch_bounds__(NT) void k_fg_update(const KTask* __restrict__ task
     as[q] = 0.0;
     ah[q] = 0.0;
   }
-  for (int tt = 0; tt < j; ++tt) {
-    const double* Vt = V + (int64_t)tt * ntot;
+  int64_t cidx[EPT];  // clamped: rows past the task end are computed but never stored
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) cidx[q] = idx[q] < t.e1 ? idx[q] : t.e1 - 1;
+  int tt = 0;
+  for (; tt + 4 <= j; tt += 4) {
+    double v[4][EPT];
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4)
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) v[u4][q] = V[(int64_t)(tt + u4) * ntot + cidx[q]];
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4) {
+      const double cs_ = coef[tt + u4], ch = coef[j + tt + u4];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        as[q] += v[u4][q] * cs_;
+        ah[q] += v[u4][q] * ch;
+      }
+    }
+  }
+  for (; tt < j; ++tt) {
     const double cs_ = coef[tt], ch = coef[j + tt];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      if (idx[q] < t.e1) {
-        const double v = Vt[idx[q]];
-        as[q] += v * cs_;
-        ah[q] += v * ch;
-      }
+      const double v = V[(int64_t)tt * ntot + cidx[q]];
+      as[q] += v * cs_;
+      ah[q] += v * ch;
     }
   }
   const double inu = 1.0 / S.nu, hj = coef[2 * j];
@@ -405,18 +472,24 @@ __global__ void k_fg_advance(KGlobal* __restrict__ gl) {
 }
 
 // ---------------------------------------------------------------- end of cycle
-// y = R^{-1} g (upper triangular from the rotated Hessenberg), one workgroup per system.
-__global__ __launch_bounds__(64) void k_fg_solve_y(const KState* __restrict__ st,
+// y = R^{-1} g (upper triangular from the rotated Hessenberg), one workgroup per system;
+// column-oriented back substitution: y_i = g_i / R_ii, then g_t -= R_ti y_i for t < i.
+__global__ __launch_bounds__(NT) void k_fg_solve_y(const KState* __restrict__ st,
                                                    KHess* __restrict__ hs, int m) {
+  extern __shared__ double gv[];
   const KState S = st[blockIdx.x];
   KHess Hh = hs[blockIdx.x];
   const int nc = S.iters;
-  if (threadIdx.x != 0) return;
+  for (int t = threadIdx.x; t < nc; t += NT) gv[t] = Hh.g[t];
+  __syncthreads();
   for (int i = nc - 1; i >= 0; --i) {
-    double acc = Hh.g[i];
-    for (int c = i + 1; c < nc; ++c) acc -= Hh.H[(int64_t)c * (m + 1) + i] * Hh.y[c];
-    const double d = Hh.H[(int64_t)i * (m + 1) + i];
-    Hh.y[i] = d != 0.0 ? acc / d : 0.0;
+    const double* Ri = Hh.H + (int64_t)i * (m + 1);
+    const double d = Ri[i];
+    const double yi = d != 0.0 ? gv[i] / d : 0.0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < i; t += NT) gv[t] -= Ri[t] * yi;
+    if (threadIdx.x == 0) Hh.y[i] = yi;
+    __syncthreads();
   }
 }
 
@@ -481,9 +554,9 @@ void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const doubl
                      m);
 }
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
-              int finalize_only, hipStream_t st) {
-  hipLaunchKernelGGL(k_fg_small, dim3(p.nsys), dim3(NT), 0, st, stt, gl, sums, hs, m,
-                     finalize_only);
+              int finalize_only, int jmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_fg_small, dim3(p.nsys), dim3(NT), (size_t)(3 * jmax + 4) * sizeof(double),
+                     st, stt, gl, sums, hs, m, finalize_only);
 }
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
@@ -496,7 +569,8 @@ void kr_advance(KGlobal* gl, hipStream_t st) {
   hipLaunchKernelGGL(k_fg_advance, dim3(1), dim3(64), 0, st, gl);
 }
 void kr_solve_y(const KPlan& p, const KState* stt, KHess* hs, int m, hipStream_t st) {
-  hipLaunchKernelGGL(k_fg_solve_y, dim3(p.nsys), dim3(64), 0, st, stt, hs, m);
+  hipLaunchKernelGGL(k_fg_solve_y, dim3(p.nsys), dim3(NT), (size_t)(m + 1) * sizeof(double), st,
+                     stt, hs, m);
 }
 void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double* Zb,
                 int64_t ntot, double* x, int m, hipStream_t st) {

@@ -6,7 +6,7 @@ namespace svar {
 
 #define KR_EPT 4                 // elements per thread of the Gram-Schmidt passes
 #define KR_TASK (256 * KR_EPT)   // elements per task (workgroup) of a pass
-#define KR_MAX_CYCLE 3000        // basis vectors per FGMRES cycle (LDS of the update pass)
+#define KR_MAX_CYCLE 2500        // basis vectors per FGMRES cycle (LDS of the small steps)
 
 struct KTask {      // a contiguous element range of one system
   int32_t sys, pad;
@@ -54,7 +54,7 @@ void kr_dot(const KPlan& p, const KState* stt, const KGlobal* gl, const double* 
 void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const double* part,
                double* sums, int m, int jmax, hipStream_t st);
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
-              int finalize_only, hipStream_t st);
+              int finalize_only, int jmax, hipStream_t st);
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
                hipStream_t st);

@@ -35,19 +35,24 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
   maxct = std::min(8, (maxcols + 15) / 16);
   const int cw = maxct * 16;
+  const int rows = 16 * gemm_rt(maxct);  // rows per workgroup
   double total_work = 0.0;
   for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
-  const int target = 1024;
+  const int lowp = probs.empty() ? 0 : probs[0].dtype != DT_F64;
+  const int target = lowp ? 1024 : 512;  // workgroups (the FP64 kernel keeps 4 waves on k)
   ws = 0;
   tasks.clear();
   for (int pi = 0; pi < (int)probs.size(); ++pi) {
     GemmProb& p = probs[pi];
-    const int rt = (p.n + 63) / 64, cg = (p.ncols + cw - 1) / cw;
+    const int rtile = lowp ? 64 : rows;
+    const int rt = (p.n + rtile - 1) / rtile, cg = (p.ncols + cw - 1) / cw;
     const double share = total_work > 0 ? (double)p.n * p.n * p.ncols / total_work : 1.0;
     const int want = (int)std::ceil(target * share / (double)(rt * cg));
-    const int maxs = std::max(1, p.n / 256);
+    const int kmin = lowp ? 256 : 512;  // at least 128 k per wave
+    const int maxs = std::max(1, p.n / kmin);
     int S = std::max(1, std::min(want, maxs));
-    const int chunk = ((p.n + S - 1) / S + 15) / 16 * 16;
+    const int align = lowp ? 16 : 64;
+    const int chunk = ((p.n + S - 1) / S + align - 1) / align * align;
     S = (p.n + chunk - 1) / chunk;
     p.splits = S;
     p.ws_off = 0;
@@ -60,7 +65,7 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
         for (int c = 0; c < cg; ++c) {
           GemmTask t;
           t.prob = pi;
-          t.row0 = r * 64;
+          t.row0 = r * rtile;
           t.k0 = sp * chunk;
           t.k1 = std::min(p.n, (sp + 1) * chunk);
           t.col0 = c * cw;

@@ -65,6 +65,8 @@ struct GemmProb {
 struct GemmTask {
   int32_t prob, row0, k0, k1, col0, split;
 };
+// row tiles (of 16) per wave of the FP64 product, by the number of 16-column tiles
+constexpr int gemm_rt(int ct) { return ct <= 5 ? 2 : 1; }
 
 // ------------------------------------------------------------------ model products
 // out[j] = in[j] + alpha * (M op x)[j], j < s, for one block; op = M_mi or M_mi^T.

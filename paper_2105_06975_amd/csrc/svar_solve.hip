@@ -136,7 +136,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
     timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, j, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, j, st);
     timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
     kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, j, st);
     timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
@@ -155,7 +155,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 0, K.part, st);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, m, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, st);
   }
   kr_solve_y(K.plan, K.st, K.hs, m, st);
   kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ntot, x, m, st);
