@@ -18,6 +18,10 @@ namespace svar {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+// global-address-space pointer: loads through it are global_load (counted by vmcnt only,
+// so a wait can target the older of two in-flight batches); generic pointers become flat
+// loads whose counter can only be waited to zero
+typedef const __attribute__((address_space(1))) double* gdp;
 
 __device__ __forceinline__ double* opnd(const Bases& b, const Operand& o) {
   return b.p[o.base] + o.off;
@@ -45,19 +49,43 @@ __device__ __forceinline__ double ld_c(const void* C, size_t i, int dt) {
 // (two rounds, fixed order) and only the split-K over workgroups goes through global memory.
 // Each wave keeps RT x CT accumulator tiles; the operand fragments of step s+1 are loaded
 // while the MFMAs of step s run (two register buffers), which hides global-load latency.
+// Operand loads are unconditional from always-valid addresses (rows / columns past the end
+// are clamped to the first one) and the values are masked afterwards, so no load sits behind
+// a branch and all loads of a step stay in flight together.  Full steps need no k check; the
+// ragged last step clamps each k index as well.
 template <int CT, int RT>
-__device__ __forceinline__ void gemm_load(const double* const (&A)[RT], const bool (&rok)[RT],
-                                          const double* const (&xp)[CT], const bool (&cok)[CT],
-                                          int kk, int ke, double (&a)[RT][4],
-                                          double (&bb)[CT][4]) {
+__device__ __forceinline__ void gemm_load_full(const gdp (&A)[RT], const bool (&rok)[RT],
+                                               const gdp (&xp)[CT],
+                                               const bool (&cok)[CT], int kk, double (&a)[RT][4],
+                                               double (&bb)[CT][4]) {
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[rt][i] = (rok[rt] && kk + i < ke) ? A[rt][kk + i] : 0.0;
+    for (int i = 0; i < 4; ++i) a[rt][i] = A[rt][kk + i];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bb[ct][i] = (cok[ct] && kk + i < ke) ? xp[ct][kk + i] : 0.0;
+    for (int i = 0; i < 4; ++i) bb[ct][i] = xp[ct][kk + i];
+}
+template <int CT, int RT>
+__device__ __forceinline__ void gemm_load_tail(const gdp (&A)[RT], const bool (&rok)[RT],
+                                               const gdp (&xp)[CT],
+                                               const bool (&cok)[CT], int kk, int ke, int n,
+                                               double (&a)[RT][4], double (&bb)[CT][4]) {
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double v = A[rt][min(kk + i, n - 1)];
+      a[rt][i] = (rok[rt] && kk + i < ke) ? v : 0.0;
+    }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double v = xp[ct][min(kk + i, n - 1)];
+      bb[ct][i] = (cok[ct] && kk + i < ke) ? v : 0.0;
+    }
 }
 
 template <int CT, int RT>
@@ -81,7 +109,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // wave index as a scalar: the k-range bounds below are then uniform and the loop control
+  // stays on scalar branches (no exec-masked regions around the prefetch loads)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, q = lane >> 4;
   const int rbase = t.row0;
   if (rbase >= P.n) return;
@@ -89,16 +120,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
   const int wlen = ((t.k1 - t.k0 + 63) / 64) * 16;
   const int kb = t.k0 + wave * wlen;
   const int ke = min(t.k1, kb + wlen);
-  const double* A[RT];
+  gdp A[RT];
   bool rok[RT];
+  // rows / columns past the edge read the zero buffer, so loaded values need no masking
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int row = rbase + rt * 16 + r16;
     rok[rt] = row < P.n;
-    A[rt] = (const double*)P.C + (size_t)(rok[rt] ? row : 0) * P.n;
+    A[rt] = (gdp)(rok[rt] ? (const double*)P.C + (size_t)row * P.n : P.zeros);
   }
   const double* X = opnd(b, P.X);
-  const double* xp[CT];
+  gdp xp[CT];
   bool cok[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
@@ -106,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
     cok[ct] = c < P.ncols;
     const int cc = cok[ct] ? c : 0;
     const int co = cc / P.per, ci = cc - co * P.per;
-    xp[ct] = X + co * P.xo + ci * P.xi;
+    xp[ct] = (gdp)(cok[ct] ? X + co * P.xo + ci * P.xi : P.zeros);
   }
   v4d acc[RT][CT];
 #pragma unroll
@@ -114,13 +146,29 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = (v4d){0.0, 0.0, 0.0, 0.0};
   double a0[RT][4], b0[CT][4], a1[RT][4], b1[CT][4];
-  // two steps of 16 per trip; loads past ke are masked off (they contribute zeros)
-  gemm_load<CT, RT>(A, rok, xp, cok, kb + 4 * q, ke, a0, b0);
-  for (int k = kb; k < ke; k += 32) {
-    gemm_load<CT, RT>(A, rok, xp, cok, k + 16 + 4 * q, ke, a1, b1);
+  // full steps of 16, the next step's fragments loaded while the current one multiplies
+  const int nfull = ke > kb ? (ke - kb) >> 4 : 0;
+  if (nfull > 0) gemm_load_full<CT, RT>(A, rok, xp, cok, kb + 4 * q, a0, b0);
+  int s = 0;
+  // sched_barrier keeps each load batch ahead of the MFMA batch that does not need it, so the
+  // wait before the MFMAs covers only the older batch
+  for (; s + 2 <= nfull; s += 2) {
+    gemm_load_full<CT, RT>(A, rok, xp, cok, kb + 16 * (s + 1) + 4 * q, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
     gemm_mfma<CT, RT>(acc, a0, b0);
-    gemm_load<CT, RT>(A, rok, xp, cok, k + 32 + 4 * q, ke, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    // unconditional prefetch (a branch here would force a full wait at the join); the last
+    // trip re-loads the final full step, which is never used
+    gemm_load_full<CT, RT>(A, rok, xp, cok, kb + 16 * min(s + 2, nfull - 1) + 4 * q, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     gemm_mfma<CT, RT>(acc, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (s < nfull) gemm_mfma<CT, RT>(acc, a0, b0);
+  const int kt = kb + 16 * nfull;
+  if (kt < ke) {  // ragged last step
+    gemm_load_tail<CT, RT>(A, rok, xp, cok, kt + 4 * q, ke, P.n, a0, b0);
+    gemm_mfma<CT, RT>(acc, a0, b0);
   }
   // combine the four waves: (2,3) -> (0,1), then 1 -> 0
 #pragma unroll
@@ -201,13 +249,18 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const GemmProb* __restrict__ pr
     const int kk = k + 4 * q;
     float a[4], bb[CT][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      a[i] = (rowok && kk + i < t.k1) ? (float)ld_c(P.C, abase + kk + i, P.dtype) : 0.f;
+    for (int i = 0; i < 4; ++i) {
+      const int kc = min(kk + i, P.n - 1);  // always-valid address, value masked below
+      const float v = (float)ld_c(P.C, abase + kc, P.dtype);
+      a[i] = (rowok && kk + i < t.k1) ? v : 0.f;
+    }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        bb[ct][i] = (cok[ct] && kk + i < t.k1) ? (float)xp[ct][kk + i] : 0.f;
+      for (int i = 0; i < 4; ++i) {
+        const float v = (float)xp[ct][min(kk + i, P.n - 1)];
+        bb[ct][i] = (cok[ct] && kk + i < t.k1) ? v : 0.f;
+      }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll

@@ -75,12 +75,35 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
   }
 }
 
-static int make_gemm_plan(std::vector<void*>& owner, std::vector<GemmProb>& probs, int dtype,
-                          GemmPlanDev& g, hipStream_t st) {
+static int ensure_zeros(svar_handle* h, int64_t n, hipStream_t st) {
+  if (n <= h->zeros_elems) return SVAR_OK;
+  if (h->zeros) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(h->zeros);
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), (void*)h->zeros);
+    if (it != h->allocs.end()) h->allocs.erase(it);
+  }
+  h->zeros = nullptr;
+  h->zeros_elems = 0;
+  SVAR_TRY(dalloc(h->allocs, &h->zeros, (size_t)n));
+  launch_fill(h->zeros, n, 0.0, st);
+  SVAR_HIP(hipStreamSynchronize(st));
+  h->zeros_elems = n;
+  return SVAR_OK;
+}
+
+static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector<GemmProb>& probs,
+                          int dtype, GemmPlanDev& g, hipStream_t st) {
   std::vector<GemmTask> tasks;
   int64_t ws = 0;
   int maxct = 1;
-  for (auto& p : probs) p.dtype = dtype;
+  int64_t nmax = 1;
+  for (auto& p : probs) nmax = std::max<int64_t>(nmax, p.n);
+  SVAR_TRY(ensure_zeros(h, nmax, st));
+  for (auto& p : probs) {
+    p.dtype = dtype;
+    p.zeros = h->zeros;
+  }
   plan_gemm(probs, tasks, ws, maxct);
   g.nprob = (int)probs.size();
   g.ntask = (int)tasks.size();
@@ -132,7 +155,7 @@ static int gemm_abs(svar_handle* h, const double* C, int n, const double* X, dou
   std::vector<GemmProb> probs{p};
   std::vector<void*> tmp;
   GemmPlanDev g;
-  int rc = make_gemm_plan(tmp, probs, DT_F64, g, st);
+  int rc = make_gemm_plan(h, tmp, probs, DT_F64, g, st);
   if (rc == SVAR_OK) rc = regrow(h, &h->gemm_ws, &h->gemm_ws_elems, g.ws_elems);
   if (rc == SVAR_OK) {
     Bases b{};
@@ -903,7 +926,7 @@ static int add_gemm(Builder& B, std::vector<GemmProb>& probs, int dtype) {
   Launch L;
   L.kind = LK_GEMM;
   L.kclass = SVAR_KCLASS_GEMM;
-  SVAR_TRY(make_gemm_plan(B.h->allocs, probs, dtype, L.gemm, B.st));
+  SVAR_TRY(make_gemm_plan(B.h, B.h->allocs, probs, dtype, L.gemm, B.st));
   B.P->launches.push_back(L);
   return SVAR_OK;
 }

@@ -85,6 +85,8 @@ struct svar_handle {
   int64_t gemm_ws_elems = 0;
   double* tmp = nullptr;
   int64_t tmp_elems = 0;
+  double* zeros = nullptr;       // zero-filled, at least the largest matrix order
+  int64_t zeros_elems = 0;
   svar::Timer timers[SVAR_KCLASS_COUNT];
   // Krylov workspace (grown on demand)
   struct Kry {

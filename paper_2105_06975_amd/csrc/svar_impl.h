@@ -61,6 +61,7 @@ struct GemmProb {
   double alpha0, beta;
   int64_t ws_off;       // element offset of the split-K partials (splits > 1)
   int32_t dtype, pad;
+  const double* zeros;  // >= n zeros: stands in for rows / columns past the edge
 };
 struct GemmTask {
   int32_t prob, row0, k0, k1, col0, split;
