@@ -202,6 +202,16 @@ int svar_apply_op(svar_handle* h, int32_t op, int32_t nrhs, const double* in, do
 int svar_solve(svar_handle* h, const svar_solve_opts* opts, int32_t nrhs, const double* rhs,
                double* x, svar_solve_info* info, void* stream);
 
+/* Outer (Gauss-Newton) loop support, §2.1: the increments b_i = M_i(x_{i-1}) - x_i need the
+   model itself.  y_0 = x_0 and y_i = M_i(x_{i-1}) for i = 1..N, one observation interval of the
+   model of window w (nonlinear for SVAR_MODEL_L96_TLM: l96_nsteps RK4 steps; the linear map for
+   the other kinds).  x, y: device state vectors of (N+1) s doubles, distinct buffers. */
+int svar_model_forecast(svar_handle* h, int32_t w, const double* x, double* y, void* stream);
+
+/* Replace the linearisation states x_0..x_N of a Lorenz-96 window (device pointer, (N+1) s
+   doubles, copied), e.g. after an outer-loop update.  E_INVAL for other model kinds. */
+int svar_set_trajectory(svar_handle* h, int32_t w, const double* traj, void* stream);
+
 /* Set-up results of window w: gamma of R_RR, T of R_ME and lambda_1(R_i) for each distinct
    R matrix (host arrays of n_rmat entries; NaN where not applicable; any may be NULL). */
 int svar_rhat_params(const svar_handle* h, int32_t w, double* gamma, double* T, double* lam1);

@@ -56,7 +56,7 @@ class ModelOps:
                     Mb[j, (j + off) % s] += w
             self.mats = [Mb] * self.N
         elif self.kind == "l96":
-            from .l96_oracle import L96Tangent  # noqa: WPS433 (oracle-internal)
+            from oracle.l96_oracle import L96Tangent
             self.l96 = L96Tangent(m["F"], m["dt"], m["nsteps"], np.asarray(m["traj"]))
         else:
             raise ValueError(self.kind)

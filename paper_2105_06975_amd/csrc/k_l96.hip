@@ -189,6 +189,32 @@ __global__ __launch_bounds__(NT) void k_mstep_l96(const MJob* __restrict__ jobs,
   }
 }
 
+// y_0 = x_0, y_i = nonlinear model over one observation interval from x_{i-1} (i = 1..N);
+// one workgroup per block, the state in registers and an LDS copy for the neighbours.
+__global__ __launch_bounds__(NT) void k_l96_forecast(const double* __restrict__ x,
+                                                     double* __restrict__ y, int s, int N, double F,
+                                                     double h, int nsteps) {
+  __shared__ double ys[MAXS];
+  const int i = blockIdx.x;
+  if (i > N) return;
+  double xr[EPT];
+  for (int q = 0; q < EPT; ++q) {
+    const int j = threadIdx.x + q * NT;
+    xr[q] = j < s ? x[(size_t)(i > 0 ? i - 1 : 0) * s + j] : 0.0;
+  }
+  if (i > 0)
+    for (int n = 0; n < nsteps; ++n) rk4_step(xr, s, F, h, ys, nullptr);
+  for (int q = 0; q < EPT; ++q) {
+    const int j = threadIdx.x + q * NT;
+    if (j < s) y[(size_t)i * s + j] = xr[q];
+  }
+}
+
+void launch_l96_forecast(const double* x, double* y, int s, int N, double F, double h, int nsteps,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_l96_forecast, dim3(N + 1), dim3(NT), 0, st, x, y, s, N, F, h, nsteps);
+}
+
 void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
                       const int* skip, hipStream_t st) {
   if (njobs == 0) return;

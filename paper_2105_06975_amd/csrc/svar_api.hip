@@ -1333,6 +1333,64 @@ int svar_apply_op(svar_handle* h, int32_t op, int32_t nrhs, const double* in, do
   return run_program(h, *P, const_cast<double*>(in), out, st, nullptr);
 }
 
+int svar_model_forecast(svar_handle* h, int32_t w, const double* x, double* y, void* stream) {
+  if (!h || !x || !y || w < 0 || w >= (int)h->wins.size()) return inval("bad arguments");
+  if (x == y) return inval("x and y must be distinct");
+  hipStream_t st = (hipStream_t)stream;
+  const WinDev& W = h->wins[w];
+  const ModelDev& M = h->models[W.model_id];
+  if (M.kind == MK_L96) {
+    launch_l96_forecast(x, y, W.s, W.N, M.F, M.dt, M.nsteps, st);
+  } else {
+    // linear models: y_i = M_i x_{i-1} through the model-step kernels (y_0 = x_0)
+    std::vector<MJob> jobs;
+    for (int i = 0; i <= W.N; ++i) {
+      MJob J{};
+      J.s = W.s;
+      J.out = Operand{B_OUT, 0, (int64_t)i * W.s};
+      if (i == 0) {
+        J.in = Operand{B_IN, 0, 0};
+        J.x = J.in;
+        J.model = -1;
+      } else {
+        J.in = Operand{B_AUX, 0, 0};  // zeros
+        J.x = Operand{B_IN, 0, (int64_t)(i - 1) * W.s};
+        J.model = W.model_id;
+        J.mi = i;
+        J.alpha = 1.0;
+      }
+      jobs.push_back(J);
+    }
+    SVAR_TRY(ensure_zeros(h, W.s, st));
+    std::vector<void*> tmp;
+    MJob* dj = nullptr;
+    SVAR_TRY(upload(tmp, &dj, jobs.data(), jobs.size(), st));
+    Bases b{};
+    b.p[B_IN] = const_cast<double*>(x);
+    b.p[B_OUT] = y;
+    b.p[B_AUX] = h->zeros;
+    if (M.kind == MK_BAND)
+      launch_mstep_band(dj, (int)jobs.size(), W.s, h->max_halo, h->models_dev, b, nullptr, st);
+    else
+      launch_mstep_dense(dj, (int)jobs.size(), W.s, h->models_dev, b, nullptr, st);
+    SVAR_HIP(hipStreamSynchronize(st));
+    free_all(tmp);
+  }
+  SVAR_HIP(hipGetLastError());
+  return SVAR_OK;
+}
+
+int svar_set_trajectory(svar_handle* h, int32_t w, const double* traj, void* stream) {
+  if (!h || !traj || w < 0 || w >= (int)h->wins.size()) return inval("bad arguments");
+  const WinDev& W = h->wins[w];
+  const ModelDev& M = h->models[W.model_id];
+  if (M.kind != MK_L96) return inval("only Lorenz-96 windows carry a trajectory");
+  SVAR_HIP(hipMemcpyAsync(const_cast<double*>(M.traj), traj,
+                          (size_t)(W.N + 1) * W.s * sizeof(double), hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+  return SVAR_OK;
+}
+
 int svar_rhat_params(const svar_handle* h, int32_t w, double* gamma, double* T, double* lam1) {
   if (!h || w < 0 || w >= (int)h->wins.size()) return inval("bad window index");
   const WinDev& W = h->wins[w];

@@ -156,6 +156,9 @@ void launch_vec(const VJob* jobs, int njobs, int64_t max_len, Bases b, const int
                 hipStream_t st);
 void launch_gemm(const GemmPlanDev& g, Bases b, double* ws, const int* skip, hipStream_t st);
 
+void launch_l96_forecast(const double* x, double* y, int s, int N, double F, double h, int nsteps,
+                         hipStream_t st);
+
 // plain helpers used by set-up and drivers
 void launch_fill(double* x, int64_t n, double v, hipStream_t st);
 void launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipStream_t st);

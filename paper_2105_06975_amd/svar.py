@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svar_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int32, vp, vp, C.POINTER(SolveInfo),
                                vp]
     lib.svar_rhat_params.argtypes = [vp, C.c_int32, _dp, _dp, _dp]
+    lib.svar_model_forecast.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.svar_set_trajectory.argtypes = [vp, C.c_int32, vp, vp]
     lib.svar_timing_enable.argtypes = [vp, C.c_int32, C.c_int32]
     lib.svar_timing_read.argtypes = [vp, C.c_int32, _dp, C.POINTER(C.c_int64), C.c_int32]
     lib.svar_last_error.restype = C.c_char_p
@@ -284,6 +286,16 @@ class Handle:
         if rc not in (OK, E_NOCONV, E_BREAKDOWN) or (check and rc != OK):
             _check(rc)
         return x, [i.as_dict() for i in infos], rc
+
+    def model_forecast(self, x, w: int = 0, out=None, stream=None):
+        """y_0 = x_0, y_i = M_i(x_{i-1}): one observation interval of the model of window w."""
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().svar_model_forecast(self._h, w, _vp(x), _vp(out), _stream(stream)))
+        return out
+
+    def set_trajectory(self, traj, w: int = 0, stream=None):
+        _check(lib().svar_set_trajectory(self._h, w, _vp(traj), _stream(stream)))
 
     def rhat_params(self, w: int = 0):
         n = len(self.windows[w].rmats)

@@ -263,3 +263,69 @@ def with_dense_model(win: Window, *, seed: int = 0, norm: float = 0.9) -> Window
         mats.append(norm * G / np.linalg.norm(G, 2))
     win.model = dict(kind="dense", mats=mats)
     return win
+
+
+# ---------------------------------------------------------------- Lorenz-96 window (nonlinear)
+def _l96_tendency(x: np.ndarray, F: float) -> np.ndarray:
+    return (np.roll(x, -1) - np.roll(x, 2)) * np.roll(x, 1) - x + F
+
+
+def _l96_run(x: np.ndarray, F: float, dt: float, nsteps: int) -> np.ndarray:
+    """Nature-run integrator (classical RK4) used only to make synthetic data."""
+    for _ in range(nsteps):
+        a = _l96_tendency(x, F)
+        b = _l96_tendency(x + 0.5 * dt * a, F)
+        c = _l96_tendency(x + 0.5 * dt * b, F)
+        d = _l96_tendency(x + dt * c, F)
+        x = x + dt / 6.0 * (a + 2 * b + 2 * c + d)
+    return x
+
+
+def make_l96_window(s: int = 2048, N: int = 32, *, F: float = 8.0, dt: float = 0.025,
+                    nsteps: int = 8, obs_stride: int = 4, r_len_cells: float = 4.0,
+                    r_var: float = 1.0, b_len: float = 0.1, b_var: float = 1.0,
+                    q_scale: float = 0.05, spinup: int = 1000, seed: int = 0,
+                    nrhs: int = 1) -> Window:
+    """A Lorenz-96 window (§7.1): truth from a spun-up nature run with model error Q^{1/2} eta,
+    background x_b = x_0^t + B^{1/2} eps, observations y_i = H x_i^t + R^{1/2} eps_i of every
+    obs_stride-th variable, first guess a free run from x_b.  model["traj"] holds the first guess
+    (the linearisation states of the first outer loop); meta keeps truth, x_b and y for the outer
+    Gauss-Newton loop.  The right-hand side is that of the first outer loop: b = 0, d_i = y_i - H x_i."""
+    ss = np.random.SeedSequence([seed, 96])
+    rng_init, rng_b, rng_q, rng_o = [np.random.default_rng(c) for c in ss.spawn(4)]
+    grid = np.arange(s, dtype=np.float64) / s
+    B = soar_matrix(grid, b_len, b_var)
+    FB = _spd_sqrt_factor(B)
+    idx = np.arange(0, s, obs_stride, dtype=np.int32)
+    p = idx.size
+    R = gaussian_grid_matrix(idx, s, r_len_cells, r_var)
+    R, shift = recondition(R)
+    FR = _spd_sqrt_factor(R)
+    FQ = np.sqrt(q_scale) * FB
+    x = F + 0.01 * rng_init.standard_normal(s)
+    x = _l96_run(x, F, dt, spinup)
+    truth = np.zeros((N + 1, s))
+    truth[0] = x
+    for i in range(1, N + 1):
+        truth[i] = _l96_run(truth[i - 1], F, dt, nsteps) + FQ @ rng_q.standard_normal(s)
+    xb = truth[0] + FB @ rng_b.standard_normal(s)
+    y = np.stack([truth[i][idx] + FR @ rng_o.standard_normal(p) for i in range(N + 1)])
+    guess = np.zeros((N + 1, s))
+    guess[0] = xb
+    for i in range(1, N + 1):
+        guess[i] = _l96_run(guess[i - 1], F, dt, nsteps)
+    nb = N + 1
+    win = Window(
+        s=s, N=N, p=np.full(nb, p, dtype=np.int32), dmats=[B], d_index=np.zeros(nb, np.int32),
+        d_scale=np.array([1.0] + [q_scale] * N), rmats=[R], r_index=np.zeros(nb, np.int32),
+        h_width=1, h_cols=[idx.reshape(p, 1).copy() for _ in range(nb)],
+        h_vals=[np.ones((p, 1)) for _ in range(nb)],
+        model=dict(kind="l96", F=F, dt=dt, nsteps=nsteps, traj=guess.copy()),
+        meta=dict(truth=truth, xb=xb, y=y, obs_idx=idx, r_shift=shift, seed=seed, config="c3"),
+    )
+    rhs = np.zeros((nrhs, win.n))
+    off = nb * s
+    for i in range(nb):
+        rhs[:, off + i * p: off + (i + 1) * p] = (y[i] - guess[i][idx])[None, :]
+    win.rhs = rhs
+    return win

@@ -1,0 +1,83 @@
+"""Lorenz-96 windows on the GPU (tangent linear / adjoint blocks, forecast, outer loop)
+against the float64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import l96_oracle as lo
+from oracle import svar_oracle as so
+from paper_2105_06975_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_06975_amd import svar
+    return svar
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_l96_blocks_and_forecast(sv):
+    win = wl.make_l96_window(s=40, N=4, nsteps=3, spinup=200, seed=1)
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    X = np.random.default_rng(2).standard_normal((2, win.nb * win.s))
+    for op, fn in {"L": orc.L_apply, "LT": orc.LT_apply, "LHAT_INV": orc.LM_inv,
+                   "LHAT_INVT": orc.LM_invT}.items():
+        out = host(h.apply_op(op, dev(X), 2)).reshape(2, -1)
+        for r in range(2):
+            assert rel(out[r], fn(X[r].reshape(win.nb, win.s)).ravel()) < 1e-12, op
+    V = wl.random_vectors(win, 1, seed=3)[0]
+    assert rel(host(h.apply_A(dev(V))), orc.apply_A(V)) < 1e-12
+    assert rel(host(h.apply_P(dev(V))), orc.apply_P_inv(V, "PI")) < 1e-10
+    x = win.model["traj"]
+    fc = host(h.model_forecast(dev(x))).reshape(win.nb, win.s)
+    T = orc.model.l96
+    assert np.array_equal(fc[0], x[0])
+    for i in range(1, win.nb):
+        assert rel(fc[i], T.forecast(x[i - 1])) < 1e-13
+
+
+def test_gauss_newton_matches_oracle(sv):
+    from paper_2105_06975_amd.gauss_newton import gauss_newton
+    win = wl.make_l96_window(s=32, N=3, nsteps=2, spinup=200, seed=4)
+    h = sv.Handle([win], sv.Precond(type="PI", k=2, rhat="RR"))
+    xg, hist = gauss_newton(h, win, n_outer=2, solve_kw=dict(rtol=1e-12, maxit=win.n,
+                                                             max_outer=3))
+    ref = lo.gauss_newton(win, 2, k=2)
+    assert all(r["rc"] == sv.OK for r in hist)
+    assert rel(host(xg).reshape(win.nb, win.s), ref[-1]) < 1e-8
+    # the increment shrinks from the first to the second outer iteration
+    assert hist[1]["norm_dx"] < hist[0]["norm_dx"]
+
+
+def test_c3_shape_operator_parity_and_solve(sv):
+    """C3 shape (s = 2048, N = 32, 8 RK4 steps of 0.025 per interval, every 4th variable
+    observed, Gaussian R): A v, P_I^{-1} v against the oracle, and a 1e-6 solve checked with
+    the oracle's own A."""
+    win = wl.make_l96_window(s=2048, N=32, seed=0)
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    V = wl.random_vectors(win, 1, seed=5)[0]
+    assert rel(host(h.apply_A(dev(V))), orc.apply_A(V)) < 1e-12
+    assert rel(host(h.apply_P(dev(V))), orc.apply_P_inv(V, "PI")) < 1e-10
+    rhs = win.rhs[0]
+    x, info, rc = h.solve(dev(rhs), rtol=1e-6, maxit=1000)
+    assert rc == sv.OK, info
+    rr = np.linalg.norm(rhs - orc.apply_A(host(x))) / np.linalg.norm(rhs)
+    assert rr <= 1e-6
