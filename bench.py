@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="print iterations and time per solve over k, restart length and "
+                         "precision (one JSON object) instead of the benchmark line")
     ap.add_argument("--cpu-iters", type=int, nargs=2, default=(3, 9),
                     help="oracle iteration counts of the two timed samples")
     return ap.parse_args()
@@ -90,7 +93,9 @@ def main():
 
     def run(precision, steps, warmup, timing=False):
         kw = dict(rtol=args.rtol, maxit=1000)
-        if precision != "FP64":
+        if precision == "FP64_F32P":
+            kw.update(precision=precision)
+        elif precision != "FP64":
             # one unrestarted inner cycle to the target (the float32 operator error is far
             # below it), then the float64 residual check and, if needed, a correction cycle
             kw.update(precision=precision, restart=0, inner_rtol=args.rtol, max_outer=4)
@@ -119,6 +124,9 @@ def main():
             f"relres={infos[0]['relres_true']:.2e}")
         return el, infos[0], tm, x
 
+    if args.sweep:
+        print(json.dumps(sweep(win, rhs, args)), flush=True)
+        return
     el64, info64, tm, x64 = run("FP64", args.steps, args.warmup, timing=True)
     sps = args.steps / el64
     it = int(info64["iters"])
@@ -164,16 +172,58 @@ def main():
     res["kernel_time_ms"] = {"gemm": gms, "gemm_launches": gl, "ortho": oms,
                              "ortho_launches": ol}
     if not args.no_mixed:
-        try:
-            elm, infom, _, xm = run("MIXED_BF16P", args.steps, args.warmup)
-            res["mixed_bf16p"] = {"value": args.steps / elm, "iters": infom["iters"],
-                                  "outer": infom["outer"], "relres_true": infom["relres_true"],
-                                  "speedup_vs_fp64": el64 / elm}
-        except Exception as e:  # reported, not fatal for the FP64 line
-            res["mixed_bf16p"] = {"error": str(e)[:200]}
+        for prec in ("FP64_F32P",):
+            try:
+                elm, infom, _, xm = run(prec, args.steps, args.warmup)
+                res[prec.lower()] = {"value": args.steps / elm, "iters": infom["iters"],
+                                     "outer": infom["outer"],
+                                     "relres_true": infom["relres_true"],
+                                     "speedup_vs_fp64": el64 / elm}
+            except Exception as e:  # reported, not fatal for the FP64 line
+                res[prec.lower()] = {"error": str(e)[:200]}
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(win, args, it)
     print(json.dumps(res), flush=True)
+
+
+def sweep(win, rhs, args):
+    """Iterations and time per solve (second of two identical solves) over k, restart length
+    and precision on the benchmark window."""
+    import torch
+
+    from paper_2105_06975_amd import svar
+    out = []
+
+    def one(h, **kw):
+        h.solve(rhs, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info, rc = h.solve(rhs, **kw)
+        torch.cuda.synchronize()
+        return dict(rc=rc, iters=info[0]["iters"], outer=info[0]["outer"],
+                    ms=1e3 * (time.perf_counter() - t), relres=info[0]["relres_true"])
+
+    for k in (1, 2, 3, 4, 6, 8, 16, win.N + 1):
+        h = svar.Handle([win], svar.Precond(type="PI", k=k, rhat="RR"))
+        r = one(h, rtol=args.rtol, maxit=1500)
+        r.update(k=k, restart=0, precision="FP64")
+        out.append(r)
+        log(r)
+        if k in (3, 16):
+            for rs in (50, 100, 200):
+                r = one(h, rtol=args.rtol, maxit=3000, restart=rs, max_outer=200)
+                r.update(k=k, restart=rs, precision="FP64")
+                out.append(r)
+                log(r)
+            for prec, kw in (("FP64_F32P", {}),
+                             ("MIXED_FP32", dict(inner_rtol=1e-5, max_outer=6)),
+                             ("MIXED_BF16P", dict(inner_rtol=1e-5, max_outer=6))):
+                r = one(h, rtol=args.rtol, maxit=3000, precision=prec, **kw)
+                r.update(k=k, restart=0, precision=prec)
+                out.append(r)
+                log(r)
+        del h
+    return {"sweep": out, "workload": "c2", "rtol": args.rtol}
 
 
 def cpu_baseline(win, args, gpu_iters):

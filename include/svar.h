@@ -121,6 +121,8 @@ typedef struct svar_prec_opts {
 #define SVAR_PRECISION_MIXED_FP32 1   /* FP64 refinement; inner A and P in float32       */
 #define SVAR_PRECISION_MIXED_BF16P 2  /* FP64 refinement; inner A float32, P covariance
                                          products bfloat16 with float32 accumulation      */
+#define SVAR_PRECISION_FP64_F32P 3    /* A in float64 (no refinement needed); P covariance
+                                         products float32 (flexible GMRES absorbs them)   */
 
 typedef struct svar_solve_opts {
   int32_t method;     /* SVAR_METHOD_*                                                      */
@@ -172,9 +174,10 @@ int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void*
 
 /* The operators of the inner loop of the mixed-precision solves (§6.2 maps with reduced-
    precision covariance products, float32 accumulation).  precision = SVAR_PRECISION_FP64 is
-   svar_apply_A / svar_apply_P; for A both mixed settings use float32 copies of D and R; for
-   P, SVAR_PRECISION_MIXED_BF16P uses bfloat16 copies of D, Rhat^{-1} and Dhat^{-1} and
-   SVAR_PRECISION_MIXED_FP32 is the float64 preconditioner.  Vectors stay float64. */
+   svar_apply_A / svar_apply_P; for A both MIXED settings use float32 copies of D and R
+   (FP64_F32P keeps A in float64); for P, SVAR_PRECISION_MIXED_BF16P uses bfloat16 copies of D,
+   Rhat^{-1} and Dhat^{-1}, SVAR_PRECISION_FP64_F32P float32 copies, and
+   SVAR_PRECISION_MIXED_FP32 the float64 preconditioner.  Vectors stay float64. */
 int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* y,
                       void* stream);
 int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* z,

@@ -36,13 +36,6 @@ __device__ __forceinline__ void gemm_store(const GemmProb& P, const Bases& b, in
   opnd(b, P.Y)[co * P.yo + ci * P.yi + r] = y;
 }
 
-// element loads of the matrix in its storage type, widened to double / float
-__device__ __forceinline__ double ld_c(const void* C, size_t i, int dt) {
-  if (dt == DT_F64) return ((const double*)C)[i];
-  if (dt == DT_F32) return (double)((const float*)C)[i];
-  const unsigned short h = ((const unsigned short*)C)[i];
-  return (double)__uint_as_float(((unsigned)h) << 16);
-}
 
 // FP64 product.  Workgroup = 4 waves sharing one (RT x 16)-row tile and its k-range: wave w
 // takes the w-th quarter of the k-range, so the workgroup's partial sums are combined in LDS
@@ -50,125 +43,152 @@ __device__ __forceinline__ double ld_c(const void* C, size_t i, int dt) {
 // Each wave keeps RT x CT accumulator tiles; the operand fragments of step s+1 are loaded
 // while the MFMAs of step s run (two register buffers), which hides global-load latency.
 // Operand loads are unconditional from always-valid addresses (rows / columns past the end
-// are clamped to the first one) and the values are masked afterwards, so no load sits behind
-// a branch and all loads of a step stay in flight together.  Full steps need no k check; the
-// ragged last step clamps each k index as well.
-template <int CT, int RT>
-__device__ __forceinline__ void gemm_load_full(const gdp (&A)[RT], const bool (&rok)[RT],
-                                               const gdp (&xp)[CT],
-                                               const bool (&cok)[CT], int kk, double (&a)[RT][4],
-                                               double (&bb)[CT][4]) {
+// read a zero buffer) so no load sits behind a branch and all loads of a step stay in flight
+// together.  Full steps need no k check; the ragged last step clamps each k index.
+//
+// One template serves three storage types of the matrix: double (float64 MFMA,
+// v_mfma_f64_16x16x4f64), float and bfloat16 (float32 MFMA, v_mfma_f32_16x16x4f32, panel
+// converted to float on load, float32 accumulation).
+template <typename CS> struct gptr_of { typedef const __attribute__((address_space(1))) CS* type; };
+
+__device__ __forceinline__ double to_acc(double v, double) { return v; }
+__device__ __forceinline__ float to_acc(double v, float) { return (float)v; }
+__device__ __forceinline__ float to_acc(float v, float) { return v; }
+__device__ __forceinline__ float to_acc(unsigned short h, float) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+template <typename AT> struct mfma_of;
+template <> struct mfma_of<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ v4d op(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // v_mfma_f64_16x16x4f64: element e of lane group q holds row q + 4 e of the tile
+  static __device__ __forceinline__ int row(int q, int e) { return q + 4 * e; }
+};
+template <> struct mfma_of<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ v4f op(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // v_mfma_f32_16x16x4f32: element e of lane group q holds row 4 q + e of the tile
+  static __device__ __forceinline__ int row(int q, int e) { return 4 * q + e; }
+};
+
+template <int CT, int RT, typename CS, typename AT>
+__device__ __forceinline__ void gemm_load_full(const typename gptr_of<CS>::type (&A)[RT],
+                                               const gdp (&xp)[CT], int kk, AT (&a)[RT][4],
+                                               AT (&bb)[CT][4]) {
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[rt][i] = A[rt][kk + i];
+    for (int i = 0; i < 4; ++i) a[rt][i] = to_acc(A[rt][kk + i], AT());
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bb[ct][i] = xp[ct][kk + i];
+    for (int i = 0; i < 4; ++i) bb[ct][i] = to_acc(xp[ct][kk + i], AT());
 }
-template <int CT, int RT>
-__device__ __forceinline__ void gemm_load_tail(const gdp (&A)[RT], const bool (&rok)[RT],
-                                               const gdp (&xp)[CT],
-                                               const bool (&cok)[CT], int kk, int ke, int n,
-                                               double (&a)[RT][4], double (&bb)[CT][4]) {
+template <int CT, int RT, typename CS, typename AT>
+__device__ __forceinline__ void gemm_load_tail(const typename gptr_of<CS>::type (&A)[RT],
+                                               const gdp (&xp)[CT], int kk, int ke, int n,
+                                               AT (&a)[RT][4], AT (&bb)[CT][4]) {
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double v = A[rt][min(kk + i, n - 1)];
-      a[rt][i] = (rok[rt] && kk + i < ke) ? v : 0.0;
+      const AT v = to_acc(A[rt][min(kk + i, n - 1)], AT());
+      a[rt][i] = kk + i < ke ? v : AT(0);
     }
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double v = xp[ct][min(kk + i, n - 1)];
-      bb[ct][i] = (cok[ct] && kk + i < ke) ? v : 0.0;
+      const AT v = to_acc(xp[ct][min(kk + i, n - 1)], AT());
+      bb[ct][i] = kk + i < ke ? v : AT(0);
     }
 }
 
-template <int CT, int RT>
-__device__ __forceinline__ void gemm_mfma(v4d (&acc)[RT][CT], const double (&a)[RT][4],
-                                          const double (&bb)[CT][4]) {
+template <int CT, int RT, typename AT>
+__device__ __forceinline__ void gemm_mfma(typename mfma_of<AT>::acc_t (&acc)[RT][CT],
+                                          const AT (&a)[RT][4], const AT (&bb)[CT][4]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
-        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][i], bb[ct][i], acc[rt][ct], 0, 0, 0);
+        acc[rt][ct] = mfma_of<AT>::op(a[rt][i], bb[ct][i], acc[rt][ct]);
 }
 
-template <int CT, int RT>
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ probs,
-                                                     const GemmTask* __restrict__ tasks,
-                                                     double* __restrict__ ws, Bases b,
-                                                     const int* __restrict__ skip) {
-  __shared__ double red[2][RT * CT * 4][64];
+// Workgroup = 4 waves sharing one (RT x 16)-row tile and its k-range: wave w takes the w-th
+// quarter, the four partial sums are combined in LDS (two rounds, fixed order) and only the
+// split-K over workgroups goes through global memory.  The next step's fragments are loaded
+// while the current step multiplies (two register buffers); scheduling barriers keep the
+// batches apart so that each wait covers only the older batch.
+template <int CT, int RT, typename CS, typename AT>
+__global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs,
+                                              const GemmTask* __restrict__ tasks,
+                                              double* __restrict__ ws, Bases b,
+                                              const int* __restrict__ skip) {
+  typedef typename mfma_of<AT>::acc_t acc_t;
+  typedef typename gptr_of<CS>::type cptr;
+  __shared__ AT red[2][RT * CT * 4][64];
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
   const int lane = threadIdx.x & 63;
-  // wave index as a scalar: the k-range bounds below are then uniform and the loop control
-  // stays on scalar branches (no exec-masked regions around the prefetch loads)
+  // wave index as a scalar: the k-range bounds are then uniform and the loop control stays on
+  // scalar branches (no exec-masked regions around the prefetch loads)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, q = lane >> 4;
   const int rbase = t.row0;
   if (rbase >= P.n) return;
-  // this wave's quarter of the workgroup k-range (multiple of 16)
   const int wlen = ((t.k1 - t.k0 + 63) / 64) * 16;
   const int kb = t.k0 + wave * wlen;
   const int ke = min(t.k1, kb + wlen);
-  gdp A[RT];
-  bool rok[RT];
-  // rows / columns past the edge read the zero buffer, so loaded values need no masking
+  cptr A[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int row = rbase + rt * 16 + r16;
-    rok[rt] = row < P.n;
-    A[rt] = (gdp)(rok[rt] ? (const double*)P.C + (size_t)row * P.n : P.zeros);
+    A[rt] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
   }
   const double* X = opnd(b, P.X);
   gdp xp[CT];
-  bool cok[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int c = t.col0 + ct * 16 + r16;
-    cok[ct] = c < P.ncols;
-    const int cc = cok[ct] ? c : 0;
+    const bool ok = c < P.ncols;
+    const int cc = ok ? c : 0;
     const int co = cc / P.per, ci = cc - co * P.per;
-    xp[ct] = (gdp)(cok[ct] ? X + co * P.xo + ci * P.xi : P.zeros);
+    xp[ct] = (gdp)(ok ? X + co * P.xo + ci * P.xi : P.zeros);
   }
-  v4d acc[RT][CT];
+  acc_t acc[RT][CT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = (v4d){0.0, 0.0, 0.0, 0.0};
-  double a0[RT][4], b0[CT][4], a1[RT][4], b1[CT][4];
-  // full steps of 16, the next step's fragments loaded while the current one multiplies
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = acc_t{};
+  AT a0[RT][4], b0[CT][4], a1[RT][4], b1[CT][4];
   const int nfull = ke > kb ? (ke - kb) >> 4 : 0;
-  if (nfull > 0) gemm_load_full<CT, RT>(A, rok, xp, cok, kb + 4 * q, a0, b0);
+  if (nfull > 0) gemm_load_full<CT, RT, CS, AT>(A, xp, kb + 4 * q, a0, b0);
   int s = 0;
-  // sched_barrier keeps each load batch ahead of the MFMA batch that does not need it, so the
-  // wait before the MFMAs covers only the older batch
   for (; s + 2 <= nfull; s += 2) {
-    gemm_load_full<CT, RT>(A, rok, xp, cok, kb + 16 * (s + 1) + 4 * q, a1, b1);
+    gemm_load_full<CT, RT, CS, AT>(A, xp, kb + 16 * (s + 1) + 4 * q, a1, b1);
     __builtin_amdgcn_sched_barrier(0);
-    gemm_mfma<CT, RT>(acc, a0, b0);
+    gemm_mfma<CT, RT, AT>(acc, a0, b0);
     __builtin_amdgcn_sched_barrier(0);
     // unconditional prefetch (a branch here would force a full wait at the join); the last
     // trip re-loads the final full step, which is never used
-    gemm_load_full<CT, RT>(A, rok, xp, cok, kb + 16 * min(s + 2, nfull - 1) + 4 * q, a0, b0);
+    gemm_load_full<CT, RT, CS, AT>(A, xp, kb + 16 * min(s + 2, nfull - 1) + 4 * q, a0, b0);
     __builtin_amdgcn_sched_barrier(0);
-    gemm_mfma<CT, RT>(acc, a1, b1);
+    gemm_mfma<CT, RT, AT>(acc, a1, b1);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (s < nfull) gemm_mfma<CT, RT>(acc, a0, b0);
+  if (s < nfull) gemm_mfma<CT, RT, AT>(acc, a0, b0);
   const int kt = kb + 16 * nfull;
   if (kt < ke) {  // ragged last step
-    gemm_load_tail<CT, RT>(A, rok, xp, cok, kt + 4 * q, ke, P.n, a0, b0);
-    gemm_mfma<CT, RT>(acc, a0, b0);
+    gemm_load_tail<CT, RT, CS, AT>(A, xp, kt + 4 * q, ke, P.n, a0, b0);
+    gemm_mfma<CT, RT, AT>(acc, a0, b0);
   }
   // combine the four waves: (2,3) -> (0,1), then 1 -> 0
 #pragma unroll
@@ -194,8 +214,6 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
     __syncthreads();
   }
   if (wave != 0) return;
-  // v_mfma_f64_16x16x4f64 result layout: accumulator element e of lane (q, r16) is row
-  // q + 4 e of the 16 x 16 tile (rows interleaved across the four lane groups), column r16
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int c = t.col0 + ct * 16 + r16;
@@ -204,83 +222,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProb* __restrict__ p
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = rbase + rt * 16 + q + 4 * e;
+        const int r = rbase + rt * 16 + mfma_of<AT>::row(q, e);
         if (r >= P.n) continue;
+        const double v = (double)acc[rt][ct][e];
         if (P.splits > 1)
-          ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = acc[rt][ct][e];
+          ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = v;
         else
-          gemm_store(P, b, r, c, acc[rt][ct][e]);
+          gemm_store(P, b, r, c, v);
       }
-  }
-}
-
-// Reduced-precision matrix (float32 or bfloat16 storage) with float32 MFMA accumulation.
-// The panel is converted to float on load; accumulation is float32 (v_mfma_f32_16x16x4f32).
-template <int CT>
-__global__ __launch_bounds__(256) void k_gemm_lp(const GemmProb* __restrict__ probs,
-                                                 const GemmTask* __restrict__ tasks,
-                                                 double* __restrict__ ws, Bases b,
-                                                 const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const GemmTask t = tasks[blockIdx.x];
-  const GemmProb P = probs[t.prob];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r16 = lane & 15, q = lane >> 4;
-  const int rbase = t.row0 + wave * 16;
-  if (rbase >= P.n) return;
-  const int rowA = rbase + r16;
-  const bool rowok = rowA < P.n;
-  const size_t abase = (size_t)(rowok ? rowA : 0) * P.n;
-  const double* X = opnd(b, P.X);
-  const double* xp[CT];
-  bool cok[CT];
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const int c = t.col0 + ct * 16 + r16;
-    cok[ct] = c < P.ncols;
-    const int cc = cok[ct] ? c : 0;
-    const int co = cc / P.per, ci = cc - co * P.per;
-    xp[ct] = X + co * P.xo + ci * P.xi;
-  }
-  v4f acc[CT];
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) acc[ct] = (v4f){0.f, 0.f, 0.f, 0.f};
-  for (int k = t.k0; k < t.k1; k += 16) {
-    const int kk = k + 4 * q;
-    float a[4], bb[CT][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int kc = min(kk + i, P.n - 1);  // always-valid address, value masked below
-      const float v = (float)ld_c(P.C, abase + kc, P.dtype);
-      a[i] = (rowok && kk + i < t.k1) ? v : 0.f;
-    }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float v = (float)xp[ct][min(kk + i, P.n - 1)];
-        bb[ct][i] = (cok[ct] && kk + i < t.k1) ? v : 0.f;
-      }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[ct][i], acc[ct], 0, 0, 0);
-  }
-  // v_mfma_f32_16x16x4f32 result layout: element e of lane (q, r16) is row 4 q + e
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const int c = t.col0 + ct * 16 + r16;
-    if (c >= P.ncols) continue;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = rbase + 4 * q + e;
-      if (r >= P.n) continue;
-      if (P.splits > 1)
-        ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = (double)acc[ct][e];
-      else
-        gemm_store(P, b, r, c, (double)acc[ct][e]);
-    }
   }
 }
 
@@ -302,12 +251,16 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict_
 template <int CT>
 static void launch_ct(const GemmPlanDev& g, Bases b, double* ws, const int* skip,
                       hipStream_t st) {
+  constexpr int RT = gemm_rt(CT);
   if (g.dtype == DT_F64)
-    hipLaunchKernelGGL((k_gemm_f64<CT, gemm_rt(CT)>), dim3(g.ntask), dim3(256), 0, st, g.probs,
+    hipLaunchKernelGGL((k_gemm<CT, RT, double, double>), dim3(g.ntask), dim3(256), 0, st, g.probs,
+                       g.tasks, ws, b, skip);
+  else if (g.dtype == DT_F32)
+    hipLaunchKernelGGL((k_gemm<CT, RT, float, float>), dim3(g.ntask), dim3(256), 0, st, g.probs,
                        g.tasks, ws, b, skip);
   else
-    hipLaunchKernelGGL(k_gemm_lp<CT>, dim3(g.ntask), dim3(256), 0, st, g.probs, g.tasks, ws, b,
-                       skip);
+    hipLaunchKernelGGL((k_gemm<CT, RT, unsigned short, float>), dim3(g.ntask), dim3(256), 0, st,
+                       g.probs, g.tasks, ws, b, skip);
 }
 
 void launch_gemm(const GemmPlanDev& g, Bases b, double* ws, const int* skip, hipStream_t st) {

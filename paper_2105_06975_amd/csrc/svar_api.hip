@@ -38,20 +38,19 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
   const int rows = 16 * gemm_rt(maxct);  // rows per workgroup
   double total_work = 0.0;
   for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
-  const int lowp = probs.empty() ? 0 : probs[0].dtype != DT_F64;
-  const int target = lowp ? 1024 : 512;  // workgroups (the FP64 kernel keeps 4 waves on k)
+  const int target = 512;  // workgroups of 4 waves (the waves of a workgroup split k)
   ws = 0;
   tasks.clear();
   for (int pi = 0; pi < (int)probs.size(); ++pi) {
     GemmProb& p = probs[pi];
-    const int rtile = lowp ? 64 : rows;
+    const int rtile = rows;
     const int rt = (p.n + rtile - 1) / rtile, cg = (p.ncols + cw - 1) / cw;
     const double share = total_work > 0 ? (double)p.n * p.n * p.ncols / total_work : 1.0;
     const int want = (int)std::ceil(target * share / (double)(rt * cg));
-    const int kmin = lowp ? 256 : 512;  // at least 128 k per wave
+    const int kmin = 512;  // at least 128 k per wave
     const int maxs = std::max(1, p.n / kmin);
     int S = std::max(1, std::min(want, maxs));
-    const int align = lowp ? 16 : 64;
+    const int align = 64;
     const int chunk = ((p.n + S - 1) / S + align - 1) / align * align;
     S = (p.n + chunk - 1) / chunk;
     p.splits = S;
@@ -629,6 +628,8 @@ static int setup_lowprec(svar_handle* h, WinDev& W, hipStream_t st) {
   SVAR_TRY(conv(W.dmats, W.dmats_bf16, ss, true, nullptr));
   SVAR_TRY(conv(W.rhat_inv, W.rhat_inv_bf16, 0, true, &W.rmat_p));
   SVAR_TRY(conv(W.dhat_inv, W.dhat_inv_bf16, ss, true, nullptr));
+  SVAR_TRY(conv(W.rhat_inv, W.rhat_inv_f32, 0, false, &W.rmat_p));
+  SVAR_TRY(conv(W.dhat_inv, W.dhat_inv_f32, ss, false, nullptr));
   SVAR_HIP(hipStreamSynchronize(st));
   return SVAR_OK;
 }
@@ -871,11 +872,13 @@ static const void* mat_ptr(const WinDev& W, MatSel sel, int idx, int dtype) {
       return dtype == DT_F64 ? (const void*)W.dmats[idx]
                              : (dtype == DT_F32 ? W.dmats_f32[idx] : W.dmats_bf16[idx]);
     case MS_DHAT:
-      return dtype == DT_BF16 ? W.dhat_inv_bf16[idx] : (const void*)W.dhat_inv[idx];
+      return dtype == DT_F64 ? (const void*)W.dhat_inv[idx]
+                             : (dtype == DT_F32 ? W.dhat_inv_f32[idx] : W.dhat_inv_bf16[idx]);
     case MS_R:
       return dtype == DT_F64 ? (const void*)W.rmats[idx] : W.rmats_f32[idx];
     default:
-      return dtype == DT_BF16 ? W.rhat_inv_bf16[idx] : (const void*)W.rhat_inv[idx];
+      return dtype == DT_F64 ? (const void*)W.rhat_inv[idx]
+                             : (dtype == DT_F32 ? W.rhat_inv_f32[idx] : W.rhat_inv_bf16[idx]);
   }
 }
 
@@ -963,7 +966,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
     return SVAR_OK;
   }
   if (op == PROG_P) {
-    const int dt = prec == PV_BF16P ? DT_BF16 : DT_F64;
+    const int dt = prec == PV_BF16P ? DT_BF16 : (prec == PV_F32P ? DT_F32 : DT_F64);
     if (ptype == SVAR_PREC_NONE) {
       std::vector<VJob> jobs;
       for (int w = 0; w < (int)h->wins.size(); ++w)
@@ -1301,23 +1304,27 @@ int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void*
 int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* y,
                       void* stream) {
   if (!h || !v || !y || nrhs < 1) return inval("bad arguments");
-  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_MIXED_BF16P)
+  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_FP64_F32P)
     return inval("bad precision");
   Program* P = nullptr;
   hipStream_t st = (hipStream_t)stream;
-  SVAR_TRY(get_program(h, PROG_A, nrhs, precision == SVAR_PRECISION_FP64 ? PV_F64 : PV_F32, &P, st));
+  const int pa = (precision == SVAR_PRECISION_FP64 || precision == SVAR_PRECISION_FP64_F32P) ? PV_F64
+                                                                                         : PV_F32;
+  SVAR_TRY(get_program(h, PROG_A, nrhs, pa, &P, st));
   return run_program(h, *P, const_cast<double*>(v), y, st, nullptr);
 }
 
 int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* z,
                       void* stream) {
   if (!h || !v || !z || nrhs < 1) return inval("bad arguments");
-  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_MIXED_BF16P)
+  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_FP64_F32P)
     return inval("bad precision");
   Program* P = nullptr;
   hipStream_t st = (hipStream_t)stream;
-  SVAR_TRY(get_program(h, PROG_P, nrhs, precision == SVAR_PRECISION_MIXED_BF16P ? PV_BF16P : PV_F64,
-                       &P, st));
+  const int pv = precision == SVAR_PRECISION_MIXED_BF16P
+                     ? PV_BF16P
+                     : (precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+  SVAR_TRY(get_program(h, PROG_P, nrhs, pv, &P, st));
   return run_program(h, *P, const_cast<double*>(v), z, st, nullptr);
 }
 

@@ -33,6 +33,7 @@ struct WinDev {
   std::vector<int> dhat_of_block;
   // low-precision copies for the mixed paths (per distinct matrix)
   std::vector<void*> dmats_f32, rmats_f32, dmats_bf16, rhat_inv_bf16, dhat_inv_bf16;
+  std::vector<void*> rhat_inv_f32, dhat_inv_f32;
   // H (ELL) and its transpose (CSR per block)
   int hw = 1;
   int32_t* h_cols = nullptr;
@@ -59,7 +60,7 @@ struct ProgKey {
 // internal program codes (beyond the public SVAR_OP_*)
 enum { PROG_A = 100, PROG_P = 101 };
 // precision variants of a program
-enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2 };
+enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2, PV_F32P = 3 };
 
 struct Timer {
   bool on = false;

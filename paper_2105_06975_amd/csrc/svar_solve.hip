@@ -181,8 +181,14 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   if (cyc < 1) return inval_msg("maxit must be >= 1");
   SVAR_TRY(ensure_krylov(h, nrhs, cyc, st));
   auto& K = h->kry;
-  const int pv_a = o->precision == SVAR_PRECISION_FP64 ? PV_F64 : PV_F32;
-  const int pv_p = o->precision == SVAR_PRECISION_MIXED_BF16P ? PV_BF16P : PV_F64;
+  // inner operators: FP64_F32P keeps A in float64 (no refinement needed: under flexible GMRES
+  // the preconditioner's rounding changes only the convergence rate, not the attainable
+  // residual); the MIXED settings use float32 A and refine in float64
+  const bool a64 = o->precision == SVAR_PRECISION_FP64 || o->precision == SVAR_PRECISION_FP64_F32P;
+  const int pv_a = a64 ? PV_F64 : PV_F32;
+  const int pv_p = o->precision == SVAR_PRECISION_MIXED_BF16P
+                       ? PV_BF16P
+                       : (o->precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
   Program *A64 = nullptr, *Ain = nullptr, *Pin = nullptr;
   SVAR_TRY(get_program(h, PROG_A, nrhs, PV_F64, &A64, st));
   SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
@@ -223,7 +229,7 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
       }
       all = false;
       double t = nr > 0 ? o->rtol * nb / nr : 1.0;
-      if (o->precision != SVAR_PRECISION_FP64) t = std::max(t, o->inner_rtol);
+      if (!a64) t = std::max(t, o->inner_rtol);
       tol[i] = t;
     }
     if (all) break;
@@ -290,7 +296,7 @@ extern "C" int svar_solve(svar_handle* h, const svar_solve_opts* o, int32_t nrhs
                           const double* rhs, double* x, svar_solve_info* info, void* stream) {
   if (!h || !o || !rhs || !x || !info || nrhs < 1) return inval_msg("bad arguments");
   if (!(o->rtol > 0.0) || o->maxit < 1) return inval_msg("need rtol > 0 and maxit >= 1");
-  if (o->precision < SVAR_PRECISION_FP64 || o->precision > SVAR_PRECISION_MIXED_BF16P)
+  if (o->precision < SVAR_PRECISION_FP64 || o->precision > SVAR_PRECISION_FP64_F32P)
     return inval_msg("bad precision");
   hipStream_t st = (hipStream_t)stream;
   if (o->method == SVAR_METHOD_FGMRES) return solve_fgmres(h, o, nrhs, rhs, x, info, st);

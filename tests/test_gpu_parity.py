@@ -272,11 +272,30 @@ def test_mixed_precision_operators(sv):
     V = wl.random_vectors(win, 2, seed=41)
     ya = host(h.apply_A(dev(V), 2, precision="MIXED_FP32")).reshape(2, -1)
     zp = host(h.apply_P(dev(V), 2, precision="MIXED_BF16P")).reshape(2, -1)
+    zf = host(h.apply_P(dev(V), 2, precision="FP64_F32P")).reshape(2, -1)
+    ya64 = host(h.apply_A(dev(V), 2, precision="FP64_F32P")).reshape(2, -1)
     for r in range(2):
         ea = rel(ya[r], orc.apply_A(V[r]))
         ep = rel(zp[r], orc.apply_P_inv(V[r], "PI"))
+        ef = rel(zf[r], orc.apply_P_inv(V[r], "PI"))
         assert 1e-12 < ea < 2e-6, ea
         assert 1e-9 < ep < 2e-2, ep
+        assert 1e-12 < ef < 2e-5, ef
+        assert rel(ya64[r], orc.apply_A(V[r])) < 1e-12
+
+
+def test_fp64_with_f32_preconditioner_solve(sv):
+    """FP64 operator with float32 preconditioner products: same true-residual target in one
+    cycle, iteration count close to the FP64 solve's."""
+    win = wl.make_config_window("c1", seed=4)
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    rhs = win.rhs[0]
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    x64, i64, rc = h.solve(dev(rhs), rtol=1e-8, maxit=win.n)
+    xf, ifp, rcf = h.solve(dev(rhs), rtol=1e-8, maxit=win.n, precision="FP64_F32P")
+    assert rc == sv.OK and rcf == sv.OK
+    assert np.linalg.norm(rhs - orc.apply_A(host(xf))) <= 1e-8 * np.linalg.norm(rhs)
+    assert abs(ifp[0]["iters"] - i64[0]["iters"]) <= max(3, i64[0]["iters"] // 20)
 
 
 # ------------------------------------------------------------------ edge cases
