@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="print iterations and time per solve over k, restart length and "
                          "precision (one JSON object) instead of the benchmark line")
+    ap.add_argument("--c3", action="store_true",
+                    help="Lorenz-96 window (s=2048, N=32): iterations vs k and the 5-iteration "
+                         "Gauss-Newton outer loop (one JSON object)")
     ap.add_argument("--cpu-iters", type=int, nargs=2, default=(3, 9),
                     help="oracle iteration counts of the two timed samples")
     return ap.parse_args()
@@ -81,6 +84,9 @@ def main():
     from paper_2105_06975_amd import svar, workloads as wl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.c3:
+        print(json.dumps(bench_c3(args)), flush=True)
+        return
     t0 = time.time()
     win = wl.make_config_window("c2", seed=0)
     log(f"workload built in {time.time() - t0:.1f}s: n={win.n}")
@@ -184,6 +190,49 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(win, args, it)
     print(json.dumps(res), flush=True)
+
+
+def bench_c3(args):
+    """Lorenz-96 configuration: s = 2048, F = 8, RK4 dt = 0.025, 8 steps per observation
+    interval, N = 32, every 4th variable observed, Gaussian R (4 cells), B SOAR(0.1), Q = 0.05 B.
+    Reports iterations / time of the first inner solve for several k, then the 5-iteration
+    Gauss-Newton loop (forecast, right-hand side, solve, update all on the GPU)."""
+    import torch
+
+    from paper_2105_06975_amd import svar, workloads as wl
+    from paper_2105_06975_amd.gauss_newton import gauss_newton
+    t0 = time.time()
+    win = wl.make_l96_window(s=2048, N=32, seed=0)
+    log(f"c3 workload built in {time.time() - t0:.1f}s, n={win.n}")
+    rhs = torch.from_numpy(win.rhs[0]).cuda()
+    out = {"workload": "c3 lorenz-96 s=2048 N=32 dt=0.025x8 p=512", "inner": [], "outer": None}
+    for k in (3, 8, win.N + 1):
+        h = svar.Handle([win], svar.Precond(type="PI", k=k, rhat="RR"))
+        h.solve(rhs, rtol=args.rtol, maxit=3000)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info, rc = h.solve(rhs, rtol=args.rtol, maxit=3000)
+        torch.cuda.synchronize()
+        r = dict(k=k, rc=rc, iters=info[0]["iters"], ms=1e3 * (time.perf_counter() - t),
+                 relres=info[0]["relres_true"])
+        out["inner"].append(r)
+        log(r)
+    h = svar.Handle([win], svar.Precond(type="PI", k=win.N + 1, rhat="RR"))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xg, hist = gauss_newton(h, win, n_outer=5, solve_kw=dict(rtol=args.rtol, maxit=3000))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    truth = np.asarray(win.meta["truth"])
+    err0 = float(np.linalg.norm(np.asarray(win.model["traj"]) - truth) / np.linalg.norm(truth))
+    err = float(np.linalg.norm(xg.cpu().numpy().reshape(truth.shape) - truth)
+                / np.linalg.norm(truth))
+    out["outer"] = dict(k=win.N + 1, seconds=el, iters=[r["iters"] for r in hist],
+                        rc=[r["rc"] for r in hist], norm_dx=[r["norm_dx"] for r in hist],
+                        norm_rhs=[r["norm_rhs"] for r in hist], rel_err_first_guess=err0,
+                        rel_err_analysis=err)
+    log(out["outer"])
+    return out
 
 
 def sweep(win, rhs, args):
