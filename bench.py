@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--c3", action="store_true",
                     help="Lorenz-96 window (s=2048, N=32): iterations vs k and the 5-iteration "
                          "Gauss-Newton outer loop (one JSON object)")
+    ap.add_argument("--c4", type=int, default=0, metavar="W",
+                    help="batched mode: W uneven advection-diffusion windows x 8 perturbed-"
+                         "observation right-hand sides in one call, against one-at-a-time "
+                         "solves of the first two windows (one JSON object)")
+    ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, nargs=2, default=(3, 9),
                     help="oracle iteration counts of the two timed samples")
     return ap.parse_args()
@@ -86,6 +91,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.c3:
         print(json.dumps(bench_c3(args)), flush=True)
+        return
+    if args.c4:
+        print(json.dumps(bench_c4(args)), flush=True)
         return
     t0 = time.time()
     win = wl.make_config_window("c2", seed=0)
@@ -233,6 +241,82 @@ def bench_c3(args):
                         rel_err_analysis=err)
     log(out["outer"])
     return out
+
+
+def c4_windows(nwin, seed=0, nrhs=8):
+    """Uneven windows: s ~ U{256..4096}, N ~ U{8..64}, p = floor(s f) with f ~ U[1/8, 1/2]
+    random observation points (fixed in time), SOAR R (0.05, 0.5), 8 right-hand sides whose
+    observation noise is redrawn from R."""
+    from paper_2105_06975_amd import workloads as wl
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4]))
+    wins = []
+    for w in range(nwin):
+        s = int(rng.integers(256, 4097))
+        N = int(rng.integers(8, 65))
+        f = float(rng.uniform(1 / 8, 1 / 2))
+        p = max(1, int(np.floor(s * f)))
+        idx = wl.obs_indices(s, "random", rng, p=p)
+        wins.append(wl.make_advdiff_window(s, N, idx, r_len=0.05, r_var=0.5, nrhs=nrhs,
+                                           seed=1000 * 4 + w))
+    return wins
+
+
+def bench_c4(args):
+    import torch
+
+    from paper_2105_06975_amd import svar
+    nrhs = 8
+    t0 = time.time()
+    wins = c4_windows(args.c4, nrhs=nrhs)
+    log(f"c4: {len(wins)} windows built in {time.time() - t0:.1f}s; "
+        f"n per rhs: {[w.n for w in wins]}")
+    prec = svar.Precond(type="PI", k=args.k, rhat="RR")
+    kw = dict(rtol=args.rtol, maxit=3000, restart=args.restart, max_outer=400)
+    t0 = time.time()
+    h = svar.Handle(wins, prec)
+    log(f"c4 set-up {time.time() - t0:.1f}s")
+    rhs = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
+    h.solve(rhs, nrhs, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x, info, rc = h.solve(rhs, nrhs, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    its = [i["iters"] for i in info]
+    res = {"workload": f"c4 wave: {len(wins)} uneven windows x {nrhs} rhs, restart {args.restart}",
+           "batched": {"systems": len(info), "seconds": el, "solves_per_s": len(info) / el,
+                       "rc": rc, "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+                       "relres_max": float(max(i["relres_true"] for i in info)),
+                       "n_total": int(sum(w.n for w in wins) * nrhs)}}
+    log(res["batched"])
+    # one at a time: the first two windows' 16 systems (same preconditioner and restart)
+    sub = wins[:2]
+    hs = svar.Handle(sub, prec)
+    one_t = 0.0
+    its1 = []
+    for wi, w in enumerate(sub):
+        hw = svar.Handle([w], prec)
+        for r in range(nrhs):
+            b = torch.from_numpy(w.rhs[r]).cuda()
+            hw.solve(b, 1, **kw) if r == 0 else None
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            xx, inf1, rc1 = hw.solve(b, 1, **kw)
+            torch.cuda.synchronize()
+            one_t += time.perf_counter() - t
+            its1.append(inf1[0]["iters"])
+    rhs_sub = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in sub])).cuda()
+    hs.solve(rhs_sub, nrhs, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xs, infs, rcs = hs.solve(rhs_sub, nrhs, **kw)
+    torch.cuda.synchronize()
+    el_sub = time.perf_counter() - t
+    res["subset"] = {"systems": 2 * nrhs, "one_at_a_time_s": one_t, "batched_s": el_sub,
+                     "batched_speedup": one_t / el_sub, "iters_one": its1,
+                     "iters_batched": [i["iters"] for i in infs]}
+    log(res["subset"])
+    return res
 
 
 def sweep(win, rhs, args):
