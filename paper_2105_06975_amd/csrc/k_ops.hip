@@ -64,6 +64,74 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
   out[j] = in[j] + J.alpha * acc;
 }
 
+// Whole L_M(k) sweep of one segment in one workgroup (band models whose taps fit a contiguous
+// window of SWEEP_H + 1 offsets, s <= SWEEP_MAXS): the running state stays in LDS (two buffers)
+// for all steps of the segment, so a sweep costs one launch instead of k - 1.
+//   forward  (trans = 0): z_b unchanged, z_i = v_i + M z_{i-1},     i = b+1 .. e
+//   backward (trans = 1): w_e unchanged, w_i = v_i + M^T w_{i+1},   i = e-1 .. b
+// in place on vec (v_i is read from vec before block i is overwritten).  Each thread computes
+// SWEEP_R consecutive outputs from a register window of SWEEP_R + SWEEP_H staged values; the
+// tap weights are uniform across the workgroup (scalar loads) and the tap loop is unrolled.
+template <int R, int H>
+__global__ __launch_bounds__(256) void k_sweep_band(const SJob* __restrict__ jobs,
+                                                    const ModelDev* __restrict__ models, Bases b,
+                                                    const int* __restrict__ skip, int njobs) {
+  extern __shared__ double st[];  // 2 s
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const SJob J = jobs[job_id()];
+  const int s = J.s;
+  const ModelDev& M = models[J.model];
+  const double* __restrict__ wd = J.trans ? M.wdT : M.wd;  // H + 1 weights, offsets o0 .. o0+H
+  const int o0 = J.trans ? M.wd0T : M.wd0;
+  double* vec = opnd(b, J.vec);
+  double* cur = st;
+  double* nxt = st + s;
+  const int first = J.trans ? J.len - 1 : 0;
+  for (int j = threadIdx.x; j < s; j += blockDim.x) cur[j] = vec[(int64_t)first * s + j];
+  __syncthreads();
+  for (int t = 1; t < J.len; ++t) {
+    const int blk = J.trans ? J.len - 1 - t : t;
+    double* row = vec + (int64_t)blk * s;
+    for (int j0 = threadIdx.x * R; j0 < s; j0 += blockDim.x * R) {
+      // window value m = cur[j0 + o0 + m] is loaded just before its first use (tap d = m - R + 1)
+      // so only R values are live at a time
+      int gb = j0 + o0;
+      gb = gb < 0 ? gb + s : (gb >= s ? gb - s : gb);
+      double xw[R + H];
+#pragma unroll
+      for (int m = 0; m < R - 1; ++m) {
+        const int g = gb + m;
+        xw[m] = cur[g >= s ? g - s : g];
+      }
+      double acc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+      for (int d = 0; d <= H; ++d) {
+        const int g = gb + d + R - 1;
+        xw[d + R - 1] = cur[g >= s ? (g >= 2 * s ? g - 2 * s : g - s) : g];
+        const double wv = wd[d];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += wv * xw[r + d];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        if (j < s) {
+          const double v = row[j] + acc[r];
+          row[j] = v;
+          nxt[j] = v;
+        }
+      }
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+}
+
 // Dense model maps (distinct M_i per block): one output element per thread.
 __global__ __launch_bounds__(TS) void k_mstep_dense(const MJob* __restrict__ jobs,
                                                     const ModelDev* __restrict__ models, Bases b,
@@ -150,6 +218,21 @@ void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
   hipLaunchKernelGGL(k_mstep_band, jgrid(tiles(max_s), njobs), dim3(TS),
                      (size_t)(TS + max_halo) * sizeof(double), st, jobs, models, b, skip, njobs);
 }
+void launch_sweep_band(const SJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
+                       const int* skip, hipStream_t st) {
+  if (njobs == 0) return;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_sweep_band<SWEEP_R, SWEEP_H>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(2 * SWEEP_MAXS * sizeof(double)));
+    attr = true;
+  }
+  const int threads = 256;
+  hipLaunchKernelGGL((k_sweep_band<SWEEP_R, SWEEP_H>), jgrid(1, njobs), dim3(threads),
+                     (size_t)2 * max_s * sizeof(double), st, jobs, models, b, skip, njobs);
+}
+
 void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
                         const int* skip, hipStream_t st) {
   if (njobs == 0) return;

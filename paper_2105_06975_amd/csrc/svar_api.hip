@@ -369,6 +369,21 @@ static int setup_model(svar_handle* h, WinDev& W, const svar_model_desc& md, hip
     M.offT = doffT;
     M.w = dw;
     M.wT = dwT;
+    // dense tap windows for the fused sweep kernel
+    if (halo <= SWEEP_H && s >= SWEEP_H + 1) {
+      std::vector<double> wdh(SWEEP_H + 1, 0.0), wdTh(SWEEP_H + 1, 0.0);
+      for (size_t tp = 0; tp < off.size(); ++tp) {
+        wdh[off[tp] - M.omin] += wts[tp];
+        wdTh[offT[tp] - M.ominT] += wts[tp];
+      }
+      double *dwd = nullptr, *dwdT = nullptr;
+      SVAR_TRY(upload(h->allocs, &dwd, wdh.data(), wdh.size(), st));
+      SVAR_TRY(upload(h->allocs, &dwdT, wdTh.data(), wdTh.size(), st));
+      M.wd = dwd;
+      M.wdT = dwdT;
+      M.wd0 = M.omin;
+      M.wd0T = M.ominT;
+    }
   } else if (md.kind == SVAR_MODEL_DENSE) {
     M.kind = MK_DENSE;
     if (!md.dense) return inval("dense model needs N matrices");
@@ -724,6 +739,43 @@ static int add_L(Builder& B, VRef in, VRef out, int trans) {
 // in-place sweep of L_M(k)^{-1} (trans = 0) or L_M(k)^{-T} (trans = 1) on vec (Lemma 1):
 // step t updates position b + t (forward) / e - t (backward) of every segment.
 static int add_sweep(Builder& B, VRef vec, int trans, int k) {
+  // band models with s <= SWEEP_MAXS: one fused launch, one workgroup per segment and rhs
+  std::vector<SJob> fused;
+  bool all_band = true;
+  for (const WinDev& W : B.h->wins)
+    if (W.model_kind != MK_BAND || W.s > SWEEP_MAXS || !B.h->models[W.model_id].wd)
+      all_band = false;
+  if (all_band && k > 1) {
+    int ms = 0;
+    for (int w = 0; w < (int)B.h->wins.size(); ++w) {
+      const WinDev& W = B.h->wins[w];
+      for (int r = 0; r < B.nrhs; ++r)
+        for (int b0 = 0; b0 <= W.N; b0 += k) {
+          const int e0 = std::min(b0 + k - 1, W.N);
+          if (e0 == b0) continue;
+          SJob J{};
+          J.vec = blk(B.h, w, r, B.nrhs, vec, b0);
+          J.model = W.model_id;
+          J.trans = trans;
+          J.s = W.s;
+          J.len = e0 - b0 + 1;
+          ms = std::max(ms, W.s);
+          fused.push_back(J);
+          B.P->cnt[trans ? 1 : 0] += e0 - b0;
+        }
+    }
+    if (fused.empty()) return SVAR_OK;
+    Launch L;
+    L.kind = LK_SWEEP_BAND;
+    L.njobs = (int)fused.size();
+    L.max_s = ms;
+    L.kclass = SVAR_KCLASS_MODEL;
+    SJob* d = nullptr;
+    SVAR_TRY(upload(B.h->allocs, &d, fused.data(), fused.size(), B.st));
+    L.jobs = d;
+    B.P->launches.push_back(L);
+    return SVAR_OK;
+  }
   for (int t = 1; t < k; ++t) {
     std::vector<MJob> jobs[3];
     for (int w = 0; w < (int)B.h->wins.size(); ++w) {
@@ -1078,6 +1130,16 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
           if (j.mi < 1 || j.mi > h->models[j.model].N) return fail("model index");
         }
       }
+    } else if (L.kind == LK_SWEEP_BAND) {
+      std::vector<SJob> J(L.njobs);
+      SVAR_HIP(hipMemcpyAsync(J.data(), L.jobs, J.size() * sizeof(SJob), hipMemcpyDeviceToHost, st));
+      SVAR_HIP(hipStreamSynchronize(st));
+      for (auto& j : J) {
+        spans.push_back({j.vec.base, j.vec.off, j.vec.off + (int64_t)j.len * j.s});
+        if (j.model < 0 || j.model >= (int)h->models.size() || h->models[j.model].kind != MK_BAND ||
+            !h->models[j.model].wd || j.s > SWEEP_MAXS || j.len < 1)
+          return fail("sweep job");
+      }
     } else if (L.kind == LK_GATHER) {
       std::vector<HJob> J(L.njobs);
       SVAR_HIP(hipMemcpyAsync(J.data(), L.jobs, J.size() * sizeof(HJob), hipMemcpyDeviceToHost, st));
@@ -1204,6 +1266,9 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
         break;
       case LK_MSTEP_DENSE:
         launch_mstep_dense((const MJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);
+        break;
+      case LK_SWEEP_BAND:
+        launch_sweep_band((const SJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);
         break;
       case LK_MSTEP_L96:
         launch_mstep_l96((const MJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);

@@ -77,6 +77,14 @@ struct MJob {
   double alpha;
 };
 enum ModelKind { MK_BAND = 0, MK_DENSE = 1, MK_L96 = 2 };
+// one whole L_M(k) sweep segment: blocks vec.off + [0, len) s, in place
+struct SJob {
+  Operand vec;
+  int32_t model, trans, s, len;
+};
+constexpr int SWEEP_MAXS = 8192;  // LDS holds two state vectors (128 KB)
+constexpr int SWEEP_R = 8;        // outputs per thread of the fused sweep
+constexpr int SWEEP_H = 63;       // widest contiguous tap window (offsets o0 .. o0 + SWEEP_H)
 struct ModelDev {
   int32_t kind, s, N, ntap;
   const int32_t* off;    // band taps of M
@@ -84,6 +92,9 @@ struct ModelDev {
   const int32_t* offT;   // band taps of M^T
   const double* wT;
   int32_t omin, omax, ominT, omaxT;
+  const double* wd;      // taps of M on the contiguous window o0 .. o0 + SWEEP_H (zero padded)
+  const double* wdT;     // same for M^T
+  int32_t wd0, wd0T;     // window starts; wd == nullptr when the taps do not fit
   const double* dense;   // N matrices, M_i at (i-1)*s*s
   // Lorenz-96 tangent linear model
   const double* traj;    // [N+1][s]
@@ -114,7 +125,7 @@ struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha), j < len
 
 // ------------------------------------------------------------------ launch programs
 enum LaunchKind { LK_MSTEP_BAND, LK_MSTEP_DENSE, LK_MSTEP_L96, LK_GATHER, LK_SCATTER, LK_VEC,
-                  LK_GEMM };
+                  LK_GEMM, LK_SWEEP_BAND };
 struct GemmPlanDev {
   GemmProb* probs = nullptr;   // device
   GemmTask* tasks = nullptr;   // device
@@ -146,6 +157,8 @@ void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
                        const ModelDev* models, Bases b, const int* skip, hipStream_t st);
 void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
                         Bases b, const int* skip, hipStream_t st);
+void launch_sweep_band(const SJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
+                       const int* skip, hipStream_t st);
 void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
                       Bases b, const int* skip, hipStream_t st);
 void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
