@@ -106,6 +106,22 @@ def test_component_maps(sv, k):
             assert rel(out[r], fn(Yo[r])) < tol, op
 
 
+@pytest.mark.parametrize("s,N", [(100, 10), (37, 6), (256, 12)])
+def test_band_model_sweeps(sv, s, N):
+    """L_M(k)^{-1}, L_M(k)^{-T}, L and L^T with the implicit advection-diffusion model for
+    several k (the fused one-launch sweep for s >= 64, per-step launches below)."""
+    win = wl.make_small_window(s=s, N=N, p=max(4, s // 3), seed=s)
+    X = np.random.default_rng(s).standard_normal((3, win.nb * win.s))
+    for k in sorted({1, 2, 3, 5, N + 1}):
+        orc = so.SaddleOracle(win, k=k, rhat="RR")
+        h = sv.Handle([win], sv.Precond(type="PI", k=k, rhat="RR"))
+        for op, fn in {"LHAT_INV": orc.LM_inv, "LHAT_INVT": orc.LM_invT, "L": orc.L_apply,
+                       "LT": orc.LT_apply}.items():
+            out = host(h.apply_op(op, dev(X), 3)).reshape(3, -1)
+            for r in range(3):
+                assert rel(out[r], fn(X[r].reshape(win.nb, win.s)).ravel()) < 1e-12, (op, k)
+
+
 @pytest.mark.parametrize("rhat", ["DIAG", "RR", "ME", "EXACT"])
 def test_rhat_kinds_and_parameters(sv, rhat):
     win = wl.make_small_window(s=64, N=2, p=40, seed=7, r_len=0.08)
