@@ -329,3 +329,19 @@ def make_l96_window(s: int = 2048, N: int = 32, *, F: float = 8.0, dt: float = 0
         rhs[:, off + i * p: off + (i + 1) * p] = (y[i] - guess[i][idx])[None, :]
     win.rhs = rhs
     return win
+
+
+def net_init(cin: int, C: int, seed: int = 0, width: int = 5) -> np.ndarray:
+    """Seeded initial parameters of the correction network, flat, float32-representable.
+
+    Layout: W1 (C, cin, width), b1 (C), W2 (C, C, width), b2, W3 (C, C, width), b3,
+    W4 (1, C, width), b4 (1).  Weights are uniform in +-sqrt(6 / fan_in) (He), the last
+    layer's scaled by 0.1 so that the initial correction is small; biases are zero.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 23]))
+    parts = []
+    for li, (co, ci) in enumerate([(C, cin), (C, C), (C, C), (1, C)]):
+        a = np.sqrt(6.0 / (ci * width)) * (0.1 if li == 3 else 1.0)
+        parts.append(rng.uniform(-a, a, size=(co, ci, width)).ravel())
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
