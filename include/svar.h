@@ -132,13 +132,25 @@ typedef struct svar_solve_opts {
   int32_t precision;  /* SVAR_PRECISION_*                                                   */
   double inner_rtol;  /* mixed precision: relative tolerance of each inner cycle            */
   int32_t max_outer;  /* refinement / restart cycles allowed (>= 1)                         */
+  /* learned path (a network attached with svar_set_net): after every FGMRES step the
+     least-squares residual must fall below (1 - fallback_drop) times the previous one; the
+     first time it does not, the system's later preconditioner applications skip the network
+     (the plain P).  <= 0 disables the check. */
+  double fallback_drop;
+  /* training-pair harvest: when non-NULL, the state component v3 of the preconditioner input
+     of each FGMRES step j < harvest_cap is copied to harvest + j * state_len (device memory,
+     state_len = the packed state-space length of all windows and rhs).  Steps after every
+     system has converged leave their slots untouched. */
+  double* harvest;
+  int32_t harvest_cap;
+  int32_t pad;
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */
   int32_t iters;        /* Krylov iterations used (all cycles)                              */
   int32_t outer;        /* refinement / restart cycles used                                 */
   int32_t status;       /* SVAR_OK, SVAR_E_NOCONV or SVAR_E_BREAKDOWN                       */
-  int32_t reserved;
+  int32_t fallbacks;    /* learned path: 1 if the network was switched off for this system  */
   double relres_true;   /* ||rhs - A x||_2 / ||rhs||_2 computed in float64 at return        */
   double relres_est;    /* the solver's own estimate at its last iteration                  */
   /* matrix-vector products with component blocks, counted as in Tables 4 and 5 */
@@ -229,6 +241,70 @@ int svar_timing_enable(svar_handle* h, int32_t kclass, int32_t on);
 /* total_ms, launches: host pointers; resets the accumulators when reset != 0. */
 int svar_timing_read(svar_handle* h, int32_t kclass, double* total_ms, int64_t* launches,
                      int32_t reset);
+
+/* ------------------------------------------------------------------ learned correction
+   Both preconditioners apply Lhat^{-T} = L_M(k)^{-T} (Definition 1) to v3: P_I as its first
+   output c1 (which also feeds the Schur term Lhat^{-1} D c1), P_D inside its Schur-complement
+   approximation Lhat^{-1} D Lhat^{-T} v3 (§2.2, §6.2).  With P(i, j) = M_{i+1}^T ... M_j^T the
+   exact sweep differs from the truncated one at block i by sum_m P(i, b_m) chat_{b_m} over the
+   later segment starts b_m = e(i) + 1 + (m - 1) k, where e(i) ends block i's segment.  A
+   network corrects the sweep output towards the exact L^{-T} v3:
+       c = chat + sigma * NN(features(chat / sigma)),   sigma = rms of chat over the system,
+   features of block i: chat_i, chat at the next n_bound segment starts (zero past block N),
+   one-hot of e(i) - i.  NN: periodic 1D convolutions over space of width 5,
+   (1 + n_bound + k) -> 64 -> 64 -> 64 -> 1 channels, ReLU after the first three.
+   Parameters (float32, host order): W1 (64, cin, 5), b1 (64), W2 (64, 64, 5), b2, W3, b3,
+   W4 (1, 64, 5), b4 (1), each row-major.  Training: mean squared error, Adam. */
+#define SVAR_NET_FP32 0   /* inference with float32 MFMA                                 */
+#define SVAR_NET_BF16 1   /* inference with bfloat16 weights and activations, float32
+                             accumulation                                                 */
+
+typedef struct svar_net svar_net;
+typedef struct svar_net_desc {
+  int32_t k;          /* segment length of the corrected sweep (the handle's k), >= 1      */
+  int32_t n_bound;    /* later segment starts used as inputs, >= 0, 1 + n_bound + k <= 16  */
+  int32_t precision;  /* SVAR_NET_* of the inference inside the preconditioner             */
+  int32_t pad;
+} svar_net_desc;
+typedef struct svar_adam_opts {
+  double lr, beta1, beta2, eps;  /* Adam (Kingma & Ba) with bias correction               */
+} svar_adam_opts;
+
+/* Create a network on the calling thread's device with zero parameters. */
+int svar_net_create(const svar_net_desc* desc, svar_net** out);
+/* Release it (NULL accepted).  A handle it is attached to must be detached first. */
+int svar_net_destroy(svar_net* net);
+/* Number of float32 parameters, or -1 for NULL. */
+int64_t svar_net_nparams(const svar_net* net);
+/* Copy all parameters from / to host memory (nparams floats); set_params also clears the
+   Adam state.  Synchronous. */
+int svar_net_set_params(svar_net* net, const float* theta);
+int svar_net_get_params(const svar_net* net, float* theta);
+
+/* Training pairs of npair systems of nb blocks of s points (device memory): chat is the
+   truncated sweep output, cexact the exact one (both float64, [npair][nb][s]); writes
+   x = chat / sigma and y = (cexact - chat) / sigma as float32 (zeros where sigma = 0). */
+int svar_net_make_pairs(int32_t npair, int32_t nb, int32_t s, const double* chat,
+                        const double* cexact, float* x, float* y, void* stream);
+
+/* out[p][i][j] = NN(features(x_p))[i][j] for normalised sweep outputs x ([npair][nb][s]
+   float32, device); precision SVAR_NET_*. */
+int svar_net_forward(svar_net* net, int32_t precision, int32_t npair, int32_t nb, int32_t s,
+                     const float* x, float* out, void* stream);
+
+/* One float32 training step on the blocks samples[2 q] (pair) / samples[2 q + 1] (block),
+   q < nsample (host array) of the pairs (x, y) ([npair][nb][s] float32, device): the loss
+   sum over those blocks of (NN - y)^2 / (nsample s), its gradient, and, when adam is not
+   NULL, one Adam update.  loss (host double) and grad (host, nparams floats, the gradient
+   before the update) may be NULL; asking for either synchronises the stream. */
+int svar_net_train_step(svar_net* net, int32_t npair, int32_t nb, int32_t s, const float* x,
+                        const float* y, int32_t nsample, const int32_t* samples,
+                        const svar_adam_opts* adam, double* loss, float* grad, void* stream);
+
+/* Attach (or with NULL detach) a network to a handle: svar_apply_P and svar_solve then
+   correct every Lhat^{-T} v3 of the preconditioner as above.  The network's k must equal
+   the handle's; it must outlive the attachment.  Training it later changes the correction. */
+int svar_set_net(svar_handle* h, svar_net* net);
 
 const char* svar_last_error(void);
 

@@ -1,0 +1,612 @@
+// Kernels of the sweep-correction network: periodic width-5 convolutions over space as
+// implicit GEMMs on the matrix cores, its training (loss, backward passes, weight gradients,
+// Adam) and its in-place application to an Lhat^{-T} sweep output.
+//
+// Convolution (64 output channels): one workgroup of 4 waves takes a tile of 64 grid points of
+// one sample, stages the 68 input rows it reads (periodic wrap inside the sample) in LDS, and
+// wave w produces output channels 16w..16w+15 for all 64 points: its 16 x (5 CIN) slice of the
+// weights stays in registers for the whole launch, the input fragments come from LDS.  The
+// contraction index is k = t * CIN + ci (tap t, input channel ci), so every lane's operand is
+// a run of consecutive channels of one staged row.  float32 uses v_mfma_f32_16x16x4f32 (one
+// value per lane), bfloat16 v_mfma_f32_16x16x16bf16_1k (four per lane); both accumulate in
+// float32 and return element e of lane group q as row 4 q + e of the 16 x 16 tile.
+//
+// Weight gradients (float32): rows = output channel, columns = k, contraction over the grid
+// points of the workgroup's tiles; partial sums per workgroup are reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "net.h"
+
+namespace svar {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+static constexpr int GRID_CAP = 1024;
+int net_grid_cap() { return GRID_CAP; }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <typename E> __device__ __forceinline__ E to_e(float v);
+template <> __device__ __forceinline__ float to_e<float>(float v) { return v; }
+template <> __device__ __forceinline__ uint16_t to_e<uint16_t>(float v) { return f2bf(v); }
+template <typename E> __device__ __forceinline__ float to_f(E v);
+template <> __device__ __forceinline__ float to_f<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_f<uint16_t>(uint16_t v) { return bf2f(v); }
+
+__device__ __forceinline__ int wrap(int p, int s) {
+  p %= s;
+  return p < 0 ? p + s : p;
+}
+
+// ------------------------------------------------------------------ MFMA traits
+template <typename E> struct NetMma;
+template <> struct NetMma<float> {
+  static constexpr int KS = 4;  // contraction length of one instruction
+  typedef float frag;
+  static __device__ __forceinline__ v4f mma(frag a, frag b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ frag ld(const float* p) { return *p; }
+};
+template <> struct NetMma<uint16_t> {
+  static constexpr int KS = 16;
+  typedef v4s frag;
+  static __device__ __forceinline__ v4f mma(frag a, frag b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ frag ld(const uint16_t* p) { return *(const v4s*)p; }
+};
+
+// LDS row strides (elements), chosen so that the 16 rows read by one lane group fall in
+// distinct banks and every row starts on an 8-byte boundary
+template <typename E, int CIN> struct ConvStride;
+template <> struct ConvStride<float, 16> { static constexpr int v = 18; };
+template <> struct ConvStride<float, 64> { static constexpr int v = 66; };
+template <> struct ConvStride<uint16_t, 16> { static constexpr int v = 20; };
+template <> struct ConvStride<uint16_t, 64> { static constexpr int v = 68; };
+
+// ------------------------------------------------------------------ parameters
+__global__ void k_net_pack(const float* __restrict__ th, NetLayout L, NetWeights W) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // layers 1..3, kernel layout [co][t * CIN + ci]
+  for (int l = 0; l < 3; ++l) {
+    const int CIN = l == 0 ? NET_CIN1 : NET_C;
+    const int cin = l == 0 ? L.cin : NET_C;
+    if (e < (int64_t)NET_C * NET_W * CIN) {
+      const int co = (int)(e / (NET_W * CIN)), kk = (int)(e % (NET_W * CIN));
+      const int t = kk / CIN, ci = kk % CIN;
+      const float v = ci < cin ? th[L.w[l] + ((int64_t)co * cin + ci) * NET_W + t] : 0.0f;
+      W.wf[l][e] = v;
+      W.wb[l][e] = f2bf(v);
+    }
+  }
+  // layers 2, 3 transposed and tap-reversed for the backward pass: [ci][t' * 64 + co]
+  for (int l = 1; l < 3; ++l) {
+    if (e < (int64_t)NET_C * NET_W * NET_C) {
+      const int ci = (int)(e / (NET_W * NET_C)), kk = (int)(e % (NET_W * NET_C));
+      const int tp = kk / NET_C, co = kk % NET_C;
+      W.wflip[l - 1][e] = th[L.w[l] + ((int64_t)co * NET_C + ci) * NET_W + (NET_W - 1 - tp)];
+    }
+  }
+  if (e < NET_W * NET_C) {
+    const int t = (int)(e / NET_C), c = (int)(e % NET_C);
+    W.w4[e] = th[L.w[3] + (int64_t)c * NET_W + t];
+  }
+}
+
+// ------------------------------------------------------------------ per-system scale
+__global__ __launch_bounds__(256) void k_net_sumsq(const double* __restrict__ v,
+                                                   const NetChunk* __restrict__ ch,
+                                                   double* __restrict__ part,
+                                                   const int* __restrict__ skip) {
+  __shared__ double red[4];
+  if (skip && *skip) return;
+  const NetChunk c = ch[blockIdx.x];
+  double acc = 0.0;
+  for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += 256) {
+    const double x = v[e];
+    acc += x * x;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// sigma = rms over the system (chunk0[sys] .. chunk0[sys + 1] hold its chunks, whose element
+// counts sum to the system length stored in chunk0's companion: the last chunk's e1 - first e0)
+__global__ void k_net_sigma(const double* __restrict__ part, const int32_t* __restrict__ chunk0,
+                            const NetChunk* __restrict__ ch, int nsys, double* __restrict__ sigma,
+                            double* __restrict__ inv_sigma, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsys) return;
+  const int c0 = chunk0[i], c1 = chunk0[i + 1];
+  double acc = 0.0;
+  for (int c = c0; c < c1; ++c) acc += part[c];
+  const double len = c1 > c0 ? (double)(ch[c1 - 1].e1 - ch[c0].e0) : 1.0;
+  const double sg = sqrt(acc / len);
+  sigma[i] = sg;
+  inv_sigma[i] = sg > 0.0 ? 1.0 / sg : 0.0;
+}
+
+__global__ void k_net_norm_pairs(const double* __restrict__ chat, const double* __restrict__ cex,
+                                 const double* __restrict__ inv, int64_t len, int npair,
+                                 float* __restrict__ x, float* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len * npair) return;
+  const double is = inv[e / len];
+  const double a = chat[e];
+  x[e] = (float)(a * is);
+  y[e] = (float)((cex[e] - a) * is);
+}
+
+// ------------------------------------------------------------------ layer-1 features
+// channel 0: own block; 1..S: block e + 1 + m k (zero past the last block); 1+S+(e-blk): 1
+template <typename E, typename SRC>
+__global__ __launch_bounds__(64) void k_net_feat(const SRC* __restrict__ src,
+                                                 const double* __restrict__ inv_sigma,
+                                                 const NetSample* __restrict__ smp,
+                                                 const NetTile* __restrict__ tiles,
+                                                 int64_t row_base, int k, int S,
+                                                 E* __restrict__ X0,
+                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const NetTile T = tiles[blockIdx.x];
+  const NetSample P = smp[T.sample];
+  const int pos = T.pos0 + threadIdx.x;
+  if (pos >= P.s) return;
+  const double isg = inv_sigma ? inv_sigma[P.sys] : 1.0;
+  const int e = min((P.blk / k) * k + k - 1, P.nb - 1);
+  const int hot = 1 + S + (e - P.blk);
+  E* o = X0 + (P.row0 - row_base + pos) * NET_CIN1;
+#pragma unroll
+  for (int c = 0; c < NET_CIN1; ++c) {
+    float v = 0.0f;
+    if (c == 0) {
+      v = (float)((double)src[P.src + (int64_t)P.blk * P.s + pos] * isg);
+    } else if (c <= S) {
+      const int b = e + 1 + (c - 1) * k;
+      if (b < P.nb) v = (float)((double)src[P.src + (int64_t)b * P.s + pos] * isg);
+    } else if (c == hot) {
+      v = 1.0f;
+    }
+    o[c] = to_e<E>(v);
+  }
+}
+
+// ------------------------------------------------------------------ convolution, 64 outputs
+template <typename E, int CIN, int BWD>
+__global__ __launch_bounds__(256) void k_net_conv(const E* __restrict__ in, E* __restrict__ out,
+                                                  const E* __restrict__ W,
+                                                  const float* __restrict__ bias,
+                                                  const float* __restrict__ mask,
+                                                  const NetSample* __restrict__ smp,
+                                                  const NetTile* __restrict__ tiles, int ntiles,
+                                                  int64_t row_base,
+                                                  const int* __restrict__ skip) {
+  typedef NetMma<E> MM;
+  constexpr int EPL = MM::KS / 4;            // operand elements per lane
+  constexpr int NKS = NET_W * CIN / MM::KS;  // contraction steps
+  constexpr int STR = ConvStride<E, CIN>::v;
+  constexpr int CPR = CIN * (int)sizeof(E) / 8;  // 8-byte pieces per row
+  __shared__ __align__(16) E tile[NET_ROWS * STR];
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int co = wave * 16 + r16;
+  typename MM::frag bw[NKS];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks)
+    bw[ks] = MM::ld(W + (int64_t)co * (NET_W * CIN) + ks * MM::KS + q * EPL);
+  const float bco = BWD ? 0.0f : bias[co];
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const NetTile T = tiles[ti];
+    const NetSample P = smp[T.sample];
+    const int64_t rb = P.row0 - row_base;
+    __syncthreads();
+    for (int c = threadIdx.x; c < NET_ROWS * CPR; c += 256) {
+      const int rr = c / CPR, cc = c - rr * CPR;
+      const int p = wrap(T.pos0 - NET_HALO + rr, P.s);
+      const uint2 v = *(const uint2*)((const char*)(in + (rb + p) * CIN) + cc * 8);
+      *(uint2*)((char*)(tile + rr * STR) + cc * 8) = v;
+    }
+    __syncthreads();
+    v4f acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int kl = ks * MM::KS + q * EPL;
+      const int t = kl / CIN, ci = kl - t * CIN;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+        acc[rt] = MM::mma(MM::ld(tile + (rt * 16 + r16 + t) * STR + ci), bw[ks], acc[rt]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pos = T.pos0 + rt * 16 + 4 * q + e;
+        if (pos >= P.s) continue;
+        const int64_t o = (rb + pos) * NET_C + co;
+        float v = acc[rt][e];
+        if (BWD)
+          v = mask[o] > 0.0f ? v : 0.0f;
+        else
+          v = fmaxf(v + bco, 0.0f);
+        out[o] = to_e<E>(v);
+      }
+  }
+}
+
+// ------------------------------------------------------------------ last layer (64 -> 1)
+template <typename E, int APPLY>
+__global__ __launch_bounds__(64) void k_net_out(const E* __restrict__ a3,
+                                                const float* __restrict__ w4,
+                                                const float* __restrict__ b4,
+                                                const NetSample* __restrict__ smp,
+                                                const NetTile* __restrict__ tiles,
+                                                int64_t row_base, float* __restrict__ outv,
+                                                double* __restrict__ dst,
+                                                const double* __restrict__ sigma,
+                                                const int* __restrict__ off,
+                                                const int* __restrict__ skip) {
+  __shared__ float w[NET_W * NET_C];
+  if (skip && *skip) return;
+  for (int i = threadIdx.x; i < NET_W * NET_C; i += 64) w[i] = w4[i];
+  __syncthreads();
+  const NetTile T = tiles[blockIdx.x];
+  const NetSample P = smp[T.sample];
+  const int pos = T.pos0 + threadIdx.x;
+  if (pos >= P.s) return;
+  const int64_t rb = P.row0 - row_base;
+  float acc = b4[0];
+  for (int t = 0; t < NET_W; ++t) {
+    const E* row = a3 + (rb + wrap(pos + t - NET_HALO, P.s)) * NET_C;
+    const float* wt = w + t * NET_C;
+#pragma unroll 16
+    for (int c = 0; c < NET_C; ++c) acc += wt[c] * to_f<E>(row[c]);
+  }
+  if (APPLY) {
+    if (off && off[P.sys]) return;
+    dst[P.src + (int64_t)P.blk * P.s + pos] += sigma[P.sys] * (double)acc;
+  } else {
+    outv[rb + pos] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ training
+__global__ __launch_bounds__(64) void k_net_loss(const float* __restrict__ outv,
+                                                 const float* __restrict__ y,
+                                                 const NetSample* __restrict__ smp,
+                                                 const NetTile* __restrict__ tiles, float scale,
+                                                 float* __restrict__ g4,
+                                                 double* __restrict__ lpart) {
+  const NetTile T = tiles[blockIdx.x];
+  const NetSample P = smp[T.sample];
+  const int pos = T.pos0 + threadIdx.x;
+  double d2 = 0.0;
+  if (pos < P.s) {
+    const int64_t r = P.row0 + pos;
+    const float d = outv[r] - y[P.src + (int64_t)P.blk * P.s + pos];
+    g4[r] = scale * d;
+    d2 = (double)d * (double)d;
+  }
+  for (int o = 32; o > 0; o >>= 1) d2 += __shfl_xor(d2, o);
+  if (threadIdx.x == 0) lpart[blockIdx.x] = d2;
+}
+
+// g3[row][c] = relu'(a3) * sum_t W4[t][c] g4[pos - t + 2]
+__global__ __launch_bounds__(256) void k_net_out_bwd(const float* __restrict__ g4,
+                                                     const float* __restrict__ w4,
+                                                     const float* __restrict__ a3,
+                                                     float* __restrict__ g3,
+                                                     const NetSample* __restrict__ smp,
+                                                     const NetTile* __restrict__ tiles) {
+  const NetTile T = tiles[blockIdx.x];
+  const NetSample P = smp[T.sample];
+  const int c = threadIdx.x & 63;
+  for (int p = threadIdx.x >> 6; p < NET_TILE; p += 4) {
+    const int pos = T.pos0 + p;
+    if (pos >= P.s) break;
+    const int64_t r = P.row0 + pos;
+    float acc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NET_W; ++t)
+      acc += w4[t * NET_C + c] * g4[P.row0 + wrap(pos - t + NET_HALO, P.s)];
+    g3[r * NET_C + c] = a3[r * NET_C + c] > 0.0f ? acc : 0.0f;
+  }
+}
+
+// dW4[t][c] = sum_pos g4[pos] a3[pos + t - 2][c], db4 = sum g4: partials per workgroup
+__global__ __launch_bounds__(256) void k_net_wgrad4(const float* __restrict__ g4,
+                                                    const float* __restrict__ a3,
+                                                    const NetSample* __restrict__ smp,
+                                                    const NetTile* __restrict__ tiles,
+                                                    int ntiles, float* __restrict__ part) {
+  __shared__ float gt[NET_TILE];
+  constexpr int NE = NET_W * NET_C + 1;
+  float acc0 = 0.0f, acc1 = 0.0f;  // elements threadIdx.x and threadIdx.x + 256
+  const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const NetTile T = tiles[ti];
+    const NetSample P = smp[T.sample];
+    __syncthreads();
+    if (threadIdx.x < NET_TILE) {
+      const int pos = T.pos0 + threadIdx.x;
+      gt[threadIdx.x] = pos < P.s ? g4[P.row0 + pos] : 0.0f;
+    }
+    __syncthreads();
+    const int np = min(NET_TILE, P.s - T.pos0);
+    {
+      const int t = e0 / NET_C, c = e0 % NET_C;
+      for (int p = 0; p < np; ++p)
+        acc0 += gt[p] * a3[(P.row0 + wrap(T.pos0 + p + t - NET_HALO, P.s)) * NET_C + c];
+    }
+    if (e1 < NE - 1) {
+      const int t = e1 / NET_C, c = e1 % NET_C;
+      for (int p = 0; p < np; ++p)
+        acc1 += gt[p] * a3[(P.row0 + wrap(T.pos0 + p + t - NET_HALO, P.s)) * NET_C + c];
+    } else if (e1 == NE - 1) {
+      for (int p = 0; p < np; ++p) acc1 += gt[p];
+    }
+  }
+  part[(int64_t)blockIdx.x * NE + e0] = acc0;
+  if (e1 < NE) part[(int64_t)blockIdx.x * NE + e1] = acc1;
+}
+
+// dW[co][t * CIN + ci] = sum_pos g[pos][co] a[pos + t - 2][ci], db[co] = sum_pos g[pos][co]
+template <int CIN>
+__global__ __launch_bounds__(256) void k_net_wgrad(const float* __restrict__ g,
+                                                   const float* __restrict__ a,
+                                                   const NetSample* __restrict__ smp,
+                                                   const NetTile* __restrict__ tiles,
+                                                   int ntiles, float* __restrict__ part) {
+  constexpr int GS = 80;                     // = 16 mod 32
+  constexpr int AS = CIN == 64 ? 80 : 48;    // = 16 mod 32
+  constexpr int NCT = NET_W * CIN / 16;      // column tiles
+  constexpr int CTW = (NCT + 3) / 4;         // column tiles per wave
+  constexpr int NE = NET_C * NET_W * CIN + NET_C;
+  __shared__ __align__(16) float gt[NET_TILE * GS];
+  __shared__ __align__(16) float at[NET_ROWS * AS];
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  v4f acc[4][CTW];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int c = 0; c < CTW; ++c) acc[rt][c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  float bacc = 0.0f;
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const NetTile T = tiles[ti];
+    const NetSample P = smp[T.sample];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NET_TILE * NET_C; e += 256) {
+      const int p = e / NET_C, c = e % NET_C;
+      const int pos = T.pos0 + p;
+      gt[p * GS + c] = pos < P.s ? g[(P.row0 + pos) * NET_C + c] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < NET_ROWS * CIN; e += 256) {
+      const int rr = e / CIN, c = e % CIN;
+      at[rr * AS + c] = a[(P.row0 + wrap(T.pos0 - NET_HALO + rr, P.s)) * CIN + c];
+    }
+    __syncthreads();
+    if (threadIdx.x < NET_C)
+      for (int p = 0; p < NET_TILE; ++p) bacc += gt[p * GS + threadIdx.x];
+#pragma unroll 4
+    for (int ks = 0; ks < NET_TILE / 4; ++ks) {
+      const int p = ks * 4 + q;
+      float af[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) af[rt] = gt[p * GS + rt * 16 + r16];
+#pragma unroll
+      for (int c = 0; c < CTW; ++c) {
+        const int ct = wave + 4 * c;
+        if (ct >= NCT) continue;
+        const int kidx = ct * 16 + r16;
+        const int t = kidx / CIN, ci = kidx - t * CIN;
+        const float bf = at[(p + t) * AS + ci];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+          acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rt], bf, acc[rt][c], 0, 0, 0);
+      }
+    }
+  }
+  float* pp = part + (int64_t)blockIdx.x * NE;
+#pragma unroll
+  for (int c = 0; c < CTW; ++c) {
+    const int ct = wave + 4 * c;
+    if (ct >= NCT) continue;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int co = rt * 16 + 4 * q + e;
+        pp[(int64_t)co * (NET_W * CIN) + ct * 16 + r16] = acc[rt][c][e];
+      }
+  }
+  if (threadIdx.x < NET_C) pp[NET_C * NET_W * CIN + threadIdx.x] = bacc;
+}
+
+// sum the workgroup partials (fixed order) and scatter into the flat gradient
+__global__ void k_net_wreduce(const float* __restrict__ part, int grid, int layer, NetLayout L,
+                              float* __restrict__ grad) {
+  const int CIN = layer == 0 ? NET_CIN1 : NET_C;
+  const int cin = layer == 0 ? L.cin : NET_C;
+  const int NE = layer == 3 ? NET_W * NET_C + 1 : NET_C * NET_W * CIN + NET_C;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NE) return;
+  float acc = 0.0f;
+  for (int g = 0; g < grid; ++g) acc += part[(int64_t)g * NE + e];
+  if (layer == 3) {
+    if (e == NE - 1) {
+      grad[L.b[3]] = acc;
+    } else {
+      const int t = e / NET_C, c = e % NET_C;
+      grad[L.w[3] + (int64_t)c * NET_W + t] = acc;
+    }
+    return;
+  }
+  const int nw = NET_C * NET_W * CIN;
+  if (e >= nw) {
+    grad[L.b[layer] + (e - nw)] = acc;
+    return;
+  }
+  const int co = e / (NET_W * CIN), kk = e % (NET_W * CIN);
+  const int t = kk / CIN, ci = kk % CIN;
+  if (ci < cin) grad[L.w[layer] + ((int64_t)co * cin + ci) * NET_W + t] = acc;
+}
+
+__global__ void k_net_adam(float* __restrict__ th, const float* __restrict__ g,
+                           float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                           float b1, float b2, float eps, float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void k_net_fill_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ launchers
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void net_fill_int(int* p, int n, int v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_net_fill_int, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}
+void net_pack(const float* theta, const NetLayout& L, const NetWeights& W, hipStream_t st) {
+  const int64_t n = (int64_t)NET_C * NET_W * NET_C;
+  hipLaunchKernelGGL(k_net_pack, dim3(nblk(n, 256)), dim3(256), 0, st, theta, L, W);
+}
+void net_sumsq(const double* v, const NetChunk* chunks, int nchunk, double* part,
+               const int* skip, hipStream_t st) {
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_net_sumsq, dim3(nchunk), dim3(256), 0, st, v, chunks, part, skip);
+}
+void net_sigma_impl(const double* part, const int32_t* chunk0, const NetChunk* ch, int nsys,
+                    double* sigma, double* inv_sigma, const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_sigma, dim3(nblk(nsys, 64)), dim3(64), 0, st, part, chunk0, ch, nsys,
+                     sigma, inv_sigma, skip);
+}
+void net_norm_pairs(const double* chat, const double* cex, const double* inv_sigma,
+                    int64_t len, int npair, float* x, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_norm_pairs, dim3(nblk(len * npair, 256)), dim3(256), 0, st, chat,
+                     cex, inv_sigma, len, npair, x, y);
+}
+void net_feat_f(const float* src, const NetSample* smp, const NetTile* tiles, int ntiles,
+                int64_t row_base, int k, int S, int bf16, void* X0, hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (bf16)
+    hipLaunchKernelGGL((k_net_feat<uint16_t, float>), dim3(ntiles), dim3(64), 0, st, src,
+                       (const double*)nullptr, smp, tiles, row_base, k, S, (uint16_t*)X0,
+                       (const int*)nullptr);
+  else
+    hipLaunchKernelGGL((k_net_feat<float, float>), dim3(ntiles), dim3(64), 0, st, src,
+                       (const double*)nullptr, smp, tiles, row_base, k, S, (float*)X0,
+                       (const int*)nullptr);
+}
+void net_feat_d(const double* src, const double* inv_sigma, const NetSample* smp,
+                const NetTile* tiles, int ntiles, int64_t row_base, int k, int S, int bf16,
+                void* X0, const int* skip, hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (bf16)
+    hipLaunchKernelGGL((k_net_feat<uint16_t, double>), dim3(ntiles), dim3(64), 0, st, src,
+                       inv_sigma, smp, tiles, row_base, k, S, (uint16_t*)X0, skip);
+  else
+    hipLaunchKernelGGL((k_net_feat<float, double>), dim3(ntiles), dim3(64), 0, st, src,
+                       inv_sigma, smp, tiles, row_base, k, S, (float*)X0, skip);
+}
+void net_conv(int bf16, int cin16, int bwd, const void* in, void* out, const void* W,
+              const float* bias, const float* mask, const NetSample* smp, const NetTile* tiles,
+              int ntiles, int64_t row_base, const int* skip, hipStream_t st) {
+  if (ntiles <= 0) return;
+  const dim3 g((unsigned)std::min(ntiles, GRID_CAP)), b(256);
+#define NET_CONV(E, CIN, BWD)                                                               \
+  hipLaunchKernelGGL((k_net_conv<E, CIN, BWD>), g, b, 0, st, (const E*)in, (E*)out,         \
+                     (const E*)W, bias, mask, smp, tiles, ntiles, row_base, skip)
+  if (bf16) {
+    if (cin16)
+      NET_CONV(uint16_t, 16, 0);
+    else
+      NET_CONV(uint16_t, 64, 0);
+  } else if (bwd) {
+    NET_CONV(float, 64, 1);
+  } else if (cin16) {
+    NET_CONV(float, 16, 0);
+  } else {
+    NET_CONV(float, 64, 0);
+  }
+#undef NET_CONV
+}
+void net_out(int bf16, const void* a3, const float* w4, const float* b4, const NetSample* smp,
+             const NetTile* tiles, int ntiles, int64_t row_base, float* outv, double* dst,
+             const double* sigma, const int* off, const int* skip, hipStream_t st) {
+  if (ntiles <= 0) return;
+  const dim3 g(ntiles), b(64);
+  if (dst) {
+    if (bf16)
+      hipLaunchKernelGGL((k_net_out<uint16_t, 1>), g, b, 0, st, (const uint16_t*)a3, w4, b4, smp,
+                         tiles, row_base, outv, dst, sigma, off, skip);
+    else
+      hipLaunchKernelGGL((k_net_out<float, 1>), g, b, 0, st, (const float*)a3, w4, b4, smp,
+                         tiles, row_base, outv, dst, sigma, off, skip);
+  } else {
+    if (bf16)
+      hipLaunchKernelGGL((k_net_out<uint16_t, 0>), g, b, 0, st, (const uint16_t*)a3, w4, b4, smp,
+                         tiles, row_base, outv, dst, sigma, off, skip);
+    else
+      hipLaunchKernelGGL((k_net_out<float, 0>), g, b, 0, st, (const float*)a3, w4, b4, smp,
+                         tiles, row_base, outv, dst, sigma, off, skip);
+  }
+}
+void net_loss(const float* outv, const float* y, const NetSample* smp, const NetTile* tiles,
+              int ntiles, float scale, float* g4, double* lpart, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_loss, dim3(ntiles), dim3(64), 0, st, outv, y, smp, tiles, scale, g4,
+                     lpart);
+}
+void net_out_bwd(const float* g4, const float* w4, const float* a3, float* g3,
+                 const NetSample* smp, const NetTile* tiles, int ntiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_out_bwd, dim3(ntiles), dim3(256), 0, st, g4, w4, a3, g3, smp, tiles);
+}
+void net_wgrad4(const float* g4, const float* a3, const NetSample* smp, const NetTile* tiles,
+                int ntiles, int grid, float* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_wgrad4, dim3(grid), dim3(256), 0, st, g4, a3, smp, tiles, ntiles,
+                     part);
+}
+void net_wgrad(int cin16, const float* g, const float* a, const NetSample* smp,
+               const NetTile* tiles, int ntiles, int grid, float* part, hipStream_t st) {
+  if (cin16)
+    hipLaunchKernelGGL(k_net_wgrad<NET_CIN1>, dim3(grid), dim3(256), 0, st, g, a, smp, tiles,
+                       ntiles, part);
+  else
+    hipLaunchKernelGGL(k_net_wgrad<NET_C>, dim3(grid), dim3(256), 0, st, g, a, smp, tiles,
+                       ntiles, part);
+}
+void net_wreduce(const float* part, int grid, int layer, const NetLayout& L, float* grad,
+                 hipStream_t st) {
+  const int CIN = layer == 0 ? NET_CIN1 : NET_C;
+  const int NE = layer == 3 ? NET_W * NET_C + 1 : NET_C * NET_W * CIN + NET_C;
+  hipLaunchKernelGGL(k_net_wreduce, dim3(nblk(NE, 256)), dim3(256), 0, st, part, grid, layer, L,
+                     grad);
+}
+void net_adam(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,
+              float b1, float b2, float eps, float bc1, float bc2, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_adam, dim3(nblk(n, 256)), dim3(256), 0, st, theta, grad, m, v, n, lr,
+                     b1, b2, eps, bc1, bc2);
+}
+
+}  // namespace svar

@@ -17,7 +17,7 @@ struct KSys {
   int32_t task0, ntask;
 };
 struct KState {     // per system, per cycle
-  int32_t done, iters, status, pad;
+  int32_t done, iters, status, fallback;  // fallback: the learned correction was switched off
   double beta;      // norm of the cycle's initial residual
   double tol_abs;   // stop when the residual estimate is <= tol_abs
   double sigma;     // scale applied to the current candidate u_j
@@ -54,7 +54,7 @@ void kr_dot(const KPlan& p, const KState* stt, const KGlobal* gl, const double* 
 void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const double* part,
                double* sums, int m, int jmax, hipStream_t st);
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
-              int finalize_only, int jmax, hipStream_t st);
+              int finalize_only, int jmax, int* net_off, double drop, hipStream_t st);
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
                hipStream_t st);

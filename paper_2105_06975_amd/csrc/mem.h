@@ -35,6 +35,7 @@ int get_program(svar_handle* h, int op, int nrhs, int prec, Program** out, hipSt
 int run_program(svar_handle* h, const Program& P, double* in, double* out, hipStream_t st,
                 const int* skip);
 int64_t handle_total(const svar_handle* h, int nrhs);
+int64_t state_total(const svar_handle* h, int nrhs);
 void timed_begin(svar_handle* h, int kc, hipStream_t st, hipEvent_t* e0, hipEvent_t* e1);
 void timed_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st);

@@ -834,6 +834,80 @@ static int add_copy_state(Builder& B, VRef in, VRef out, double alpha) {
   }
   return add_vjobs(B, jobs);
 }
+// In-place network correction of the state vector vec (every window and rhs): one sample per
+// (system, block), 64-point tiles, activations in row chunks of bounded size.
+static int add_net(Builder& B, VRef vec) {
+  const int64_t ROW_CHUNK = (int64_t)1 << 24;
+  const int64_t SUM_CHUNK = (int64_t)1 << 16;
+  auto app = std::make_unique<NetApp>();
+  app->base = vec.base;
+  std::vector<NetChunk> ch;
+  std::vector<int32_t> c0;
+  std::vector<NetSample> smp;
+  std::vector<NetTile> tiles;
+  int64_t rows = 0;
+  int sys = 0;
+  app->tile0.push_back(0);
+  app->row0.push_back(0);
+  for (int w = 0; w < (int)B.h->wins.size(); ++w) {
+    const WinDev& W = B.h->wins[w];
+    const int64_t len = (int64_t)W.nb * W.s;
+    const int tps = (W.s + NET_TILE - 1) / NET_TILE;
+    for (int r = 0; r < B.nrhs; ++r, ++sys) {
+      const int64_t off = blk(B.h, w, r, B.nrhs, vec, 0).off;
+      app->spans.push_back({off, off + len});
+      c0.push_back((int)ch.size());
+      for (int64_t e = 0; e < len; e += SUM_CHUNK) {
+        NetChunk c{};
+        c.sys = sys;
+        c.e0 = off + e;
+        c.e1 = off + std::min(len, e + SUM_CHUNK);
+        ch.push_back(c);
+      }
+      // start a new row chunk when this system would overflow the current one
+      if (rows - app->row0.back() + len > ROW_CHUNK && rows > app->row0.back()) {
+        app->max_rows = std::max(app->max_rows, rows - app->row0.back());
+        app->tile0.push_back((int)tiles.size());
+        app->row0.push_back(rows);
+      }
+      for (int i = 0; i < W.nb; ++i) {
+        NetSample S{};
+        S.src = off;
+        S.row0 = rows;
+        S.s = W.s;
+        S.nb = W.nb;
+        S.blk = i;
+        S.sys = sys;
+        const int q = (int)smp.size();
+        smp.push_back(S);
+        for (int t = 0; t < tps; ++t) tiles.push_back(NetTile{q, t * NET_TILE});
+        rows += W.s;
+      }
+    }
+  }
+  c0.push_back((int)ch.size());
+  app->max_rows = std::max(app->max_rows, rows - app->row0.back());
+  app->tile0.push_back((int)tiles.size());
+  app->nsys = sys;
+  app->nchunk = (int)ch.size();
+  app->ntiles = (int)tiles.size();
+  auto& A = B.h->allocs;
+  SVAR_TRY(upload(A, &app->chunks, ch.data(), ch.size(), B.st));
+  SVAR_TRY(upload(A, &app->chunk0, c0.data(), c0.size(), B.st));
+  SVAR_TRY(upload(A, &app->smp, smp.data(), smp.size(), B.st));
+  SVAR_TRY(upload(A, &app->tiles, tiles.data(), tiles.size(), B.st));
+  SVAR_TRY(dalloc(A, &app->part, ch.size()));
+  SVAR_TRY(dalloc(A, &app->sigma, (size_t)sys));
+  SVAR_TRY(dalloc(A, &app->inv_sigma, (size_t)sys));
+  SVAR_HIP(hipStreamSynchronize(B.st));
+  Launch L;
+  L.kind = LK_NET;
+  L.jobs = app.get();
+  L.kclass = SVAR_KCLASS_MODEL;
+  B.P->launches.push_back(L);
+  B.h->netapps.push_back(std::move(app));
+  return SVAR_OK;
+}
 static int add_copy_obs(Builder& B, VRef in, VRef out, bool diag_rhat) {
   std::vector<VJob> jobs;
   for (int w = 0; w < (int)B.h->wins.size(); ++w) {
@@ -1036,6 +1110,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
       // z1 = Lhat^{-T} v3 ; z3 = Lhat^{-1}(v1 - D z1) ; z2 = Rhat^{-1} v2   (§6.2)
       SVAR_TRY(add_copy_state(B, IN_SAD_X, OUT_SAD_ETA, 1.0));
       SVAR_TRY(add_sweep(B, OUT_SAD_ETA, 1, k));
+      if (h->net) SVAR_TRY(add_net(B, OUT_SAD_ETA));
       std::vector<GemmProb> probs;
       add_cov(B, probs, MS_D, dt, OUT_SAD_ETA, OUT_SAD_X, IN_SAD_ETA, true, -1.0, 1.0);
       if (!diag) add_cov(B, probs, MS_RHAT, dt, IN_SAD_NU, OUT_SAD_NU, NONE_REF, false, 1.0, 0.0);
@@ -1049,6 +1124,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
     P.tmp_elems = std::max(P.tmp_elems, total_len(h, nrhs, SP_STATE));
     SVAR_TRY(add_copy_state(B, IN_SAD_X, TMP_ST, 1.0));
     SVAR_TRY(add_sweep(B, TMP_ST, 1, k));
+    if (h->net) SVAR_TRY(add_net(B, TMP_ST));
     std::vector<GemmProb> probs;
     add_cov(B, probs, MS_D, dt, TMP_ST, OUT_SAD_X, NONE_REF, true, 1.0, 0.0);
     add_cov(B, probs, MS_DHAT, dt, IN_SAD_ETA, OUT_SAD_ETA, NONE_REF, false, 1.0, 0.0);
@@ -1060,6 +1136,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
   }
   // component maps on state / obs vectors
   const VRef IS{B_IN, SP_STATE, C_X}, OS{B_OUT, SP_STATE, C_X};
+  if (op == PROG_HARVEST) return add_copy_state(B, IN_SAD_X, OS, 1.0);
   const VRef IO{B_IN, SP_OBS, C_NU}, OO{B_OUT, SP_OBS, C_NU};
   std::vector<GemmProb> probs;
   switch (op) {
@@ -1164,6 +1241,11 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
         spans.push_back({j.out.base, j.out.off, j.out.off + j.len});
         if (j.scale || j.alpha != 0.0) spans.push_back({j.in.base, j.in.off, j.in.off + j.len});
       }
+    } else if (L.kind == LK_NET) {
+      const NetApp* a = (const NetApp*)L.jobs;
+      for (auto& sp : a->spans) spans.push_back({a->base, sp.first, sp.second});
+      if (a->tile0.size() != a->row0.size() + 1 || a->tile0.back() != a->ntiles)
+        return fail("network tiles");
     } else if (L.kind == LK_GEMM) {
       std::vector<GemmProb> G(L.gemm.nprob);
       SVAR_HIP(hipMemcpyAsync(G.data(), L.gemm.probs, G.size() * sizeof(GemmProb),
@@ -1191,6 +1273,8 @@ static void op_spaces(int op, int* in_sp, int* out_sp) {
   *in_sp = *out_sp = SP_STATE;
   if (op == PROG_A || op == PROG_P) {
     *in_sp = *out_sp = SP_SADDLE;
+  } else if (op == PROG_HARVEST) {
+    *in_sp = SP_SADDLE;
   } else if (op == SVAR_OP_R || op == SVAR_OP_RHAT_INV) {
     *in_sp = *out_sp = SP_OBS;
   } else if (op == SVAR_OP_H) {
@@ -1285,6 +1369,11 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
       case LK_GEMM:
         launch_gemm(L.gemm, b, h->gemm_ws, skip, st);
         break;
+      case LK_NET: {
+        const NetApp* a = (const NetApp*)L.jobs;
+        SVAR_TRY(run_net(h, *a, b.p[a->base], skip, st));
+        break;
+      }
     }
     timer_end(h, L.kclass, st, e0, e1);
   }
@@ -1297,6 +1386,7 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
 }
 
 int64_t handle_total(const svar_handle* h, int nrhs) { return total_len(h, nrhs, SP_SADDLE); }
+int64_t state_total(const svar_handle* h, int nrhs) { return total_len(h, nrhs, SP_STATE); }
 
 }  // namespace svar
 
@@ -1363,6 +1453,7 @@ int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void*
   Program* P = nullptr;
   hipStream_t st = (hipStream_t)stream;
   SVAR_TRY(get_program(h, PROG_P, nrhs, PV_F64, &P, st));
+  h->net_off = nullptr;  // outside a solve the correction always applies
   return run_program(h, *P, const_cast<double*>(v), z, st, nullptr);
 }
 
@@ -1390,6 +1481,7 @@ int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const dou
                      ? PV_BF16P
                      : (precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
   SVAR_TRY(get_program(h, PROG_P, nrhs, pv, &P, st));
+  h->net_off = nullptr;
   return run_program(h, *P, const_cast<double*>(v), z, st, nullptr);
 }
 

@@ -3,6 +3,7 @@
 #include <memory>
 
 #include "krylov.h"
+#include "net.h"
 #include "svar_impl.h"
 
 struct svar_handle;
@@ -58,7 +59,7 @@ struct ProgKey {
 };
 
 // internal program codes (beyond the public SVAR_OP_*)
-enum { PROG_A = 100, PROG_P = 101 };
+enum { PROG_A = 100, PROG_P = 101, PROG_HARVEST = 102 };
 // precision variants of a program
 enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2, PV_F32P = 3 };
 
@@ -89,6 +90,12 @@ struct svar_handle {
   double* zeros = nullptr;       // zero-filled, at least the largest matrix order
   int64_t zeros_elems = 0;
   svar::Timer timers[SVAR_KCLASS_COUNT];
+  // learned correction of the Lhat^{-T} sweep
+  svar_net* net = nullptr;
+  const int* net_off = nullptr;   // per-system switch-off flags during a solve (device) or NULL
+  std::vector<std::unique_ptr<svar::NetApp>> netapps;
+  void* net_ws = nullptr;         // activations of the in-place application
+  int64_t net_ws_bytes = 0;
   // Krylov workspace (grown on demand)
   struct Kry {
     int nrhs = -1, m = 0;
@@ -102,6 +109,7 @@ struct svar_handle {
     svar::KGlobal* gl = nullptr;
     svar::KHess* hs = nullptr;
     svar::KGlobal* gl_host = nullptr;  // pinned
+    int* net_off = nullptr;            // per system: learned correction switched off
     std::vector<void*> allocs;
   } kry;
 };

@@ -125,7 +125,7 @@ struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha), j < len
 
 // ------------------------------------------------------------------ launch programs
 enum LaunchKind { LK_MSTEP_BAND, LK_MSTEP_DENSE, LK_MSTEP_L96, LK_GATHER, LK_SCATTER, LK_VEC,
-                  LK_GEMM, LK_SWEEP_BAND };
+                  LK_GEMM, LK_SWEEP_BAND, LK_NET };
 struct GemmPlanDev {
   GemmProb* probs = nullptr;   // device
   GemmTask* tasks = nullptr;   // device

@@ -74,6 +74,7 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   SVAR_TRY(dalloc(A, &K.sysv, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.tol_rel, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.st, (size_t)nsys));
+  SVAR_TRY(dalloc(A, &K.net_off, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.gl, 1));
   // Hessenberg storage per system
   const size_t per = (size_t)(m + 1) * m + m + m + (m + 1) + m + (m + 1) + m;
@@ -115,9 +116,17 @@ int sys_norm2(svar_handle* h, const double* x, std::vector<double>& out, hipStre
 }
 
 // One FGMRES cycle of at most m iterations on A d = r (K.r), accumulating x += d.
+struct Harvest {
+  double* buf = nullptr;
+  int cap = 0, count = 0;
+  int64_t len = 0;
+  const Program* prog = nullptr;
+};
+
 static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
                         const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
-                        hipStream_t st) {
+                        double drop, Harvest& hv, hipStream_t st) {
+  int* net_off = h->net_off ? h->kry.net_off : nullptr;
   auto& K = h->kry;
   SVAR_HIP(hipMemcpyAsync(K.tol_rel, tol_rel.data(), tol_rel.size() * sizeof(double),
                           hipMemcpyHostToDevice, st));
@@ -129,6 +138,10 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
   int j = 0;
   for (; j < m; ++j) {
     if (j > 0) kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
+    if (hv.buf && hv.count < hv.cap) {
+      SVAR_TRY(run_program(h, *hv.prog, K.u, hv.buf + (int64_t)hv.count * hv.len, st, skip));
+      ++hv.count;
+    }
     SVAR_TRY(run_program(h, PP, K.u, K.z, st, skip));
     SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip));
     hipEvent_t e0, e1;
@@ -136,7 +149,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
     timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, j, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, j, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, j, net_off, drop, st);
     timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
     kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, j, st);
     timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
@@ -155,7 +168,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 0, K.part, st);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, m, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, net_off, drop, st);
   }
   kr_solve_y(K.plan, K.st, K.hs, m, st);
   kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ntot, x, m, st);
@@ -194,9 +207,23 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
   SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &Pin, st));
   launch_fill(x, K.ntot, 0.0, st);
+  // learned correction: per-system switch-off flags, cleared for this solve
+  const double drop = o->fallback_drop;
+  h->net_off = nullptr;
+  if (h->net && drop > 0.0) {
+    net_fill_int(K.net_off, nsys, 0, st);
+    h->net_off = K.net_off;
+  }
+  Harvest hv;
+  if (o->harvest && o->harvest_cap > 0) {
+    SVAR_TRY(get_program(h, PROG_HARVEST, nrhs, PV_F64, const_cast<Program**>(&hv.prog), st));
+    hv.buf = o->harvest;
+    hv.cap = o->harvest_cap;
+    hv.len = state_total(h, nrhs);
+  }
   std::vector<double> rhs2;
   SVAR_TRY(sys_norm2(h, rhs, rhs2, st));
-  std::vector<int> iters(nsys, 0), status(nsys, SVAR_OK), cycles(nsys, 0);
+  std::vector<int> iters(nsys, 0), status(nsys, SVAR_OK), cycles(nsys, 0), fallbacks(nsys, 0);
   std::vector<double> est(nsys, 0.0), relres(nsys, 1.0);
   for (int i = 0; i < nsys; ++i) {
     relres[i] = rhs2[i] > 0 ? 1.0 : 0.0;
@@ -236,18 +263,26 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     const int m = std::min(cyc, o->maxit - used);
     if (m < 1) break;
     std::vector<KState> ks;
-    SVAR_TRY(fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, st));
+    {
+      const int rc = fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop, hv, st);
+      if (rc != SVAR_OK) {
+        h->net_off = nullptr;
+        return rc;
+      }
+    }
     int jmax = 0;
     for (int i = 0; i < nsys; ++i) {
       if (tol[i] >= 1.0) continue;
       iters[i] += ks[i].iters;
       cycles[i] += 1;
+      fallbacks[i] = std::max(fallbacks[i], (int)ks[i].fallback);
       est[i] = ks[i].est / std::max(std::sqrt(rhs2[i]), 1e-300);
       if (ks[i].status == SVAR_E_BREAKDOWN) status[i] = SVAR_E_BREAKDOWN;
       jmax = std::max(jmax, ks[i].iters);
     }
     used += std::max(jmax, 1);
   }
+  h->net_off = nullptr;
   // final true residual in float64
   SVAR_TRY(run_program(h, *A64, x, K.r, st, nullptr));
   kr_resid(K.r, rhs, K.ntot, st);
@@ -265,6 +300,7 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     I.relres_true = rr;
     I.relres_est = est[i];
     I.status = status[i];
+    I.fallbacks = fallbacks[i];
     if (I.status == SVAR_OK && !(rr <= o->rtol)) I.status = std::isfinite(rr) ? SVAR_E_NOCONV
                                                                             : SVAR_E_BREAKDOWN;
     const double per_rhs = 1.0 / (double)nsys;

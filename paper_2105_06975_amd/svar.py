@@ -59,17 +59,28 @@ class PrecOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
                 ("restart", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int32)]
+                ("max_outer", C.c_int32), ("fallback_drop", C.c_double),
+                ("harvest", C.c_void_p), ("harvest_cap", C.c_int32), ("pad", C.c_int32)]
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("k", C.c_int32), ("n_bound", C.c_int32), ("precision", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class AdamOpts(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer", C.c_int32), ("status", C.c_int32),
-                ("reserved", C.c_int32), ("relres_true", C.c_double), ("relres_est", C.c_double),
+                ("fallbacks", C.c_int32), ("relres_true", C.c_double), ("relres_est", C.c_double),
                 ("n_M", C.c_int64), ("n_MT", C.c_int64), ("n_D", C.c_int64), ("n_R", C.c_int64),
                 ("n_Rhat_inv", C.c_int64), ("n_Dhat_inv", C.c_int64)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -95,6 +106,17 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svar_set_trajectory.argtypes = [vp, C.c_int32, vp, vp]
     lib.svar_timing_enable.argtypes = [vp, C.c_int32, C.c_int32]
     lib.svar_timing_read.argtypes = [vp, C.c_int32, _dp, C.POINTER(C.c_int64), C.c_int32]
+    lib.svar_net_create.argtypes = [C.POINTER(NetDesc), C.POINTER(vp)]
+    lib.svar_net_destroy.argtypes = [vp]
+    lib.svar_net_nparams.argtypes = [vp]
+    lib.svar_net_nparams.restype = C.c_int64
+    lib.svar_net_set_params.argtypes = [vp, C.POINTER(C.c_float)]
+    lib.svar_net_get_params.argtypes = [vp, C.POINTER(C.c_float)]
+    lib.svar_net_make_pairs.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
+    lib.svar_net_forward.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+    lib.svar_net_train_step.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_int32,
+                                        _ip, C.POINTER(AdamOpts), _dp, C.POINTER(C.c_float), vp]
+    lib.svar_set_net.argtypes = [vp, vp]
     lib.svar_last_error.restype = C.c_char_p
     return lib
 
@@ -273,12 +295,18 @@ class Handle:
 
     def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
               precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
-              check=False):
-        """Solve A x = rhs; returns (x, [info dicts], status)."""
+              check=False, fallback_drop=1e-3, harvest=None):
+        """Solve A x = rhs; returns (x, [info dicts], status).
+
+        harvest: optional float64 device tensor of shape (cap, state_len): receives the state
+        component of the preconditioner input of each FGMRES step.
+        """
         import torch
         x = torch.empty_like(rhs) if x is None else x
+        hv, cap = (None, 0) if harvest is None else (C.c_void_p(harvest.data_ptr()),
+                                                     int(harvest.shape[0]))
         o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
-                      float(inner_rtol), int(max_outer))
+                      float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap, 0)
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
@@ -286,6 +314,11 @@ class Handle:
         if rc not in (OK, E_NOCONV, E_BREAKDOWN) or (check and rc != OK):
             _check(rc)
         return x, [i.as_dict() for i in infos], rc
+
+    def set_net(self, net):
+        """Attach a Net (or None): the preconditioner then corrects its Lhat^{-T} output."""
+        _check(lib().svar_set_net(self._h, None if net is None else net._n))
+        self._net = net
 
     def model_forecast(self, x, w: int = 0, out=None, stream=None):
         """y_0 = x_0, y_i = M_i(x_{i-1}): one observation interval of the model of window w."""
@@ -313,3 +346,77 @@ class Handle:
         _check(lib().svar_timing_read(self._h, KCLASS[kclass], C.byref(ms), C.byref(n),
                                       1 if reset else 0))
         return ms.value, n.value
+
+
+NET_PRECISION = {"FP32": 0, "BF16": 1}
+
+
+class Net:
+    """The sweep-correction network (svar_net_* of include/svar.h)."""
+
+    def __init__(self, k: int, n_bound: int, precision: str = "BF16"):
+        self.k, self.n_bound = int(k), int(n_bound)
+        self.cin = 1 + self.n_bound + self.k
+        d = NetDesc(self.k, self.n_bound, NET_PRECISION[precision], 0)
+        h = C.c_void_p()
+        _check(lib().svar_net_create(C.byref(d), C.byref(h)))
+        self._n = h
+        self.nparams = int(lib().svar_net_nparams(self._n))
+
+    def close(self):
+        if getattr(self, "_n", None):
+            lib().svar_net_destroy(self._n)
+            self._n = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.nparams
+        _check(lib().svar_net_set_params(self._n, _ptr(a, C.c_float)))
+
+    def get_params(self):
+        a = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().svar_net_get_params(self._n, _ptr(a, C.c_float)))
+        return a
+
+    def forward(self, x, precision: str = "FP32", out=None, stream=None):
+        """x: float32 device tensor (npair, nb, s) of normalised sweep outputs."""
+        import torch
+        npair, nb, s = x.shape
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().svar_net_forward(self._n, NET_PRECISION[precision], npair, nb, s, _vp(x),
+                                      _vp(out), _stream(stream)))
+        return out
+
+    def train_step(self, x, y, samples, adam=None, want_loss=True, want_grad=False,
+                   stream=None):
+        """samples: int array (nsample, 2) of (pair, block); adam: dict(lr, beta1, beta2, eps)."""
+        npair, nb, s = x.shape
+        smp = np.ascontiguousarray(samples, dtype=np.int32).reshape(-1)
+        ao = None
+        if adam is not None:
+            ao = AdamOpts(float(adam.get("lr", 1e-3)), float(adam.get("beta1", 0.9)),
+                          float(adam.get("beta2", 0.999)), float(adam.get("eps", 1e-8)))
+        loss = C.c_double(0.0)
+        grad = np.zeros(self.nparams, dtype=np.float32) if want_grad else None
+        _check(lib().svar_net_train_step(
+            self._n, npair, nb, s, _vp(x), _vp(y), smp.size // 2, _ptr(smp, C.c_int32),
+            None if ao is None else C.byref(ao), C.byref(loss) if want_loss else None,
+            None if grad is None else _ptr(grad, C.c_float), _stream(stream)))
+        return (loss.value if want_loss else None), grad
+
+
+def make_pairs(chat, cexact, stream=None):
+    """(chat / sigma, (cexact - chat) / sigma) as float32 tensors; chat: (npair, nb, s) float64."""
+    import torch
+    npair, nb, s = chat.shape
+    x = torch.empty(chat.shape, dtype=torch.float32, device=chat.device)
+    y = torch.empty_like(x)
+    _check(lib().svar_net_make_pairs(npair, nb, s, _vp(chat), _vp(cexact), _vp(x), _vp(y),
+                                     _stream(stream)))
+    return x, y

@@ -345,3 +345,17 @@ def net_init(cin: int, C: int, seed: int = 0, width: int = 5) -> np.ndarray:
         parts.append(rng.uniform(-a, a, size=(co, ci, width)).ravel())
         parts.append(np.zeros(co))
     return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
+def make_c5_like(s: int, N: int, *, seed: int = 0, nrhs: int = 1) -> Window:
+    """The learned-correction workload's recipe (advection-diffusion, SOAR B and R with the
+    config-5 lengths, p = s/2 random observation points) at a chosen size."""
+    cfg = dict(CONFIGS["c5"])
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 7]))
+    idx = obs_indices(s, "random", rng, p=s // 2)
+    win = make_advdiff_window(s, N, idx, r_kind=cfg["r_kind"], r_len=cfg["r_len"],
+                              r_var=cfg["r_var"], b_len=cfg["b_len"], b_var=cfg["b_var"],
+                              q_scale=cfg["q_scale"], courant=cfg["courant"], nu=cfg["nu"],
+                              nrhs=nrhs, seed=seed)
+    win.meta["config"] = f"c5-like s={s} N={N}"
+    return win

@@ -46,9 +46,9 @@ def test_binding_struct_sizes_match_header_layout():
 #include <stdio.h>
 #include "svar.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(svar_model_desc), sizeof(svar_window_desc),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(svar_model_desc), sizeof(svar_window_desc),
          sizeof(svar_prec_opts), sizeof(svar_solve_opts), sizeof(svar_solve_info),
-         (size_t)0);
+         sizeof(svar_net_desc), sizeof(svar_adam_opts));
   return 0;
 }
 '''
@@ -58,9 +58,10 @@ int main(void) {
         open(c, "w").write(src)
         subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         sizes = [int(x) for x in subprocess.check_output([exe]).split()]
-    assert sizes[:5] == [ctypes.sizeof(sv.ModelDesc), ctypes.sizeof(sv.WindowDesc),
-                         ctypes.sizeof(sv.PrecOpts), ctypes.sizeof(sv.SolveOpts),
-                         ctypes.sizeof(sv.SolveInfo)]
+    assert sizes == [ctypes.sizeof(sv.ModelDesc), ctypes.sizeof(sv.WindowDesc),
+                     ctypes.sizeof(sv.PrecOpts), ctypes.sizeof(sv.SolveOpts),
+                     ctypes.sizeof(sv.SolveInfo), ctypes.sizeof(sv.NetDesc),
+                     ctypes.sizeof(sv.AdamOpts)]
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libsvar.so not built")
@@ -73,4 +74,11 @@ def test_errors_without_device_calls():
     assert rc == sv.E_INVAL
     assert b"window" in lib.svar_last_error()
     assert lib.svar_system_size(None, 0) == -1
+    # network argument checks (no device call before validation)
+    n = ctypes.c_void_p()
+    d = sv.NetDesc(3, 20, 1, 0)  # 1 + 20 + 3 > 16 input channels
+    assert lib.svar_net_create(ctypes.byref(d), ctypes.byref(n)) == sv.E_INVAL
+    assert b"n_bound" in lib.svar_last_error()
+    assert lib.svar_net_nparams(None) == -1
+    assert lib.svar_set_net(None, None) == sv.E_INVAL
     assert lib.svar_destroy(None) == sv.OK
