@@ -132,10 +132,10 @@ typedef struct svar_solve_opts {
   int32_t precision;  /* SVAR_PRECISION_*                                                   */
   double inner_rtol;  /* mixed precision: relative tolerance of each inner cycle            */
   int32_t max_outer;  /* refinement / restart cycles allowed (>= 1)                         */
-  /* learned path (a network attached with svar_set_net): after every FGMRES step the
-     least-squares residual must fall below (1 - fallback_drop) times the previous one; the
-     first time it does not, the system's later preconditioner applications skip the network
-     (the plain P).  <= 0 disables the check. */
+  /* learned path (a network attached with svar_set_net): a FGMRES step fails when the
+     least-squares residual does not fall below (1 - fallback_drop) times the previous one;
+     after fallback_patience failing steps in a row the system's later preconditioner
+     applications skip the network (the plain P).  fallback_drop <= 0 disables the check. */
   double fallback_drop;
   /* training-pair harvest: when non-NULL, the state component v3 of the preconditioner input
      of each FGMRES step j < harvest_cap is copied to harvest + j * state_len (device memory,
@@ -143,7 +143,7 @@ typedef struct svar_solve_opts {
      system has converged leave their slots untouched. */
   double* harvest;
   int32_t harvest_cap;
-  int32_t pad;
+  int32_t fallback_patience;  /* >= 1 (values below 1 count as 1)                           */
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */

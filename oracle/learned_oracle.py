@@ -201,14 +201,15 @@ def apply_PD_inv_learned(orc, theta, v, C: int, S: int, net_fn=None):
 
 
 def fgmres_with_fallback(apply_A, apply_P_learned, apply_P_plain, rhs, rtol: float,
-                         maxit: int, drop: float = 1e-3):
+                         maxit: int, drop: float = 1e-3, patience: int = 3):
     """Flexible GMRES whose preconditioner falls back from the learned to the plain one.
 
-    After step j the least-squares residual must be below (1 - drop) times the one after
-    step j-1; the first time it is not, every preconditioner application from step j+2 on is
-    the plain one (step j+1's has already been made when the residual of step j is known in
-    a pipelined implementation).  Modified Gram-Schmidt, Givens rotations, x0 = 0.
-    Returns (x, iters, hist, fallbacks).
+    Step j fails when its least-squares residual is not below (1 - drop) times the one after
+    step j-1.  After `patience` failing steps in a row (the last being step j), every
+    preconditioner application from step j+2 on is the plain one (step j+1's has already
+    been made when the residual of step j is known in a pipelined implementation).  Plain
+    FGMRES itself has isolated steps of almost no progress, hence the patience.  Modified
+    Gram-Schmidt, Givens rotations, x0 = 0.  Returns (x, iters, hist, fallbacks).
     """
     beta = float(np.linalg.norm(rhs))
     n = rhs.size
@@ -225,6 +226,7 @@ def fgmres_with_fallback(apply_A, apply_P_learned, apply_P_plain, rhs, rtol: flo
     iters = maxit
     plain_from = None
     fallbacks = 0
+    stall = 0
     prev = beta
     for j in range(maxit):
         use_plain = plain_from is not None and j >= plain_from
@@ -247,9 +249,11 @@ def fgmres_with_fallback(apply_A, apply_P_learned, apply_P_plain, rhs, rtol: flo
         g[j] = cs[j] * g[j]
         res = abs(g[j + 1])
         hist.append(res / beta)
-        if plain_from is None and not (res < (1.0 - drop) * prev):
-            plain_from = j + 2
-            fallbacks += 1
+        if plain_from is None:
+            stall = 0 if res < (1.0 - drop) * prev else stall + 1
+            if stall >= max(1, patience):
+                plain_from = j + 2
+                fallbacks += 1
         prev = res
         if res <= rtol * beta or hnext == 0.0:
             iters = j + 1

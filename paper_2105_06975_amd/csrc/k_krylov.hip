@@ -111,6 +111,8 @@ __global__ __launch_bounds__(NT) void k_fg_start(const KTask* __restrict__ tasks
     s0.status = isfinite(nrm) ? 0 : SVAR_E_BREAKDOWN;
     if (!isfinite(nrm)) s0.done = 1;
     s0.fallback = 0;
+    s0.stall = 0;
+    s0.pad2 = 0;
     s0.beta = nrm;
     s0.tol_abs = tol_rel[t.sys] * nrm;
     s0.sigma = sig;
@@ -287,7 +289,8 @@ __global__ __launch_bounds__(NT) void k_fg_reduce(const KSys* __restrict__ sys,
 __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGlobal* __restrict__ gl,
                                                  const double* __restrict__ sums,
                                                  KHess* __restrict__ hs, int m, int finalize_only,
-                                                 int* __restrict__ net_off, double drop) {
+                                                 int* __restrict__ net_off, double drop,
+                                                 int patience) {
   __shared__ double red[NT / 64];
   __shared__ double col[1];
   extern __shared__ double dyn[];  // 3 j + 1 doubles
@@ -351,12 +354,16 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
       Hh.g[j - 1] = c * gj;
       const double prev = S.est;
       S.est = fabs(Hh.g[j]);
-      // learned preconditioner: a step that does not reduce the least-squares residual by the
-      // factor (1 - drop) switches the correction off for this system from the next
-      // application on
-      if (net_off && drop > 0.0 && !net_off[blockIdx.x] && !(S.est < (1.0 - drop) * prev)) {
-        net_off[blockIdx.x] = 1;
-        S.fallback = 1;
+      // learned preconditioner: `patience` steps in a row that do not reduce the least-
+      // squares residual by the factor (1 - drop) switch the correction off for this system
+      // from the next application on
+      if (net_off && drop > 0.0 && !net_off[blockIdx.x]) {
+        if (S.est < (1.0 - drop) * prev) {
+          S.stall = 0;
+        } else if (++S.stall >= patience) {
+          net_off[blockIdx.x] = 1;
+          S.fallback = 1;
+        }
       }
       S.iters = j;
       bool fin = isfinite(S.est) && isfinite(rho);
@@ -563,9 +570,11 @@ void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const doubl
                      m);
 }
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
-              int finalize_only, int jmax, int* net_off, double drop, hipStream_t st) {
+              int finalize_only, int jmax, int* net_off, double drop, int patience,
+              hipStream_t st) {
   hipLaunchKernelGGL(k_fg_small, dim3(p.nsys), dim3(NT), (size_t)(3 * jmax + 4) * sizeof(double),
-                     st, stt, gl, sums, hs, m, finalize_only, net_off, drop);
+                     st, stt, gl, sums, hs, m, finalize_only, net_off, drop,
+                     patience < 1 ? 1 : patience);
 }
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,

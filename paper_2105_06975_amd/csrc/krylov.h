@@ -23,6 +23,8 @@ struct KState {     // per system, per cycle
   double sigma;     // scale applied to the current candidate u_j
   double nu;        // norm of the re-orthogonalised candidate
   double est;       // latest residual estimate
+  int32_t stall;    // consecutive steps that failed the learned path's decrease test
+  int32_t pad2;
 };
 struct KGlobal {
   int32_t j, remaining, all_done, pad;
@@ -54,7 +56,8 @@ void kr_dot(const KPlan& p, const KState* stt, const KGlobal* gl, const double* 
 void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const double* part,
                double* sums, int m, int jmax, hipStream_t st);
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
-              int finalize_only, int jmax, int* net_off, double drop, hipStream_t st);
+              int finalize_only, int jmax, int* net_off, double drop, int patience,
+              hipStream_t st);
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
                hipStream_t st);

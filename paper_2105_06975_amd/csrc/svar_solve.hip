@@ -125,7 +125,7 @@ struct Harvest {
 
 static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
                         const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
-                        double drop, Harvest& hv, hipStream_t st) {
+                        double drop, int patience, Harvest& hv, hipStream_t st) {
   int* net_off = h->net_off ? h->kry.net_off : nullptr;
   auto& K = h->kry;
   SVAR_HIP(hipMemcpyAsync(K.tol_rel, tol_rel.data(), tol_rel.size() * sizeof(double),
@@ -149,7 +149,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
     timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, j, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, j, net_off, drop, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, j, net_off, drop, patience, st);
     timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
     kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, j, st);
     timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
@@ -168,7 +168,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 0, K.part, st);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, m, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, net_off, drop, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, net_off, drop, patience, st);
   }
   kr_solve_y(K.plan, K.st, K.hs, m, st);
   kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ntot, x, m, st);
@@ -264,7 +264,8 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     if (m < 1) break;
     std::vector<KState> ks;
     {
-      const int rc = fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop, hv, st);
+      const int rc = fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
+                                  o->fallback_patience, hv, st);
       if (rc != SVAR_OK) {
         h->net_off = nullptr;
         return rc;

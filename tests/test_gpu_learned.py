@@ -233,6 +233,8 @@ def test_training_gain_on_held_out_windows(sv):
         xp, ip, rcp = h.solve(rhs, rtol=1e-6, maxit=600)
         h.set_net(net)
         xl, il, rcl = h.solve(rhs, rtol=1e-6, maxit=600)
+        _, il0, _ = h.solve(rhs, rtol=1e-6, maxit=600, fallback_drop=0.0)
+        print(f"seed {sd}: learned without fallback {il0[0]['iters']} its")
         assert rcp == sv.OK and rcl == sv.OK
         ep, el = rel(host(xp), x_ref), rel(host(xl), x_ref)
         print(f"seed {sd}: plain {ip[0]['iters']} its (err {ep:.1e}), learned {il[0]['iters']}"

@@ -210,3 +210,23 @@ def test_fallback_rescues_a_useless_learned_preconditioner():
                                                   rhs, 1e-10, 400)
     x3, it3, hist3 = so.fgmres(orc.apply_A, orc.apply_PI_inv, rhs, 1e-10, 400)
     assert it2 == it3 and np.allclose(hist2, hist3, rtol=1e-10, atol=0)
+
+
+def test_fallback_patience_ignores_isolated_plateaus():
+    # a preconditioner that is useless on every third call only: each useless step is an
+    # isolated plateau, so patience 3 never falls back while patience 1 does at once
+    win, orc = _small()
+    rhs = wl.random_vectors(win, 1, seed=16)[0]
+    rhs[-win.nb * win.s:] = 0.0
+    calls = {"n": 0}
+
+    def flaky(v):
+        calls["n"] += 1
+        return orc.apply_PI_inv(v) if calls["n"] % 3 else np.zeros_like(v) + 1e-14 * v
+
+    _, _, _, fb3 = lo.fgmres_with_fallback(orc.apply_A, flaky, orc.apply_PI_inv, rhs, 1e-8, 400,
+                                           patience=3)
+    calls["n"] = 0
+    _, _, _, fb1 = lo.fgmres_with_fallback(orc.apply_A, flaky, orc.apply_PI_inv, rhs, 1e-8, 400,
+                                           patience=1)
+    assert fb3 == 0 and fb1 == 1
