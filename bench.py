@@ -1,17 +1,21 @@
 """Benchmark: preconditioned saddle-point solves per second on one MI355X.
 
-Workload (one "step" = one complete solve of the hot path): a linearised weak-constraint
-4D-Var window shaped like the paper's experiments, s = 4096 state variables, N = 64 (65 time
-blocks), p_i = 2048 random observation points, dense SOAR B (length 0.1), Q_i = 0.1 B,
-dense SOAR R_i (length 0.05), implicit advection-diffusion model; right-hand side (0; d; 0)
-with synthetic innovations.  Inexact-constraint preconditioner P_I with L_M(3) and the
-ridge-regression Rhat, flexible GMRES to a 1e-6 true relative residual, x0 = 0.
+Workload: a linearised weak-constraint 4D-Var window shaped like the paper's experiments,
+s = 4096 state variables, N = 64 (65 time blocks), p_i = 2048 random observation points,
+dense SOAR B (length 0.1), Q_i = 0.1 B, dense SOAR R_i (length 0.05), implicit
+advection-diffusion model; 8 right-hand sides (0; d_r; 0) whose innovations share the signal
+and redraw the observation noise (perturbed observations).  Inexact-constraint
+preconditioner P_I with L_M(3) and the ridge-regression Rhat, flexible GMRES to a 1e-6 true
+relative residual, x0 = 0, no restart.
 
-Paths timed: the plain float64 solve (the reference path) and the mixed-precision one
-(float64 refinement, float32 inner operator, bfloat16 preconditioner products).  The JSON
-line reports the plain float64 path as `value` and the others alongside.
+Two paths on the same window, right-hand sides, P, k, Rhat and tolerance:
+  * plain FP64: one right-hand side per solve (the reference path);
+  * learned + batched (`value`): all 8 right-hand sides in one call, the network
+    correction of the Lhat^{-T} sweep (trained beforehand, untimed, on pairs harvested from
+    plain solves of other seeds of the same workload), float32 covariance products in P.
+One step = one batched solve of the 8 right-hand sides.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--plain-only]
 """
 from __future__ import annotations
 
@@ -50,6 +54,19 @@ def parse():
                          "observation right-hand sides in one call, against one-at-a-time "
                          "solves of the first two windows (one JSON object)")
     ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--precision", default="FP64_F32P",
+                    help="precision of the learned + batched path")
+    ap.add_argument("--train-windows", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="time only the plain FP64 path (no training)")
+    ap.add_argument("--patience", type=int, default=10,
+                    help="failing FGMRES steps in a row before the network is switched off")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the benchmark, copy a 1 GiB float64 buffer three times (the "
+                         "reference kernel for scaling HBM byte counters)")
     ap.add_argument("--cpu-iters", type=int, nargs=2, default=(3, 9),
                     help="oracle iteration counts of the two timed samples")
     return ap.parse_args()
@@ -96,108 +113,157 @@ def main():
         print(json.dumps(bench_c4(args)), flush=True)
         return
     t0 = time.time()
-    win = wl.make_config_window("c2", seed=0)
-    log(f"workload built in {time.time() - t0:.1f}s: n={win.n}")
+    win = wl.make_config_window("c2", seed=0, nrhs=args.nrhs)
+    log(f"workload built in {time.time() - t0:.1f}s: n={win.n}, nrhs={args.nrhs}")
     t0 = time.time()
     h = svar.Handle([win], svar.Precond(type="PI", k=args.k, rhat="RR"))
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log(f"handle set-up {setup_s:.2f}s")
-    rhs = torch.from_numpy(win.rhs[0]).to(dev)
+    R = args.nrhs
+    rhs_all = torch.from_numpy(np.ascontiguousarray(win.rhs[:R]).reshape(-1)).to(dev)
+    rhs1 = [rhs_all[r * win.n:(r + 1) * win.n] for r in range(R)]
 
-    def run(precision, steps, warmup, timing=False):
-        kw = dict(rtol=args.rtol, maxit=1000)
-        if precision == "FP64_F32P":
-            kw.update(precision=precision)
-        elif precision != "FP64":
-            # one unrestarted inner cycle to the target (the float32 operator error is far
-            # below it), then the float64 residual check and, if needed, a correction cycle
-            kw.update(precision=precision, restart=0, inner_rtol=args.rtol, max_outer=4)
-        infos = None
+    if args.sweep:
+        print(json.dumps(sweep(win, rhs1[0], args)), flush=True)
+        return
+
+    def timed(fn, steps, warmup, classes=()):
         for _ in range(warmup):
-            x, infos, rc = h.solve(rhs, **kw)
-            log(f"  warmup {precision}: rc={rc} iters={infos[0]['iters']} "
-                f"relres={infos[0]['relres_true']:.2e}")
-        if timing:
-            for kc in ("GEMM", "ORTHO"):
-                h.timing_enable(kc, True)
-                h.timing_read(kc, reset=True)
+            fn(0)
+        for kc in classes:
+            h.timing_enable(kc, True)
+            h.timing_read(kc, reset=True)
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        for i in range(steps):
-            x, infos, rc = h.solve(rhs, **kw)
-            assert rc == svar.OK, infos
+        outs = [fn(i) for i in range(steps)]
         torch.cuda.synchronize()
         el = time.perf_counter() - ts
         tm = {}
-        if timing:
-            for kc in ("GEMM", "ORTHO"):
-                tm[kc] = h.timing_read(kc, reset=True)
-                h.timing_enable(kc, False)
-        log(f"  {precision}: {steps} solves in {el:.3f}s, iters={infos[0]['iters']}, "
-            f"relres={infos[0]['relres_true']:.2e}")
-        return el, infos[0], tm, x
+        for kc in classes:
+            tm[kc] = h.timing_read(kc, reset=True)
+            h.timing_enable(kc, False)
+        return el, outs, tm
 
-    if args.sweep:
-        print(json.dumps(sweep(win, rhs, args)), flush=True)
-        return
-    el64, info64, tm, x64 = run("FP64", args.steps, args.warmup, timing=True)
-    sps = args.steps / el64
-    it = int(info64["iters"])
+    # ---- plain FP64, one right-hand side per solve (reference path)
+    xs_plain = {}
+
+    def plain(i):
+        r = i % R
+        x, info, rc = h.solve(rhs1[r], rtol=args.rtol, maxit=1000)
+        assert rc == svar.OK, info
+        xs_plain[r] = x
+        return info[0]
+    nplain = max(args.steps, 2)
+    el_p, infos_p, tm_p = timed(plain, nplain, args.warmup, ("GEMM", "ORTHO", "MODEL"))
+    sps_plain = nplain / el_p
+    it_plain = float(np.mean([i["iters"] for i in infos_p]))
+    log(f"plain FP64: {sps_plain:.3f} solves/s, iters {it_plain:.1f}")
     res = {
         "metric": "saddle solves/sec to 1e-6 rel residual; learned+batched vs plain FP64, 1 GPU",
-        "value": sps,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * el64 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c2 single window: s=4096, N=64, p_i=2048 random obs, SOAR B "
-                               "l=0.1, Q=0.1B, SOAR R l=0.05, implicit advection-diffusion; "
-                               f"P_I with L_M({args.k}) and R_RR; FGMRES rtol {args.rtol}",
-                   "path": "plain FP64 FGMRES (no restart)", "n_unknowns": int(win.n)},
-        "iters": it,
-        "relres_true": info64["relres_true"],
+        "config": {"workload": "c2 window with 8 perturbed-observation rhs: s=4096, N=64, "
+                               "p_i=2048 random obs, SOAR B l=0.1, Q=0.1B, SOAR R l=0.05, "
+                               "implicit advection-diffusion; P_I with L_M(%d) and R_RR; FGMRES "
+                               "rtol %g, no restart" % (args.k, args.rtol),
+                   "n_unknowns_per_rhs": int(win.n), "nrhs": R},
+        "plain_fp64": {"value": sps_plain, "iters": it_plain, "ms_per_solve": 1e3 / sps_plain,
+                       "path": "one rhs per FGMRES solve, every operator float64"},
         "setup_s": setup_s,
     }
+    if args.plain_only:
+        tm, it_main, ntot_main, steps_main, el_main = tm_p, it_plain, win.n, nplain, el_p
+        res.update(value=sps_plain, ms_per_step=1e3 * el_p / nplain)
+        res["config"]["path"] = "plain FP64 only"
+    else:
+        # ---- training (untimed): pairs from plain solves of other seeds of the workload
+        from paper_2105_06975_amd import learned
+        t0 = time.time()
+        tw = [wl.make_config_window("c2", seed=101 + i) for i in range(args.train_windows)]
+        chat, cex = learned.harvest_pairs(tw, args.k, rtol=args.rtol, maxit=1000,
+                                          cap=args.harvest)
+        del tw
+        x, y = svar.make_pairs(chat, cex)
+        del chat, cex
+        t_h = time.time() - t0
+        net = svar.Net(args.k, 2, "BF16")
+        net.set_params(wl.net_init(net.cin, 64, seed=0))
+        t0 = time.time()
+        hist = learned.train(net, x, y, epochs=args.epochs, batch=64, lr=1e-3, seed=0, log=log)
+        torch.cuda.synchronize()
+        t_t = time.time() - t0
+        npairs = int(x.shape[0])
+        del x, y
+        torch.cuda.empty_cache()
+        log(f"training: {npairs} pairs harvested in {t_h:.1f}s, {args.epochs} epochs in "
+            f"{t_t:.1f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+        h.set_net(net)
+        # ---- learned + batched
+        kw = dict(rtol=args.rtol, maxit=700, fallback_patience=args.patience)
+        if args.precision != "FP64":
+            kw["precision"] = args.precision
+
+        def batched(i):
+            x, infos, rc = h.solve(rhs_all, R, **kw)
+            assert rc == svar.OK, infos
+            return x, infos
+        el_b, outs, tm = timed(batched, args.steps, args.warmup, ("GEMM", "ORTHO", "MODEL"))
+        xb, infos_b = outs[-1]
+        sps = R * args.steps / el_b
+        it_b = float(np.mean([i["iters"] for i in infos_b]))
+        # agreement with the plain float64 solutions (both at the same true residual)
+        errs = []
+        for r, xp in xs_plain.items():
+            a = xb[r * win.n:(r + 1) * win.n]
+            errs.append(float(torch.linalg.norm(a - xp) / torch.linalg.norm(xp)))
+        log(f"learned+batched: {sps:.3f} solves/s, iters {it_b:.1f}, "
+            f"x vs plain {max(errs):.1e}")
+        res.update(value=sps, ms_per_step=1e3 * el_b / args.steps)
+        res["config"]["path"] = ("learned + batched: 8 rhs per call, network correction of "
+                                 "the Lhat^-T sweep (bf16 MFMA), %s" % args.precision)
+        res["speedup_vs_plain_fp64"] = sps / sps_plain
+        res["learned_batched"] = {
+            "iters_mean": it_b, "fallbacks": int(sum(i["fallbacks"] for i in infos_b)),
+            "relres_true_max": float(max(i["relres_true"] for i in infos_b)),
+            "x_rel_diff_vs_plain_fp64_max": max(errs),
+            "training": {"pairs": npairs, "windows": args.train_windows, "epochs": args.epochs,
+                         "harvest_s": t_h, "train_s": t_t, "loss_first": hist[0],
+                         "loss_last": hist[-1]}}
+        tm, it_main, ntot_main, steps_main, el_main = tm, it_b, win.n * R, args.steps, el_b
+    res["iters"] = it_main
     # roofline of the dominant kernel class (by measured time in the timed region)
     gms, gl = tm["GEMM"]
     oms, ol = tm["ORTHO"]
-    applies_a64 = 2  # refinement check after the cycle + final true residual
-    if gms >= oms:
-        flops = gemm_flops(win, it, applies_a64) * args.steps
-        ach = flops / (gms * 1e-3) / 1e12
-        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm_f64 (covariance products)",
-                           "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
-                           "launches": gl, "avg_ms": gms / max(gl, 1)}
-    else:
-        byts = ortho_bytes(win.n, it) * args.steps
+    mms, ml = tm["MODEL"]
+    res["kernel_time_ms"] = {"gemm": gms, "gemm_launches": gl, "ortho": oms,
+                             "ortho_launches": ol, "model_and_net": mms, "model_launches": ml,
+                             "timed_region_ms": 1e3 * el_main}
+    if oms >= gms:
+        byts = ortho_bytes(ntot_main, int(round(it_main))) * steps_main
         ach = byts / (oms * 1e-3) / 1e9
         res["roofline"] = {"bound": "hbm", "kernel": "k_fg_dot + k_fg_update (Gram-Schmidt)",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
                            "launches": ol, "avg_ms": oms / max(ol, 1)}
-    res["kernel_time_ms"] = {"gemm": gms, "gemm_launches": gl, "ortho": oms,
-                             "ortho_launches": ol}
-    if not args.no_mixed:
-        for prec in ("FP64_F32P",):
-            try:
-                elm, infom, _, xm = run(prec, args.steps, args.warmup)
-                res[prec.lower()] = {"value": args.steps / elm, "iters": infom["iters"],
-                                     "outer": infom["outer"],
-                                     "relres_true": infom["relres_true"],
-                                     "speedup_vs_fp64": el64 / elm}
-            except Exception as e:  # reported, not fatal for the FP64 line
-                res[prec.lower()] = {"error": str(e)[:200]}
+    else:
+        flops = gemm_flops(win, int(round(it_main)), 2) * steps_main * (R if ntot_main > win.n
+                                                                          else 1)
+        ach = flops / (gms * 1e-3) / 1e12
+        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm (covariance products)",
+                           "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                           "launches": gl, "avg_ms": gms / max(gl, 1)}
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(win, args, it)
+        res["cpu_baseline"] = cpu_baseline(win, args, int(round(it_plain)))
     print(json.dumps(res), flush=True)
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
 
 def bench_c3(args):

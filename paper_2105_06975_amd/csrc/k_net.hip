@@ -156,10 +156,12 @@ __global__ __launch_bounds__(64) void k_net_feat(const SRC* __restrict__ src,
                                                  const NetTile* __restrict__ tiles,
                                                  int64_t row_base, int k, int S,
                                                  E* __restrict__ X0,
-                                                 const int* __restrict__ skip) {
+                                                 const int* __restrict__ skip,
+                                                 const int* __restrict__ off) {
   if (skip && *skip) return;
   const NetTile T = tiles[blockIdx.x];
   const NetSample P = smp[T.sample];
+  if (off && off[P.sys]) return;  // switched off: the correction is not applied
   const int pos = T.pos0 + threadIdx.x;
   if (pos >= P.s) return;
   const double isg = inv_sigma ? inv_sigma[P.sys] : 1.0;
@@ -190,7 +192,8 @@ __global__ __launch_bounds__(256) void k_net_conv(const E* __restrict__ in, E* _
                                                   const NetSample* __restrict__ smp,
                                                   const NetTile* __restrict__ tiles, int ntiles,
                                                   int64_t row_base,
-                                                  const int* __restrict__ skip) {
+                                                  const int* __restrict__ skip,
+                                                  const int* __restrict__ off) {
   typedef NetMma<E> MM;
   constexpr int EPL = MM::KS / 4;            // operand elements per lane
   constexpr int NKS = NET_W * CIN / MM::KS;  // contraction steps
@@ -209,6 +212,7 @@ __global__ __launch_bounds__(256) void k_net_conv(const E* __restrict__ in, E* _
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const NetTile T = tiles[ti];
     const NetSample P = smp[T.sample];
+    if (off && off[P.sys]) continue;  // uniform over the workgroup
     const int64_t rb = P.row0 - row_base;
     __syncthreads();
     for (int c = threadIdx.x; c < NET_ROWS * CPR; c += 256) {
@@ -260,10 +264,11 @@ __global__ __launch_bounds__(64) void k_net_out(const E* __restrict__ a3,
                                                 const int* __restrict__ skip) {
   __shared__ float w[NET_W * NET_C];
   if (skip && *skip) return;
-  for (int i = threadIdx.x; i < NET_W * NET_C; i += 64) w[i] = w4[i];
-  __syncthreads();
   const NetTile T = tiles[blockIdx.x];
   const NetSample P = smp[T.sample];
+  if (off && off[P.sys]) return;
+  for (int i = threadIdx.x; i < NET_W * NET_C; i += 64) w[i] = w4[i];
+  __syncthreads();
   const int pos = T.pos0 + threadIdx.x;
   if (pos >= P.s) return;
   const int64_t rb = P.row0 - row_base;
@@ -275,7 +280,6 @@ __global__ __launch_bounds__(64) void k_net_out(const E* __restrict__ a3,
     for (int c = 0; c < NET_C; ++c) acc += wt[c] * to_f<E>(row[c]);
   }
   if (APPLY) {
-    if (off && off[P.sys]) return;
     dst[P.src + (int64_t)P.blk * P.s + pos] += sigma[P.sys] * (double)acc;
   } else {
     outv[rb + pos] = acc;
@@ -513,31 +517,31 @@ void net_feat_f(const float* src, const NetSample* smp, const NetTile* tiles, in
   if (bf16)
     hipLaunchKernelGGL((k_net_feat<uint16_t, float>), dim3(ntiles), dim3(64), 0, st, src,
                        (const double*)nullptr, smp, tiles, row_base, k, S, (uint16_t*)X0,
-                       (const int*)nullptr);
+                       (const int*)nullptr, (const int*)nullptr);
   else
     hipLaunchKernelGGL((k_net_feat<float, float>), dim3(ntiles), dim3(64), 0, st, src,
                        (const double*)nullptr, smp, tiles, row_base, k, S, (float*)X0,
-                       (const int*)nullptr);
+                       (const int*)nullptr, (const int*)nullptr);
 }
 void net_feat_d(const double* src, const double* inv_sigma, const NetSample* smp,
                 const NetTile* tiles, int ntiles, int64_t row_base, int k, int S, int bf16,
-                void* X0, const int* skip, hipStream_t st) {
+                void* X0, const int* skip, const int* off, hipStream_t st) {
   if (ntiles <= 0) return;
   if (bf16)
     hipLaunchKernelGGL((k_net_feat<uint16_t, double>), dim3(ntiles), dim3(64), 0, st, src,
-                       inv_sigma, smp, tiles, row_base, k, S, (uint16_t*)X0, skip);
+                       inv_sigma, smp, tiles, row_base, k, S, (uint16_t*)X0, skip, off);
   else
     hipLaunchKernelGGL((k_net_feat<float, double>), dim3(ntiles), dim3(64), 0, st, src,
-                       inv_sigma, smp, tiles, row_base, k, S, (float*)X0, skip);
+                       inv_sigma, smp, tiles, row_base, k, S, (float*)X0, skip, off);
 }
 void net_conv(int bf16, int cin16, int bwd, const void* in, void* out, const void* W,
               const float* bias, const float* mask, const NetSample* smp, const NetTile* tiles,
-              int ntiles, int64_t row_base, const int* skip, hipStream_t st) {
+              int ntiles, int64_t row_base, const int* skip, const int* off, hipStream_t st) {
   if (ntiles <= 0) return;
   const dim3 g((unsigned)std::min(ntiles, GRID_CAP)), b(256);
 #define NET_CONV(E, CIN, BWD)                                                               \
   hipLaunchKernelGGL((k_net_conv<E, CIN, BWD>), g, b, 0, st, (const E*)in, (E*)out,         \
-                     (const E*)W, bias, mask, smp, tiles, ntiles, row_base, skip)
+                     (const E*)W, bias, mask, smp, tiles, ntiles, row_base, skip, off)
   if (bf16) {
     if (cin16)
       NET_CONV(uint16_t, 16, 0);

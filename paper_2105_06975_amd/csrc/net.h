@@ -80,11 +80,12 @@ void net_feat_f(const float* src, const NetSample* smp, const NetTile* tiles, in
                 int64_t row_base, int k, int S, int bf16, void* X0, hipStream_t st);
 void net_feat_d(const double* src, const double* inv_sigma, const NetSample* smp,
                 const NetTile* tiles, int ntiles, int64_t row_base, int k, int S, int bf16,
-                void* X0, const int* skip, hipStream_t st);
-// hidden layer: out = relu(conv(in) + b) (fwd) or conv(in) * (mask > 0) (bwd, float only)
+                void* X0, const int* skip, const int* off, hipStream_t st);
+// hidden layer: out = relu(conv(in) + b) (fwd) or conv(in) * (mask > 0) (bwd, float only);
+// tiles of systems whose off flag is set are skipped (off may be NULL)
 void net_conv(int bf16, int cin16, int bwd, const void* in, void* out, const void* W,
               const float* bias, const float* mask, const NetSample* smp, const NetTile* tiles,
-              int ntiles, int64_t row_base, const int* skip, hipStream_t st);
+              int ntiles, int64_t row_base, const int* skip, const int* off, hipStream_t st);
 // last layer: training output (outv) or in-place correction dst += sigma * NN (apply)
 void net_out(int bf16, const void* a3, const float* w4, const float* b4, const NetSample* smp,
              const NetTile* tiles, int ntiles, int64_t row_base, float* outv, double* dst,

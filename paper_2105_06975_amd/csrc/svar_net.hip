@@ -137,13 +137,15 @@ int run_net(svar_handle* h, const NetApp& app, double* base, const int* skip, hi
     const int t0 = app.tile0[c], nt = app.tile0[c + 1] - t0;
     const NetTile* tl = app.tiles + t0;
     const int64_t rb = app.row0[c];
-    net_feat_d(base, app.inv_sigma, app.smp, tl, nt, rb, n->d.k, n->d.n_bound, bf, X0, skip, st);
+    const int* off = h->net_off;
+    net_feat_d(base, app.inv_sigma, app.smp, tl, nt, rb, n->d.k, n->d.n_bound, bf, X0, skip, off,
+               st);
     net_conv(bf, 1, 0, X0, A, wl[0], n->theta + n->L.b[0], nullptr, app.smp, tl, nt, rb, skip,
-             st);
+             off, st);
     net_conv(bf, 0, 0, A, B, wl[1], n->theta + n->L.b[1], nullptr, app.smp, tl, nt, rb, skip,
-             st);
+             off, st);
     net_conv(bf, 0, 0, B, A, wl[2], n->theta + n->L.b[2], nullptr, app.smp, tl, nt, rb, skip,
-             st);
+             off, st);
     net_out(bf, A, n->W.w4, n->theta + n->L.b[3], app.smp, tl, nt, rb, nullptr, base, app.sigma,
             h->net_off, skip, st);
   }
@@ -284,11 +286,11 @@ int svar_net_forward(svar_net* n, int32_t precision, int32_t npair, int32_t nb, 
   // bfloat16 activations reuse the float32 buffers (half of each is used)
   net_feat_f(x, n->smp, n->tiles, ntiles, 0, n->d.k, n->d.n_bound, bf, n->X0, st);
   net_conv(bf, 1, 0, n->X0, n->a1, wl[0], n->theta + n->L.b[0], nullptr, n->smp, n->tiles,
-           ntiles, 0, nullptr, st);
+           ntiles, 0, nullptr, nullptr, st);
   net_conv(bf, 0, 0, n->a1, n->a2, wl[1], n->theta + n->L.b[1], nullptr, n->smp, n->tiles,
-           ntiles, 0, nullptr, st);
+           ntiles, 0, nullptr, nullptr, st);
   net_conv(bf, 0, 0, n->a2, n->a3, wl[2], n->theta + n->L.b[2], nullptr, n->smp, n->tiles,
-           ntiles, 0, nullptr, st);
+           ntiles, 0, nullptr, nullptr, st);
   net_out(bf, n->a3, n->W.w4, n->theta + n->L.b[3], n->smp, n->tiles, ntiles, 0, out, nullptr,
           nullptr, nullptr, nullptr, st);
   hipError_t e = hipGetLastError();
@@ -313,11 +315,11 @@ int svar_net_train_step(svar_net* n, int32_t npair, int32_t nb, int32_t s, const
   // forward (float32), keeping the activations
   net_feat_f(x, S, T, ntiles, 0, n->d.k, n->d.n_bound, 0, n->X0, st);
   net_conv(0, 1, 0, n->X0, n->a1, n->W.wf[0], b + n->L.b[0], nullptr, S, T, ntiles, 0, nullptr,
-           st);
+           nullptr, st);
   net_conv(0, 0, 0, n->a1, n->a2, n->W.wf[1], b + n->L.b[1], nullptr, S, T, ntiles, 0, nullptr,
-           st);
+           nullptr, st);
   net_conv(0, 0, 0, n->a2, n->a3, n->W.wf[2], b + n->L.b[2], nullptr, S, T, ntiles, 0, nullptr,
-           st);
+           nullptr, st);
   net_out(0, n->a3, n->W.w4, b + n->L.b[3], S, T, ntiles, 0, n->outv, nullptr, nullptr, nullptr,
           nullptr, st);
   // loss and backward
@@ -329,10 +331,12 @@ int svar_net_train_step(svar_net* n, int32_t npair, int32_t nb, int32_t s, const
   net_wreduce(n->part, G, 3, n->L, n->grad, st);
   net_wgrad(0, n->gA, n->a2, S, T, ntiles, G, n->part, st);
   net_wreduce(n->part, G, 2, n->L, n->grad, st);
-  net_conv(0, 0, 1, n->gA, n->gB, n->W.wflip[1], nullptr, n->a2, S, T, ntiles, 0, nullptr, st);
+  net_conv(0, 0, 1, n->gA, n->gB, n->W.wflip[1], nullptr, n->a2, S, T, ntiles, 0, nullptr, nullptr,
+           st);
   net_wgrad(0, n->gB, n->a1, S, T, ntiles, G, n->part, st);
   net_wreduce(n->part, G, 1, n->L, n->grad, st);
-  net_conv(0, 0, 1, n->gB, n->gA, n->W.wflip[0], nullptr, n->a1, S, T, ntiles, 0, nullptr, st);
+  net_conv(0, 0, 1, n->gB, n->gA, n->W.wflip[0], nullptr, n->a1, S, T, ntiles, 0, nullptr, nullptr,
+           st);
   net_wgrad(1, n->gA, n->X0, S, T, ntiles, G, n->part, st);
   net_wreduce(n->part, G, 0, n->L, n->grad, st);
   if (grad)
