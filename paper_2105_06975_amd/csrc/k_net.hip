@@ -439,7 +439,18 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const float* __restrict__ g,
   if (threadIdx.x < NET_C) pp[NET_C * NET_W * CIN + threadIdx.x] = bacc;
 }
 
-// sum the workgroup partials (fixed order) and scatter into the flat gradient
+// sum the workgroup partials (fixed order: groups of WR_G partials, then the groups) and
+// scatter into the flat gradient
+#define WR_G 16
+__global__ void k_net_wreduce1(const float* __restrict__ part, int grid, int NE,
+                               float* __restrict__ part2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NE) return;
+  const int g0 = blockIdx.y * WR_G, g1 = min(grid, g0 + WR_G);
+  float acc = 0.0f;
+  for (int g = g0; g < g1; ++g) acc += part[(int64_t)g * NE + e];
+  part2[(int64_t)blockIdx.y * NE + e] = acc;
+}
 __global__ void k_net_wreduce(const float* __restrict__ part, int grid, int layer, NetLayout L,
                               float* __restrict__ grad) {
   const int CIN = layer == 0 ? NET_CIN1 : NET_C;
@@ -600,11 +611,14 @@ void net_wgrad(int cin16, const float* g, const float* a, const NetSample* smp,
     hipLaunchKernelGGL(k_net_wgrad<NET_C>, dim3(grid), dim3(256), 0, st, g, a, smp, tiles,
                        ntiles, part);
 }
-void net_wreduce(const float* part, int grid, int layer, const NetLayout& L, float* grad,
-                 hipStream_t st) {
+void net_wreduce(const float* part, float* part2, int grid, int layer, const NetLayout& L,
+                 float* grad, hipStream_t st) {
   const int CIN = layer == 0 ? NET_CIN1 : NET_C;
   const int NE = layer == 3 ? NET_W * NET_C + 1 : NET_C * NET_W * CIN + NET_C;
-  hipLaunchKernelGGL(k_net_wreduce, dim3(nblk(NE, 256)), dim3(256), 0, st, part, grid, layer, L,
+  const int ng = (grid + WR_G - 1) / WR_G;
+  hipLaunchKernelGGL(k_net_wreduce1, dim3(nblk(NE, 256), ng), dim3(256), 0, st, part, grid, NE,
+                     part2);
+  hipLaunchKernelGGL(k_net_wreduce, dim3(nblk(NE, 256)), dim3(256), 0, st, part2, ng, layer, L,
                      grad);
 }
 void net_adam(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,

@@ -99,8 +99,9 @@ void net_wgrad4(const float* g4, const float* a3, const NetSample* smp, const Ne
                 int ntiles, int grid, float* part, hipStream_t st);
 void net_wgrad(int cin16, const float* g, const float* a, const NetSample* smp,
                const NetTile* tiles, int ntiles, int grid, float* part, hipStream_t st);
-void net_wreduce(const float* part, int grid, int layer, const NetLayout& L, float* grad,
-                 hipStream_t st);
+// part2: scratch of ceil(grid / 16) partial rows
+void net_wreduce(const float* part, float* part2, int grid, int layer, const NetLayout& L,
+                 float* grad, hipStream_t st);
 void net_adam(float* theta, const float* grad, float* m, float* v, int64_t n, float lr,
               float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
 int net_grid_cap();

@@ -838,7 +838,7 @@ static int add_copy_state(Builder& B, VRef in, VRef out, double alpha) {
 // (system, block), 64-point tiles, activations in row chunks of bounded size.
 static int add_net(Builder& B, VRef vec) {
   const int64_t ROW_CHUNK = (int64_t)1 << 24;
-  const int64_t SUM_CHUNK = (int64_t)1 << 16;
+  const int64_t SUM_CHUNK = (int64_t)1 << 13;
   auto app = std::make_unique<NetApp>();
   app->base = vec.base;
   std::vector<NetChunk> ch;

@@ -26,7 +26,7 @@ struct svar_net {
   std::vector<void*> ws_allocs;
   int64_t rows_cap = 0, tiles_cap = 0;
   float *X0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *gA = nullptr,
-        *gB = nullptr, *outv = nullptr, *g4 = nullptr, *part = nullptr;
+        *gB = nullptr, *outv = nullptr, *g4 = nullptr, *part = nullptr, *part2 = nullptr;
   double* lpart = nullptr;
   NetSample* smp = nullptr;
   NetTile* tiles = nullptr;
@@ -58,6 +58,7 @@ int net_ensure(svar_net* n, int64_t rows, int64_t ntiles, hipStream_t st) {
   SVAR_TRY(dalloc(A, &n->smp, T));  // at most one sample per tile
   SVAR_TRY(dalloc(A, &n->tiles, T));
   SVAR_TRY(dalloc(A, &n->part, (size_t)net_grid_cap() * NET_WG_PART));
+  SVAR_TRY(dalloc(A, &n->part2, (size_t)(net_grid_cap() / 16 + 1) * NET_WG_PART));
   return SVAR_OK;
 }
 
@@ -232,7 +233,7 @@ int svar_net_make_pairs(int32_t npair, int32_t nb, int32_t s, const double* chat
   if (!chat || !cexact || !x || !y) return inv("NULL buffer");
   hipStream_t st = (hipStream_t)stream;
   const int64_t len = (int64_t)nb * s;
-  const int64_t CH = 1 << 16;
+  const int64_t CH = 1 << 13;
   std::vector<NetChunk> ch;
   std::vector<int32_t> c0(npair + 1);
   for (int p = 0; p < npair; ++p) {
@@ -328,17 +329,17 @@ int svar_net_train_step(svar_net* n, int32_t npair, int32_t nb, int32_t s, const
   const int G = std::min(ntiles, net_grid_cap());
   net_out_bwd(n->g4, n->W.w4, n->a3, n->gA, S, T, ntiles, st);
   net_wgrad4(n->g4, n->a3, S, T, ntiles, G, n->part, st);
-  net_wreduce(n->part, G, 3, n->L, n->grad, st);
+  net_wreduce(n->part, n->part2, G, 3, n->L, n->grad, st);
   net_wgrad(0, n->gA, n->a2, S, T, ntiles, G, n->part, st);
-  net_wreduce(n->part, G, 2, n->L, n->grad, st);
+  net_wreduce(n->part, n->part2, G, 2, n->L, n->grad, st);
   net_conv(0, 0, 1, n->gA, n->gB, n->W.wflip[1], nullptr, n->a2, S, T, ntiles, 0, nullptr, nullptr,
            st);
   net_wgrad(0, n->gB, n->a1, S, T, ntiles, G, n->part, st);
-  net_wreduce(n->part, G, 1, n->L, n->grad, st);
+  net_wreduce(n->part, n->part2, G, 1, n->L, n->grad, st);
   net_conv(0, 0, 1, n->gB, n->gA, n->W.wflip[0], nullptr, n->a1, S, T, ntiles, 0, nullptr, nullptr,
            st);
   net_wgrad(1, n->gA, n->X0, S, T, ntiles, G, n->part, st);
-  net_wreduce(n->part, G, 0, n->L, n->grad, st);
+  net_wreduce(n->part, n->part2, G, 0, n->L, n->grad, st);
   if (grad)
     SVAR_HIP(hipMemcpyAsync(grad, n->grad, (size_t)n->L.n * sizeof(float),
                             hipMemcpyDeviceToHost, st));
