@@ -144,6 +144,11 @@ typedef struct svar_solve_opts {
   double* harvest;
   int32_t harvest_cap;
   int32_t fallback_patience;  /* >= 1 (values below 1 count as 1)                           */
+  /* 1: replay FGMRES steps in chunks of 4 from a captured HIP graph (launched on a private
+     stream ordered after / before the caller's stream with events); the results are those
+     of the step-by-step launches.  Ignored while harvesting or timing. */
+  int32_t use_graph;
+  int32_t pad;
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */

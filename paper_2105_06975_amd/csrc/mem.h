@@ -36,6 +36,7 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
                 const int* skip);
 int64_t handle_total(const svar_handle* h, int nrhs);
 int64_t state_total(const svar_handle* h, int nrhs);
+bool timing_any(const svar_handle* h);
 void timed_begin(svar_handle* h, int kc, hipStream_t st, hipEvent_t* e0, hipEvent_t* e1);
 void timed_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st);

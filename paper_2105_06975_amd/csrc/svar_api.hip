@@ -74,6 +74,83 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
   }
 }
 
+// Plan of the LDS-tiled kernel: 128-row x (16 maxct)-column tiles, split-K to fill the chip.
+// Tasks that read the same panel chunk (same problem, k-range and column group) are placed on
+// one XCD (workgroup i runs on XCD i mod 8), so the chunk is fetched into one L2 only.
+static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks,
+                            int64_t& ws, int& maxct) {
+  int maxcols = 1;
+  for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
+  maxct = std::min(8, (maxcols + 15) / 16);
+  const int cw = maxct * 16;
+  const int rows = 128;
+  double total_work = 0.0;
+  for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
+  const int target = 512;  // two 4-wave workgroups per CU
+  ws = 0;
+  std::vector<std::vector<GemmTask>> groups;
+  for (int pi = 0; pi < (int)probs.size(); ++pi) {
+    GemmProb& p = probs[pi];
+    const int rt = (p.n + rows - 1) / rows, cg = (p.ncols + cw - 1) / cw;
+    const double share = total_work > 0 ? (double)p.n * p.n * p.ncols / total_work : 1.0;
+    const int want = (int)std::ceil(target * share / (double)(rt * cg));
+    const int kmin = 256;
+    const int maxs = std::max(1, p.n / kmin);
+    int S = std::max(1, std::min(want, maxs));
+    const int align = 64;
+    const int chunk = ((p.n + S - 1) / S + align - 1) / align * align;
+    S = (p.n + chunk - 1) / chunk;
+    p.splits = S;
+    p.ws_off = 0;
+    if (S > 1) {
+      p.ws_off = ws;
+      ws += (int64_t)S * p.ncols * p.n;
+    }
+    for (int sp = 0; sp < S; ++sp)
+      for (int c = 0; c < cg; ++c) {
+        std::vector<GemmTask> grp;
+        for (int r = 0; r < rt; ++r) {
+          GemmTask t;
+          t.prob = pi;
+          t.row0 = r * rows;
+          t.k0 = sp * chunk;
+          t.k1 = std::min(p.n, (sp + 1) * chunk);
+          t.col0 = c * cw;
+          t.split = sp;
+          grp.push_back(t);
+        }
+        groups.push_back(std::move(grp));
+      }
+  }
+  // deal the groups to 8 XCD queues (largest queue-balance first fit), then interleave
+  const int NX = 8;
+  std::vector<std::vector<GemmTask>> q(NX);
+  for (auto& g : groups) {
+    int best = 0;
+    for (int x = 1; x < NX; ++x)
+      if (q[x].size() < q[best].size()) best = x;
+    q[best].insert(q[best].end(), g.begin(), g.end());
+  }
+  tasks.clear();
+  std::vector<size_t> pos(NX, 0);
+  size_t left = 0;
+  for (auto& v : q) left += v.size();
+  while (left > 0) {
+    for (int x = 0; x < NX; ++x) {
+      int src = x;
+      if (pos[src] >= q[src].size()) {  // an exhausted queue: take from the fullest one
+        src = 0;
+        for (int y = 1; y < NX; ++y)
+          if (q[y].size() - pos[y] > q[src].size() - pos[src]) src = y;
+        if (pos[src] >= q[src].size()) break;
+      }
+      tasks.push_back(q[src][pos[src]++]);
+      --left;
+      if (left == 0) break;
+    }
+  }
+}
+
 static int ensure_zeros(svar_handle* h, int64_t n, hipStream_t st) {
   if (n <= h->zeros_elems) return SVAR_OK;
   if (h->zeros) {
@@ -103,7 +180,13 @@ static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector
     p.dtype = dtype;
     p.zeros = h->zeros;
   }
-  plan_gemm(probs, tasks, ws, maxct);
+  int maxcols = 1;
+  for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
+  g.tiled = maxcols >= 32 ? 1 : 0;
+  if (g.tiled)
+    plan_gemm_tiled(probs, tasks, ws, maxct);
+  else
+    plan_gemm(probs, tasks, ws, maxct);
   g.nprob = (int)probs.size();
   g.ntask = (int)tasks.size();
   g.maxct = maxct;
@@ -1321,6 +1404,11 @@ static void timer_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hip
   h->timers[kc].pending.emplace_back(e0, e1);
   h->timers[kc].launches += 1;
 }
+bool timing_any(const svar_handle* h) {
+  for (const auto& T : h->timers)
+    if (T.on) return true;
+  return false;
+}
 void timed_begin(svar_handle* h, int kc, hipStream_t st, hipEvent_t* e0, hipEvent_t* e1) {
   timer_begin(h, kc, st, e0, e1);
 }
@@ -1412,6 +1500,17 @@ int svar_create(const svar_window_desc* windows, int32_t nwin, const svar_prec_o
   int rc = SVAR_OK;
   if (hipGetDevice(&h->device) != hipSuccess) rc = inval("no HIP device");
   h->wins.resize(nwin);
+  // the zero buffer that GEMM plans read past matrix edges is sized once for the largest
+  // order (later growth would leave earlier plans pointing at a freed buffer)
+  if (rc == SVAR_OK) {
+    int64_t nmax = 1;
+    for (int w = 0; w < nwin; ++w) {
+      nmax = std::max<int64_t>(nmax, windows[w].s);
+      if (windows[w].p && windows[w].N >= 0)
+        for (int i = 0; i <= windows[w].N; ++i) nmax = std::max<int64_t>(nmax, windows[w].p[i]);
+    }
+    rc = ensure_zeros(h, nmax, st);
+  }
   for (int w = 0; rc == SVAR_OK && w < nwin; ++w) {
     const int k = popts->k;
     if (k < 1 || k > windows[w].N + 1) rc = inval("k must satisfy 1 <= k <= N+1 (Definition 1)");
@@ -1597,6 +1696,10 @@ int svar_timing_read(svar_handle* h, int32_t kclass, double* total_ms, int64_t* 
 int svar_destroy(svar_handle* h) {
   if (!h) return SVAR_OK;
   (void)hipDeviceSynchronize();
+  if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
+  if (h->graph.ev_in) (void)hipEventDestroy(h->graph.ev_in);
+  if (h->graph.ev_out) (void)hipEventDestroy(h->graph.ev_out);
+  if (h->graph.ps) (void)hipStreamDestroy(h->graph.ps);
   for (auto& T : h->timers) {
     for (auto& pr : T.pending) {
       (void)hipEventDestroy(pr.first);

@@ -96,6 +96,19 @@ struct svar_handle {
   std::vector<std::unique_ptr<svar::NetApp>> netapps;
   void* net_ws = nullptr;         // activations of the in-place application
   int64_t net_ws_bytes = 0;
+  int prog_gen = 0;               // bumped when cached programs are dropped
+  // captured FGMRES step chunk (see fgmres_cycle)
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t ps = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int nrhs = -1, m = -1, gen = -1, patience = 0;
+    const void* pa = nullptr;
+    const void* pp = nullptr;
+    const int* net_off = nullptr;
+    const void* bufs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // workspaces used
+    double drop = 0.0;
+  } graph;
   // Krylov workspace (grown on demand)
   struct Kry {
     int nrhs = -1, m = 0;

@@ -135,6 +135,7 @@ struct GemmPlanDev {
   int64_t max_reduce_elems = 0;
   int64_t ws_elems = 0;
   int dtype = DT_F64;
+  int tiled = 0;                  // 1: LDS-tiled kernel (128-row tiles), 0: k-split kernel
 };
 struct Launch {
   LaunchKind kind;

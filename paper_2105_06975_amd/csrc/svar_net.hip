@@ -377,6 +377,7 @@ int svar_set_net(svar_handle* h, svar_net* n) {
   SVAR_HIP(hipDeviceSynchronize());
   h->net = n;
   h->net_off = nullptr;
+  h->prog_gen += 1;
   // preconditioner programs are rebuilt with (or without) the correction
   for (auto it = h->progs.begin(); it != h->progs.end();) {
     if (it->first.op == PROG_P)

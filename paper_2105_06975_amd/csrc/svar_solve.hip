@@ -123,38 +123,126 @@ struct Harvest {
   const Program* prog = nullptr;
 };
 
+// One FGMRES step: P and A products, the fused Gram-Schmidt passes and the Hessenberg step.
+// The step index itself lives on the device; jl only sizes grids and LDS (any jl >= the
+// device's j gives the same results, which lets a captured chunk use jl = m throughout).
+static int fg_step(svar_handle* h, int m, const Program& PA, const Program& PP, int jl,
+                   bool scale, int* net_off, double drop, int patience, Harvest& hv,
+                   hipStream_t st) {
+  auto& K = h->kry;
+  const int* skip = &K.gl->all_done;
+  if (scale) kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
+  if (hv.buf && hv.count < hv.cap) {
+    SVAR_TRY(run_program(h, *hv.prog, K.u, hv.buf + (int64_t)hv.count * hv.len, st, skip));
+    ++hv.count;
+  }
+  SVAR_TRY(run_program(h, PP, K.u, K.z, st, skip));
+  SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip));
+  hipEvent_t e0, e1;
+  timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+  kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
+  timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+  kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, jl, st);
+  kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, jl, net_off, drop, patience, st);
+  timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+  kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, jl, st);
+  timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+  kr_advance(K.gl, st);
+  return SVAR_OK;
+}
+
+static constexpr int GRAPH_STEPS = 4;
+
+// The executable graph of GRAPH_STEPS steps for this configuration (captured on first use).
+static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
+                      int* net_off, double drop, int patience, hipGraphExec_t* out) {
+  auto& G = h->graph;
+  // every device buffer whose address the captured launches hold
+  const void* bufs[5] = {h->kry.V, h->tmp, h->gemm_ws, h->net_ws, h->zeros};
+  bool same_bufs = true;
+  for (int i = 0; i < 5; ++i) same_bufs = same_bufs && G.bufs[i] == bufs[i];
+  if (G.exec && same_bufs && G.nrhs == nrhs && G.m == m && G.pa == &PA && G.pp == &PP &&
+      G.gen == h->prog_gen && G.net_off == net_off && G.drop == drop &&
+      G.patience == patience) {
+    *out = G.exec;
+    return SVAR_OK;
+  }
+  if (!G.ps) {
+    SVAR_HIP(hipStreamCreateWithFlags(&G.ps, hipStreamNonBlocking));
+    SVAR_HIP(hipEventCreateWithFlags(&G.ev_in, hipEventDisableTiming));
+    SVAR_HIP(hipEventCreateWithFlags(&G.ev_out, hipEventDisableTiming));
+  }
+  if (G.exec) {
+    SVAR_HIP(hipStreamSynchronize(G.ps));
+    (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+  }
+  Harvest none;
+  hipGraph_t graph = nullptr;
+  SVAR_HIP(hipStreamBeginCapture(G.ps, hipStreamCaptureModeThreadLocal));
+  int rc = SVAR_OK;
+  for (int i = 0; i < GRAPH_STEPS && rc == SVAR_OK; ++i)
+    rc = fg_step(h, m, PA, PP, m, true, net_off, drop, patience, none, G.ps);
+  hipError_t ce = hipStreamEndCapture(G.ps, &graph);
+  if (rc != SVAR_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ce != hipSuccess) {
+    set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+    return SVAR_E_HIP;
+  }
+  hipError_t ie = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    G.exec = nullptr;
+    set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+    return SVAR_E_HIP;
+  }
+  G.nrhs = nrhs;
+  G.m = m;
+  G.pa = &PA;
+  G.pp = &PP;
+  G.gen = h->prog_gen;
+  G.net_off = net_off;
+  G.drop = drop;
+  G.patience = patience;
+  for (int i = 0; i < 5; ++i) G.bufs[i] = bufs[i];
+  *out = G.exec;
+  return SVAR_OK;
+}
+
 static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
                         const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
-                        double drop, int patience, Harvest& hv, hipStream_t st) {
+                        double drop, int patience, Harvest& hv, bool use_graph,
+                        hipStream_t st) {
   int* net_off = h->net_off ? h->kry.net_off : nullptr;
   auto& K = h->kry;
   SVAR_HIP(hipMemcpyAsync(K.tol_rel, tol_rel.data(), tol_rel.size() * sizeof(double),
                           hipMemcpyHostToDevice, st));
   kr_nrm2_part(K.plan, K.r, K.npart, st);
   kr_start(K.plan, K.npart, K.r, K.u, K.st, K.tol_rel, K.gl, st);
-  const int* skip = &K.gl->all_done;
-  const int check_every = 4;
+  const int check_every = GRAPH_STEPS;
+  const bool graph = use_graph && !hv.buf && !timing_any(h);
   bool all_done = false;
   int j = 0;
-  for (; j < m; ++j) {
-    if (j > 0) kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
-    if (hv.buf && hv.count < hv.cap) {
-      SVAR_TRY(run_program(h, *hv.prog, K.u, hv.buf + (int64_t)hv.count * hv.len, st, skip));
-      ++hv.count;
+  while (j < m) {
+    int done_steps = 1;
+    if (graph && j >= check_every && j % check_every == 0 && j + GRAPH_STEPS <= m) {
+      // replay a captured chunk on the private stream, ordered inside the caller's stream
+      hipGraphExec_t ex = nullptr;
+      SVAR_TRY(step_graph(h, nrhs, m, PA, PP, net_off, drop, patience, &ex));
+      SVAR_HIP(hipEventRecord(h->graph.ev_in, st));
+      SVAR_HIP(hipStreamWaitEvent(h->graph.ps, h->graph.ev_in, 0));
+      SVAR_HIP(hipGraphLaunch(ex, h->graph.ps));
+      SVAR_HIP(hipEventRecord(h->graph.ev_out, h->graph.ps));
+      SVAR_HIP(hipStreamWaitEvent(st, h->graph.ev_out, 0));
+      done_steps = GRAPH_STEPS;
+    } else {
+      SVAR_TRY(fg_step(h, m, PA, PP, j, j > 0, net_off, drop, patience, hv, st));
     }
-    SVAR_TRY(run_program(h, PP, K.u, K.z, st, skip));
-    SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip));
-    hipEvent_t e0, e1;
-    timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
-    kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
-    timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
-    kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, j, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, j, net_off, drop, patience, st);
-    timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
-    kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, j, st);
-    timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
-    kr_advance(K.gl, st);
-    if ((j + 1) % check_every == 0 || j + 1 == m) {
+    j += done_steps;
+    if (j % check_every == 0 || j == m) {
       SVAR_HIP(hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
       SVAR_HIP(hipStreamSynchronize(st));
       if (K.gl_host->all_done) {
@@ -265,7 +353,7 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     std::vector<KState> ks;
     {
       const int rc = fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
-                                  o->fallback_patience, hv, st);
+                                  o->fallback_patience, hv, o->use_graph != 0, st);
       if (rc != SVAR_OK) {
         h->net_off = nullptr;
         return rc;

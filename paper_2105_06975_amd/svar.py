@@ -61,7 +61,7 @@ class SolveOpts(C.Structure):
                 ("restart", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("max_outer", C.c_int32), ("fallback_drop", C.c_double),
                 ("harvest", C.c_void_p), ("harvest_cap", C.c_int32),
-                ("fallback_patience", C.c_int32)]
+                ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("pad", C.c_int32)]
 
 
 class NetDesc(C.Structure):
@@ -296,7 +296,8 @@ class Handle:
 
     def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
               precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
-              check=False, fallback_drop=1e-3, fallback_patience=3, harvest=None):
+              check=False, fallback_drop=1e-3, fallback_patience=3, harvest=None,
+              graph=False):
         """Solve A x = rhs; returns (x, [info dicts], status).
 
         harvest: optional float64 device tensor of shape (cap, state_len): receives the state
@@ -308,7 +309,7 @@ class Handle:
                                                      int(harvest.shape[0]))
         o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
                       float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap,
-                      int(fallback_patience))
+                      int(fallback_patience), 1 if graph else 0, 0)
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
