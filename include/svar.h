@@ -311,6 +311,19 @@ int svar_net_train_step(svar_net* net, int32_t npair, int32_t nb, int32_t s, con
    the handle's; it must outlive the attachment.  Training it later changes the correction. */
 int svar_set_net(svar_handle* h, svar_net* net);
 
+/* Tile autotuning of the covariance products (matrix-panel GEMMs): for every GEMM launch of
+   the A and P programs of nrhs right-hand sides at `precision` (SVAR_PRECISION_*), time the
+   candidate plans (k-split kernel or LDS-tiled kernel, several workgroup counts; one warm-up
+   and five timed launches on zero-filled scratch vectors, HIP events on `stream`), keep the
+   fastest per shape key (precision | n x ncols of each product) in the handle and rebuild the
+   programs with it.  Shapes already tuned are skipped.  When cache_path is not NULL the
+   choices are merged into that JSON file (one entry per line: key, tiled, target, us,
+   default_us).  Synchronous.  Results do not depend on the plan beyond rounding order. */
+int svar_autotune(svar_handle* h, int32_t nrhs, int32_t precision, const char* cache_path,
+                  void* stream);
+/* Load the choices of a cache written by svar_autotune (unknown shapes keep the default). */
+int svar_autotune_load(svar_handle* h, const char* cache_path);
+
 const char* svar_last_error(void);
 
 #ifdef __cplusplus

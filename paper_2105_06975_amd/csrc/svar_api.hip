@@ -1,6 +1,8 @@
 // libsvar host code: handle set-up, launch programs for A v and P^{-1} v, and the C ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <numeric>
@@ -30,7 +32,7 @@ static int host_sum(const double* dpart, int n, hipStream_t st, double* out) {
 // Tasks: 64-row tiles x column groups x k-splits.  The k-range is split so that the launch
 // has about four workgroups per CU; split partials are reduced in a fixed order.
 static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks, int64_t& ws,
-                      int& maxct) {
+                      int& maxct, int target) {
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
   maxct = std::min(8, (maxcols + 15) / 16);
@@ -38,7 +40,6 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
   const int rows = 16 * gemm_rt(maxct);  // rows per workgroup
   double total_work = 0.0;
   for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
-  const int target = 512;  // workgroups of 4 waves (the waves of a workgroup split k)
   ws = 0;
   tasks.clear();
   for (int pi = 0; pi < (int)probs.size(); ++pi) {
@@ -78,7 +79,7 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
 // Tasks that read the same panel chunk (same problem, k-range and column group) are placed on
 // one XCD (workgroup i runs on XCD i mod 8), so the chunk is fetched into one L2 only.
 static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks,
-                            int64_t& ws, int& maxct) {
+                            int64_t& ws, int& maxct, int target) {
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
   maxct = std::min(8, (maxcols + 15) / 16);
@@ -86,7 +87,6 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
   const int rows = 128;
   double total_work = 0.0;
   for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
-  const int target = 512;  // two 4-wave workgroups per CU
   ws = 0;
   std::vector<std::vector<GemmTask>> groups;
   for (int pi = 0; pi < (int)probs.size(); ++pi) {
@@ -168,8 +168,16 @@ static int ensure_zeros(svar_handle* h, int64_t n, hipStream_t st) {
   return SVAR_OK;
 }
 
+static std::string gemm_key(int dtype, const std::vector<GemmProb>& probs) {
+  std::string k = dtype == DT_F64 ? "f64" : (dtype == DT_F32 ? "f32" : "bf16");
+  for (auto& p : probs) k += "|" + std::to_string(p.n) + "x" + std::to_string(p.ncols);
+  return k;
+}
+
+// tiled < 0: the autotuned choice for this shape if one is known, else the default
 static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector<GemmProb>& probs,
-                          int dtype, GemmPlanDev& g, hipStream_t st) {
+                          int dtype, GemmPlanDev& g, hipStream_t st, int tiled = -1,
+                          int target = 512) {
   std::vector<GemmTask> tasks;
   int64_t ws = 0;
   int maxct = 1;
@@ -182,11 +190,23 @@ static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector
   }
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
-  g.tiled = maxcols >= 32 ? 1 : 0;
+  g.key = gemm_key(dtype, probs);
+  if (tiled < 0) {
+    tiled = maxcols >= 32 ? 1 : 0;
+    auto it = h->tune.find(g.key);
+    if (it != h->tune.end()) {
+      tiled = it->second.first;
+      target = it->second.second;
+    }
+  }
+  if (maxcols < 32) tiled = 0;  // the tiled kernel needs two or more 16-column tiles
+  g.tiled = tiled;
+  g.target = target;
+  g.hprobs = probs;
   if (g.tiled)
-    plan_gemm_tiled(probs, tasks, ws, maxct);
+    plan_gemm_tiled(probs, tasks, ws, maxct, target);
   else
-    plan_gemm(probs, tasks, ws, maxct);
+    plan_gemm(probs, tasks, ws, maxct, target);
   g.nprob = (int)probs.size();
   g.ntask = (int)tasks.size();
   g.maxct = maxct;
@@ -1474,6 +1494,106 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
 }
 
 int64_t handle_total(const svar_handle* h, int nrhs) { return total_len(h, nrhs, SP_SADDLE); }
+// ------------------------------------------------------------------ GEMM autotuning
+struct TuneEntry {
+  std::string key;
+  int tiled, target;
+  double us, default_us;
+};
+
+static void pv_of(int precision, int* pv_a, int* pv_p) {
+  const bool a64 = precision == SVAR_PRECISION_FP64 || precision == SVAR_PRECISION_FP64_F32P;
+  *pv_a = a64 ? PV_F64 : PV_F32;
+  *pv_p = precision == SVAR_PRECISION_MIXED_BF16P
+              ? PV_BF16P
+              : (precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+}
+
+// Time each candidate plan of every covariance-product launch of the A and P programs for
+// nrhs right-hand sides (one warm-up and five timed launches on zero-filled scratch vectors);
+// keep the fastest per shape key.
+static int autotune(svar_handle* h, int nrhs, int precision, std::vector<TuneEntry>& out,
+                    hipStream_t st) {
+  int pv_a, pv_p;
+  pv_of(precision, &pv_a, &pv_p);
+  Program *PA = nullptr, *PP = nullptr;
+  SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &PA, st));
+  SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &PP, st));
+  const int64_t len = total_len(h, nrhs, SP_SADDLE);
+  std::vector<void*> tmp;
+  double *vin = nullptr, *vout = nullptr;
+  SVAR_TRY(dalloc(tmp, &vin, (size_t)len));
+  int rc = dalloc(tmp, &vout, (size_t)len);
+  if (rc == SVAR_OK) {
+    launch_fill(vin, len, 0.0, st);
+    launch_fill(vout, len, 0.0, st);
+  }
+  const int64_t tmp_need = std::max(PA->tmp_elems, PP->tmp_elems);
+  if (rc == SVAR_OK && tmp_need > h->tmp_elems) rc = regrow(h, &h->tmp, &h->tmp_elems, tmp_need);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rc == SVAR_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = inval("event creation failed");
+  std::vector<GemmPlanDev> seen;
+  for (const Program* P : {PA, PP}) {
+    for (const Launch& L : P->launches) {
+      if (rc != SVAR_OK) break;
+      if (L.kind != LK_GEMM) continue;
+      if (h->tune.count(L.gemm.key) || std::any_of(out.begin(), out.end(), [&](const TuneEntry& e) {
+            return e.key == L.gemm.key;
+          }))
+        continue;
+      int maxcols = 1;
+      for (auto& p : L.gemm.hprobs) maxcols = std::max(maxcols, p.ncols);
+      std::vector<std::pair<int, int>> cands = {{0, 512}, {0, 1024}, {0, 2048}};
+      if (maxcols >= 32) cands.insert(cands.end(), {{1, 256}, {1, 512}, {1, 1024}});
+      TuneEntry best{L.gemm.key, -1, 0, 1e30, 0.0};
+      for (auto& c : cands) {
+        std::vector<void*> owner;
+        std::vector<GemmProb> probs = L.gemm.hprobs;
+        GemmPlanDev g;
+        rc = make_gemm_plan(h, owner, probs, L.gemm.dtype, g, st, c.first, c.second);
+        if (rc == SVAR_OK && g.ws_elems > h->gemm_ws_elems)
+          rc = regrow(h, &h->gemm_ws, &h->gemm_ws_elems, g.ws_elems);
+        if (rc == SVAR_OK) {
+          Bases b{};
+          b.p[B_IN] = vin;
+          b.p[B_OUT] = vout;
+          b.p[B_TMP] = h->tmp;
+          launch_gemm(g, b, h->gemm_ws, nullptr, st);
+          (void)hipEventRecord(e0, st);
+          for (int r = 0; r < 5; ++r) launch_gemm(g, b, h->gemm_ws, nullptr, st);
+          (void)hipEventRecord(e1, st);
+          if (hipEventSynchronize(e1) != hipSuccess) rc = inval("autotune launch failed");
+          float ms = 0.0f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double us = 1e3 * ms / 5.0;
+          const bool is_default = c.first == ((maxcols >= 32) ? 1 : 0) && c.second == 512;
+          if (is_default) best.default_us = us;
+          if (us < best.us) {
+            best.us = us;
+            best.tiled = c.first;
+            best.target = c.second;
+          }
+        }
+        (void)hipStreamSynchronize(st);
+        free_all(owner);
+        if (rc != SVAR_OK) break;
+      }
+      if (rc == SVAR_OK && best.tiled >= 0) out.push_back(best);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  free_all(tmp);
+  return rc;
+}
+
+static void drop_programs(svar_handle* h) {
+  h->progs.clear();  // rebuilt on next use with the tuned plans
+  h->prog_gen += 1;
+}
+
 int64_t state_total(const svar_handle* h, int nrhs) { return total_len(h, nrhs, SP_STATE); }
 
 }  // namespace svar
@@ -1484,6 +1604,76 @@ using namespace svar;
 extern "C" {
 
 const char* svar_last_error(void) { return g_err.c_str(); }
+
+int svar_autotune(svar_handle* h, int32_t nrhs, int32_t precision, const char* cache_path,
+                  void* stream) {
+  if (!h || nrhs < 1) return inval("bad arguments");
+  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_FP64_F32P)
+    return inval("bad precision");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<TuneEntry> found;
+  SVAR_TRY(autotune(h, nrhs, precision, found, st));
+  for (auto& e : found) h->tune[e.key] = {e.tiled, e.target};
+  if (!found.empty()) drop_programs(h);
+  if (cache_path) {
+    // merge with an existing cache: entries of this run replace those of the same key
+    std::map<std::string, std::string> lines;
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char buf[1024];
+      while (std::fgets(buf, sizeof(buf), f)) {
+        std::string s(buf);
+        const size_t a = s.find("\"key\": \"");
+        if (a == std::string::npos) continue;
+        const size_t b = s.find('"', a + 8);
+        if (b == std::string::npos) continue;
+        while (!s.empty() && (s.back() == '\n' || s.back() == ',')) s.pop_back();
+        lines[s.substr(a + 8, b - a - 8)] = s;
+      }
+      std::fclose(f);
+    }
+    for (auto& e : found) {
+      char buf[512];
+      std::snprintf(buf, sizeof(buf),
+                    "  {\"key\": \"%s\", \"tiled\": %d, \"target\": %d, \"us\": %.2f, "
+                    "\"default_us\": %.2f}",
+                    e.key.c_str(), e.tiled, e.target, e.us, e.default_us);
+      lines[e.key] = buf;
+    }
+    FILE* f = std::fopen(cache_path, "w");
+    if (!f) return inval(std::string("cannot write ") + cache_path);
+    std::fprintf(f, "{\"version\": 1, \"entries\": [\n");
+    size_t i = 0;
+    for (auto& kv : lines)
+      std::fprintf(f, "%s%s\n", kv.second.c_str(), ++i < lines.size() ? "," : "");
+    std::fprintf(f, "]}\n");
+    std::fclose(f);
+  }
+  return SVAR_OK;
+}
+
+int svar_autotune_load(svar_handle* h, const char* cache_path) {
+  if (!h || !cache_path) return inval("bad arguments");
+  FILE* f = std::fopen(cache_path, "r");
+  if (!f) return inval(std::string("cannot read ") + cache_path);
+  char buf[1024];
+  int n = 0;
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string s(buf);
+    const size_t a = s.find("\"key\": \"");
+    if (a == std::string::npos) continue;
+    const size_t b = s.find('"', a + 8);
+    const size_t ti = s.find("\"tiled\": "), ta = s.find("\"target\": ");
+    if (b == std::string::npos || ti == std::string::npos || ta == std::string::npos) continue;
+    const int tiled = std::atoi(s.c_str() + ti + 9);
+    const int target = std::atoi(s.c_str() + ta + 10);
+    if ((tiled != 0 && tiled != 1) || target < 1 || target > (1 << 20)) continue;
+    h->tune[s.substr(a + 8, b - a - 8)] = {tiled, target};
+    ++n;
+  }
+  std::fclose(f);
+  if (n > 0) drop_programs(h);
+  return SVAR_OK;
+}
 
 int svar_create(const svar_window_desc* windows, int32_t nwin, const svar_prec_opts* popts,
                 svar_handle** out, void* stream) {

@@ -97,6 +97,8 @@ struct svar_handle {
   void* net_ws = nullptr;         // activations of the in-place application
   int64_t net_ws_bytes = 0;
   int prog_gen = 0;               // bumped when cached programs are dropped
+  // autotuned GEMM plans: shape key -> (tiled kernel, target workgroups)
+  std::map<std::string, std::pair<int, int>> tune;
   // captured FGMRES step chunk (see fgmres_cycle)
   struct StepGraph {
     hipGraphExec_t exec = nullptr;

@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svar_net_train_step.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_int32,
                                         _ip, C.POINTER(AdamOpts), _dp, C.POINTER(C.c_float), vp]
     lib.svar_set_net.argtypes = [vp, vp]
+    lib.svar_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p, vp]
+    lib.svar_autotune_load.argtypes = [vp, C.c_char_p]
     lib.svar_last_error.restype = C.c_char_p
     return lib
 
@@ -317,6 +319,15 @@ class Handle:
         if rc not in (OK, E_NOCONV, E_BREAKDOWN) or (check and rc != OK):
             _check(rc)
         return x, [i.as_dict() for i in infos], rc
+
+    def autotune(self, nrhs: int = 1, precision: str = "FP64", cache_path=None, stream=None):
+        """Time the GEMM plan candidates of this handle's A and P programs (svar_autotune)."""
+        _check(lib().svar_autotune(self._h, nrhs, PRECISION[precision],
+                                   None if cache_path is None else str(cache_path).encode(),
+                                   _stream(stream)))
+
+    def autotune_load(self, cache_path):
+        _check(lib().svar_autotune_load(self._h, str(cache_path).encode()))
 
     def set_net(self, net):
         """Attach a Net (or None): the preconditioner then corrects its Lhat^{-T} output."""

@@ -74,3 +74,26 @@ def test_graph_with_learned_correction(sv):
         assert [a["iters"] for a in i1] == [a["iters"] for a in i0]
         assert [a["fallbacks"] for a in i1] == [a["fallbacks"] for a in i0]
         assert np.array_equal(host(x1), host(x0)), rep
+
+
+def test_autotune_cache_roundtrip(sv, tmp_path):
+    wins = _batch()
+    nrhs = 4
+    rhs = np.concatenate([wl.random_vectors(w, nrhs, seed=30 + i).ravel()
+                          for i, w in enumerate(wins)])
+    h = sv.Handle(wins, sv.Precond(type="PI", k=3, rhat="RR"))
+    x0, i0, _ = h.solve(dev(rhs), nrhs, rtol=1e-9, maxit=400)
+    x0 = host(x0)
+    path = tmp_path / "tune.json"
+    h.autotune(nrhs, "FP64", path)
+    text = path.read_text()
+    assert '"entries"' in text and text.count('"key"') >= 2
+    x1, i1, _ = h.solve(dev(rhs), nrhs, rtol=1e-9, maxit=400)
+    x1 = host(x1)
+    # another plan changes only the rounding order of the products
+    assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-8
+    assert all(abs(a["iters"] - b["iters"]) <= 2 for a, b in zip(i0, i1))
+    h2 = sv.Handle(wins, sv.Precond(type="PI", k=3, rhat="RR"))
+    h2.autotune_load(path)
+    x2, _, _ = h2.solve(dev(rhs), nrhs, rtol=1e-9, maxit=400)
+    assert np.array_equal(host(x2), x1)  # same plans, same results
