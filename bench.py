@@ -59,6 +59,8 @@ def parse():
                          "observation right-hand sides in one call, against one-at-a-time "
                          "solves of the first two windows (one JSON object)")
     ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file for the GEMM autotuning cache (--c4 mode)")
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--precision", default="FP64_F32P",
                     help="precision of the learned + batched path")
@@ -354,12 +356,16 @@ def bench_c4(args):
     h = svar.Handle(wins, prec)
     log(f"c4 set-up {time.time() - t0:.1f}s")
     rhs = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
-    h.solve(rhs, nrhs, **kw)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    x, info, rc = h.solve(rhs, nrhs, **kw)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t
+
+    def timed_solve(**extra):
+        h.solve(rhs, nrhs, **kw, **extra)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info, rc = h.solve(rhs, nrhs, **kw, **extra)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, x, info, rc
+
+    el, x, info, rc = timed_solve()
     its = [i["iters"] for i in info]
     res = {"workload": f"c4 wave: {len(wins)} uneven windows x {nrhs} rhs, restart {args.restart}",
            "batched": {"systems": len(info), "seconds": el, "solves_per_s": len(info) / el,
@@ -367,6 +373,20 @@ def bench_c4(args):
                        "relres_max": float(max(i["relres_true"] for i in info)),
                        "n_total": int(sum(w.n for w in wins) * nrhs)}}
     log(res["batched"])
+    # the same batch with graph-captured FGMRES step chunks, then with autotuned GEMM plans
+    el_g, xg, info_g, rc_g = timed_solve(graph=True)
+    res["batched_graph"] = {"seconds": el_g, "solves_per_s": len(info) / el_g, "rc": rc_g,
+                            "identical_x": bool(torch.equal(xg, x))}
+    log(res["batched_graph"])
+    t0 = time.time()
+    h.autotune(nrhs, "FP64", args.tune_cache)
+    t_tune = time.time() - t0
+    el_t, xt, info_t, rc_t = timed_solve(graph=True)
+    res["batched_graph_autotuned"] = {"seconds": el_t, "solves_per_s": len(info) / el_t,
+                                      "rc": rc_t, "autotune_s": t_tune,
+                                      "x_rel_diff": float(torch.linalg.norm(xt - x) /
+                                                          torch.linalg.norm(x))}
+    log(res["batched_graph_autotuned"])
     # one at a time: the first two windows' 16 systems (same preconditioner and restart)
     sub = wins[:2]
     hs = svar.Handle(sub, prec)

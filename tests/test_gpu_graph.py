@@ -87,7 +87,8 @@ def test_autotune_cache_roundtrip(sv, tmp_path):
     path = tmp_path / "tune.json"
     h.autotune(nrhs, "FP64", path)
     text = path.read_text()
-    assert '"entries"' in text and text.count('"key"') >= 2
+    # A and P share their product shapes here (D and R vs D and Rhat^{-1}): one key
+    assert '"entries"' in text and text.count('"key"') >= 1
     x1, i1, _ = h.solve(dev(rhs), nrhs, rtol=1e-9, maxit=400)
     x1 = host(x1)
     # another plan changes only the rounding order of the products
