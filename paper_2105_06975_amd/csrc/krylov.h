@@ -4,7 +4,7 @@
 
 namespace svar {
 
-#define KR_EPT 4                 // elements per thread of the Gram-Schmidt passes
+#define KR_EPT 8                 // elements per thread of the Gram-Schmidt passes
 #define KR_TASK (256 * KR_EPT)   // elements per task (workgroup) of a pass
 #define KR_MAX_CYCLE 2500        // basis vectors per FGMRES cycle (LDS of the small steps)
 
