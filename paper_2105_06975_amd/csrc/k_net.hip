@@ -167,7 +167,7 @@ __global__ __launch_bounds__(64) void k_net_feat(const SRC* __restrict__ src,
   const double isg = inv_sigma ? inv_sigma[P.sys] : 1.0;
   const int e = min((P.blk / k) * k + k - 1, P.nb - 1);
   const int hot = 1 + S + (e - P.blk);
-  E* o = X0 + (P.row0 - row_base + pos) * NET_CIN1;
+  alignas(16) E vals[NET_CIN1];
 #pragma unroll
   for (int c = 0; c < NET_CIN1; ++c) {
     float v = 0.0f;
@@ -179,8 +179,13 @@ __global__ __launch_bounds__(64) void k_net_feat(const SRC* __restrict__ src,
     } else if (c == hot) {
       v = 1.0f;
     }
-    o[c] = to_e<E>(v);
+    vals[c] = to_e<E>(v);
   }
+  // the row (16 channels) is written as 16-byte pieces
+  uint4* o = (uint4*)(X0 + (P.row0 - row_base + pos) * NET_CIN1);
+  const uint4* vv = (const uint4*)vals;
+#pragma unroll
+  for (int i = 0; i < NET_CIN1 * (int)sizeof(E) / 16; ++i) o[i] = vv[i];
 }
 
 // ------------------------------------------------------------------ convolution, 64 outputs
@@ -209,19 +214,51 @@ __global__ __launch_bounds__(256) void k_net_conv(const E* __restrict__ in, E* _
   for (int ks = 0; ks < NKS; ++ks)
     bw[ks] = MM::ld(W + (int64_t)co * (NET_W * CIN) + ks * MM::KS + q * EPL);
   const float bco = BWD ? 0.0f : bias[co];
-  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+  // the input rows of the next tile are loaded into registers while the current tile's
+  // MFMAs run (PF pieces of 8 bytes per thread), then moved to LDS between two barriers
+  constexpr int NPC = NET_ROWS * CPR;             // 8-byte pieces per tile
+  constexpr int PF = (NPC + 255) / 256;
+  uint2 pre[PF];
+  auto fetch = [&](int ti, bool& act) {
     const NetTile T = tiles[ti];
     const NetSample P = smp[T.sample];
-    if (off && off[P.sys]) continue;  // uniform over the workgroup
+    act = !(off && off[P.sys]);  // uniform over the workgroup
+    if (!act) return;
     const int64_t rb = P.row0 - row_base;
-    __syncthreads();
-    for (int c = threadIdx.x; c < NET_ROWS * CPR; c += 256) {
-      const int rr = c / CPR, cc = c - rr * CPR;
-      const int p = wrap(T.pos0 - NET_HALO + rr, P.s);
-      const uint2 v = *(const uint2*)((const char*)(in + (rb + p) * CIN) + cc * 8);
-      *(uint2*)((char*)(tile + rr * STR) + cc * 8) = v;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int c = threadIdx.x + 256 * i;
+      if (c < NPC) {
+        const int rr = c / CPR, cc = c - rr * CPR;
+        const int p = wrap(T.pos0 - NET_HALO + rr, P.s);
+        pre[i] = *(const uint2*)((const char*)(in + (rb + p) * CIN) + cc * 8);
+      }
     }
-    __syncthreads();
+  };
+  auto park = [&]() {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int c = threadIdx.x + 256 * i;
+      if (c < NPC) {
+        const int rr = c / CPR, cc = c - rr * CPR;
+        *(uint2*)((char*)(tile + rr * STR) + cc * 8) = pre[i];
+      }
+    }
+  };
+  bool act_cur = false;
+  if ((int)blockIdx.x < ntiles) {
+    fetch(blockIdx.x, act_cur);
+    if (act_cur) park();
+  }
+  __syncthreads();
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const int tn = ti + gridDim.x;
+    bool act_next = false;
+    if (tn < ntiles) fetch(tn, act_next);
+    const NetTile T = tiles[ti];
+    const NetSample P = smp[T.sample];
+    const int64_t rb = P.row0 - row_base;
+    if (act_cur) {
     v4f acc[4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -247,6 +284,122 @@ __global__ __launch_bounds__(256) void k_net_conv(const E* __restrict__ in, E* _
           v = fmaxf(v + bco, 0.0f);
         out[o] = to_e<E>(v);
       }
+    }
+    __syncthreads();  // every wave is done with this tile's rows
+    if (tn < ntiles && act_next) park();
+    __syncthreads();
+    act_cur = act_next;
+  }
+}
+
+// bfloat16 inference variant: the 4 waves form a 2 x 2 grid over (grid points, output
+// channels): wave w takes points 32 (w & 1) .. +31 and channels 32 (w >> 1) .. +31, i.e. 2 x 2
+// accumulator tiles, with its two 16-channel weight slices in registers.  Each staged input
+// fragment is read from LDS by two waves (four in the float32 kernel above) and feeds two
+// MFMAs, and each workgroup loads every weight twice (once per channel half).
+template <int CIN>
+__global__ __launch_bounds__(256) void k_net_conv_bf(const uint16_t* __restrict__ in,
+                                                     uint16_t* __restrict__ out,
+                                                     const uint16_t* __restrict__ W,
+                                                     const float* __restrict__ bias,
+                                                     const NetSample* __restrict__ smp,
+                                                     const NetTile* __restrict__ tiles,
+                                                     int ntiles, int64_t row_base,
+                                                     const int* __restrict__ skip,
+                                                     const int* __restrict__ off) {
+  typedef NetMma<uint16_t> MM;
+  constexpr int NKS = NET_W * CIN / 16;
+  constexpr int STR = ConvStride<uint16_t, CIN>::v;
+  constexpr int CPR = CIN * 2 / 8;
+  __shared__ __align__(16) uint16_t tile[NET_ROWS * STR];
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rh = wave & 1, chh = wave >> 1;
+  v4s bw[2][NKS];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+      bw[c][ks] =
+          MM::ld(W + (int64_t)((chh * 2 + c) * 16 + r16) * (NET_W * CIN) + ks * 16 + q * 4);
+  float bco[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) bco[c] = bias[(chh * 2 + c) * 16 + r16];
+  constexpr int NPC = NET_ROWS * CPR;
+  constexpr int PF = (NPC + 255) / 256;
+  uint2 pre[PF];
+  auto fetch = [&](int ti, bool& act) {
+    const NetTile T = tiles[ti];
+    const NetSample P = smp[T.sample];
+    act = !(off && off[P.sys]);
+    if (!act) return;
+    const int64_t rb = P.row0 - row_base;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int c = threadIdx.x + 256 * i;
+      if (c < NPC) {
+        const int rr = c / CPR, cc = c - rr * CPR;
+        const int p = wrap(T.pos0 - NET_HALO + rr, P.s);
+        pre[i] = *(const uint2*)((const char*)(in + (rb + p) * CIN) + cc * 8);
+      }
+    }
+  };
+  auto park = [&]() {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int c = threadIdx.x + 256 * i;
+      if (c < NPC) {
+        const int rr = c / CPR, cc = c - rr * CPR;
+        *(uint2*)((char*)(tile + rr * STR) + cc * 8) = pre[i];
+      }
+    }
+  };
+  bool act_cur = false;
+  if ((int)blockIdx.x < ntiles) {
+    fetch(blockIdx.x, act_cur);
+    if (act_cur) park();
+  }
+  __syncthreads();
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const int tn = ti + gridDim.x;
+    bool act_next = false;
+    if (tn < ntiles) fetch(tn, act_next);
+    if (act_cur) {
+      const NetTile T = tiles[ti];
+      const NetSample P = smp[T.sample];
+      const int64_t rb = P.row0 - row_base;
+      v4f acc[2][2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[rt][c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int kl = ks * 16 + q * 4;
+        const int tp = kl / CIN, ci = kl - tp * CIN;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          const v4s a = MM::ld(tile + (rh * 32 + rt * 16 + r16 + tp) * STR + ci);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) acc[rt][c] = MM::mma(a, bw[c][ks], acc[rt][c]);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int pos = T.pos0 + rh * 32 + rt * 16 + 4 * q + e;
+          if (pos >= P.s) continue;
+          uint16_t* o = out + (rb + pos) * NET_C + chh * 32 + r16;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) o[c * 16] = f2bf(fmaxf(acc[rt][c][e] + bco[c], 0.0f));
+        }
+    }
+    __syncthreads();
+    if (tn < ntiles && act_next) park();
+    __syncthreads();
+    act_cur = act_next;
   }
 }
 
@@ -262,22 +415,39 @@ __global__ __launch_bounds__(64) void k_net_out(const E* __restrict__ a3,
                                                 const double* __restrict__ sigma,
                                                 const int* __restrict__ off,
                                                 const int* __restrict__ skip) {
+  // the tile's 68 input rows are staged in LDS (16-byte pieces, coalesced) and each thread
+  // contracts its 5 x 64 window from there
+  constexpr int VE = 16 / (int)sizeof(E);        // elements per 16-byte piece
+  constexpr int OSTR = NET_C + VE;               // row stride (elements), 16-byte aligned
+  constexpr int PPR = NET_C / VE;                // pieces per row
   __shared__ float w[NET_W * NET_C];
+  __shared__ __align__(16) E tile[NET_ROWS * OSTR];
   if (skip && *skip) return;
   const NetTile T = tiles[blockIdx.x];
   const NetSample P = smp[T.sample];
   if (off && off[P.sys]) return;
+  const int64_t rb = P.row0 - row_base;
   for (int i = threadIdx.x; i < NET_W * NET_C; i += 64) w[i] = w4[i];
+  for (int c = threadIdx.x; c < NET_ROWS * PPR; c += 64) {
+    const int rr = c / PPR, cc = c - rr * PPR;
+    const int p = wrap(T.pos0 - NET_HALO + rr, P.s);
+    *(uint4*)(tile + rr * OSTR + cc * VE) = *(const uint4*)(a3 + (rb + p) * NET_C + cc * VE);
+  }
   __syncthreads();
   const int pos = T.pos0 + threadIdx.x;
   if (pos >= P.s) return;
-  const int64_t rb = P.row0 - row_base;
   float acc = b4[0];
+#pragma unroll
   for (int t = 0; t < NET_W; ++t) {
-    const E* row = a3 + (rb + wrap(pos + t - NET_HALO, P.s)) * NET_C;
+    const E* row = tile + (threadIdx.x + t) * OSTR;
     const float* wt = w + t * NET_C;
-#pragma unroll 16
-    for (int c = 0; c < NET_C; ++c) acc += wt[c] * to_f<E>(row[c]);
+#pragma unroll
+    for (int c16 = 0; c16 < PPR; ++c16) {
+      const uint4 v = *(const uint4*)(row + c16 * VE);
+      const E* e = (const E*)&v;
+#pragma unroll
+      for (int i = 0; i < VE; ++i) acc += wt[c16 * VE + i] * to_f<E>(e[i]);
+    }
   }
   if (APPLY) {
     dst[P.src + (int64_t)P.blk * P.s + pos] += sigma[P.sys] * (double)acc;
@@ -555,8 +725,9 @@ void net_conv(int bf16, int cin16, int bwd, const void* in, void* out, const voi
                      (const E*)W, bias, mask, smp, tiles, ntiles, row_base, skip, off)
   if (bf16) {
     if (cin16)
-      NET_CONV(uint16_t, 16, 0);
-    else
+      hipLaunchKernelGGL(k_net_conv_bf<NET_CIN1>, g, b, 0, st, (const uint16_t*)in, (uint16_t*)out,
+                         (const uint16_t*)W, bias, smp, tiles, ntiles, row_base, skip, off);
+    else  // measured faster for 64 input channels than the 2 x 2 variant
       NET_CONV(uint16_t, 64, 0);
   } else if (bwd) {
     NET_CONV(float, 64, 1);
