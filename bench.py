@@ -69,6 +69,10 @@ def parse():
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
     ap.add_argument("--plain-only", action="store_true",
                     help="time only the plain FP64 path (no training)")
+    ap.add_argument("--n-bound", type=int, default=6,
+                    help="later segment starts the network sees (1 + n_bound + k <= 16)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the GEMM autotuning of the batched path")
     ap.add_argument("--patience", type=int, default=10,
                     help="failing FGMRES steps in a row before the network is switched off")
     ap.add_argument("--calib-copy", action="store_true",
@@ -195,7 +199,7 @@ def main():
         x, y = svar.make_pairs(chat, cex)
         del chat, cex
         t_h = time.time() - t0
-        net = svar.Net(args.k, 2, "BF16")
+        net = svar.Net(args.k, args.n_bound, "BF16")
         net.set_params(wl.net_init(net.cin, 64, seed=0))
         t0 = time.time()
         hist = learned.train(net, x, y, epochs=args.epochs, batch=64, lr=1e-3, seed=0, log=log)
@@ -207,6 +211,12 @@ def main():
         log(f"training: {npairs} pairs harvested in {t_h:.1f}s, {args.epochs} epochs in "
             f"{t_t:.1f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
         h.set_net(net)
+        t_tune = 0.0
+        if not args.no_autotune:
+            t0 = time.time()
+            h.autotune(R, args.precision, args.tune_cache)
+            t_tune = time.time() - t0
+            log(f"GEMM autotuning for {R} rhs: {t_tune:.1f}s")
         # ---- learned + batched
         kw = dict(rtol=args.rtol, maxit=700, fallback_patience=args.patience)
         if args.precision != "FP64":
@@ -235,6 +245,7 @@ def main():
             "iters_mean": it_b, "fallbacks": int(sum(i["fallbacks"] for i in infos_b)),
             "relres_true_max": float(max(i["relres_true"] for i in infos_b)),
             "x_rel_diff_vs_plain_fp64_max": max(errs),
+            "autotune_s": t_tune, "n_bound": args.n_bound,
             "training": {"pairs": npairs, "windows": args.train_windows, "epochs": args.epochs,
                          "harvest_s": t_h, "train_s": t_t, "loss_first": hist[0],
                          "loss_last": hist[-1]}}
