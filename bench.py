@@ -33,9 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Gram-Schmidt passes, C2 x 8 rhs: HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters
 # (fetch scaled by 2.000, write by 1.000 from the calibration map in the same runs) over the
-# timed region, divided by the algorithmic bytes per launch of that run (8.976 GB / 8.97 GB).
+# timed region, divided by the algorithmic bytes per launch of that run (6.991 GB / 7.028 GB).
 # Valid while k_fg_dot / k_fg_update are unchanged.
-ORTHO_TRAFFIC_RATIO = 8.976 / 8.97
+ORTHO_TRAFFIC_RATIO = 6.991 / 7.028
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -156,7 +156,9 @@ def main():
             h.timing_enable(kc, False)
         return el, outs, tm
 
-    # ---- plain FP64, one right-hand side per solve (reference path)
+    # ---- plain FP64, one right-hand side per solve (reference path), with its own tuned plans
+    if not args.no_autotune:
+        h.autotune(1, "FP64", args.tune_cache)
     xs_plain = {}
 
     def plain(i):
