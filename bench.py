@@ -33,9 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Gram-Schmidt passes, C2 x 8 rhs: HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters
 # (fetch scaled by 2.000, write by 1.000 from the calibration map in the same runs) over the
-# timed region, divided by the algorithmic bytes per launch of that run (6.991 GB / 7.028 GB).
+# timed region, divided by the algorithmic bytes per launch of that run (6.975 GB / 7.028 GB).
 # Valid while k_fg_dot / k_fg_update are unchanged.
-ORTHO_TRAFFIC_RATIO = 6.991 / 7.028
+ORTHO_TRAFFIC_RATIO = 6.975 / 7.028
 FP64_PEAK_TFLOPS = 78.6
 
 
