@@ -115,6 +115,7 @@ struct svar_handle {
   struct Kry {
     int nrhs = -1, m = 0;
     int64_t ntot = 0;
+    int64_t ldv = 0;  // element stride between basis vectors (ntot padded, see ensure_krylov)
     svar::KPlan plan;
     double *V = nullptr, *Z = nullptr, *u = nullptr, *w = nullptr, *z = nullptr;
     double *r = nullptr, *xs = nullptr, *part = nullptr, *npart = nullptr, *sums = nullptr;

@@ -51,6 +51,9 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   K.nrhs = nrhs;
   K.m = m;
   K.ntot = ntot;
+  // basis stride: ntot rounded to 4 KB plus 12.5 KB, so that consecutive basis vectors do not
+  // start at the same offset modulo large powers of two (they are read side by side)
+  K.ldv = (ntot + 511) / 512 * 512 + 1600;
   const int SL = 2 * m + 2;
   auto& A = K.allocs;
   SVAR_TRY(dalloc(A, &K.plan.tasks, tasks.size()));
@@ -61,8 +64,8 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
                           st));
   K.plan.ntask = (int)tasks.size();
   K.plan.nsys = nsys;
-  SVAR_TRY(dalloc(A, &K.V, (size_t)m * ntot));
-  SVAR_TRY(dalloc(A, &K.Z, (size_t)m * ntot));
+  SVAR_TRY(dalloc(A, &K.V, (size_t)m * K.ldv));
+  SVAR_TRY(dalloc(A, &K.Z, (size_t)m * K.ldv));
   SVAR_TRY(dalloc(A, &K.u, (size_t)ntot));
   SVAR_TRY(dalloc(A, &K.w, (size_t)ntot));
   SVAR_TRY(dalloc(A, &K.z, (size_t)ntot));
@@ -140,12 +143,12 @@ static int fg_step(svar_handle* h, int m, const Program& PA, const Program& PP, 
   SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip));
   hipEvent_t e0, e1;
   timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
-  kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 1, K.part, st);
+  kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ldv, m, 1, K.part, st);
   timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
   kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, jl, st);
   kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, jl, net_off, drop, patience, st);
   timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
-  kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ntot, K.npart, jl, st);
+  kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ldv, K.npart, jl, st);
   timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
   kr_advance(K.gl, st);
   return SVAR_OK;
@@ -254,12 +257,12 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
   if (!all_done) {
     // every basis slot is used: finalise column m-1 without a new product
     kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
-    kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ntot, m, 0, K.part, st);
+    kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ldv, m, 0, K.part, st);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, m, st);
     kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, net_off, drop, patience, st);
   }
   kr_solve_y(K.plan, K.st, K.hs, m, st);
-  kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ntot, x, m, st);
+  kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ldv, x, m, st);
   out.resize(K.plan.nsys);
   SVAR_HIP(hipMemcpyAsync(out.data(), K.st, K.plan.nsys * sizeof(KState), hipMemcpyDeviceToHost,
                           st));
