@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict_
 // stage's global loads are in flight while the MFMAs consume the current stage (two LDS
 // buffers, one barrier per stage).
 template <int CT, typename CS, typename AT>
-__global__ __launch_bounds__(256) void k_gemm_tiled(const GemmProb* __restrict__ probs,
+__global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restrict__ probs,
                                                     const GemmTask* __restrict__ tasks,
                                                     double* __restrict__ ws, Bases b,
                                                     const int* __restrict__ skip) {
@@ -340,6 +340,9 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(const GemmProb* __restrict__
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma_of<AT>::op(av[rt], bv[ct], acc[rt][ct]);
+      // keep each sub-step's LDS reads next to its MFMAs (fewer live registers: two waves
+      // per SIMD fit, which hides the LDS latency and the stage barrier)
+      __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (s + 1 < nst) sstore(buf ^ 1);
