@@ -63,13 +63,29 @@ template <> struct NetMma<uint16_t> {
   static __device__ __forceinline__ frag ld(const uint16_t* p) { return *(const v4s*)p; }
 };
 
+// bfloat16 with a 32-long contraction per instruction (v_mfma_f32_16x16x32_bf16: lane l holds
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j < 8; result row 4 (l / 16) + e, as
+// checked on the device against a host product); used where the contraction length is a
+// multiple of 32 (64 input channels)
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+struct NetMma32 {
+  static constexpr int KS = 32;
+  typedef bf8 frag;
+  static __device__ __forceinline__ v4f mma(frag a, frag b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ frag ld(const uint16_t* p) { return *(const bf8*)p; }
+};
+template <typename E, int CIN> struct ConvMma { typedef NetMma<E> type; };
+template <> struct ConvMma<uint16_t, 64> { typedef NetMma32 type; };
+
 // LDS row strides (elements), chosen so that the 16 rows read by one lane group fall in
-// distinct banks and every row starts on an 8-byte boundary
+// distinct banks and every row starts on an 8-byte (16-byte for 16-byte reads) boundary
 template <typename E, int CIN> struct ConvStride;
 template <> struct ConvStride<float, 16> { static constexpr int v = 18; };
 template <> struct ConvStride<float, 64> { static constexpr int v = 66; };
 template <> struct ConvStride<uint16_t, 16> { static constexpr int v = 20; };
-template <> struct ConvStride<uint16_t, 64> { static constexpr int v = 68; };
+template <> struct ConvStride<uint16_t, 64> { static constexpr int v = 72; };
 
 // ------------------------------------------------------------------ parameters
 __global__ void k_net_pack(const float* __restrict__ th, NetLayout L, NetWeights W) {
@@ -199,7 +215,7 @@ __global__ __launch_bounds__(256) void k_net_conv(const E* __restrict__ in, E* _
                                                   int64_t row_base,
                                                   const int* __restrict__ skip,
                                                   const int* __restrict__ off) {
-  typedef NetMma<E> MM;
+  typedef typename ConvMma<E, CIN>::type MM;
   constexpr int EPL = MM::KS / 4;            // operand elements per lane
   constexpr int NKS = NET_W * CIN / MM::KS;  // contraction steps
   constexpr int STR = ConvStride<E, CIN>::v;
