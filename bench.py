@@ -69,8 +69,8 @@ def parse():
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
     ap.add_argument("--plain-only", action="store_true",
                     help="time only the plain FP64 path (no training)")
-    ap.add_argument("--n-bound", type=int, default=12,
-                    help="later segment starts the network sees (1 + n_bound + k <= 16)")
+    ap.add_argument("--n-bound", type=int, default=20,
+                    help="later segment starts the network sees (1 + n_bound + k <= 32)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the GEMM autotuning of the batched path")
     ap.add_argument("--patience", type=int, default=10,

@@ -267,7 +267,7 @@ int svar_timing_read(svar_handle* h, int32_t kclass, double* total_ms, int64_t* 
 typedef struct svar_net svar_net;
 typedef struct svar_net_desc {
   int32_t k;          /* segment length of the corrected sweep (the handle's k), >= 1      */
-  int32_t n_bound;    /* later segment starts used as inputs, >= 0, 1 + n_bound + k <= 16  */
+  int32_t n_bound;    /* later segment starts used as inputs, >= 0, 1 + n_bound + k <= 32  */
   int32_t precision;  /* SVAR_NET_* of the inference inside the preconditioner             */
   int32_t pad;
 } svar_net_desc;

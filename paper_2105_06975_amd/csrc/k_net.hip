@@ -24,6 +24,7 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 
 static constexpr int GRID_CAP = 1024;
 int net_grid_cap() { return GRID_CAP; }
+static_assert(NET_CIN1 == 16 || NET_CIN1 == 32, "layer-1 kernels are instantiated for 16 or 32 channels");
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
   uint32_t u = __float_as_uint(f);
@@ -83,8 +84,10 @@ template <> struct ConvMma<uint16_t, 64> { typedef NetMma32 type; };
 // distinct banks and every row starts on an 8-byte (16-byte for 16-byte reads) boundary
 template <typename E, int CIN> struct ConvStride;
 template <> struct ConvStride<float, 16> { static constexpr int v = 18; };
+template <> struct ConvStride<float, 32> { static constexpr int v = 34; };
 template <> struct ConvStride<float, 64> { static constexpr int v = 66; };
 template <> struct ConvStride<uint16_t, 16> { static constexpr int v = 20; };
+template <> struct ConvStride<uint16_t, 32> { static constexpr int v = 36; };
 template <> struct ConvStride<uint16_t, 64> { static constexpr int v = 72; };
 
 // ------------------------------------------------------------------ parameters
@@ -560,7 +563,7 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const float* __restrict__ g,
                                                    const NetTile* __restrict__ tiles,
                                                    int ntiles, float* __restrict__ part) {
   constexpr int GS = 80;                     // = 16 mod 32
-  constexpr int AS = CIN == 64 ? 80 : 48;    // = 16 mod 32
+  constexpr int AS = CIN == 64 ? 80 : 48;    // = 16 mod 32 (CIN = 16 or 32 fit in 48)
   constexpr int NCT = NET_W * CIN / 16;      // column tiles
   constexpr int CTW = (NCT + 3) / 4;         // column tiles per wave
   constexpr int NE = NET_C * NET_W * CIN + NET_C;
@@ -748,7 +751,7 @@ void net_conv(int bf16, int cin16, int bwd, const void* in, void* out, const voi
   } else if (bwd) {
     NET_CONV(float, 64, 1);
   } else if (cin16) {
-    NET_CONV(float, 16, 0);
+    NET_CONV(float, NET_CIN1, 0);
   } else {
     NET_CONV(float, 64, 0);
   }

@@ -2,7 +2,7 @@
 // inside the preconditioner).  Layout conventions:
 //   * an activation tensor is [row][channel] with the channel contiguous; the rows of one
 //     sample (one block of one system) are its s grid points, consecutive;
-//   * layer l's weights for the MFMA kernels are Wk[co][t * CIN + ci] (CIN = 16 padded
+//   * layer l's weights for the MFMA kernels are Wk[co][t * CIN + ci] (CIN = 32 padded
 //     input channels for layer 1, 64 otherwise), t the tap of the width-5 stencil;
 //   * the flat parameter vector keeps the host order W1 (64, cin, 5), b1, W2, b2, W3, b3,
 //     W4 (1, 64, 5), b4.
@@ -20,7 +20,7 @@ namespace svar {
 #define NET_C 64                        // hidden channels
 #define NET_W 5                         // stencil width
 #define NET_HALO 2
-#define NET_CIN1 16                     // padded input channels of layer 1
+#define NET_CIN1 32                     // padded input channels of layer 1
 #define NET_TILE 64                     // grid points per tile
 #define NET_ROWS (NET_TILE + NET_W - 1) // staged input rows per tile
 #define NET_WG_PART (NET_C * NET_W * NET_C + NET_C)  // largest per-workgroup gradient part

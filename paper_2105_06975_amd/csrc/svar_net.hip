@@ -163,7 +163,7 @@ int svar_net_create(const svar_net_desc* d, svar_net** out) {
   if (!d) return inv("desc is NULL");
   if (d->k < 1) return inv("need k >= 1");
   if (d->n_bound < 0 || 1 + d->n_bound + d->k > NET_CIN1)
-    return inv("need n_bound >= 0 and 1 + n_bound + k <= 16");
+    return inv("need n_bound >= 0 and 1 + n_bound + k <= 32");
   if (d->precision != SVAR_NET_FP32 && d->precision != SVAR_NET_BF16)
     return inv("bad network precision");
   svar_net* n = new svar_net();

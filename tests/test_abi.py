@@ -76,7 +76,7 @@ def test_errors_without_device_calls():
     assert lib.svar_system_size(None, 0) == -1
     # network argument checks (no device call before validation)
     n = ctypes.c_void_p()
-    d = sv.NetDesc(3, 20, 1, 0)  # 1 + 20 + 3 > 16 input channels
+    d = sv.NetDesc(3, 40, 1, 0)  # 1 + 40 + 3 > 32 input channels
     assert lib.svar_net_create(ctypes.byref(d), ctypes.byref(n)) == sv.E_INVAL
     assert b"n_bound" in lib.svar_last_error()
     assert lib.svar_net_nparams(None) == -1
