@@ -595,6 +595,18 @@ void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double
   hipLaunchKernelGGL(k_fg_xupdate, dim3(p.ntask), dim3(NT), (size_t)(m + 1) * sizeof(double), st,
                      p.tasks, stt, hs, Zb, ntot, x);
 }
+int kr_resident_tasks() {
+  int dev = 0, cus = 0, a = 0, b = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_fg_dot<KR_EPT>, NT, 0) != hipSuccess)
+    return 0;
+  // the update pass's dynamic LDS (2 m + 2 doubles) is far below what limits its occupancy
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fg_update<KR_EPT>, NT, 0) != hipSuccess)
+    return 0;
+  return cus * std::min(a, b);
+}
 void kr_resid(double* r, const double* rhs, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_resid, dim3(capg(n)), dim3(NT), 0, st, r, rhs, n);
 }

@@ -66,5 +66,8 @@ void kr_solve_y(const KPlan& p, const KState* stt, KHess* hs, int m, hipStream_t
 void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double* Zb,
                 int64_t ntot, double* x, int m, hipStream_t st);
 void kr_resid(double* r, const double* rhs, int64_t n, hipStream_t st);
+// workgroups of the Gram-Schmidt passes resident on the current device at once (both passes:
+// the smaller of the two), 0 if the runtime cannot tell
+int kr_resident_tasks();
 
 }  // namespace svar

@@ -16,6 +16,51 @@
 
 namespace svar {
 
+// Task plan of the Gram-Schmidt passes.  Every workgroup streams the whole basis over its rows,
+// so all tasks run about equally long and a pass proceeds in rounds of `resident` workgroups.
+// The fewest tasks of at most KR_TASK rows can leave the last round partly idle (C2 with 8 rhs:
+// 2600 tasks on 768 slots fill 3.4 rounds).  The rows are then spread over as many tasks as the
+// whole rounds hold, in chunks of 16 rows (128-byte aligned ends), provided every task keeps at
+// least 3/4 of KR_TASK rows: a thread loads its KR_EPT elements whatever the task length, so
+// short tasks waste loads (measured: 1 rhs of C2, 325 full tasks beat 757 tasks of 880 rows by
+// 18 %, while 8 rhs gain 4 % from 3056 tasks of 1744 rows).
+static void gs_tasks(const std::vector<int64_t>& ns, int resident, std::vector<KSys>& sys,
+                     std::vector<KTask>& tasks) {
+  int64_t need = 0;
+  for (int64_t n : ns) need += (n + KR_TASK - 1) / KR_TASK;
+  double grow = 1.0;
+  if (resident > 0 && need > 0) {
+    const int64_t rounds = (need + resident - 1) / resident;
+    grow = (double)(rounds * resident) / (double)need;
+  }
+  auto rows_of = [&](int64_t n, double g) {
+    const int64_t t0 = (n + KR_TASK - 1) / KR_TASK;
+    const int64_t want = std::max<int64_t>(t0, (int64_t)(t0 * g));
+    return std::min<int64_t>(KR_TASK, ((n + want - 1) / want + 15) / 16 * 16);
+  };
+  for (int64_t n : ns)
+    if (n >= KR_TASK && 4 * rows_of(n, grow) < 3 * KR_TASK) grow = 1.0;
+  sys.assign(ns.size(), KSys{});
+  tasks.clear();
+  int64_t off = 0;
+  for (size_t si = 0; si < ns.size(); ++si) {
+    const int64_t n = ns[si];
+    const int64_t rows = rows_of(n, grow);
+    sys[si].off = off;
+    sys[si].n = n;
+    sys[si].task0 = (int)tasks.size();
+    for (int64_t e = 0; e < n; e += rows) {
+      KTask t{};
+      t.sys = (int32_t)si;
+      t.e0 = off + e;
+      t.e1 = off + std::min<int64_t>(n, e + rows);
+      tasks.push_back(t);
+    }
+    sys[si].ntask = (int)tasks.size() - sys[si].task0;
+    off += n;
+  }
+}
+
 int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   auto& K = h->kry;
   if (K.nrhs == nrhs && K.m >= m) return SVAR_OK;
@@ -29,25 +74,12 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   const int nw = (int)h->wins.size();
   const int nsys = nw * nrhs;
   const int64_t ntot = handle_total(h, nrhs);
-  std::vector<KSys> sys(nsys);
+  std::vector<int64_t> ns;
+  for (int w = 0; w < nw; ++w)
+    for (int r = 0; r < nrhs; ++r) ns.push_back(h->wins[w].n);
+  std::vector<KSys> sys;
   std::vector<KTask> tasks;
-  int64_t off = 0;
-  for (int w = 0, si = 0; w < nw; ++w)
-    for (int r = 0; r < nrhs; ++r, ++si) {
-      const int64_t n = h->wins[w].n;
-      sys[si].off = off;
-      sys[si].n = n;
-      sys[si].task0 = (int)tasks.size();
-      for (int64_t e = 0; e < n; e += KR_TASK) {
-        KTask t{};
-        t.sys = si;
-        t.e0 = off + e;
-        t.e1 = off + std::min<int64_t>(n, e + KR_TASK);
-        tasks.push_back(t);
-      }
-      sys[si].ntask = (int)tasks.size() - sys[si].task0;
-      off += n;
-    }
+  gs_tasks(ns, kr_resident_tasks(), sys, tasks);
   K.nrhs = nrhs;
   K.m = m;
   K.ntot = ntot;
