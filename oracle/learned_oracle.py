@@ -129,6 +129,28 @@ def forward(theta: np.ndarray, X: np.ndarray, C: int, keep: bool = False):
     return out
 
 
+# =================================================================== bfloat16 storage model
+def round_bf16(x) -> np.ndarray:
+    """Round to float32 (ties to even), then to bfloat16 (8 significant bits, ties to even);
+    the storage format of the matrix-core inference.  Returns float64 values."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta: np.ndarray, X: np.ndarray, C: int) -> np.ndarray:
+    """The network with bfloat16 storage: inputs, the weights of the three hidden layers and
+    the hidden activations rounded to bfloat16, every sum exact (float64), biases and the
+    output layer's weights as given (float32 values).  The bfloat16 inference kernels
+    accumulate in float32, so they differ from this only by accumulation rounding."""
+    W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta, X.shape[1], C)
+    a = round_bf16(X)
+    for W, b in ((W1, b1), (W2, b2), (W3, b3)):
+        a = round_bf16(np.maximum(conv_periodic(a, round_bf16(W), b), 0.0))
+    return conv_periodic(a, W4, b4)[:, 0, :]
+
+
 def loss_and_grad(theta: np.ndarray, X: np.ndarray, Y: np.ndarray, C: int):
     """Mean squared error L = sum (out - Y)^2 / Y.size and dL/dtheta (flat layout)."""
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta, X.shape[1], C)

@@ -475,6 +475,175 @@ __global__ __launch_bounds__(64) void k_net_out(const E* __restrict__ a3,
   }
 }
 
+// ------------------------------------------------------------------ fused inference (bfloat16)
+// The whole network on one tile of NET_FTILE output points of one sample, every intermediate
+// activation in LDS: the features of NET_FTILE + 16 staged rows (8 halo rows per side, 2 per
+// width-5 layer), three MFMA convolutions and the output layer.  Every layer is computed on all
+// staged rows; an output row depends on input rows r-2..r+2 only, so the valid rows shrink by 2
+// per side and layer and the last layer's rows 8 .. 8 + NET_FTILE - 1 are exact.  The staged
+// rows are the periodic extension of the sample (positions mod s), which makes this the same
+// as applying each periodic layer to the whole sample, for any s.  Wave w keeps the weights of
+// output channels 16w..16w+15 of the three convolutions in registers for the whole launch
+// (persistent workgroups loop over the tiles); hidden activations are rounded to bfloat16 as in
+// the layer-by-layer kernels, accumulation is float32.  The output (the normalised correction,
+// float32) goes to a workspace row per grid point and k_net_apply adds sigma times it to the
+// sweep output afterwards: adding it in place here would race with tiles that still read the
+// vector (halo rows, later segment starts).
+namespace fz {
+constexpr int ROWS = NET_FTILE + 16;    // computed rows per layer
+constexpr int PADR = NET_HALO;          // zero rows above and below (taps past both ends)
+constexpr int LROWS = ROWS + 2 * PADR;  // LDS rows per buffer
+constexpr int SX = NET_CIN1 + 8;        // row strides (elements): 16-byte aligned rows, and the
+constexpr int SA = NET_C + 8;           // 8 rows of one 16-byte read phase in distinct banks
+constexpr int RT = ROWS / 16;           // MFMA row tiles per layer
+constexpr int FRG = 3;                  // row tiles accumulated together
+}  // namespace fz
+static_assert(fz::ROWS % 16 == 0 && 2 * NET_FTILE == 256, "fused tile shape");
+static_assert(NET_CIN1 % 32 == 0, "the fused layer 1 contracts 32 channels per instruction");
+
+// one convolution of the fused kernel: out rows PADR.. = relu(conv(in) + bias) for this
+// lane's output channel co; the RT row tiles in groups of RG independent accumulation chains
+template <int CIN, int STR, int RG>
+__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in,
+                                            uint16_t* __restrict__ out,
+                                            const bf8 (&bw)[NET_W * CIN / 32], float bias, int q,
+                                            int r16, int co) {
+  constexpr int NKS = NET_W * CIN / 32;
+  static_assert(fz::RT % RG == 0, "row tile groups");
+#pragma unroll
+  for (int g = 0; g < fz::RT; g += RG) {
+    v4f acc[RG];
+#pragma unroll
+    for (int j = 0; j < RG; ++j) acc[j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int kl = ks * 32 + q * 8;
+      const int t = kl / CIN, ci = kl - t * CIN;
+      // output row m, tap t reads input row m + t - 2, stored at LDS row m + t
+#pragma unroll
+      for (int j = 0; j < RG; ++j)
+        acc[j] = NetMma32::mma(*(const bf8*)(in + ((g + j) * 16 + r16 + t) * STR + ci), bw[ks],
+                               acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < RG; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        out[((g + j) * 16 + 4 * q + e + fz::PADR) * fz::SA + co] =
+            f2bf(fmaxf(acc[j][e] + bias, 0.0f));
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_net_fused(
+    const double* __restrict__ src, const double* __restrict__ inv_sigma,
+    const NetSample* __restrict__ smp, const NetTile* __restrict__ tiles, int ntiles,
+    int64_t row_base, int k, int S, const uint16_t* __restrict__ W1,
+    const uint16_t* __restrict__ W2, const uint16_t* __restrict__ W3,
+    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
+    const float* __restrict__ w4, const float* __restrict__ b4, float* __restrict__ corr,
+    const int* __restrict__ skip, const int* __restrict__ off) {
+  using namespace fz;
+  __shared__ __align__(16) uint16_t X[LROWS * SX];
+  __shared__ __align__(16) uint16_t A1[LROWS * SA];
+  __shared__ __align__(16) uint16_t A2[LROWS * SA];
+  __shared__ float w4s[NET_W * NET_C];
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int co = wave * 16 + r16;
+  bf8 bw1[NET_W * NET_CIN1 / 32], bw2[NET_W * NET_C / 32], bw3[NET_W * NET_C / 32];
+#pragma unroll
+  for (int ks = 0; ks < NET_W * NET_CIN1 / 32; ++ks)
+    bw1[ks] = *(const bf8*)(W1 + (int64_t)co * (NET_W * NET_CIN1) + ks * 32 + q * 8);
+#pragma unroll
+  for (int ks = 0; ks < NET_W * NET_C / 32; ++ks) {
+    bw2[ks] = *(const bf8*)(W2 + (int64_t)co * (NET_W * NET_C) + ks * 32 + q * 8);
+    bw3[ks] = *(const bf8*)(W3 + (int64_t)co * (NET_W * NET_C) + ks * 32 + q * 8);
+  }
+  const float c1 = b1[co], c2 = b2[co], c3 = b3[co], c4 = b4[0];
+  // zero the buffers once: the pad rows are never written again
+  const uint4 z4 = {0u, 0u, 0u, 0u};
+  for (int i = threadIdx.x; i < LROWS * SX / 8; i += 256) ((uint4*)X)[i] = z4;
+  for (int i = threadIdx.x; i < LROWS * SA / 8; i += 256) {
+    ((uint4*)A1)[i] = z4;
+    ((uint4*)A2)[i] = z4;
+  }
+  for (int i = threadIdx.x; i < NET_W * NET_C; i += 256) w4s[i] = w4[i];
+  __syncthreads();
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const NetTile T = tiles[ti];
+    const NetSample P = smp[T.sample];
+    if (off && off[P.sys]) continue;  // uniform over the workgroup
+    const double isg = inv_sigma[P.sys];
+    const int e = min((P.blk / k) * k + k - 1, P.nb - 1);
+    const int hot = 1 + S + (e - P.blk);
+    // features, channel 0: own block, 1..S: later segment starts (zero past the last block),
+    // then the one-hot of e - blk.  The block values are loaded with consecutive threads on
+    // consecutive grid points (coalesced), the constant channels in a second pass.
+    const int nval = (1 + S) * ROWS;
+#pragma unroll 4
+    for (int it = threadIdx.x; it < nval; it += 256) {
+      const int m = it / ROWS, r = it - m * ROWS;
+      const int b = m == 0 ? P.blk : e + 1 + (m - 1) * k;
+      const int pos = wrap(T.pos0 - 4 * NET_HALO + r, P.s);
+      float x = 0.0f;
+      if (b < P.nb) x = (float)(src[P.src + (int64_t)b * P.s + pos] * isg);
+      X[(r + PADR) * SX + m] = f2bf(x);
+    }
+    for (int it = threadIdx.x; it < ROWS * NET_CIN1; it += 256) {
+      const int r = it / NET_CIN1, c = it - r * NET_CIN1;
+      if (c > S) X[(r + PADR) * SX + c] = c == hot ? (uint16_t)0x3f80u : (uint16_t)0;
+    }
+    __syncthreads();
+    fused_layer<NET_CIN1, SX, FRG>(X, A1, bw1, c1, q, r16, co);
+    __syncthreads();
+    fused_layer<NET_C, SA, FRG>(A1, A2, bw2, c2, q, r16, co);
+    __syncthreads();
+    fused_layer<NET_C, SA, FRG>(A2, A1, bw3, c3, q, r16, co);
+    __syncthreads();
+    // output layer (64 -> 1, float32 weights): point p at row 8 + p, two threads per point
+    // with 32 channels each.  A1 is next written by the following tile's layer 1, after the
+    // barrier that follows its features, so no barrier is needed here.
+    {
+      const int p = threadIdx.x >> 1, h = threadIdx.x & 1;
+      float acc = 0.0f;
+#pragma unroll
+      for (int t = 0; t < NET_W; ++t) {
+        const uint16_t* row = A1 + (4 * NET_HALO + p + t) * SA + h * 32;
+        const float* wt = w4s + t * NET_C + h * 32;
+#pragma unroll
+        for (int c8 = 0; c8 < 4; ++c8) {
+          const uint4 vv = *(const uint4*)(row + c8 * 8);
+          const uint16_t* ev = (const uint16_t*)&vv;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc += wt[c8 * 8 + i] * bf2f(ev[i]);
+        }
+      }
+      acc += __shfl_xor(acc, 1);
+      const int pos = T.pos0 + p;
+      if (h == 0 && pos < P.s) corr[P.row0 - row_base + pos] = acc + c4;
+    }
+  }
+}
+
+// dst += sigma * corr for every point of the tiles (the fused kernel's output)
+__global__ __launch_bounds__(64) void k_net_apply(const float* __restrict__ corr,
+                                                  const NetSample* __restrict__ smp,
+                                                  const NetTile* __restrict__ tiles,
+                                                  int64_t row_base, double* __restrict__ dst,
+                                                  const double* __restrict__ sigma,
+                                                  const int* __restrict__ off,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const NetTile T = tiles[blockIdx.x];
+  const NetSample P = smp[T.sample];
+  if (off && off[P.sys]) return;
+  const int pos = T.pos0 + threadIdx.x;
+  if (pos >= P.s) return;
+  dst[P.src + (int64_t)P.blk * P.s + pos] +=
+      sigma[P.sys] * (double)corr[P.row0 - row_base + pos];
+}
+
 // ------------------------------------------------------------------ training
 __global__ __launch_bounds__(64) void k_net_loss(const float* __restrict__ outv,
                                                  const float* __restrict__ y,
@@ -777,6 +946,34 @@ void net_out(int bf16, const void* a3, const float* w4, const float* b4, const N
       hipLaunchKernelGGL((k_net_out<float, 0>), g, b, 0, st, (const float*)a3, w4, b4, smp,
                          tiles, row_base, outv, dst, sigma, off, skip);
   }
+}
+void net_fused(const double* src, const double* inv_sigma, const NetSample* smp,
+               const NetTile* ftiles, int nftiles, int64_t row_base, int k, int S,
+               const NetWeights& W, const float* theta, const NetLayout& L, float* corr,
+               const int* skip, const int* off, hipStream_t st) {
+  if (nftiles <= 0) return;
+  static int resident = 0;  // workgroups resident on the device at once (2 per CU by design)
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_net_fused, 256, 0) == hipSuccess &&
+        per > 0)
+      resident = cus * per;
+    else
+      resident = GRID_CAP;
+  }
+  hipLaunchKernelGGL(k_net_fused, dim3((unsigned)std::min(nftiles, resident)), dim3(256), 0, st,
+                     src, inv_sigma, smp, ftiles, nftiles, row_base, k, S, W.wb[0], W.wb[1],
+                     W.wb[2], theta + L.b[0], theta + L.b[1], theta + L.b[2], W.w4,
+                     theta + L.b[3], corr, skip, off);
+}
+void net_apply(const float* corr, const NetSample* smp, const NetTile* tiles, int ntiles,
+               int64_t row_base, double* dst, const double* sigma, const int* off,
+               const int* skip, hipStream_t st) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_net_apply, dim3(ntiles), dim3(64), 0, st, corr, smp, tiles, row_base, dst,
+                     sigma, off, skip);
 }
 void net_loss(const float* outv, const float* y, const NetSample* smp, const NetTile* tiles,
               int ntiles, float scale, float* g4, double* lpart, hipStream_t st) {

@@ -22,6 +22,7 @@ namespace svar {
 #define NET_HALO 2
 #define NET_CIN1 32                     // padded input channels of layer 1
 #define NET_TILE 64                     // grid points per tile
+#define NET_FTILE 128                   // grid points per tile of the fused inference kernel
 #define NET_ROWS (NET_TILE + NET_W - 1) // staged input rows per tile
 #define NET_WG_PART (NET_C * NET_W * NET_C + NET_C)  // largest per-workgroup gradient part
 
@@ -90,6 +91,15 @@ void net_conv(int bf16, int cin16, int bwd, const void* in, void* out, const voi
 void net_out(int bf16, const void* a3, const float* w4, const float* b4, const NetSample* smp,
              const NetTile* tiles, int ntiles, int64_t row_base, float* outv, double* dst,
              const double* sigma, const int* off, const int* skip, hipStream_t st);
+// fused bfloat16 inference: corr[row] = NN(features) (normalised, float32) for the fused
+// tiles (NET_FTILE points), then dst += sigma * corr over the ordinary tiles
+void net_fused(const double* src, const double* inv_sigma, const NetSample* smp,
+               const NetTile* ftiles, int nftiles, int64_t row_base, int k, int S,
+               const NetWeights& W, const float* theta, const NetLayout& L, float* corr,
+               const int* skip, const int* off, hipStream_t st);
+void net_apply(const float* corr, const NetSample* smp, const NetTile* tiles, int ntiles,
+               int64_t row_base, double* dst, const double* sigma, const int* off,
+               const int* skip, hipStream_t st);
 // training
 void net_loss(const float* outv, const float* y, const NetSample* smp, const NetTile* tiles,
               int ntiles, float scale, float* g4, double* lpart, hipStream_t st);
@@ -116,6 +126,9 @@ struct NetApp {
   int32_t* chunk0 = nullptr;         // device, nsys + 1
   NetSample* smp = nullptr;          // device
   NetTile* tiles = nullptr;          // device
+  NetTile* ftiles = nullptr;         // device: tiles of NET_FTILE points (fused kernel)
+  int nftiles = 0;
+  std::vector<int> ftile0;           // row chunks: first fused tile (size nrc + 1)
   double *part = nullptr, *sigma = nullptr, *inv_sigma = nullptr;
   std::vector<int> tile0;            // row chunks: first tile (size nrc + 1)
   std::vector<int64_t> row0;         // row chunks: first activation row

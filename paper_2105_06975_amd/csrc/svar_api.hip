@@ -949,15 +949,17 @@ static int add_net(Builder& B, VRef vec) {
   std::vector<NetChunk> ch;
   std::vector<int32_t> c0;
   std::vector<NetSample> smp;
-  std::vector<NetTile> tiles;
+  std::vector<NetTile> tiles, ftiles;
   int64_t rows = 0;
   int sys = 0;
   app->tile0.push_back(0);
+  app->ftile0.push_back(0);
   app->row0.push_back(0);
   for (int w = 0; w < (int)B.h->wins.size(); ++w) {
     const WinDev& W = B.h->wins[w];
     const int64_t len = (int64_t)W.nb * W.s;
     const int tps = (W.s + NET_TILE - 1) / NET_TILE;
+    const int ftps = (W.s + NET_FTILE - 1) / NET_FTILE;
     for (int r = 0; r < B.nrhs; ++r, ++sys) {
       const int64_t off = blk(B.h, w, r, B.nrhs, vec, 0).off;
       app->spans.push_back({off, off + len});
@@ -973,6 +975,7 @@ static int add_net(Builder& B, VRef vec) {
       if (rows - app->row0.back() + len > ROW_CHUNK && rows > app->row0.back()) {
         app->max_rows = std::max(app->max_rows, rows - app->row0.back());
         app->tile0.push_back((int)tiles.size());
+        app->ftile0.push_back((int)ftiles.size());
         app->row0.push_back(rows);
       }
       for (int i = 0; i < W.nb; ++i) {
@@ -986,6 +989,7 @@ static int add_net(Builder& B, VRef vec) {
         const int q = (int)smp.size();
         smp.push_back(S);
         for (int t = 0; t < tps; ++t) tiles.push_back(NetTile{q, t * NET_TILE});
+        for (int t = 0; t < ftps; ++t) ftiles.push_back(NetTile{q, t * NET_FTILE});
         rows += W.s;
       }
     }
@@ -993,14 +997,17 @@ static int add_net(Builder& B, VRef vec) {
   c0.push_back((int)ch.size());
   app->max_rows = std::max(app->max_rows, rows - app->row0.back());
   app->tile0.push_back((int)tiles.size());
+  app->ftile0.push_back((int)ftiles.size());
   app->nsys = sys;
   app->nchunk = (int)ch.size();
   app->ntiles = (int)tiles.size();
+  app->nftiles = (int)ftiles.size();
   auto& A = B.h->allocs;
   SVAR_TRY(upload(A, &app->chunks, ch.data(), ch.size(), B.st));
   SVAR_TRY(upload(A, &app->chunk0, c0.data(), c0.size(), B.st));
   SVAR_TRY(upload(A, &app->smp, smp.data(), smp.size(), B.st));
   SVAR_TRY(upload(A, &app->tiles, tiles.data(), tiles.size(), B.st));
+  SVAR_TRY(upload(A, &app->ftiles, ftiles.data(), ftiles.size(), B.st));
   SVAR_TRY(dalloc(A, &app->part, ch.size()));
   SVAR_TRY(dalloc(A, &app->sigma, (size_t)sys));
   SVAR_TRY(dalloc(A, &app->inv_sigma, (size_t)sys));

@@ -110,7 +110,10 @@ int run_net(svar_handle* h, const NetApp& app, double* base, const int* skip, hi
   if (!n) return SVAR_OK;
   const int bf = n->d.precision == SVAR_NET_BF16 ? 1 : 0;
   const size_t es = bf ? 2 : 4;
-  const int64_t need = app.max_rows * (NET_CIN1 + 2 * NET_C) * (int64_t)es;
+  // bfloat16: the fused kernel needs one float per grid point; float32: the layer-by-layer
+  // kernels need the layer-1 features and two hidden activations
+  const int64_t need = bf ? app.max_rows * (int64_t)sizeof(float)
+                          : app.max_rows * (NET_CIN1 + 2 * NET_C) * (int64_t)es;
   if (need > h->net_ws_bytes) {
     SVAR_HIP(hipStreamSynchronize(st));
     if (h->net_ws) {
@@ -131,9 +134,21 @@ int run_net(svar_handle* h, const NetApp& app, double* base, const int* skip, hi
   void* B = (char*)A + app.max_rows * NET_C * es;
   net_sumsq(base, app.chunks, app.nchunk, app.part, skip, st);
   net_sigma_impl(app.part, app.chunk0, app.chunks, app.nsys, app.sigma, app.inv_sigma, skip, st);
+  const int nrc = (int)app.row0.size();
+  if (bf) {
+    float* corr = (float*)ws;
+    for (int c = 0; c < nrc; ++c) {
+      const int f0 = app.ftile0[c], nf = app.ftile0[c + 1] - f0;
+      const int t0 = app.tile0[c], nt = app.tile0[c + 1] - t0;
+      net_fused(base, app.inv_sigma, app.smp, app.ftiles + f0, nf, app.row0[c], n->d.k,
+                n->d.n_bound, n->W, n->theta, n->L, corr, skip, h->net_off, st);
+      net_apply(corr, app.smp, app.tiles + t0, nt, app.row0[c], base, app.sigma, h->net_off,
+                skip, st);
+    }
+    return SVAR_OK;
+  }
   const void* wl[3];
   for (int l = 0; l < 3; ++l) wl[l] = bf ? (const void*)n->W.wb[l] : (const void*)n->W.wf[l];
-  const int nrc = (int)app.row0.size();
   for (int c = 0; c < nrc; ++c) {
     const int t0 = app.tile0[c], nt = app.tile0[c + 1] - t0;
     const NetTile* tl = app.tiles + t0;

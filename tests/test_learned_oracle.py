@@ -9,7 +9,9 @@
 * the corrected preconditioners: a zero network gives the plain P exactly, an ideal
   correction gives P with the exact L^{-T} (dense solves);
 * the fallback of the flexible GMRES: a useless learned preconditioner triggers it and the
-  solve still reaches the dense solution.
+  solve still reaches the dense solution;
+* the bfloat16 storage model: the rounding on hand-checked bit patterns (ties to even, the
+  float32 step first) and the network on values every step represents exactly.
 """
 import numpy as np
 import pytest
@@ -230,3 +232,43 @@ def test_fallback_patience_ignores_isolated_plateaus():
     _, _, _, fb1 = lo.fgmres_with_fallback(orc.apply_A, flaky, orc.apply_PI_inv, rhs, 1e-8, 400,
                                            patience=1)
     assert fb3 == 0 and fb1 == 1
+
+
+def test_round_bf16_hand_checked():
+    # near 1 the bfloat16 spacing is 2^-7: halfway cases go to the even significand
+    cases = [
+        (1.0, 1.0),
+        (1 + 2**-8, 1.0),                          # tie, 1.0 is even
+        (1 + 3 * 2**-8, 1 + 2**-6),                # tie between odd 1+2^-7 and even 1+2^-6
+        (1 + 2**-8 + 2**-20, 1 + 2**-7),           # above the tie
+        (1 + 2**-8 + 2**-30, 1.0),                 # float32 first drops 2^-30: a tie again
+        (-(1 + 3 * 2**-8), -(1 + 2**-6)),
+        (3.0, 3.0),
+        (255.0, 255.0),                            # 8 significant bits: exact
+        (257.0, 256.0),                            # tie between 256 (even) and 258
+        (0.0, 0.0),
+    ]
+    x = np.array([c[0] for c in cases])
+    y = lo.round_bf16(x)
+    assert np.array_equal(y, np.array([c[1] for c in cases])), y
+
+
+def test_forward_bf16_exact_on_representable_values():
+    # one hidden channel passing channel 0 through (centre tap 1), integer inputs: every
+    # value is a small integer, so the bfloat16 model and the exact network agree bit for bit
+    rng = np.random.default_rng(17)
+    cin, C, s = 3, 1, 10
+    parts = [np.zeros(sh) for sh in lo.param_shapes(cin, C)]
+    parts[0][0, 0, 2] = 1.0                        # W1: relu(x0)
+    parts[2][0, 0, 2] = 1.0                        # W2, W3: identity
+    parts[4][0, 0, 2] = 1.0
+    parts[6][0, 0, :] = [1.0, -2.0, 0.5, 0.25, 3.0]  # W4 (float32 values, kept as given)
+    parts[7][0] = 0.125
+    theta = lo.pack(parts)
+    X = rng.integers(-8, 9, size=(2, cin, s)).astype(np.float64)
+    assert np.array_equal(lo.forward_bf16(theta, X, C), lo.forward(theta, X, C))
+    # and on general values it stays within the bfloat16 error of the exact network
+    theta_r = rng.standard_normal(lo.nparams(cin, 4)) * 0.5
+    Xr = rng.standard_normal((2, cin, s))
+    out, ref = lo.forward_bf16(theta_r, Xr, 4), lo.forward(theta_r, Xr, 4)
+    assert 0 < np.linalg.norm(out - ref) / np.linalg.norm(ref) < 3e-2
