@@ -36,6 +36,10 @@ HBM_PEAK_GBS = 8000.0
 # timed region, divided by the algorithmic bytes per launch of that run (6.9447 GB / 6.9426 GB).
 # Valid while k_fg_dot / k_fg_update and their task plan are unchanged.
 ORTHO_TRAFFIC_RATIO = 6.9447 / 6.9426
+# the same ratio for block Gram-Schmidt (blocks of BLOCK_TRAFFIC_B columns); None until the
+# counters have been taken for the current block kernels
+BLOCK_TRAFFIC_RATIO = None
+BLOCK_TRAFFIC_B = 8
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -64,6 +68,13 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--precision", default="FP64_F32P",
                     help="precision of the learned + batched path")
+    ap.add_argument("--block", type=int, default=0,
+                    help="s-step FGMRES block size of the learned + batched path (0: one "
+                         "column at a time; with the nonlinear network the block basis "
+                         "stagnates)")
+    ap.add_argument("--plain-block", type=int, default=8,
+                    help="also time the batched solve with the plain preconditioner in "
+                         "s-step FGMRES with this block size (0: skip)")
     ap.add_argument("--train-windows", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
@@ -93,6 +104,19 @@ def ortho_bytes(n, iters):
     tot = 0
     for j in range(iters + 1):
         tot += (2 * j + 9) * n * 8
+    return tot
+
+
+def block_ortho_bytes(n, iters, b):
+    """Algorithmic HBM bytes of the four passes over the basis of block Gram-Schmidt
+    (k_bk_dot twice, k_bk_update twice) over all blocks of b columns: a block starting at
+    column j reads V_{0..j} in each pass, the projections read the block's b columns and the
+    updates read and write them: (4 (j + 1) + 6 b) * 8 n."""
+    tot, j = 0, 0
+    while j < iters:
+        bb = min(b, iters - j)
+        tot += (4 * (j + 1) + 6 * bb) * n * 8
+        j += bb
     return tot
 
 
@@ -196,7 +220,7 @@ def main():
         t0 = time.time()
         tw = [wl.make_config_window("c2", seed=101 + i) for i in range(args.train_windows)]
         chat, cex = learned.harvest_pairs(tw, args.k, rtol=args.rtol, maxit=1000,
-                                          cap=args.harvest)
+                                          cap=args.harvest, block=args.block)
         del tw
         x, y = svar.make_pairs(chat, cex)
         del chat, cex
@@ -220,7 +244,7 @@ def main():
             t_tune = time.time() - t0
             log(f"GEMM autotuning for {R} rhs: {t_tune:.1f}s")
         # ---- learned + batched
-        kw = dict(rtol=args.rtol, maxit=700, fallback_patience=args.patience)
+        kw = dict(rtol=args.rtol, maxit=700, fallback_patience=args.patience, block=args.block)
         if args.precision != "FP64":
             kw["precision"] = args.precision
 
@@ -241,7 +265,9 @@ def main():
             f"x vs plain {max(errs):.1e}")
         res.update(value=sps, ms_per_step=1e3 * el_b / args.steps)
         res["config"]["path"] = ("learned + batched: 8 rhs per call, network correction of "
-                                 "the Lhat^-T sweep (bf16 MFMA), %s" % args.precision)
+                                 "the Lhat^-T sweep (bf16 MFMA), %s, %s"
+                                 % (args.precision, "s-step FGMRES, blocks of %d" % args.block
+                                    if args.block >= 2 else "one column per step"))
         res["speedup_vs_plain_fp64"] = sps / sps_plain
         res["learned_batched"] = {
             "iters_mean": it_b, "fallbacks": int(sum(i["fallbacks"] for i in infos_b)),
@@ -252,6 +278,27 @@ def main():
                          "harvest_s": t_h, "train_s": t_t, "loss_first": hist[0],
                          "loss_last": hist[-1]}}
         tm, it_main, ntot_main, steps_main, el_main = tm, it_b, win.n * R, args.steps, el_b
+        if args.plain_block >= 2:
+            # context, not `value`: the batched solve without the network, s-step FGMRES
+            h.set_net(None)
+            kwp = dict(rtol=args.rtol, maxit=700, block=args.plain_block)
+            if args.precision != "FP64":
+                kwp["precision"] = args.precision
+
+            def pblock(i):
+                x, infos, rc = h.solve(rhs_all, R, **kwp)
+                assert rc == svar.OK, infos
+                return infos
+            el_pb, outs_pb, _ = timed(pblock, args.steps, 1)
+            infos_pb = outs_pb[-1]
+            res["plain_batched_block"] = {
+                "value": R * args.steps / el_pb, "unit": "solves/s",
+                "iters_mean": float(np.mean([i["iters"] for i in infos_pb])),
+                "relres_true_max": float(max(i["relres_true"] for i in infos_pb)),
+                "path": "plain P_I (no network), 8 rhs per call, %s, s-step FGMRES with blocks "
+                        "of %d" % (args.precision, args.plain_block)}
+            log(f"plain+batched, blocks of {args.plain_block}: "
+                f"{res['plain_batched_block']['value']:.3f} solves/s")
     res["iters"] = it_main
     # roofline of the dominant kernel class (by measured time in the timed region)
     gms, gl = tm["GEMM"]
@@ -260,7 +307,25 @@ def main():
     res["kernel_time_ms"] = {"gemm": gms, "gemm_launches": gl, "ortho": oms,
                              "ortho_launches": ol, "model_and_net": mms, "model_launches": ml,
                              "timed_region_ms": 1e3 * el_main}
-    if oms >= gms:
+    blk = args.block if (not args.plain_only and args.block >= 2) else 0
+    if oms >= gms and blk:
+        # four timed launches per block: the two projections and the two updates
+        byts = block_ortho_bytes(ntot_main, int(round(it_main)), blk) * steps_main
+        ach = byts / (oms * 1e-3) / 1e9
+        per_launch = byts / max(ol, 1)
+        res["roofline"] = {"bound": "hbm",
+                           "kernel": "k_bk_dot + k_bk_update (block Gram-Schmidt passes over "
+                                     "the basis)",
+                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS,
+                           "traffic": (BLOCK_TRAFFIC_RATIO * per_launch
+                                       if BLOCK_TRAFFIC_RATIO and blk == BLOCK_TRAFFIC_B else None),
+                           "traffic_note": "HBM bytes per launch: measured/algorithmic ratio of "
+                                           "the byte counters (calibrated) times this run's "
+                                           "algorithmic bytes per launch",
+                           "algorithmic_bytes_per_launch": per_launch,
+                           "launches": ol, "avg_ms": oms / max(ol, 1)}
+    elif oms >= gms:
         byts = ortho_bytes(ntot_main, int(round(it_main))) * steps_main
         ach = byts / (oms * 1e-3) / 1e9
         per_launch = byts / max(ol, 1)

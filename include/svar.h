@@ -148,7 +148,17 @@ typedef struct svar_solve_opts {
      stream ordered after / before the caller's stream with events); the results are those
      of the step-by-step launches.  Ignored while harvesting or timing. */
   int32_t use_graph;
-  int32_t pad;
+  /* s-step FGMRES: block >= 2 builds the basis in blocks of `block` (at most 8) columns from
+     one starting vector (preconditioner and A products back to back, each normalised), then
+     orthogonalises the block against the basis with two block classical Gram-Schmidt passes
+     and within itself with two Cholesky QR rounds: four reads of the basis per block instead
+     of two per column.  With a linear preconditioner the iterates are those of one column at
+     a time in exact arithmetic.  A block whose Gram matrix is numerically rank deficient is
+     cut short and ends its cycle (the solve restarts from the float64 true residual while
+     maxit allows).  Cycles hold at most 768 columns.  0 or 1: one column at a time.  A
+     harvest then records every preconditioner input (the block's first vector and its
+     normalised products); no graph replay in block mode. */
+  int32_t block;
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */

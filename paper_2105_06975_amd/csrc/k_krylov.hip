@@ -595,6 +595,557 @@ void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double
   hipLaunchKernelGGL(k_fg_xupdate, dim3(p.ntask), dim3(NT), (size_t)(m + 1) * sizeof(double), st,
                      p.tasks, stt, hs, Zb, ntot, x);
 }
+// ================================================================ s-step (block) FGMRES
+// A block of b columns starts from the last orthonormal basis vector v_j: z_{j+i} =
+// P^{-1} w_i with w_0 = v_j and w_{i+1} = A z_{j+i} / d_i, d_i = ||A z_{j+i}||.  The block
+// W = [w_1..w_b] (basis slots j+1..j+b) is projected out of V_{0..j} twice (block classical
+// Gram-Schmidt with re-orthogonalisation, C = C1 + C2) and orthonormalised by two Cholesky QR
+// rounds (W = Q R, R = R2 R1).  Then A z_{j+i} = d_i (V C e_i + Q R e_i): column j+i of Hbar
+// holds d_i C[:, i] in rows 0..j and d_i R[0..i, i] in rows j+1..j+1+i, which is upper
+// Hessenberg.  Four reads of V per block of b columns instead of two per column.  With a
+// linear preconditioner the columns span the same Krylov space as one vector at a time.
+
+// x *= 1 / ||x|| per system (norm from k_nrm2_part); the norm is kept as d_i of the block
+__global__ __launch_bounds__(NT) void k_bk_scale(const KTask* __restrict__ tasks,
+                                                 const KSys* __restrict__ sys,
+                                                 const double* __restrict__ part,
+                                                 double* __restrict__ x,
+                                                 const KState* __restrict__ st,
+                                                 const KGlobal* __restrict__ gl,
+                                                 KBlock* __restrict__ kb, int i) {
+  __shared__ double red[NT / 64];
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  if (st[t.sys].done) return;
+  const KSys S = sys[t.sys];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < S.ntask; k += NT) acc += part[S.task0 + k];
+  const double nrm = sqrt(block_sum(acc, red));
+  const double sig = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+  for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) x[e] *= sig;
+  if (threadIdx.x == 0 && blockIdx.x == (unsigned)S.task0) kb[t.sys].d[i] = nrm;
+}
+
+// partial sums per task of V_{0..j}^T W: part[task][t * B + i] (columns i >= b are zero)
+template <int B>
+__global__ __launch_bounds__(NT) void k_bk_dot(const KTask* __restrict__ tasks,
+                                               const KState* __restrict__ st,
+                                               const KGlobal* __restrict__ gl,
+                                               const double* __restrict__ V, int64_t ldv, int j,
+                                               int b, int SLB, double* __restrict__ part) {
+  constexpr int EPT = KR_EPT;
+  constexpr int TB = 16 / B;  // basis vectors per exchange batch (16 sums)
+  constexpr int TW = 64 / B;  // basis vectors per LDS window
+  __shared__ double lr[NT / 64][64];
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  if (st[t.sys].done) return;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int len = (int)(t.e1 - t.e0);
+  const double* V0 = V + t.e0;
+  const double* W0 = V0 + (int64_t)(j + 1) * ldv;
+  int cidx[EPT];
+  double wr[B][EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int o = (int)threadIdx.x + q * NT;
+    cidx[q] = min(o, len - 1);
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+      wr[i][q] = (o < len && i < b) ? W0[(int64_t)i * ldv + cidx[q]] : 0.0;
+  }
+  double* P = part + (int64_t)blockIdx.x * SLB;
+  const int nv = j + 1;
+  for (int t0 = 0; t0 < nv; t0 += TW) {
+    const int tn = min(TW, nv - t0);
+    for (int tt = 0; tt < tn; tt += TB) {
+      double acc[16];
+#pragma unroll
+      for (int v = 0; v < TB; ++v) {
+        const double* Vt = V0 + (int64_t)min(t0 + tt + v, nv - 1) * ldv;
+        double a[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) a[i] = 0.0;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const double x = Vt[cidx[q]];
+#pragma unroll
+          for (int i = 0; i < B; ++i) a[i] += x * wr[i][q];
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i) acc[v * B + i] = a[i];
+      }
+      const double s = wave_sum16(acc);
+      const int id = (ln >> 2) & 15, vv = id / B, ii = id - vv * B;
+      if ((ln & 3) == 0 && tt + vv < tn) lr[wv][(tt + vv) * B + ii] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < tn * B) {
+      double a = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) a += lr[w][threadIdx.x];
+      P[t0 * B + threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+}
+
+// sums[sys][slot] = sum over the system's tasks of part[task][slot], slot < nused (fixed
+// order); grid (nsys, ceil(nused / 8)), 8 slots x 32 task lanes per workgroup
+__global__ __launch_bounds__(NT) void k_bk_reduce(const KSys* __restrict__ sys,
+                                                  const KState* __restrict__ st,
+                                                  const KGlobal* __restrict__ gl,
+                                                  const double* __restrict__ part, int SL,
+                                                  int nused, double* __restrict__ sums) {
+  __shared__ double red[8][33];
+  if (gl->all_done) return;
+  if (st[blockIdx.x].done) return;
+  const KSys S = sys[blockIdx.x];
+  const int sl = threadIdx.x >> 5, tl = threadIdx.x & 31;
+  const int slot = blockIdx.y * 8 + sl;
+  double acc = 0.0;
+  if (slot < nused)
+    for (int i = tl; i < S.ntask; i += 32) acc += part[(int64_t)(S.task0 + i) * SL + slot];
+  red[sl][tl] = acc;
+  __syncthreads();
+  if (tl == 0 && slot < nused) {
+    double s = 0.0;
+    for (int i = 0; i < 32; ++i) s += red[sl][i];
+    sums[(int64_t)blockIdx.x * SL + slot] = s;
+  }
+}
+
+// W -= V_{0..j} C (C = the system's reduced sums, [t * B + i])
+template <int B>
+__global__ __launch_bounds__(NT) void k_bk_update(const KTask* __restrict__ tasks,
+                                                  const KState* __restrict__ st,
+                                                  const KGlobal* __restrict__ gl,
+                                                  double* __restrict__ V, int64_t ldv, int j,
+                                                  int b, int SLB, const double* __restrict__ C) {
+  constexpr int EPT = KR_EPT;
+  extern __shared__ double cf[];  // (j + 1) B
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  if (st[t.sys].done) return;
+  const int nv = j + 1;
+  const double* Cs = C + (int64_t)t.sys * SLB;
+  for (int i = threadIdx.x; i < nv * B; i += NT) cf[i] = Cs[i];
+  __syncthreads();
+  const int len = (int)(t.e1 - t.e0);
+  const double* V0 = V + t.e0;
+  int cidx[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) cidx[q] = min((int)threadIdx.x + q * NT, len - 1);
+  double acc[B][EPT];
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) acc[i][q] = 0.0;
+  int tt = 0;
+  for (; tt + 2 <= nv; tt += 2) {
+    double v[2][EPT];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) v[u][q] = V0[(int64_t)(tt + u) * ldv + cidx[q]];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const double c = cf[(tt + u) * B + i];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) acc[i][q] += v[u][q] * c;
+      }
+  }
+  for (; tt < nv; ++tt) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const double x = V0[(int64_t)tt * ldv + cidx[q]];
+#pragma unroll
+      for (int i = 0; i < B; ++i) acc[i][q] += x * cf[tt * B + i];
+    }
+  }
+  double* W0 = V + t.e0 + (int64_t)(j + 1) * ldv;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    if (i >= b) break;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int o = (int)threadIdx.x + q * NT;
+      if (o < len) W0[(int64_t)i * ldv + o] -= acc[i][q];
+    }
+  }
+}
+
+// partial Gram matrix W^T W per task: part[task][i * B + l]
+template <int B>
+__global__ __launch_bounds__(NT) void k_bk_gram(const KTask* __restrict__ tasks,
+                                                const KState* __restrict__ st,
+                                                const KGlobal* __restrict__ gl,
+                                                const double* __restrict__ V, int64_t ldv, int j,
+                                                int b, double* __restrict__ part) {
+  constexpr int EPT = KR_EPT;
+  constexpr int NG = B * B;
+  __shared__ double lr[NT / 64][64];
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  if (st[t.sys].done) return;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int len = (int)(t.e1 - t.e0);
+  const double* W0 = V + t.e0 + (int64_t)(j + 1) * ldv;
+  double wr[B][EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int o = (int)threadIdx.x + q * NT;
+    const int c = min(o, len - 1);
+#pragma unroll
+    for (int i = 0; i < B; ++i) wr[i][q] = (o < len && i < b) ? W0[(int64_t)i * ldv + c] : 0.0;
+  }
+#pragma unroll
+  for (int r0 = 0; r0 < NG; r0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int g = r0 + u, i = g / B, l = g - i * B;
+      double a = 0.0;
+      if (g < NG) {
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) a += wr[i][q] * wr[l][q];
+      }
+      acc[u] = a;
+    }
+    const double s = wave_sum16(acc);
+    const int id = (ln >> 2) & 15;
+    if ((ln & 3) == 0 && r0 + id < NG) lr[wv][r0 + id] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NG) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) a += lr[w][threadIdx.x];
+    part[(int64_t)blockIdx.x * NG + threadIdx.x] = a;
+  }
+}
+
+// Cholesky factor of the block's Gram matrix (one thread per system): G = Rc^T Rc for the
+// leading columns whose pivot keeps more than 1e-12 of the column's squared norm; round 0
+// sets R = Rc and blen, round 1 sets R = Rc R and blen = min(blen, passing columns)
+template <int B>
+__global__ void k_bk_chol(const KState* __restrict__ st, const KGlobal* __restrict__ gl,
+                          const double* __restrict__ gsum, KBlock* __restrict__ kb, int nsys,
+                          int b, int round) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys || gl->all_done || st[s].done) return;
+  const double* G = gsum + (int64_t)s * B * B;
+  KBlock& K = kb[s];
+  double R[B][B];
+#pragma unroll
+  for (int l = 0; l < B; ++l)
+#pragma unroll
+    for (int i = 0; i < B; ++i) R[l][i] = 0.0;
+  int nb = 0;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    if (i < b && ok) {
+#pragma unroll
+      for (int l = 0; l < B; ++l) {
+        if (l < i) {
+          double v = G[l * B + i];
+#pragma unroll
+          for (int p = 0; p < B; ++p)
+            if (p < l) v -= R[p][l] * R[p][i];
+          R[l][i] = v / R[l][l];
+        }
+      }
+      double piv = G[i * B + i];
+#pragma unroll
+      for (int p = 0; p < B; ++p)
+        if (p < i) piv -= R[p][i] * R[p][i];
+      if (piv > 1e-12 * G[i * B + i] && piv > 0.0 && isfinite(piv)) {
+        R[i][i] = sqrt(piv);
+        nb = i + 1;
+      } else {
+        ok = false;
+      }
+    }
+  }
+  // columns past the last passing one are not used: keep their factor entries finite
+#pragma unroll
+  for (int l = 0; l < B; ++l)
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      if (i >= nb) R[l][i] = (l == i) ? 1.0 : 0.0;
+      K.Rc[l * B + i] = R[l][i];
+    }
+  if (round == 0) {
+    K.blen = nb;
+#pragma unroll
+    for (int l = 0; l < B; ++l)
+#pragma unroll
+      for (int i = 0; i < B; ++i) K.R[l * B + i] = R[l][i];
+  } else {
+    K.blen = min(K.blen, nb);
+    double P[B][B];
+#pragma unroll
+    for (int l = 0; l < B; ++l)
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < B; ++p) v += R[l][p] * K.R[p * B + i];
+        P[l][i] = v;
+      }
+#pragma unroll
+    for (int l = 0; l < B; ++l)
+#pragma unroll
+      for (int i = 0; i < B; ++i) K.R[l * B + i] = P[l][i];
+  }
+}
+
+// W <- W Rc^{-1} over the leading blen columns (forward substitution per row)
+template <int B>
+__global__ __launch_bounds__(NT) void k_bk_trsm(const KTask* __restrict__ tasks,
+                                                const KState* __restrict__ st,
+                                                const KGlobal* __restrict__ gl,
+                                                double* __restrict__ V, int64_t ldv, int j,
+                                                int b, const KBlock* __restrict__ kb) {
+  constexpr int EPT = KR_EPT;
+  if (gl->all_done) return;
+  const KTask t = tasks[blockIdx.x];
+  if (st[t.sys].done) return;
+  const KBlock& K = kb[t.sys];
+  const int blen = min(K.blen, b);
+  const int len = (int)(t.e1 - t.e0);
+  double* W0 = V + t.e0 + (int64_t)(j + 1) * ldv;
+  double w[B][EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int c = min((int)threadIdx.x + q * NT, len - 1);
+#pragma unroll
+    for (int i = 0; i < B; ++i) w[i][q] = i < blen ? W0[(int64_t)i * ldv + c] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    if (i >= blen) break;
+    const double inv = 1.0 / K.Rc[i * B + i];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      if (l < i) {
+        const double r = K.Rc[l * B + i];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) w[i][q] -= w[l][q] * r;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) w[i][q] *= inv;
+  }
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    if (i >= blen) break;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int o = (int)threadIdx.x + q * NT;
+      if (o < len) W0[(int64_t)i * ldv + o] = w[i][q];
+    }
+  }
+}
+
+// The block's Hessenberg columns j..j+blen-1 of one system (one workgroup per system): built
+// from C = S1 + S2, R and d in LDS; the rotations of earlier columns are applied to every new
+// column at once (one thread per column), then the block's own rotations one column after
+// the other; residual estimate, convergence and the learned-path stall test per column, as in
+// the step-by-step kernel.  A block cut short by the Cholesky test, or the last block of the
+// cycle, ends the system's cycle (the refinement loop restarts it from the true residual).
+template <int B>
+__global__ __launch_bounds__(NT) void k_bk_hess(KState* __restrict__ st, KGlobal* __restrict__ gl,
+                                                const double* __restrict__ S1,
+                                                const double* __restrict__ S2, int SLB,
+                                                const KBlock* __restrict__ kbs,
+                                                KHess* __restrict__ hs, int m, int j, int b,
+                                                int* __restrict__ net_off, double drop,
+                                                int patience) {
+  extern __shared__ double sm[];  // cs[j], sn[j], block cs/sn [2B], columns [b][j + b + 1]
+  __shared__ int nused_s;
+  if (gl->all_done) return;
+  KState S = st[blockIdx.x];
+  if (S.done) return;
+  KHess Hh = hs[blockIdx.x];
+  const KBlock& K = kbs[blockIdx.x];
+  const int blen = min(K.blen, b);
+  const int rows = j + b + 1;
+  double* lcs = sm;
+  double* lsn = sm + j;
+  double* bcs = sm + 2 * j;
+  double* bsn = bcs + B;
+  double* col = bsn + B;
+  const double* C1 = S1 + (int64_t)blockIdx.x * SLB;
+  const double* C2 = S2 + (int64_t)blockIdx.x * SLB;
+  for (int r = threadIdx.x; r < j; r += NT) {
+    lcs[r] = Hh.cs[r];
+    lsn[r] = Hh.sn[r];
+  }
+  for (int idx = threadIdx.x; idx < b * rows; idx += NT) {
+    const int i = idx / rows, r = idx - i * rows;
+    double v = 0.0;
+    if (i < blen) {
+      if (r <= j)
+        v = (C1[r * B + i] + C2[r * B + i]) * K.d[i];
+      else if (r - j - 1 <= i)
+        v = K.R[(r - j - 1) * B + i] * K.d[i];
+    }
+    col[idx] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < blen && j > 0) {
+    double* c = col + threadIdx.x * rows;
+    double carry = c[0];
+    for (int r = 0; r < j; ++r) {
+      const double bq = c[r + 1];
+      c[r] = lcs[r] * carry + lsn[r] * bq;
+      carry = -lsn[r] * carry + lcs[r] * bq;
+    }
+    c[j] = carry;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (j == 0) Hh.g[0] = S.beta;  // r0 = beta v_0
+    int used = 0;
+    for (int i = 0; i < blen && !S.done; ++i) {
+      const int c = j + i;
+      double* cl = col + i * rows;
+      double carry = cl[j];
+      for (int r = j; r < c; ++r) {
+        const double bq = cl[r + 1];
+        cl[r] = bcs[r - j] * carry + bsn[r - j] * bq;
+        carry = -bsn[r - j] * carry + bcs[r - j] * bq;
+      }
+      cl[c] = carry;
+      const double a = cl[c], sub = cl[c + 1];
+      const double rho = hypot(a, sub);
+      double cs = 1.0, sn = 0.0;
+      if (rho > 0.0) {
+        cs = a / rho;
+        sn = sub / rho;
+      }
+      bcs[i] = cs;
+      bsn[i] = sn;
+      cl[c] = rho;
+      cl[c + 1] = 0.0;
+      const double gj = Hh.g[c];
+      Hh.g[c + 1] = -sn * gj;
+      Hh.g[c] = cs * gj;
+      const double prev = S.est;
+      S.est = fabs(Hh.g[c + 1]);
+      if (net_off && drop > 0.0 && !net_off[blockIdx.x]) {
+        if (S.est < (1.0 - drop) * prev) {
+          S.stall = 0;
+        } else if (++S.stall >= patience) {
+          net_off[blockIdx.x] = 1;
+          S.fallback = 1;
+        }
+      }
+      S.iters = c + 1;
+      used = i + 1;
+      if (!(isfinite(S.est) && isfinite(rho))) {
+        S.status = SVAR_E_BREAKDOWN;
+        S.done = 1;
+      } else if (S.est <= S.tol_abs || !(fabs(sub) > 1e-300) || rho == 0.0) {
+        S.done = 1;  // converged, or happy breakdown (invariant Krylov space)
+      }
+    }
+    if (!S.done && (blen < b || j + b >= m)) {
+      S.done = 1;  // cycle ended: block cut short or every basis slot used
+      S.status = SVAR_E_NOCONV;
+    }
+    nused_s = used;
+  }
+  __syncthreads();
+  const int used = nused_s;
+  for (int idx = threadIdx.x; idx < used * rows; idx += NT) {
+    const int i = idx / rows, r = idx - i * rows;
+    if (r <= j + i + 1) Hh.H[(int64_t)(j + i) * (m + 1) + r] = col[idx];
+  }
+  for (int i = threadIdx.x; i < used; i += NT) {
+    Hh.cs[j + i] = bcs[i];
+    Hh.sn[j + i] = bsn[i];
+  }
+  if (threadIdx.x == 0) {
+    st[blockIdx.x] = S;
+    if (S.done) {
+      const int left = atomicSub(&gl->remaining, 1) - 1;
+      if (left == 0) gl->all_done = 1;
+    }
+  }
+}
+
+void kb_scale(const KPlan& p, const double* part, double* x, const KState* stt,
+              const KGlobal* gl, KBlock* kb, int i, hipStream_t st) {
+  hipLaunchKernelGGL(k_bk_scale, dim3(p.ntask), dim3(NT), 0, st, p.tasks, p.sys, part, x, stt, gl,
+                     kb, i);
+}
+void kb_dot(int B, const KPlan& p, const KState* stt, const KGlobal* gl, const double* V,
+            int64_t ldv, int j, int b, int SLB, double* part, hipStream_t st) {
+  if (B == 4)
+    hipLaunchKernelGGL(k_bk_dot<4>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V, ldv,
+                       j, b, SLB, part);
+  else
+    hipLaunchKernelGGL(k_bk_dot<KB_MAX>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V,
+                       ldv, j, b, SLB, part);
+}
+void kb_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const double* part, int SL,
+               int nused, double* sums, hipStream_t st) {
+  hipLaunchKernelGGL(k_bk_reduce, dim3(p.nsys, (nused + 7) / 8), dim3(NT), 0, st, p.sys, stt, gl,
+                     part, SL, nused, sums);
+}
+void kb_update(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double* V,
+               int64_t ldv, int j, int b, int SLB, const double* C, hipStream_t st) {
+  const size_t lds = (size_t)(j + 1) * B * sizeof(double);
+  if (B == 4)
+    hipLaunchKernelGGL(k_bk_update<4>, dim3(p.ntask), dim3(NT), lds, st, p.tasks, stt, gl, V,
+                       ldv, j, b, SLB, C);
+  else
+    hipLaunchKernelGGL(k_bk_update<KB_MAX>, dim3(p.ntask), dim3(NT), lds, st, p.tasks, stt, gl,
+                       V, ldv, j, b, SLB, C);
+}
+void kb_gram(int B, const KPlan& p, const KState* stt, const KGlobal* gl, const double* V,
+             int64_t ldv, int j, int b, double* part, hipStream_t st) {
+  if (B == 4)
+    hipLaunchKernelGGL(k_bk_gram<4>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V, ldv, j,
+                       b, part);
+  else
+    hipLaunchKernelGGL(k_bk_gram<KB_MAX>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V,
+                       ldv, j, b, part);
+}
+void kb_chol(int B, const KPlan& p, const KState* stt, const KGlobal* gl, const double* gsum,
+             KBlock* kb, int b, int round, hipStream_t st) {
+  const dim3 g((p.nsys + 63) / 64), t(64);
+  if (B == 4)
+    hipLaunchKernelGGL(k_bk_chol<4>, g, t, 0, st, stt, gl, gsum, kb, p.nsys, b, round);
+  else
+    hipLaunchKernelGGL(k_bk_chol<KB_MAX>, g, t, 0, st, stt, gl, gsum, kb, p.nsys, b, round);
+}
+void kb_trsm(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double* V, int64_t ldv,
+             int j, int b, const KBlock* kb, hipStream_t st) {
+  if (B == 4)
+    hipLaunchKernelGGL(k_bk_trsm<4>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V, ldv, j,
+                       b, kb);
+  else
+    hipLaunchKernelGGL(k_bk_trsm<KB_MAX>, dim3(p.ntask), dim3(NT), 0, st, p.tasks, stt, gl, V, ldv,
+                       j, b, kb);
+}
+void kb_hess(int B, const KPlan& p, KState* stt, KGlobal* gl, const double* S1, const double* S2,
+             int SLB, const KBlock* kb, KHess* hs, int m, int j, int b, int* net_off,
+             double drop, int patience, hipStream_t st) {
+  const size_t lds = (size_t)(2 * j + 2 * B + b * (j + b + 1)) * sizeof(double);
+  if (B == 4)
+    hipLaunchKernelGGL(k_bk_hess<4>, dim3(p.nsys), dim3(NT), lds, st, stt, gl, S1, S2, SLB, kb, hs,
+                       m, j, b, net_off, drop, patience < 1 ? 1 : patience);
+  else
+    hipLaunchKernelGGL(k_bk_hess<KB_MAX>, dim3(p.nsys), dim3(NT), lds, st, stt, gl, S1, S2, SLB,
+                       kb, hs, m, j, b, net_off, drop, patience < 1 ? 1 : patience);
+}
+
 int kr_resident_tasks() {
   int dev = 0, cus = 0, a = 0, b = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;

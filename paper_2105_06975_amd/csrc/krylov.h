@@ -38,6 +38,15 @@ struct KHess {      // per-system dense storage (device pointers)
   double* hprev;    // m+1: provisional column
   double* coef_s;   // m: re-orthogonalisation coefficients
 };
+// s-step (block) FGMRES: per-system state of the current block of at most KB_MAX columns
+#define KB_MAX 8
+#define KB_MAX_CYCLE 768   // columns per cycle in block mode (LDS of the Hessenberg step)
+struct KBlock {
+  double d[KB_MAX];             // norms of the block's products A z before normalisation
+  double Rc[KB_MAX * KB_MAX];   // the current Cholesky QR round's factor (row major, upper)
+  double R[KB_MAX * KB_MAX];    // product of the rounds' factors
+  int32_t blen, pad;            // leading columns that passed both Cholesky rounds
+};
 struct KPlan {
   KTask* tasks = nullptr;
   KSys* sys = nullptr;
@@ -66,6 +75,25 @@ void kr_solve_y(const KPlan& p, const KState* stt, KHess* hs, int m, hipStream_t
 void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double* Zb,
                 int64_t ntot, double* x, int m, hipStream_t st);
 void kr_resid(double* r, const double* rhs, int64_t n, hipStream_t st);
+// block mode (s-step FGMRES); B = KB_MAX or 4 (template width), b <= B columns, basis slots:
+// V[0..j] orthonormal, V[j+1..j+b] the block W, Z[j..j+b-1] its preconditioned inputs
+void kb_scale(const KPlan& p, const double* part, double* x, const KState* stt,
+              const KGlobal* gl, KBlock* kb, int i, hipStream_t st);
+void kb_dot(int B, const KPlan& p, const KState* stt, const KGlobal* gl, const double* V,
+            int64_t ldv, int j, int b, int SLB, double* part, hipStream_t st);
+void kb_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const double* part, int SL,
+               int nused, double* sums, hipStream_t st);
+void kb_update(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double* V,
+               int64_t ldv, int j, int b, int SLB, const double* C, hipStream_t st);
+void kb_gram(int B, const KPlan& p, const KState* stt, const KGlobal* gl, const double* V,
+             int64_t ldv, int j, int b, double* part, hipStream_t st);
+void kb_chol(int B, const KPlan& p, const KState* stt, const KGlobal* gl, const double* gsum,
+             KBlock* kb, int b, int round, hipStream_t st);
+void kb_trsm(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double* V, int64_t ldv,
+             int j, int b, const KBlock* kb, hipStream_t st);
+void kb_hess(int B, const KPlan& p, KState* stt, KGlobal* gl, const double* S1, const double* S2,
+             int SLB, const KBlock* kb, KHess* hs, int m, int j, int b, int* net_off,
+             double drop, int patience, hipStream_t st);
 // workgroups of the Gram-Schmidt passes resident on the current device at once (both passes:
 // the smaller of the two), 0 if the runtime cannot tell
 int kr_resident_tasks();

@@ -126,6 +126,11 @@ struct svar_handle {
     svar::KHess* hs = nullptr;
     svar::KGlobal* gl_host = nullptr;  // pinned
     int* net_off = nullptr;            // per system: learned correction switched off
+    // block (s-step) mode, allocated on first use: partial and reduced sums of the two
+    // projections (stride slb per task / system), Gram partials and sums, per-system blocks
+    double *bpart = nullptr, *bs1 = nullptr, *bs2 = nullptr, *gpart = nullptr, *gsum = nullptr;
+    svar::KBlock* kb = nullptr;
+    int slb = 0;
     std::vector<void*> allocs;
   } kry;
 };

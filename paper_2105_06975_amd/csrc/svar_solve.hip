@@ -307,15 +307,104 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
   return SVAR_OK;
 }
 
+static int ensure_block(svar_handle* h) {
+  auto& K = h->kry;
+  if (K.bpart) return SVAR_OK;
+  const int slb = (K.m + 1) * KB_MAX;
+  const size_t G = (size_t)KB_MAX * KB_MAX;
+  SVAR_TRY(dalloc(K.allocs, &K.bpart, (size_t)K.plan.ntask * slb));
+  SVAR_TRY(dalloc(K.allocs, &K.bs1, (size_t)K.plan.nsys * slb));
+  SVAR_TRY(dalloc(K.allocs, &K.bs2, (size_t)K.plan.nsys * slb));
+  SVAR_TRY(dalloc(K.allocs, &K.gpart, (size_t)K.plan.ntask * G));
+  SVAR_TRY(dalloc(K.allocs, &K.gsum, (size_t)K.plan.nsys * G));
+  SVAR_TRY(dalloc(K.allocs, &K.kb, (size_t)K.plan.nsys));
+  K.slb = slb;
+  return SVAR_OK;
+}
+
+// One cycle of s-step FGMRES (blocks of s columns, see the block kernels): basis slots
+// V[0..m], Z[0..m-1]; the host reads the all-done flag after every block.
+static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Program& PP,
+                       const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
+                       double drop, int patience, Harvest& hv, hipStream_t st) {
+  int* net_off = h->net_off ? h->kry.net_off : nullptr;
+  SVAR_TRY(ensure_block(h));
+  auto& K = h->kry;
+  const int B = s <= 4 ? 4 : KB_MAX;
+  const int SLB = K.slb;
+  const int* skip = &K.gl->all_done;
+  SVAR_HIP(hipMemcpyAsync(K.tol_rel, tol_rel.data(), tol_rel.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+  kr_nrm2_part(K.plan, K.r, K.npart, st);
+  kr_start(K.plan, K.npart, K.r, K.V, K.st, K.tol_rel, K.gl, st);
+  int j = 0;
+  while (j < m) {
+    const int b = std::min(s, m - j);
+    for (int i = 0; i < b; ++i) {
+      double* in = K.V + (int64_t)(j + i) * K.ldv;
+      double* zo = K.Z + (int64_t)(j + i) * K.ldv;
+      double* wo = K.V + (int64_t)(j + i + 1) * K.ldv;
+      if (hv.buf && hv.count < hv.cap) {
+        SVAR_TRY(run_program(h, *hv.prog, in, hv.buf + (int64_t)hv.count * hv.len, st, skip));
+        ++hv.count;
+      }
+      SVAR_TRY(run_program(h, PP, in, zo, st, skip));
+      SVAR_TRY(run_program(h, PA, zo, wo, st, skip));
+      kr_nrm2_part(K.plan, wo, K.npart, st);
+      kb_scale(K.plan, K.npart, wo, K.st, K.gl, K.kb, i, st);
+    }
+    // the ORTHO timing class covers the four passes over the basis (projections, updates)
+    double* sums[2] = {K.bs1, K.bs2};
+    for (int pass = 0; pass < 2; ++pass) {
+      hipEvent_t e0, e1;
+      timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+      kb_dot(B, K.plan, K.st, K.gl, K.V, K.ldv, j, b, SLB, K.bpart, st);
+      timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+      kb_reduce(K.plan, K.st, K.gl, K.bpart, SLB, (j + 1) * B, sums[pass], st);
+      timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+      kb_update(B, K.plan, K.st, K.gl, K.V, K.ldv, j, b, SLB, sums[pass], st);
+      timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+    }
+    for (int round = 0; round < 2; ++round) {
+      kb_gram(B, K.plan, K.st, K.gl, K.V, K.ldv, j, b, K.gpart, st);
+      kb_reduce(K.plan, K.st, K.gl, K.gpart, B * B, B * B, K.gsum, st);
+      kb_chol(B, K.plan, K.st, K.gl, K.gsum, K.kb, b, round, st);
+      kb_trsm(B, K.plan, K.st, K.gl, K.V, K.ldv, j, b, K.kb, st);
+    }
+    kb_hess(B, K.plan, K.st, K.gl, K.bs1, K.bs2, SLB, K.kb, K.hs, m, j, b, net_off, drop,
+            patience, st);
+    j += b;
+    SVAR_HIP(hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
+    SVAR_HIP(hipStreamSynchronize(st));
+    if (K.gl_host->all_done) break;
+  }
+  kr_solve_y(K.plan, K.st, K.hs, m, st);
+  kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ldv, x, m, st);
+  out.resize(K.plan.nsys);
+  SVAR_HIP(hipMemcpyAsync(out.data(), K.st, K.plan.nsys * sizeof(KState), hipMemcpyDeviceToHost,
+                          st));
+  SVAR_HIP(hipStreamSynchronize(st));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("Krylov kernel failed: ") + hipGetErrorString(e));
+    return SVAR_E_HIP;
+  }
+  return SVAR_OK;
+}
+
 static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, const double* rhs,
                         double* x, svar_solve_info* info, hipStream_t st) {
   const int nsys = (int)h->wins.size() * nrhs;
   // one cycle holds at most KR_MAX_CYCLE basis vectors (LDS of the update pass); longer
   // unrestarted runs continue as further cycles of the refinement loop
+  // block mode (s-step) when block >= 2; its cycles hold at most KB_MAX_CYCLE
+  // columns (LDS of the Hessenberg step) and use basis slots 0..m
+  const int blk = o->block >= 2 ? std::min((int)o->block, KB_MAX) : 0;
+  const int cap = blk ? KB_MAX_CYCLE : KR_MAX_CYCLE;
   int cyc = o->restart > 0 ? std::min(o->restart, o->maxit) : o->maxit;
-  cyc = std::min(cyc, KR_MAX_CYCLE);
+  cyc = std::min(cyc, cap);
   if (cyc < 1) return inval_msg("maxit must be >= 1");
-  SVAR_TRY(ensure_krylov(h, nrhs, cyc, st));
+  SVAR_TRY(ensure_krylov(h, nrhs, blk ? cyc + 1 : cyc, st));
   auto& K = h->kry;
   // inner operators: FP64_F32P keeps A in float64 (no refinement needed: under flexible GMRES
   // the preconditioner's rounding changes only the convergence rate, not the attainable
@@ -355,8 +444,11 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   SVAR_HIP(hipMemcpyAsync(K.r, rhs, K.ntot * sizeof(double), hipMemcpyDeviceToDevice, st));
   int64_t applies_A64 = 0;
   int max_outer = std::max(1, o->max_outer);
-  if (o->restart <= 0 && o->maxit > KR_MAX_CYCLE)
-    max_outer = std::max(max_outer, (o->maxit + KR_MAX_CYCLE - 1) / KR_MAX_CYCLE + 1);
+  if (o->restart <= 0 && o->maxit > cap)
+    max_outer = std::max(max_outer, (o->maxit + cap - 1) / cap + 1);
+  // a block cut short (rank-deficient block) ends its cycle early: restarts then continue
+  // until maxit iterations are used
+  if (blk) max_outer = std::max(max_outer, o->maxit);
   int used = 0;
   for (int outer = 0; outer < max_outer; ++outer) {
     std::vector<double> r2 = rhs2;
@@ -387,8 +479,10 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     if (m < 1) break;
     std::vector<KState> ks;
     {
-      const int rc = fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
-                                  o->fallback_patience, hv, o->use_graph != 0, st);
+      const int rc = blk ? block_cycle(h, m, blk, *Ain, *Pin, tol, x, ks, drop,
+                                       o->fallback_patience, hv, st)
+                         : fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
+                                        o->fallback_patience, hv, o->use_graph != 0, st);
       if (rc != SVAR_OK) {
         h->net_off = nullptr;
         return rc;

@@ -16,9 +16,10 @@ from . import svar as sv
 
 
 def harvest_pairs(windows: Sequence, k: int, rtol: float = 1e-6, maxit: int = 1000,
-                  cap: int = 400, rhat: str = "RR", rhs_index: int = 0):
-    """Plain P_I solves of the given windows; returns float64 device tensors (chat, cexact)
-    of shape (npair, N+1, s).  All windows must share N and s."""
+                  cap: int = 400, rhat: str = "RR", rhs_index: int = 0, block: int = 0):
+    """Plain P_I solves of the given windows (s-step FGMRES with the given block size, 0 =
+    one column at a time: the inputs the preconditioner sees differ); returns float64 device
+    tensors (chat, cexact) of shape (npair, N+1, s).  All windows must share N and s."""
     import torch
     chats: List = []
     cexs: List = []
@@ -28,7 +29,7 @@ def harvest_pairs(windows: Sequence, k: int, rtol: float = 1e-6, maxit: int = 10
         L = win.nb * win.s
         buf = torch.zeros((cap, L), dtype=torch.float64, device="cuda")
         rhs = torch.from_numpy(np.ascontiguousarray(win.rhs[rhs_index])).cuda()
-        _, info, _ = h.solve(rhs, rtol=rtol, maxit=maxit, harvest=buf)
+        _, info, _ = h.solve(rhs, rtol=rtol, maxit=maxit, harvest=buf, block=block)
         n = min(cap, info[0]["iters"])
         V = buf[:n].contiguous()
         V = V[V.abs().amax(dim=1) > 0]  # the first input of an innovation right-hand side

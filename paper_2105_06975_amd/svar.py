@@ -61,7 +61,7 @@ class SolveOpts(C.Structure):
                 ("restart", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("max_outer", C.c_int32), ("fallback_drop", C.c_double),
                 ("harvest", C.c_void_p), ("harvest_cap", C.c_int32),
-                ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("pad", C.c_int32)]
+                ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("block", C.c_int32)]
 
 
 class NetDesc(C.Structure):
@@ -299,11 +299,12 @@ class Handle:
     def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
               precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
               check=False, fallback_drop=1e-3, fallback_patience=3, harvest=None,
-              graph=False):
+              graph=False, block=0):
         """Solve A x = rhs; returns (x, [info dicts], status).
 
         harvest: optional float64 device tensor of shape (cap, state_len): receives the state
         component of the preconditioner input of each FGMRES step.
+        block: s-step FGMRES with blocks of this many columns (2..8; 0 = one at a time).
         """
         import torch
         x = torch.empty_like(rhs) if x is None else x
@@ -311,7 +312,7 @@ class Handle:
                                                      int(harvest.shape[0]))
         o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
                       float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap,
-                      int(fallback_patience), 1 if graph else 0, 0)
+                      int(fallback_patience), 1 if graph else 0, int(block))
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
