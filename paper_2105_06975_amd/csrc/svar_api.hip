@@ -82,7 +82,17 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
                             int64_t& ws, int& maxct, int target) {
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
-  maxct = std::min(8, (maxcols + 15) / 16);
+  // column tile 16 ct, ct in 4..8 with the fewest padded columns (ties: the wider tile):
+  // 520 columns (8 rhs x 65 blocks) take 5 tiles of 112 (560 computed) instead of 5 of 128
+  int best = 8, bestpad = 1 << 30;
+  for (int ct = 8; ct >= 4; --ct) {
+    const int pad = (maxcols + 16 * ct - 1) / (16 * ct) * ct;
+    if (pad < bestpad) {
+      bestpad = pad;
+      best = ct;
+    }
+  }
+  maxct = std::min(best, (maxcols + 15) / 16);
   const int cw = maxct * 16;
   const int rows = 128;
   double total_work = 0.0;
