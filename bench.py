@@ -33,9 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Gram-Schmidt passes, C2 x 8 rhs: HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters
 # (fetch scaled by 2.000, write by 1.000 from the calibration map in the same runs) over the
-# timed region, divided by the algorithmic bytes per launch of that run (6.9447 GB / 6.9426 GB).
+# timed region, divided by the algorithmic bytes per launch of that run (7.0255 GB / 6.9426 GB).
 # Valid while k_fg_dot / k_fg_update and their task plan are unchanged.
-ORTHO_TRAFFIC_RATIO = 6.9447 / 6.9426
+ORTHO_TRAFFIC_RATIO = 7.0255 / 6.9426
 # the same ratio for block Gram-Schmidt (blocks of BLOCK_TRAFFIC_B columns); None until the
 # counters have been taken for the current block kernels
 BLOCK_TRAFFIC_RATIO = None
