@@ -72,6 +72,8 @@ def parse():
                     help="s-step FGMRES block size of the learned + batched path (0: one "
                          "column at a time; with the nonlinear network the block basis "
                          "stagnates)")
+    ap.add_argument("--c4-block", type=int, default=4,
+                    help="--c4 mode: also time s-step FGMRES with this block size (0: skip)")
     ap.add_argument("--plain-block", type=int, default=8,
                     help="also time the batched solve with the plain preconditioner in "
                          "s-step FGMRES with this block size (0: skip)")
@@ -465,6 +467,15 @@ def bench_c4(args):
                                       "x_rel_diff": float(torch.linalg.norm(xt - x) /
                                                           torch.linalg.norm(x))}
     log(res["batched_graph_autotuned"])
+    if args.c4_block >= 2:
+        el_k, xk, info_k, rc_k = timed_solve(block=args.c4_block)
+        res["batched_block"] = {"block": args.c4_block, "seconds": el_k,
+                                "solves_per_s": len(info) / el_k, "rc": rc_k,
+                                "iters_mean": float(np.mean([i["iters"] for i in info_k])),
+                                "relres_max": float(max(i["relres_true"] for i in info_k)),
+                                "x_rel_diff": float(torch.linalg.norm(xk - x) /
+                                                    torch.linalg.norm(x))}
+        log(res["batched_block"])
     # one at a time: the first two windows' 16 systems (same preconditioner and restart)
     sub = wins[:2]
     hs = svar.Handle(sub, prec)
