@@ -123,6 +123,8 @@ typedef struct svar_prec_opts {
                                          products bfloat16 with float32 accumulation      */
 #define SVAR_PRECISION_FP64_F32P 3    /* A in float64 (no refinement needed); P covariance
                                          products float32 (flexible GMRES absorbs them)   */
+#define SVAR_PRECISION_FP64_BF16P 4   /* A in float64; P covariance products bfloat16 with
+                                         float32 accumulation                              */
 
 typedef struct svar_solve_opts {
   int32_t method;     /* SVAR_METHOD_*                                                      */

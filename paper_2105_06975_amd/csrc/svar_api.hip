@@ -1521,11 +1521,8 @@ struct TuneEntry {
 };
 
 static void pv_of(int precision, int* pv_a, int* pv_p) {
-  const bool a64 = precision == SVAR_PRECISION_FP64 || precision == SVAR_PRECISION_FP64_F32P;
-  *pv_a = a64 ? PV_F64 : PV_F32;
-  *pv_p = precision == SVAR_PRECISION_MIXED_BF16P
-              ? PV_BF16P
-              : (precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+  *pv_a = prec_a64(precision) ? PV_F64 : PV_F32;
+  *pv_p = prec_pv_p(precision);
 }
 
 // Time each candidate plan of every covariance-product launch of the A and P programs for
@@ -1627,8 +1624,7 @@ const char* svar_last_error(void) { return g_err.c_str(); }
 int svar_autotune(svar_handle* h, int32_t nrhs, int32_t precision, const char* cache_path,
                   void* stream) {
   if (!h || nrhs < 1) return inval("bad arguments");
-  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_FP64_F32P)
-    return inval("bad precision");
+  if (!prec_valid(precision)) return inval("bad precision");
   hipStream_t st = (hipStream_t)stream;
   std::vector<TuneEntry> found;
   SVAR_TRY(autotune(h, nrhs, precision, found, st));
@@ -1768,12 +1764,10 @@ int svar_apply_P(svar_handle* h, int32_t nrhs, const double* v, double* z, void*
 int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* y,
                       void* stream) {
   if (!h || !v || !y || nrhs < 1) return inval("bad arguments");
-  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_FP64_F32P)
-    return inval("bad precision");
+  if (!prec_valid(precision)) return inval("bad precision");
   Program* P = nullptr;
   hipStream_t st = (hipStream_t)stream;
-  const int pa = (precision == SVAR_PRECISION_FP64 || precision == SVAR_PRECISION_FP64_F32P) ? PV_F64
-                                                                                         : PV_F32;
+  const int pa = prec_a64(precision) ? PV_F64 : PV_F32;
   SVAR_TRY(get_program(h, PROG_A, nrhs, pa, &P, st));
   return run_program(h, *P, const_cast<double*>(v), y, st, nullptr);
 }
@@ -1781,13 +1775,10 @@ int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const dou
 int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* z,
                       void* stream) {
   if (!h || !v || !z || nrhs < 1) return inval("bad arguments");
-  if (precision < SVAR_PRECISION_FP64 || precision > SVAR_PRECISION_FP64_F32P)
-    return inval("bad precision");
+  if (!prec_valid(precision)) return inval("bad precision");
   Program* P = nullptr;
   hipStream_t st = (hipStream_t)stream;
-  const int pv = precision == SVAR_PRECISION_MIXED_BF16P
-                     ? PV_BF16P
-                     : (precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+  const int pv = prec_pv_p(precision);
   SVAR_TRY(get_program(h, PROG_P, nrhs, pv, &P, st));
   h->net_off = nullptr;
   return run_program(h, *P, const_cast<double*>(v), z, st, nullptr);

@@ -62,6 +62,19 @@ struct ProgKey {
 enum { PROG_A = 100, PROG_P = 101, PROG_HARVEST = 102 };
 // precision variants of a program
 enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2, PV_F32P = 3 };
+// program variants of the inner A and P of a SVAR_PRECISION_* setting
+inline bool prec_valid(int p) {
+  return p >= SVAR_PRECISION_FP64 && p <= SVAR_PRECISION_FP64_BF16P;
+}
+inline bool prec_a64(int p) {
+  return p == SVAR_PRECISION_FP64 || p == SVAR_PRECISION_FP64_F32P ||
+         p == SVAR_PRECISION_FP64_BF16P;
+}
+inline int prec_pv_p(int p) {
+  return (p == SVAR_PRECISION_MIXED_BF16P || p == SVAR_PRECISION_FP64_BF16P)
+             ? PV_BF16P
+             : (p == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+}
 
 struct Timer {
   bool on = false;

@@ -406,14 +406,12 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   if (cyc < 1) return inval_msg("maxit must be >= 1");
   SVAR_TRY(ensure_krylov(h, nrhs, blk ? cyc + 1 : cyc, st));
   auto& K = h->kry;
-  // inner operators: FP64_F32P keeps A in float64 (no refinement needed: under flexible GMRES
+  // inner operators: FP64_F32P / FP64_BF16P keep A in float64 (no refinement needed: under flexible GMRES
   // the preconditioner's rounding changes only the convergence rate, not the attainable
   // residual); the MIXED settings use float32 A and refine in float64
-  const bool a64 = o->precision == SVAR_PRECISION_FP64 || o->precision == SVAR_PRECISION_FP64_F32P;
+  const bool a64 = prec_a64(o->precision);
   const int pv_a = a64 ? PV_F64 : PV_F32;
-  const int pv_p = o->precision == SVAR_PRECISION_MIXED_BF16P
-                       ? PV_BF16P
-                       : (o->precision == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+  const int pv_p = prec_pv_p(o->precision);
   Program *A64 = nullptr, *Ain = nullptr, *Pin = nullptr;
   SVAR_TRY(get_program(h, PROG_A, nrhs, PV_F64, &A64, st));
   SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
@@ -550,8 +548,7 @@ extern "C" int svar_solve(svar_handle* h, const svar_solve_opts* o, int32_t nrhs
                           const double* rhs, double* x, svar_solve_info* info, void* stream) {
   if (!h || !o || !rhs || !x || !info || nrhs < 1) return inval_msg("bad arguments");
   if (!(o->rtol > 0.0) || o->maxit < 1) return inval_msg("need rtol > 0 and maxit >= 1");
-  if (o->precision < SVAR_PRECISION_FP64 || o->precision > SVAR_PRECISION_FP64_F32P)
-    return inval_msg("bad precision");
+  if (!prec_valid(o->precision)) return inval_msg("bad precision");
   hipStream_t st = (hipStream_t)stream;
   if (o->method == SVAR_METHOD_FGMRES) return solve_fgmres(h, o, nrhs, rhs, x, info, st);
   if (o->method == SVAR_METHOD_MINRES) {

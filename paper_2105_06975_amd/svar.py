@@ -24,7 +24,7 @@ MODEL = {"dense": 0, "band": 1, "tridiag_inv": 2, "l96": 3}
 PREC = {"NONE": 0, "PD": 1, "PI": 2}
 RHAT = {"DIAG": 0, "RR": 1, "ME": 2, "EXACT": 3}
 METHOD = {"FGMRES": 0, "MINRES": 1}
-PRECISION = {"FP64": 0, "MIXED_FP32": 1, "MIXED_BF16P": 2, "FP64_F32P": 3}
+PRECISION = {"FP64": 0, "MIXED_FP32": 1, "MIXED_BF16P": 2, "FP64_F32P": 3, "FP64_BF16P": 4}
 OPS = {"L": 0, "LT": 1, "LHAT_INV": 2, "LHAT_INVT": 3, "D": 4, "DHAT_INV": 5, "R": 6,
        "RHAT_INV": 7, "H": 8, "HT": 9}
 OP_SPACES = {"L": ("state", "state"), "LT": ("state", "state"), "LHAT_INV": ("state", "state"),

@@ -290,6 +290,10 @@ def test_mixed_precision_operators(sv):
     zp = host(h.apply_P(dev(V), 2, precision="MIXED_BF16P")).reshape(2, -1)
     zf = host(h.apply_P(dev(V), 2, precision="FP64_F32P")).reshape(2, -1)
     ya64 = host(h.apply_A(dev(V), 2, precision="FP64_F32P")).reshape(2, -1)
+    # FP64_BF16P: the float64 A with the bfloat16 preconditioner, the same programs
+    assert np.array_equal(host(h.apply_P(dev(V), 2, precision="FP64_BF16P")).reshape(2, -1), zp)
+    assert np.array_equal(host(h.apply_A(dev(V), 2, precision="FP64_BF16P")).reshape(2, -1),
+                          host(h.apply_A(dev(V), 2)).reshape(2, -1))
     for r in range(2):
         ea = rel(ya[r], orc.apply_A(V[r]))
         ep = rel(zp[r], orc.apply_P_inv(V[r], "PI"))
@@ -300,18 +304,24 @@ def test_mixed_precision_operators(sv):
         assert rel(ya64[r], orc.apply_A(V[r])) < 1e-12
 
 
-def test_fp64_with_f32_preconditioner_solve(sv):
-    """FP64 operator with float32 preconditioner products: same true-residual target in one
-    cycle, iteration count close to the FP64 solve's."""
+@pytest.mark.parametrize("prec", ["FP64_F32P", "FP64_BF16P"])
+def test_fp64_with_low_precision_preconditioner_solve(sv, prec):
+    """FP64 operator with float32 / bfloat16 preconditioner products: same true-residual
+    target in one cycle; float32 products keep the FP64 iteration count (within 5 %),
+    bfloat16 ones cost more steps (measured 112 against 77 here)."""
     win = wl.make_config_window("c1", seed=4)
     orc = so.SaddleOracle(win, k=3, rhat="RR")
     rhs = win.rhs[0]
     h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
     x64, i64, rc = h.solve(dev(rhs), rtol=1e-8, maxit=win.n)
-    xf, ifp, rcf = h.solve(dev(rhs), rtol=1e-8, maxit=win.n, precision="FP64_F32P")
+    xf, ifp, rcf = h.solve(dev(rhs), rtol=1e-8, maxit=win.n, precision=prec)
+    print(prec, "iterations", ifp[0]["iters"], "FP64", i64[0]["iters"])
     assert rc == sv.OK and rcf == sv.OK
     assert np.linalg.norm(rhs - orc.apply_A(host(xf))) <= 1e-8 * np.linalg.norm(rhs)
-    assert abs(ifp[0]["iters"] - i64[0]["iters"]) <= max(3, i64[0]["iters"] // 20)
+    if prec == "FP64_F32P":
+        assert abs(ifp[0]["iters"] - i64[0]["iters"]) <= max(3, i64[0]["iters"] // 20)
+    else:
+        assert i64[0]["iters"] <= ifp[0]["iters"] <= 2 * i64[0]["iters"]
 
 
 # ------------------------------------------------------------------ edge cases
