@@ -64,6 +64,47 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
   out[j] = in[j] + J.alpha * acc;
 }
 
+// The same products for band models whose taps fit the window o0 .. o0 + H (the dense tap
+// windows of the fused sweep): the H + 1 weights and TS + H values of x are staged in LDS and
+// each thread forms its output with the taps unrolled (no offset table, no global loads in the
+// tap loop).
+template <int H>
+__global__ __launch_bounds__(TS) void k_mstep_win(const MJob* __restrict__ jobs,
+                                                  const ModelDev* __restrict__ models, Bases b,
+                                                  const int* __restrict__ skip, int njobs) {
+  __shared__ double lw[H + 1];
+  __shared__ double lx[TS + H];
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const MJob J = jobs[job_id()];
+  const int s = J.s;
+  const int j0 = blockIdx.x * TS;
+  if (j0 >= s) return;
+  const double* in = opnd(b, J.in);
+  double* out = opnd(b, J.out);
+  const int j = j0 + threadIdx.x;
+  if (J.model < 0) {  // plain copy (first block of L, segment starts)
+    if (j < s) out[j] = in[j];
+    return;
+  }
+  const ModelDev& M = models[J.model];
+  const double* __restrict__ wd = J.trans ? M.wdT : M.wd;  // H + 1 weights, offsets o0 .. o0+H
+  const int o0 = J.trans ? M.wd0T : M.wd0;
+  const double* x = opnd(b, J.x);
+  for (int d = threadIdx.x; d <= H; d += TS) lw[d] = wd[d];
+  for (int t2 = threadIdx.x; t2 < TS + H; t2 += TS) {
+    int g = (j0 + o0 + t2) % s;
+    if (g < 0) g += s;
+    lx[t2] = x[g];
+  }
+  __syncthreads();
+  if (j >= s) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int d = 0; d <= H; ++d) acc += lw[d] * lx[threadIdx.x + d];
+  out[j] = in[j] + J.alpha * acc;
+}
+
 // Whole L_M(k) sweep of one segment in one workgroup (band models whose taps fit a contiguous
 // window of SWEEP_H + 1 offsets, s <= SWEEP_MAXS): the running state stays in LDS (two buffers)
 // for all steps of the segment, so a sweep costs one launch instead of k - 1.
@@ -212,8 +253,14 @@ __global__ void k_axpby(double* y, const double* x, int64_t n, double a, double 
 static unsigned tiles(int64_t n) { return (unsigned)((n + TS - 1) / TS); }
 
 void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
-                       const ModelDev* models, Bases b, const int* skip, hipStream_t st) {
+                       const ModelDev* models, Bases b, const int* skip, hipStream_t st,
+                       bool windowed) {
   if (njobs == 0) return;
+  if (windowed) {  // every band model has a dense tap window (s >= SWEEP_H + 1)
+    hipLaunchKernelGGL((k_mstep_win<SWEEP_H>), jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs,
+                       models, b, skip, njobs);
+    return;
+  }
   // LDS: the output tile plus the widest halo of any band model (checked at set-up)
   hipLaunchKernelGGL(k_mstep_band, jgrid(tiles(max_s), njobs), dim3(TS),
                      (size_t)(TS + max_halo) * sizeof(double), st, jobs, models, b, skip, njobs);

@@ -498,6 +498,8 @@ static int setup_model(svar_handle* h, WinDev& W, const svar_model_desc& md, hip
       M.wdT = dwdT;
       M.wd0 = M.omin;
       M.wd0T = M.ominT;
+    } else {
+      h->band_window = false;
     }
   } else if (md.kind == SVAR_MODEL_DENSE) {
     M.kind = MK_DENSE;
@@ -1473,7 +1475,7 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
     switch (L.kind) {
       case LK_MSTEP_BAND:
         launch_mstep_band((const MJob*)L.jobs, L.njobs, L.max_s, h->max_halo, h->models_dev, b,
-                          skip, st);
+                          skip, st, h->band_window);
         break;
       case LK_MSTEP_DENSE:
         launch_mstep_dense((const MJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);
@@ -1833,7 +1835,8 @@ int svar_model_forecast(svar_handle* h, int32_t w, const double* x, double* y, v
     b.p[B_OUT] = y;
     b.p[B_AUX] = h->zeros;
     if (M.kind == MK_BAND)
-      launch_mstep_band(dj, (int)jobs.size(), W.s, h->max_halo, h->models_dev, b, nullptr, st);
+      launch_mstep_band(dj, (int)jobs.size(), W.s, h->max_halo, h->models_dev, b, nullptr, st,
+                        h->band_window);
     else
       launch_mstep_dense(dj, (int)jobs.size(), W.s, h->models_dev, b, nullptr, st);
     SVAR_HIP(hipStreamSynchronize(st));

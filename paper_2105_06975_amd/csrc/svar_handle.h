@@ -93,6 +93,7 @@ struct svar_handle {
   std::vector<svar::ModelDev> models;       // host copy
   svar::ModelDev* models_dev = nullptr;
   int max_halo = 0;
+  bool band_window = true;  // every band model has a dense tap window (windowed M-step kernel)
   std::vector<void*> allocs;                // every device allocation owned by the handle
   std::map<svar::ProgKey, svar::Program> progs;
   // workspaces

@@ -158,7 +158,8 @@ struct Program {
 
 // kernel launchers (defined in the .hip files)
 void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
-                       const ModelDev* models, Bases b, const int* skip, hipStream_t st);
+                       const ModelDev* models, Bases b, const int* skip, hipStream_t st,
+                       bool windowed = false);
 void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
                         Bases b, const int* skip, hipStream_t st);
 void launch_sweep_band(const SJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
