@@ -122,7 +122,9 @@ typedef struct svar_prec_opts {
 #define SVAR_PRECISION_MIXED_BF16P 2  /* FP64 refinement; inner A float32, P covariance
                                          products bfloat16 with float32 accumulation      */
 #define SVAR_PRECISION_FP64_F32P 3    /* A in float64 (no refinement needed); P covariance
-                                         products float32 (flexible GMRES absorbs them)   */
+                                         products float32 (flexible GMRES absorbs them),
+                                         except that FGMRES with P_I forms D z1 in float64
+                                         (it is shared with the next A z)                  */
 #define SVAR_PRECISION_FP64_BF16P 4   /* A in float64; P covariance products bfloat16 with
                                          float32 accumulation                              */
 
@@ -170,7 +172,9 @@ typedef struct svar_solve_info {   /* one per (window, right-hand side), packed 
   int32_t fallbacks;    /* learned path: 1 if the network was switched off for this system  */
   double relres_true;   /* ||rhs - A x||_2 / ||rhs||_2 computed in float64 at return        */
   double relres_est;    /* the solver's own estimate at its last iteration                  */
-  /* matrix-vector products with component blocks, counted as in Tables 4 and 5 */
+  /* matrix-vector products with component blocks, counted as in Tables 4 and 5 but as
+     formed: under P_I with a float64 operator, FGMRES forms D z1 once per step (inside P)
+     and the next A z reuses it, so n_D counts one D product per step there */
   int64_t n_M, n_MT, n_D, n_R, n_Rhat_inv, n_Dhat_inv;
 } svar_solve_info;
 

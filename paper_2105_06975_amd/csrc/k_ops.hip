@@ -234,8 +234,12 @@ __global__ __launch_bounds__(TS) void k_vec(const VJob* __restrict__ jobs, Bases
   const VJob J = jobs[job_id()];
   const double* in = opnd(b, J.in);
   double* out = opnd(b, J.out);
-  for (int64_t j = (int64_t)blockIdx.x * TS + threadIdx.x; j < J.len; j += (int64_t)gridDim.x * TS)
-    out[j] = J.scale ? in[j] * J.scale[j] : (J.alpha == 0.0 ? 0.0 : in[j] * J.alpha);
+  const double* add = J.beta != 0.0 ? opnd(b, J.add) : nullptr;
+  for (int64_t j = (int64_t)blockIdx.x * TS + threadIdx.x; j < J.len; j += (int64_t)gridDim.x * TS) {
+    double v = J.scale ? in[j] * J.scale[j] : (J.alpha == 0.0 ? 0.0 : in[j] * J.alpha);
+    if (add) v += J.beta * add[j];
+    out[j] = v;
+  }
 }
 
 __global__ void k_fill(double* x, int64_t n, double v) {

@@ -936,6 +936,24 @@ static int add_vjobs(Builder& B, std::vector<VJob>& jobs) {
 }
 
 // out_state_component = alpha * in_state_component (whole state component of each system)
+// out = in + beta * add over every system's state-sized component
+static int add_axpy_state(Builder& B, VRef in, VRef add, double beta, VRef out) {
+  std::vector<VJob> jobs;
+  for (int w = 0; w < (int)B.h->wins.size(); ++w) {
+    const WinDev& W = B.h->wins[w];
+    for (int r = 0; r < B.nrhs; ++r) {
+      VJob J{};
+      J.in = blk(B.h, w, r, B.nrhs, in, 0);
+      J.out = blk(B.h, w, r, B.nrhs, out, 0);
+      J.add = blk(B.h, w, r, B.nrhs, add, 0);
+      J.alpha = 1.0;
+      J.beta = beta;
+      J.len = (int64_t)W.nb * W.s;
+      jobs.push_back(J);
+    }
+  }
+  return add_vjobs(B, jobs);
+}
 static int add_copy_state(Builder& B, VRef in, VRef out, double alpha) {
   std::vector<VJob> jobs;
   for (int w = 0; w < (int)B.h->wins.size(); ++w) {
@@ -1202,6 +1220,38 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
   const bool diag = h->popts.rhat == SVAR_RHAT_DIAG;
   // precisions: A's covariances in float32 for the mixed paths, P's covariances in bfloat16
   // for MIXED_BF16P (products with float32 accumulation)
+  const VRef DZ1{B_AUX, SP_STATE, C_X};
+  if (op == PROG_AD) {
+    // A z for z = P_I u just formed by PROG_PD: c1 = L z3 + D z1 with D z1 from the buffer
+    P.aux_elems = total_len(h, nrhs, SP_STATE);
+    SVAR_TRY(add_L(B, IN_SAD_X, OUT_SAD_ETA, 0));
+    SVAR_TRY(add_L(B, IN_SAD_ETA, OUT_SAD_X, 1));
+    SVAR_TRY(add_gather(B, IN_SAD_X, OUT_SAD_NU));
+    SVAR_TRY(add_scatter(B, IN_SAD_NU, OUT_SAD_X));
+    SVAR_TRY(add_axpy_state(B, OUT_SAD_ETA, DZ1, 1.0, OUT_SAD_ETA));
+    std::vector<GemmProb> probs;
+    add_cov(B, probs, MS_R, DT_F64, IN_SAD_NU, OUT_SAD_NU, OUT_SAD_NU, false, 1.0, 1.0);
+    SVAR_TRY(add_gemm(B, probs, DT_F64));
+    return SVAR_OK;
+  }
+  if (op == PROG_PD) {
+    // P_I with D z1 formed in float64 and kept for PROG_AD; Rhat^{-1} in the given precision
+    const int dt = prec == PV_BF16P ? DT_BF16 : (prec == PV_F32P ? DT_F32 : DT_F64);
+    P.aux_elems = total_len(h, nrhs, SP_STATE);
+    SVAR_TRY(add_copy_state(B, IN_SAD_X, OUT_SAD_ETA, 1.0));
+    SVAR_TRY(add_sweep(B, OUT_SAD_ETA, 1, k));
+    if (h->net) SVAR_TRY(add_net(B, OUT_SAD_ETA));
+    std::vector<GemmProb> pd, pr;
+    add_cov(B, pd, MS_D, DT_F64, OUT_SAD_ETA, DZ1, NONE_REF, true, 1.0, 0.0);
+    if (!diag) add_cov(B, dt == DT_F64 ? pd : pr, MS_RHAT, dt, IN_SAD_NU, OUT_SAD_NU, NONE_REF,
+                       false, 1.0, 0.0);
+    SVAR_TRY(add_gemm(B, pd, DT_F64));
+    if (!pr.empty()) SVAR_TRY(add_gemm(B, pr, dt));
+    if (diag) SVAR_TRY(add_copy_obs(B, IN_SAD_NU, OUT_SAD_NU, true));
+    SVAR_TRY(add_axpy_state(B, IN_SAD_ETA, DZ1, -1.0, OUT_SAD_X));  // v1 - D z1
+    SVAR_TRY(add_sweep(B, OUT_SAD_X, 0, k));
+    return SVAR_OK;
+  }
   if (op == PROG_A) {
     const int dt = prec == PV_F64 ? DT_F64 : DT_F32;
     // c1 = L v3 (+ D v1 below), c3 = L^T v1 (+ H^T v2 below), c2 = H v3 (+ R v2 below)
@@ -1311,7 +1361,7 @@ static bool span_ok(const Span& s, const int64_t len[4]) {
 }
 static int validate_program(const svar_handle* h, const Program& P, int64_t in_len,
                             int64_t out_len, hipStream_t st) {
-  const int64_t len[4] = {in_len, out_len, P.tmp_elems, 0};
+  const int64_t len[4] = {in_len, out_len, P.tmp_elems, P.aux_elems};
   auto fail = [](const char* what) {
     set_error(std::string("internal layout error in ") + what);
     return SVAR_E_INVAL;
@@ -1364,6 +1414,7 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
       for (auto& j : J) {
         spans.push_back({j.out.base, j.out.off, j.out.off + j.len});
         if (j.scale || j.alpha != 0.0) spans.push_back({j.in.base, j.in.off, j.in.off + j.len});
+        if (j.beta != 0.0) spans.push_back({j.add.base, j.add.off, j.add.off + j.len});
       }
     } else if (L.kind == LK_NET) {
       const NetApp* a = (const NetApp*)L.jobs;
@@ -1395,7 +1446,7 @@ static int64_t space_total(const svar_handle* h, int nrhs, int sp) {
 }
 static void op_spaces(int op, int* in_sp, int* out_sp) {
   *in_sp = *out_sp = SP_STATE;
-  if (op == PROG_A || op == PROG_P) {
+  if (op == PROG_A || op == PROG_P || op == PROG_AD || op == PROG_PD) {
     *in_sp = *out_sp = SP_SADDLE;
   } else if (op == PROG_HARVEST) {
     *in_sp = SP_SADDLE;
@@ -1461,6 +1512,7 @@ void timed_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hipEvent_t
 int run_program(svar_handle* h, const Program& P, double* in, double* out, hipStream_t st,
                 const int* skip) {
   if (P.tmp_elems > h->tmp_elems) SVAR_TRY(regrow(h, &h->tmp, &h->tmp_elems, P.tmp_elems));
+  if (P.aux_elems > h->dz1_elems) SVAR_TRY(regrow(h, &h->dz1, &h->dz1_elems, P.aux_elems));
   for (const Launch& L : P.launches)
     if (L.kind == LK_GEMM && L.gemm.ws_elems > h->gemm_ws_elems)
       SVAR_TRY(regrow(h, &h->gemm_ws, &h->gemm_ws_elems, L.gemm.ws_elems));
@@ -1468,7 +1520,7 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
   b.p[B_IN] = in;
   b.p[B_OUT] = out;
   b.p[B_TMP] = h->tmp;
-  b.p[B_AUX] = nullptr;
+  b.p[B_AUX] = P.aux_elems > 0 ? h->dz1 : nullptr;
   for (const Launch& L : P.launches) {
     hipEvent_t e0, e1;
     timer_begin(h, L.kclass, st, &e0, &e1);
@@ -1534,9 +1586,17 @@ static int autotune(svar_handle* h, int nrhs, int precision, std::vector<TuneEnt
                     hipStream_t st) {
   int pv_a, pv_p;
   pv_of(precision, &pv_a, &pv_p);
-  Program *PA = nullptr, *PP = nullptr;
+  Program *PA = nullptr, *PP = nullptr, *PAD = nullptr, *PPD = nullptr;
   SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &PA, st));
   SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &PP, st));
+  std::vector<const Program*> progs = {PA, PP};
+  if (h->popts.type == SVAR_PREC_PI && pv_a == PV_F64) {  // the solver's P_I / A pair
+    SVAR_TRY(get_program(h, PROG_AD, nrhs, PV_F64, &PAD, st));
+    SVAR_TRY(get_program(h, PROG_PD, nrhs, pv_p, &PPD, st));
+    progs.push_back(PAD);
+    progs.push_back(PPD);
+    if (PPD->aux_elems > h->dz1_elems) SVAR_TRY(regrow(h, &h->dz1, &h->dz1_elems, PPD->aux_elems));
+  }
   const int64_t len = total_len(h, nrhs, SP_SADDLE);
   std::vector<void*> tmp;
   double *vin = nullptr, *vout = nullptr;
@@ -1552,7 +1612,7 @@ static int autotune(svar_handle* h, int nrhs, int precision, std::vector<TuneEnt
   if (rc == SVAR_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = inval("event creation failed");
   std::vector<GemmPlanDev> seen;
-  for (const Program* P : {PA, PP}) {
+  for (const Program* P : progs) {
     for (const Launch& L : P->launches) {
       if (rc != SVAR_OK) break;
       if (L.kind != LK_GEMM) continue;
@@ -1577,6 +1637,7 @@ static int autotune(svar_handle* h, int nrhs, int precision, std::vector<TuneEnt
           b.p[B_IN] = vin;
           b.p[B_OUT] = vout;
           b.p[B_TMP] = h->tmp;
+          b.p[B_AUX] = h->dz1;  // written by the P_I program's D z1 product
           launch_gemm(g, b, h->gemm_ws, nullptr, st);
           (void)hipEventRecord(e0, st);
           for (int r = 0; r < 5; ++r) launch_gemm(g, b, h->gemm_ws, nullptr, st);

@@ -59,7 +59,9 @@ struct ProgKey {
 };
 
 // internal program codes (beyond the public SVAR_OP_*)
-enum { PROG_A = 100, PROG_P = 101, PROG_HARVEST = 102 };
+// PROG_PD / PROG_AD: P_I that also leaves D z1 (float64) in the handle's dz1 buffer, and the
+// A that adds that buffer instead of forming D z1 again (A is applied to z = P u right after)
+enum { PROG_A = 100, PROG_P = 101, PROG_HARVEST = 102, PROG_PD = 103, PROG_AD = 104 };
 // precision variants of a program
 enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2, PV_F32P = 3 };
 // program variants of the inner A and P of a SVAR_PRECISION_* setting
@@ -101,6 +103,8 @@ struct svar_handle {
   int64_t gemm_ws_elems = 0;
   double* tmp = nullptr;
   int64_t tmp_elems = 0;
+  double* dz1 = nullptr;  // D z1 of the last PROG_PD application (state layout)
+  int64_t dz1_elems = 0;
   double* zeros = nullptr;       // zero-filled, at least the largest matrix order
   int64_t zeros_elems = 0;
   svar::Timer timers[SVAR_KCLASS_COUNT];
@@ -122,7 +126,7 @@ struct svar_handle {
     const void* pa = nullptr;
     const void* pp = nullptr;
     const int* net_off = nullptr;
-    const void* bufs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // workspaces used
+    const void* bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // workspaces
     double drop = 0.0;
   } graph;
   // Krylov workspace (grown on demand)

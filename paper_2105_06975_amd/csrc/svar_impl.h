@@ -116,11 +116,13 @@ struct HTJob {           // scatter-add: out[j] += sum_{e in ptr[j]..ptr[j+1]} v
   const double* val;
   int32_t s, pad;
 };
-struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha), j < len
+struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha) + beta * add[j], j < len
   Operand in, out;
   const double* scale;
   double alpha;
   int64_t len;
+  Operand add;            // read only when beta != 0
+  double beta;
 };
 
 // ------------------------------------------------------------------ launch programs
@@ -152,6 +154,7 @@ struct Launch {
 struct Program {
   std::vector<Launch> launches;
   int64_t tmp_elems = 0;  // B_TMP workspace needed
+  int64_t aux_elems = 0;  // B_AUX: the handle's shared D z1 buffer (P_I with A in float64)
   // component counters per application (Tables 4 and 5 style): M, M^T, D, R, Rhat^-1, Dhat^-1
   int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
 };

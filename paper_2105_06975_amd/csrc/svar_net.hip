@@ -395,7 +395,7 @@ int svar_set_net(svar_handle* h, svar_net* n) {
   h->prog_gen += 1;
   // preconditioner programs are rebuilt with (or without) the correction
   for (auto it = h->progs.begin(); it != h->progs.end();) {
-    if (it->first.op == PROG_P)
+    if (it->first.op == PROG_P || it->first.op == PROG_PD)
       it = h->progs.erase(it);
     else
       ++it;

@@ -193,9 +193,9 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
                       int* net_off, double drop, int patience, hipGraphExec_t* out) {
   auto& G = h->graph;
   // every device buffer whose address the captured launches hold
-  const void* bufs[5] = {h->kry.V, h->tmp, h->gemm_ws, h->net_ws, h->zeros};
+  const void* bufs[6] = {h->kry.V, h->tmp, h->gemm_ws, h->net_ws, h->zeros, h->dz1};
   bool same_bufs = true;
-  for (int i = 0; i < 5; ++i) same_bufs = same_bufs && G.bufs[i] == bufs[i];
+  for (int i = 0; i < 6; ++i) same_bufs = same_bufs && G.bufs[i] == bufs[i];
   if (G.exec && same_bufs && G.nrhs == nrhs && G.m == m && G.pa == &PA && G.pp == &PP &&
       G.gen == h->prog_gen && G.net_off == net_off && G.drop == drop &&
       G.patience == patience) {
@@ -242,7 +242,7 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
   G.net_off = net_off;
   G.drop = drop;
   G.patience = patience;
-  for (int i = 0; i < 5; ++i) G.bufs[i] = bufs[i];
+  for (int i = 0; i < 6; ++i) G.bufs[i] = bufs[i];
   *out = G.exec;
   return SVAR_OK;
 }
@@ -414,8 +414,14 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   const int pv_p = prec_pv_p(o->precision);
   Program *A64 = nullptr, *Ain = nullptr, *Pin = nullptr;
   SVAR_TRY(get_program(h, PROG_A, nrhs, PV_F64, &A64, st));
-  SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
-  SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &Pin, st));
+  if (h->popts.type == SVAR_PREC_PI && a64) {
+    // every inner A z follows z = P_I u at once: P keeps D z1 (float64) and A reuses it
+    SVAR_TRY(get_program(h, PROG_AD, nrhs, PV_F64, &Ain, st));
+    SVAR_TRY(get_program(h, PROG_PD, nrhs, pv_p, &Pin, st));
+  } else {
+    SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
+    SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &Pin, st));
+  }
   launch_fill(x, K.ntot, 0.0, st);
   // learned correction: per-system switch-off flags, cleared for this solve
   const double drop = o->fallback_drop;
