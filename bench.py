@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--c3", action="store_true",
                     help="Lorenz-96 window (s=2048, N=32): iterations vs k and the 5-iteration "
                          "Gauss-Newton outer loop (one JSON object)")
+    ap.add_argument("--c5", type=int, default=0, metavar="W",
+                    help="learned-correction mode: train on C5-shaped windows (s=4096, N=32), "
+                         "then solve W held-out windows x 8 rhs batched with the network "
+                         "against every system one at a time in plain FP64 (one JSON object)")
     ap.add_argument("--c4", type=int, default=0, metavar="W",
                     help="batched mode: W uneven advection-diffusion windows x 8 perturbed-"
                          "observation right-hand sides in one call, against one-at-a-time "
@@ -74,6 +78,9 @@ def parse():
                     help="s-step FGMRES block size of the learned + batched path (0: one "
                          "column at a time; with the nonlinear network the block basis "
                          "stagnates)")
+    ap.add_argument("--c4-learned", action="store_true",
+                    help="--c4 mode: also solve the batch with the network trained on the C5 "
+                         "shape (FP64_F32P)")
     ap.add_argument("--c4-block", type=int, default=4,
                     help="--c4 mode: also time s-step FGMRES with this block size (0: skip)")
     ap.add_argument("--lb-restart", type=int, default=200,
@@ -153,6 +160,9 @@ def main():
         return
     if args.c4:
         print(json.dumps(bench_c4(args)), flush=True)
+        return
+    if args.c5:
+        print(json.dumps(bench_c5(args)), flush=True)
         return
     t0 = time.time()
     win = wl.make_config_window("c2", seed=0, nrhs=args.nrhs)
@@ -431,6 +441,83 @@ def c4_windows(nwin, seed=0, nrhs=8):
     return wins
 
 
+def train_c5_net(args):
+    """The network of the C5 shape (s = 4096, N = 32): pairs from plain solves of seeds
+    0..train_windows-1, Adam epochs (untimed)."""
+    from paper_2105_06975_amd import learned, svar
+    from paper_2105_06975_amd import workloads as wl
+    t0 = time.time()
+    tw = [wl.make_c5_like(4096, 32, seed=sd) for sd in range(args.train_windows)]
+    chat, cex = learned.harvest_pairs(tw, args.k, rtol=args.rtol, maxit=1000, cap=args.harvest)
+    del tw
+    x, y = svar.make_pairs(chat, cex)
+    del chat, cex
+    net = svar.Net(args.k, args.n_bound, "BF16")
+    net.set_params(wl.net_init(net.cin, 64, seed=0))
+    hist = learned.train(net, x, y, epochs=args.epochs, batch=64, lr=1e-3, seed=0)
+    t_train = time.time() - t0
+    log(f"c5 training: {x.shape[0]} pairs, loss {hist[0]:.4f} -> {hist[-1]:.4f}, {t_train:.1f}s")
+    return net, hist, t_train
+
+
+def bench_c5(args):
+    """Learned correction on the C5 shape: training on seeds 0..2 (untimed), evaluation on
+    held-out seeds 10^6 + w, 8 rhs each: the learned + batched solve (FP64_F32P, restart as
+    the main path) against plain FP64 solves of every system one at a time."""
+    import torch
+
+    from paper_2105_06975_amd import svar
+    from paper_2105_06975_amd import workloads as wl
+    s, N, nrhs = 4096, 32, 8
+    net, hist, t_train = train_c5_net(args)
+    wins = [wl.make_c5_like(s, N, seed=10**6 + w, nrhs=nrhs) for w in range(args.c5)]
+    prec = svar.Precond(type="PI", k=args.k, rhat="RR")
+    rhs = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
+    # plain FP64, one system at a time (the reference path: no restart)
+    one_t, its1 = 0.0, []
+    for w in wins:
+        hw = svar.Handle([w], prec)
+        for r in range(nrhs):
+            b = torch.from_numpy(w.rhs[r]).cuda()
+            if r == 0:
+                hw.solve(b, 1, rtol=args.rtol, maxit=1000)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, inf1, rc1 = hw.solve(b, 1, rtol=args.rtol, maxit=1000)
+            torch.cuda.synchronize()
+            one_t += time.perf_counter() - t
+            assert rc1 == svar.OK, inf1
+            its1.append(inf1[0]["iters"])
+        hw.close()
+    # learned + batched
+    h = svar.Handle(wins, prec)
+    h.set_net(net)
+    kw = dict(rtol=args.rtol, maxit=2000, precision=args.precision,
+              fallback_patience=args.patience)
+    if args.lb_restart > 0:
+        kw.update(restart=args.lb_restart, max_outer=100)
+    h.solve(rhs, nrhs, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xb, infb, rcb = h.solve(rhs, nrhs, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    nsys = len(infb)
+    res = {"workload": f"c5: {args.c5} held-out windows (s={s}, N={N}, p=s/2) x {nrhs} rhs",
+           "training": {"windows": args.train_windows, "epochs": args.epochs,
+                        "loss_first": hist[0], "loss_last": hist[-1], "seconds": t_train},
+           "plain_fp64_one_at_a_time": {"systems": len(its1), "solves_per_s": len(its1) / one_t,
+                                        "iters_mean": float(np.mean(its1))},
+           "learned_batched": {"systems": nsys, "solves_per_s": nsys / el, "rc": rcb,
+                               "iters_mean": float(np.mean([i["iters"] for i in infb])),
+                               "fallbacks": int(sum(i["fallbacks"] for i in infb)),
+                               "relres_max": float(max(i["relres_true"] for i in infb))}}
+    res["speedup"] = res["learned_batched"]["solves_per_s"] / \
+        res["plain_fp64_one_at_a_time"]["solves_per_s"]
+    log(res)
+    return res
+
+
 def bench_c4(args):
     import torch
 
@@ -486,6 +573,22 @@ def bench_c4(args):
                                 "x_rel_diff": float(torch.linalg.norm(xk - x) /
                                                     torch.linalg.norm(x))}
         log(res["batched_block"])
+    if args.c4_learned:
+        # the network trained on the C5 shape, applied to this batch (a convolution over space
+        # with per-block inputs does not depend on s or N)
+        net, hist, t_train = train_c5_net(args)
+        h.set_net(net)
+        el_l, xl, info_l, rc_l = timed_solve(precision=args.precision,
+                                             fallback_patience=args.patience)
+        h.set_net(None)
+        res["learned_batched"] = {"seconds": el_l, "solves_per_s": len(info) / el_l, "rc": rc_l,
+                                  "precision": args.precision,
+                                  "iters_mean": float(np.mean([i["iters"] for i in info_l])),
+                                  "fallbacks": int(sum(i["fallbacks"] for i in info_l)),
+                                  "relres_max": float(max(i["relres_true"] for i in info_l)),
+                                  "training": {"loss_first": hist[0], "loss_last": hist[-1],
+                                               "seconds": t_train}}
+        log(res["learned_batched"])
     # one at a time: the first two windows' 16 systems (same preconditioner and restart)
     sub = wins[:2]
     hs = svar.Handle(sub, prec)
@@ -512,6 +615,10 @@ def bench_c4(args):
     res["subset"] = {"systems": 2 * nrhs, "one_at_a_time_s": one_t, "batched_s": el_sub,
                      "batched_speedup": one_t / el_sub, "iters_one": its1,
                      "iters_batched": [i["iters"] for i in infs]}
+    if "learned_batched" in res:
+        # the whole batch learned + batched against the one-at-a-time plain FP64 rate
+        res["learned_batched_vs_one_at_a_time"] = (res["learned_batched"]["solves_per_s"] /
+                                                   (2 * nrhs / one_t))
     log(res["subset"])
     return res
 
