@@ -251,36 +251,47 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict_
 // LDS-tiled product for panels of 32 or more columns.  A workgroup owns a 128-row x (16 CT)-
 // column tile and a k-range; its four waves split the rows (32 each: 2 x CT accumulator
 // tiles), so every staged panel element feeds 128 rows instead of 16-32, which cuts the
-// panel re-reads of wide (batched) panels four- to eight-fold.  Each 16-wide k-stage of the
-// matrix rows and panel columns is loaded with consecutive lanes on consecutive addresses
-// (16 lanes per 128-byte row run), converted to the accumulation type and stored in LDS
-// (row stride 17 elements: the 16 rows read by a lane group hit distinct banks); the next
-// stage's global loads are in flight while the MFMAs consume the current stage (two LDS
-// buffers, one barrier per stage).
+// panel re-reads of wide (batched) panels four- to eight-fold.  Only the panel goes through
+// LDS: each 16-wide k-stage of the panel columns is loaded with consecutive lanes on
+// consecutive addresses (16 lanes per 128-byte column run), converted to the accumulation
+// type and stored in LDS (column stride 17 elements: the 16 columns read by a lane group hit
+// distinct banks); the next stage's loads are in flight while the MFMAs consume the current
+// stage (two LDS buffers, one barrier per stage).  The matrix rows belong to one wave each,
+// so a wave reads them straight into registers: within a stage lane group q takes the four
+// consecutive k = 4q..4q+3 (one 4-element vector load per row tile) and sub-step i of the
+// MFMAs consumes k = 4q + i of both operands, the same k for matrix and panel.
+template <typename CS> struct vec4_of {
+  typedef CS raw __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) raw* ptr;
+};
+
 template <int CT, typename CS, typename AT>
 __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restrict__ probs,
                                                     const GemmTask* __restrict__ tasks,
                                                     double* __restrict__ ws, Bases b,
                                                     const int* __restrict__ skip) {
-  constexpr int KT = 16, MT = 128, NT = 16 * CT, AS = KT + 1;
+  constexpr int KT = 16, NT = 16 * CT, AS = KT + 1;
   typedef typename mfma_of<AT>::acc_t acc_t;
   typedef typename gptr_of<CS>::type cptr;
+  typedef typename vec4_of<CS>::raw craw4;
+  typedef typename vec4_of<CS>::ptr cptr4;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  AT* As = (AT*)lds_raw;             // [2][MT * AS]
-  AT* Xs = As + 2 * MT * AS;         // [2][NT * AS]
+  AT* Xs = (AT*)lds_raw;  // [2][NT * AS]
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
   const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // loader role: k offset kl, row / column rsub + 16 j
+  // panel loader role: k offset kl, column rsub + 16 j
   const int kl = tid & 15, rsub = tid >> 4;
-  cptr arow[8];
+  cptr arow[2];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int row = t.row0 + rsub + 16 * j;
-    arow[j] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
+  for (int rt = 0; rt < 2; ++rt) {
+    const int row = t.row0 + wave * 32 + rt * 16 + r16;
+    arow[rt] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
   }
+  // 4-element loads need 4-aligned rows; the k-ranges start on multiples of 64
+  const bool avec = (P.n & 3) == 0 && ((uintptr_t)P.C & (4 * sizeof(CS) - 1)) == 0;
   const double* X = opnd(b, P.X);
   gdp xcol[CT];
 #pragma unroll
@@ -297,7 +308,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = acc_t{};
   const int nst = (t.k1 - t.k0 + KT - 1) / KT;
-  CS ra[8];
+  craw4 ra[2];
   double rx[CT];
   bool okk = false;
   auto gload = [&](int s) {
@@ -305,47 +316,63 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
     okk = k < t.k1;
     const int kc = okk ? k : t.k0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ra[j] = arow[j][kc];
-#pragma unroll
     for (int j = 0; j < CT; ++j) rx[j] = xcol[j][kc];
+    const int ka = t.k0 + s * KT + 4 * q;
+    if (avec && ka + 4 <= t.k1) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) ra[rt] = *(cptr4)(arow[rt] + ka);
+    } else {  // ragged last stage or unaligned rows: element loads, zero past the k-range
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const CS v = arow[rt][min(ka + i, t.k1 - 1)];
+          ra[rt][i] = ka + i < t.k1 ? v : CS(0);
+        }
+    }
   };
   auto sstore = [&](int buf) {
-    AT* a = As + buf * MT * AS;
     AT* x = Xs + buf * NT * AS;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a[(rsub + 16 * j) * AS + kl] = okk ? to_acc(ra[j], AT()) : AT(0);
-#pragma unroll
     for (int j = 0; j < CT; ++j) x[(rsub + 16 * j) * AS + kl] = okk ? to_acc(rx[j], AT()) : AT(0);
+  };
+  AT av[2][4];
+  auto aconv = [&]() {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[rt][i] = to_acc(ra[rt][i], AT());
   };
   if (nst > 0) {
     gload(0);
     sstore(0);
+    aconv();
   }
   __syncthreads();
   for (int s = 0; s < nst; ++s) {
     const int buf = s & 1;
     if (s + 1 < nst) gload(s + 1);
     __builtin_amdgcn_sched_barrier(0);
-    const AT* a = As + buf * MT * AS + (wave * 32 + r16) * AS;
-    const AT* x = Xs + buf * NT * AS + r16 * AS;
+    const AT* x = Xs + buf * NT * AS + r16 * AS + 4 * q;
 #pragma unroll
     for (int sub = 0; sub < 4; ++sub) {
-      const int kk = 4 * sub + q;
-      AT av[2], bv[CT];
+      AT bv[CT];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) av[rt] = a[rt * 16 * AS + kk];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) bv[ct] = x[ct * 16 * AS + kk];
+      for (int ct = 0; ct < CT; ++ct) bv[ct] = x[ct * 16 * AS + sub];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma_of<AT>::op(av[rt], bv[ct], acc[rt][ct]);
+        for (int ct = 0; ct < CT; ++ct)
+          acc[rt][ct] = mfma_of<AT>::op(av[rt][sub], bv[ct], acc[rt][ct]);
       // keep each sub-step's LDS reads next to its MFMAs (fewer live registers: two waves
       // per SIMD fit, which hides the LDS latency and the stage barrier)
       __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    if (s + 1 < nst) sstore(buf ^ 1);
+    if (s + 1 < nst) {
+      sstore(buf ^ 1);
+      aconv();
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -370,7 +397,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
 template <int CT, typename CS, typename AT>
 static void launch_tiled_t(const GemmPlanDev& g, Bases b, double* ws, const int* skip,
                            hipStream_t st) {
-  const size_t lds = (size_t)2 * (128 + 16 * CT) * 17 * sizeof(AT);
+  const size_t lds = (size_t)2 * (16 * CT) * 17 * sizeof(AT);
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_gemm_tiled<CT, CS, AT>,

@@ -75,7 +75,8 @@ static void plan_gemm(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks
   }
 }
 
-// Plan of the LDS-tiled kernel: 128-row x (16 maxct)-column tiles, split-K to fill the chip.
+// Plan of the LDS-tiled kernel: 128-row x (16 maxct)-column tiles, split-K to fill `target`
+// resident workgroups (CUs x workgroups per CU).
 // Tasks that read the same panel chunk (same problem, k-range and column group) are placed on
 // one XCD (workgroup i runs on XCD i mod 8), so the chunk is fetched into one L2 only.
 static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>& tasks,
@@ -95,28 +96,45 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
   maxct = std::min(best, (maxcols + 15) / 16);
   const int cw = maxct * 16;
   const int rows = 128;
-  double total_work = 0.0;
-  for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
+  // split-K: one k-chunk length (in 16-wide stages) for all problems, chosen so that the
+  // tasks fill whole rounds of the `target` resident workgroups: estimated time = rounds x
+  // longest chunk + one stage per split (the partials' write and fixed-order reduce).
+  // C2's D product (32 x 5 tiles, 256 stages) on 512 slots: 3 splits, 480 tasks in one round
+  int maxst = 1;
+  for (auto& p : probs) maxst = std::max(maxst, (p.n + 15) / 16);
+  const int umin = std::min(maxst, 8);
+  int bestU = maxst;
+  double bestcost = 1e300;
+  for (int U = maxst; U >= umin; --U) {
+    int64_t ntask = 0;
+    int longest = 0, maxS = 1;
+    for (auto& p : probs) {
+      const int st = (p.n + 15) / 16, S = (st + U - 1) / U, ch = (st + S - 1) / S;
+      ntask += (int64_t)((p.n + rows - 1) / rows) * ((p.ncols + cw - 1) / cw) * S;
+      longest = std::max(longest, ch);
+      maxS = std::max(maxS, S);
+    }
+    const double cost = (double)((ntask + target - 1) / target) * longest + maxS;
+    if (cost < bestcost) {
+      bestcost = cost;
+      bestU = U;
+    }
+  }
   ws = 0;
   std::vector<std::vector<GemmTask>> groups;
   for (int pi = 0; pi < (int)probs.size(); ++pi) {
     GemmProb& p = probs[pi];
     const int rt = (p.n + rows - 1) / rows, cg = (p.ncols + cw - 1) / cw;
-    const double share = total_work > 0 ? (double)p.n * p.n * p.ncols / total_work : 1.0;
-    const int want = (int)std::ceil(target * share / (double)(rt * cg));
-    const int kmin = 256;
-    const int maxs = std::max(1, p.n / kmin);
-    int S = std::max(1, std::min(want, maxs));
-    const int align = 64;
-    const int chunk = ((p.n + S - 1) / S + align - 1) / align * align;
-    S = (p.n + chunk - 1) / chunk;
-    p.splits = S;
+    const int st = (p.n + 15) / 16;
+    const int S = (st + bestU - 1) / bestU;
+    const int chunk = 16 * ((st + S - 1) / S);
+    p.splits = (p.n + chunk - 1) / chunk;
     p.ws_off = 0;
-    if (S > 1) {
+    if (p.splits > 1) {
       p.ws_off = ws;
-      ws += (int64_t)S * p.ncols * p.n;
+      ws += (int64_t)p.splits * p.ncols * p.n;
     }
-    for (int sp = 0; sp < S; ++sp)
+    for (int sp = 0; sp < p.splits; ++sp)
       for (int c = 0; c < cg; ++c) {
         std::vector<GemmTask> grp;
         for (int r = 0; r < rt; ++r) {
@@ -1623,7 +1641,7 @@ static int autotune(svar_handle* h, int nrhs, int precision, std::vector<TuneEnt
       int maxcols = 1;
       for (auto& p : L.gemm.hprobs) maxcols = std::max(maxcols, p.ncols);
       std::vector<std::pair<int, int>> cands = {{0, 512}, {0, 1024}, {0, 2048}};
-      if (maxcols >= 32) cands.insert(cands.end(), {{1, 256}, {1, 512}, {1, 1024}});
+      if (maxcols >= 32) cands.insert(cands.end(), {{1, 256}, {1, 512}, {1, 768}, {1, 1024}});
       TuneEntry best{L.gemm.key, -1, 0, 1e30, 0.0};
       for (auto& c : cands) {
         std::vector<void*> owner;

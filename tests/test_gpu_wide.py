@@ -2,7 +2,8 @@
 columns, i.e. several right-hand sides) and the learned correction at the benchmark's size.
 
 * A v and P^{-1} v for 12 right-hand sides of small uneven windows (tile rows past n, ragged
-  column groups) against the oracle, element by element;
+  column groups) against the oracle, element by element, with float64 matrices and with
+  float32 / bfloat16 copies;
 * A v at the full C2 size for 3 right-hand sides (195-column panels) against the oracle;
 * the learned correction inside P_I at the full C2 size, sampled: three time blocks of one
   right-hand side against the oracle's network on the same blocks.
@@ -58,6 +59,32 @@ def test_many_rhs_small_windows(sv, ptype):
             assert rel(ya[a:a + win.n], orc.apply_A(v)) < 1e-12, (w, r)
             ref = orc.apply_PI_inv(v) if ptype == "PI" else orc.apply_PD_inv(v)
             assert rel(yp[a:a + win.n], ref) < 1e-10, (w, r)
+
+
+def test_many_rhs_low_precision_products(sv):
+    """float32 and bfloat16 matrix copies in the tiled kernel (ragged tiles, rows of 150 and
+    70 entries that take element loads, 100 and 40 that take 4-element loads): errors at the
+    level of the storage precision against the float64 oracle, and above float64 rounding."""
+    wins = [wl.make_small_window(s=100, N=10, p=40, seed=1),
+            wl.make_small_window(s=150, N=12, p=70, seed=2)]
+    nrhs = 12
+    h = sv.Handle(wins, sv.Precond(type="PI", k=3, rhat="RR"))
+    V = np.concatenate([wl.random_vectors(w, nrhs, seed=5 + i).ravel() for i, w in enumerate(wins)])
+    ya = host(h.apply_A(dev(V), nrhs, precision="MIXED_FP32"))
+    zf = host(h.apply_P(dev(V), nrhs, precision="FP64_F32P"))
+    zb = host(h.apply_P(dev(V), nrhs, precision="MIXED_BF16P"))
+    off = h.offsets(nrhs)
+    worst = [0.0, 0.0, 0.0]
+    for w, win in enumerate(wins):
+        orc = so.SaddleOracle(win, k=3, rhat="RR")
+        for r in range(nrhs):
+            a = off[w] + r * win.n
+            v = V[a:a + win.n]
+            e = (rel(ya[a:a + win.n], orc.apply_A(v)), rel(zf[a:a + win.n], orc.apply_PI_inv(v)),
+                 rel(zb[a:a + win.n], orc.apply_PI_inv(v)))
+            worst = [max(x, y) for x, y in zip(worst, e)]
+            assert 1e-12 < e[0] < 1e-5 and 1e-12 < e[1] < 1e-4 and 1e-9 < e[2] < 5e-2, (w, r, e)
+    print("worst relative errors (A float32, P float32, P bfloat16):", worst)
 
 
 def test_c2_three_rhs_apply_A(sv):
