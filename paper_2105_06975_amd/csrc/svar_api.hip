@@ -1994,6 +1994,8 @@ int svar_destroy(svar_handle* h) {
   }
   free_all(h->kry.allocs);
   if (h->kry.gl_host) (void)hipHostFree(h->kry.gl_host);
+  for (int i = 0; i < 2; ++i)
+    if (h->kry.gl_ev[i]) (void)hipEventDestroy(h->kry.gl_ev[i]);
   free_all(h->allocs);
   delete h;
   return SVAR_OK;

@@ -142,7 +142,8 @@ struct svar_handle {
     svar::KState* st = nullptr;
     svar::KGlobal* gl = nullptr;
     svar::KHess* hs = nullptr;
-    svar::KGlobal* gl_host = nullptr;  // pinned
+    svar::KGlobal* gl_host = nullptr;  // pinned, two slots (lagged convergence checks)
+    hipEvent_t gl_ev[2] = {nullptr, nullptr};
     int* net_off = nullptr;            // per system: learned correction switched off
     // block (s-step) mode, allocated on first use: partial and reduced sums of the two
     // projections (stride slb per task / system), Gram partials and sums, per-system blocks

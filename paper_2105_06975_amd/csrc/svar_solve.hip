@@ -68,8 +68,11 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   free_all(K.allocs);
   {
     KGlobal* keep = K.gl_host;
+    hipEvent_t ev0 = K.gl_ev[0], ev1 = K.gl_ev[1];
     K = svar_handle::Kry();
     K.gl_host = keep;
+    K.gl_ev[0] = ev0;
+    K.gl_ev[1] = ev1;
   }
   const int nw = (int)h->wins.size();
   const int nsys = nw * nrhs;
@@ -133,7 +136,9 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   }
   SVAR_TRY(dalloc(A, &K.hs, (size_t)nsys));
   SVAR_HIP(hipMemcpyAsync(K.hs, hs.data(), nsys * sizeof(KHess), hipMemcpyHostToDevice, st));
-  if (!K.gl_host) SVAR_HIP(hipHostMalloc((void**)&K.gl_host, sizeof(KGlobal)));
+  if (!K.gl_host) SVAR_HIP(hipHostMalloc((void**)&K.gl_host, 2 * sizeof(KGlobal)));
+  for (int i = 0; i < 2; ++i)
+    if (!K.gl_ev[i]) SVAR_HIP(hipEventCreateWithFlags(&K.gl_ev[i], hipEventDisableTiming));
   SVAR_HIP(hipStreamSynchronize(st));
   return SVAR_OK;
 }
@@ -259,8 +264,14 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
   kr_start(K.plan, K.npart, K.r, K.u, K.st, K.tol_rel, K.gl, st);
   const int check_every = GRAPH_STEPS;
   const bool graph = use_graph && !hv.buf && !timing_any(h);
+  // Convergence checks: the device flag is copied to the host every check_every steps.  Read
+  // at once, the copy drains the queue and the device idles while the host enqueues the next
+  // steps; so the host reads each copy one checkpoint later, with the next steps already
+  // queued (steps enqueued after every system has converged skip their work).  Harvesting
+  // counts its vectors on the host, so it reads each copy at once.
+  const bool lagged = !hv.buf;
   bool all_done = false;
-  int j = 0;
+  int j = 0, pend = -1, slot = 0;
   while (j < m) {
     int done_steps = 1;
     if (graph && j >= check_every && j % check_every == 0 && j + GRAPH_STEPS <= m) {
@@ -278,12 +289,26 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     }
     j += done_steps;
     if (j % check_every == 0 || j == m) {
-      SVAR_HIP(hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
-      SVAR_HIP(hipStreamSynchronize(st));
-      if (K.gl_host->all_done) {
-        all_done = true;
-        break;
+      KGlobal* hb = K.gl_host + slot;
+      SVAR_HIP(hipMemcpyAsync(hb, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
+      SVAR_HIP(hipEventRecord(K.gl_ev[slot], st));
+      if (!lagged || j == m) {
+        SVAR_HIP(hipEventSynchronize(K.gl_ev[slot]));
+        if (hb->all_done || j == m) {
+          all_done = hb->all_done != 0;
+          break;
+        }
+        continue;
       }
+      if (pend >= 0) {
+        SVAR_HIP(hipEventSynchronize(K.gl_ev[pend]));
+        if (K.gl_host[pend].all_done) {
+          all_done = true;
+          break;
+        }
+      }
+      pend = slot;
+      slot ^= 1;
     }
   }
   if (!all_done) {
