@@ -443,7 +443,8 @@ void launch_gemm(const GemmPlanDev& g, Bases b, double* ws, const int* skip, hip
       case 5: launch_tiled<5>(g, b, ws, skip, st); break;
       case 6: launch_tiled<6>(g, b, ws, skip, st); break;
       case 7: launch_tiled<7>(g, b, ws, skip, st); break;
-      default: launch_tiled<8>(g, b, ws, skip, st); break;
+      case 8: launch_tiled<8>(g, b, ws, skip, st); break;
+      default: launch_tiled<9>(g, b, ws, skip, st); break;
     }
   } else switch (g.maxct) {
     case 1: launch_ct<1>(g, b, ws, skip, st); break;

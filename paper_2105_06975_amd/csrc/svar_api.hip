@@ -83,43 +83,42 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
                             int64_t& ws, int& maxct, int target) {
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
-  // column tile 16 ct, ct in 4..8 with the fewest padded columns (ties: the wider tile):
-  // 520 columns (8 rhs x 65 blocks) take 5 tiles of 112 (560 computed) instead of 5 of 128
-  int best = 8, bestpad = 1 << 30;
-  for (int ct = 8; ct >= 4; --ct) {
-    const int pad = (maxcols + 16 * ct - 1) / (16 * ct) * ct;
-    if (pad < bestpad) {
-      bestpad = pad;
-      best = ct;
-    }
-  }
-  maxct = std::min(best, (maxcols + 15) / 16);
-  const int cw = maxct * 16;
+  // Column tile 16 ct (ct in 4..9) and split-K chunk, chosen together so that the tasks fill
+  // whole rounds of the `target` resident workgroups.  Estimated time = rounds x longest chunk
+  // (16-wide stages) x (ct + 2) (the MFMAs and panel loads grow with ct, the matrix-row loads
+  // and the barrier do not) + one stage per split (the partials' write and fixed-order
+  // reduce).  One chunk length serves all problems.  C2's D product (4096 x 520) on 512
+  // slots: ct = 9, 32 x 4 tiles x 4 splits = 512 tasks in one round (576 computed columns);
+  // ct = 7 would leave 480 tasks of 86 stages.
   const int rows = 128;
-  // split-K: one k-chunk length (in 16-wide stages) for all problems, chosen so that the
-  // tasks fill whole rounds of the `target` resident workgroups: estimated time = rounds x
-  // longest chunk + one stage per split (the partials' write and fixed-order reduce).
-  // C2's D product (32 x 5 tiles, 256 stages) on 512 slots: 3 splits, 480 tasks in one round
   int maxst = 1;
   for (auto& p : probs) maxst = std::max(maxst, (p.n + 15) / 16);
   const int umin = std::min(maxst, 8);
-  int bestU = maxst;
+  const int ctmax = std::min(9, std::max(2, (maxcols + 15) / 16));
+  int bestU = maxst, bestct = ctmax;
   double bestcost = 1e300;
-  for (int U = maxst; U >= umin; --U) {
-    int64_t ntask = 0;
-    int longest = 0, maxS = 1;
-    for (auto& p : probs) {
-      const int st = (p.n + 15) / 16, S = (st + U - 1) / U, ch = (st + S - 1) / S;
-      ntask += (int64_t)((p.n + rows - 1) / rows) * ((p.ncols + cw - 1) / cw) * S;
-      longest = std::max(longest, ch);
-      maxS = std::max(maxS, S);
-    }
-    const double cost = (double)((ntask + target - 1) / target) * longest + maxS;
-    if (cost < bestcost) {
-      bestcost = cost;
-      bestU = U;
+  for (int ct = std::min(4, ctmax); ct <= ctmax; ++ct) {
+    const int cwt = 16 * ct;
+    for (int U = maxst; U >= umin; --U) {
+      int64_t ntask = 0;
+      int longest = 0, maxS = 1;
+      for (auto& p : probs) {
+        const int st = (p.n + 15) / 16, S = (st + U - 1) / U, ch = (st + S - 1) / S;
+        ntask += (int64_t)((p.n + rows - 1) / rows) * ((p.ncols + cwt - 1) / cwt) * S;
+        longest = std::max(longest, ch);
+        maxS = std::max(maxS, S);
+      }
+      const double cost =
+          ((double)((ntask + target - 1) / target) * longest + maxS) * (ct + 2);
+      if (cost < bestcost) {
+        bestcost = cost;
+        bestU = U;
+        bestct = ct;
+      }
     }
   }
+  maxct = bestct;
+  const int cw = maxct * 16;
   ws = 0;
   std::vector<std::vector<GemmTask>> groups;
   for (int pi = 0; pi < (int)probs.size(); ++pi) {
