@@ -14,6 +14,12 @@
 
 namespace svar {
 
+// out_j of a model job, with the job's optional addend
+__device__ __forceinline__ double job_out(const MJob& J, const Bases& b, int j, double v) {
+  return J.use_add ? v + b.p[J.add.base][J.add.off + j] : v;
+}
+
+
 static constexpr int TS = 256;  // outputs per workgroup
 static constexpr int YMAX = 65535;
 
@@ -40,7 +46,7 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
   double* out = opnd(b, J.out);
   const int j = j0 + threadIdx.x;
   if (J.model < 0) {  // plain copy (first block of L, segment starts)
-    if (j < s) out[j] = in[j];
+    if (j < s) out[j] = job_out(J, b, j, in[j]);
     return;
   }
   const ModelDev& M = models[J.model];
@@ -61,7 +67,7 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
   double acc = 0.0;
   const int base = threadIdx.x - omin;
   for (int tp = 0; tp < M.ntap; ++tp) acc += w[tp] * lds[base + off[tp]];
-  out[j] = in[j] + J.alpha * acc;
+  out[j] = job_out(J, b, j, in[j] + J.alpha * acc);
 }
 
 // The same products for band models whose taps fit the window o0 .. o0 + H (the dense tap
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(TS) void k_mstep_win(const MJob* __restrict__ jobs,
   double* out = opnd(b, J.out);
   const int j = j0 + threadIdx.x;
   if (J.model < 0) {  // plain copy (first block of L, segment starts)
-    if (j < s) out[j] = in[j];
+    if (j < s) out[j] = job_out(J, b, j, in[j]);
     return;
   }
   const ModelDev& M = models[J.model];
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(TS) void k_mstep_win(const MJob* __restrict__ jobs,
   double acc = 0.0;
 #pragma unroll
   for (int d = 0; d <= H; ++d) acc += lw[d] * lx[threadIdx.x + d];
-  out[j] = in[j] + J.alpha * acc;
+  out[j] = job_out(J, b, j, in[j] + J.alpha * acc);
 }
 
 // Whole L_M(k) sweep of one segment in one workgroup (band models whose taps fit a contiguous
@@ -126,14 +132,25 @@ __global__ __launch_bounds__(256) void k_sweep_band(const SJob* __restrict__ job
   const double* __restrict__ wd = J.trans ? M.wdT : M.wd;  // H + 1 weights, offsets o0 .. o0+H
   const int o0 = J.trans ? M.wd0T : M.wd0;
   double* vec = opnd(b, J.vec);
+  const bool outplace = J.src.base >= 0 || J.sub.base >= 0;
+  const double* src = J.src.base >= 0 ? opnd(b, J.src) : vec;
+  const double* sub = J.sub.base >= 0 ? opnd(b, J.sub) : nullptr;
   double* cur = st;
   double* nxt = st + s;
   const int first = J.trans ? J.len - 1 : 0;
-  for (int j = threadIdx.x; j < s; j += blockDim.x) cur[j] = vec[(int64_t)first * s + j];
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    const int64_t e = (int64_t)first * s + j;
+    double v = src[e];
+    if (sub) v -= sub[e];
+    cur[j] = v;
+    if (outplace) vec[e] = v;
+  }
   __syncthreads();
   for (int t = 1; t < J.len; ++t) {
     const int blk = J.trans ? J.len - 1 - t : t;
     double* row = vec + (int64_t)blk * s;
+    const double* srow = src + (int64_t)blk * s;
+    const double* brow = sub ? sub + (int64_t)blk * s : nullptr;
     for (int j0 = threadIdx.x * R; j0 < s; j0 += blockDim.x * R) {
       // window value m = cur[j0 + o0 + m] is loaded just before its first use (tap d = m - R + 1)
       // so only R values are live at a time
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(256) void k_sweep_band(const SJob* __restrict__ job
       for (int r = 0; r < R; ++r) {
         const int j = j0 + r;
         if (j < s) {
-          const double v = row[j] + acc[r];
+          const double v = (brow ? srow[j] - brow[j] : srow[j]) + acc[r];
           row[j] = v;
           nxt[j] = v;
         }
@@ -186,7 +203,7 @@ __global__ __launch_bounds__(TS) void k_mstep_dense(const MJob* __restrict__ job
   const double* in = opnd(b, J.in);
   double* out = opnd(b, J.out);
   if (J.model < 0) {
-    out[j] = in[j];
+    out[j] = job_out(J, b, j, in[j]);
     return;
   }
   const ModelDev& M = models[J.model];
@@ -197,7 +214,7 @@ __global__ __launch_bounds__(TS) void k_mstep_dense(const MJob* __restrict__ job
     for (int m = 0; m < s; ++m) acc += Mi[(size_t)m * s + j] * x[m];
   else
     for (int m = 0; m < s; ++m) acc += Mi[(size_t)j * s + m] * x[m];
-  out[j] = in[j] + J.alpha * acc;
+  out[j] = job_out(J, b, j, in[j] + J.alpha * acc);
 }
 
 __global__ __launch_bounds__(TS) void k_gather(const HJob* __restrict__ jobs, Bases b,

@@ -842,7 +842,17 @@ static int kind_slot(const WinDev& W) {
 }
 
 // out = L in (trans = 0) or L^T in (trans = 1), eq. def:L
-static int add_L(Builder& B, VRef in, VRef out, int trans) {
+static int add_axpy_state(Builder& B, VRef in, VRef add, double beta, VRef out);
+
+// out = L in (trans: L^T in), plus `add` when given (folded into the model kernels for band and
+// dense models; Lorenz-96 windows take a separate vector pass)
+static int add_L(Builder& B, VRef in, VRef out, int trans, VRef add = VRef{-1, SP_STATE, 0}) {
+  if (add.base >= 0)
+    for (const WinDev& W : B.h->wins)
+      if (W.model_kind == MK_L96) {
+        SVAR_TRY(add_L(B, in, out, trans));
+        return add_axpy_state(B, out, add, 1.0, out);
+      }
   std::vector<MJob> jobs[3];
   for (int w = 0; w < (int)B.h->wins.size(); ++w) {
     const WinDev& W = B.h->wins[w];
@@ -854,6 +864,10 @@ static int add_L(Builder& B, VRef in, VRef out, int trans) {
         J.s = W.s;
         J.alpha = -1.0;
         J.trans = trans;
+        if (add.base >= 0) {
+          J.add = blk(B.h, w, r, B.nrhs, add, i);
+          J.use_add = 1;
+        }
         const bool has = trans ? (i < W.N) : (i >= 1);
         if (has) {
           J.model = W.model_id;
@@ -872,22 +886,39 @@ static int add_L(Builder& B, VRef in, VRef out, int trans) {
 
 // in-place sweep of L_M(k)^{-1} (trans = 0) or L_M(k)^{-T} (trans = 1) on vec (Lemma 1):
 // step t updates position b + t (forward) / e - t (backward) of every segment.
-static int add_sweep(Builder& B, VRef vec, int trans, int k) {
+static int add_copy_state(Builder& B, VRef in, VRef out, double alpha);
+
+static bool sweep_fusable(const Builder& B, int k) {
+  for (const WinDev& W : B.h->wins)
+    if (W.model_kind != MK_BAND || W.s > SWEEP_MAXS || !B.h->models[W.model_id].wd) return false;
+  return k > 1;
+}
+
+// vec = L_M(k)^{-1} (src - sub) (trans: L_M(k)^{-T}); src / sub NONE_REF: in place on vec
+static int add_sweep(Builder& B, VRef vec, int trans, int k, VRef src = VRef{-1, SP_STATE, 0},
+                     VRef sub = VRef{-1, SP_STATE, 0}) {
   // band models with s <= SWEEP_MAXS: one fused launch, one workgroup per segment and rhs
   std::vector<SJob> fused;
-  bool all_band = true;
-  for (const WinDev& W : B.h->wins)
-    if (W.model_kind != MK_BAND || W.s > SWEEP_MAXS || !B.h->models[W.model_id].wd)
-      all_band = false;
-  if (all_band && k > 1) {
+  const bool outplace = src.base >= 0 || sub.base >= 0;
+  if (outplace && !sweep_fusable(B, k)) {
+    // the per-step path sweeps in place: form src - sub (or copy src) first
+    if (sub.base >= 0)
+      SVAR_TRY(add_axpy_state(B, src, sub, -1.0, vec));
+    else
+      SVAR_TRY(add_copy_state(B, src, vec, 1.0));
+    return add_sweep(B, vec, trans, k);
+  }
+  if (sweep_fusable(B, k)) {
     int ms = 0;
     for (int w = 0; w < (int)B.h->wins.size(); ++w) {
       const WinDev& W = B.h->wins[w];
       for (int r = 0; r < B.nrhs; ++r)
         for (int b0 = 0; b0 <= W.N; b0 += k) {
           const int e0 = std::min(b0 + k - 1, W.N);
-          if (e0 == b0) continue;
+          if (e0 == b0 && !outplace) continue;
           SJob J{};
+          J.src = src.base >= 0 ? blk(B.h, w, r, B.nrhs, src, b0) : Operand{-1, 0, 0};
+          J.sub = sub.base >= 0 ? blk(B.h, w, r, B.nrhs, sub, b0) : Operand{-1, 0, 0};
           J.vec = blk(B.h, w, r, B.nrhs, vec, b0);
           J.model = W.model_id;
           J.trans = trans;
@@ -1241,11 +1272,10 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
   if (op == PROG_AD) {
     // A z for z = P_I u just formed by PROG_PD: c1 = L z3 + D z1 with D z1 from the buffer
     P.aux_elems = total_len(h, nrhs, SP_STATE);
-    SVAR_TRY(add_L(B, IN_SAD_X, OUT_SAD_ETA, 0));
+    SVAR_TRY(add_L(B, IN_SAD_X, OUT_SAD_ETA, 0, DZ1));  // L z3 + D z1
     SVAR_TRY(add_L(B, IN_SAD_ETA, OUT_SAD_X, 1));
     SVAR_TRY(add_gather(B, IN_SAD_X, OUT_SAD_NU));
     SVAR_TRY(add_scatter(B, IN_SAD_NU, OUT_SAD_X));
-    SVAR_TRY(add_axpy_state(B, OUT_SAD_ETA, DZ1, 1.0, OUT_SAD_ETA));
     std::vector<GemmProb> probs;
     add_cov(B, probs, MS_R, DT_F64, IN_SAD_NU, OUT_SAD_NU, OUT_SAD_NU, false, 1.0, 1.0);
     SVAR_TRY(add_gemm(B, probs, DT_F64));
@@ -1255,8 +1285,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
     // P_I with D z1 formed in float64 and kept for PROG_AD; Rhat^{-1} in the given precision
     const int dt = prec == PV_BF16P ? DT_BF16 : (prec == PV_F32P ? DT_F32 : DT_F64);
     P.aux_elems = total_len(h, nrhs, SP_STATE);
-    SVAR_TRY(add_copy_state(B, IN_SAD_X, OUT_SAD_ETA, 1.0));
-    SVAR_TRY(add_sweep(B, OUT_SAD_ETA, 1, k));
+    SVAR_TRY(add_sweep(B, OUT_SAD_ETA, 1, k, IN_SAD_X));  // c1 = Lhat^{-T} v3
     if (h->net) SVAR_TRY(add_net(B, OUT_SAD_ETA));
     std::vector<GemmProb> pd, pr;
     add_cov(B, pd, MS_D, DT_F64, OUT_SAD_ETA, DZ1, NONE_REF, true, 1.0, 0.0);
@@ -1265,8 +1294,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
     SVAR_TRY(add_gemm(B, pd, DT_F64));
     if (!pr.empty()) SVAR_TRY(add_gemm(B, pr, dt));
     if (diag) SVAR_TRY(add_copy_obs(B, IN_SAD_NU, OUT_SAD_NU, true));
-    SVAR_TRY(add_axpy_state(B, IN_SAD_ETA, DZ1, -1.0, OUT_SAD_X));  // v1 - D z1
-    SVAR_TRY(add_sweep(B, OUT_SAD_X, 0, k));
+    SVAR_TRY(add_sweep(B, OUT_SAD_X, 0, k, IN_SAD_ETA, DZ1));  // Lhat^{-1} (v1 - D z1)
     return SVAR_OK;
   }
   if (op == PROG_A) {
@@ -1392,6 +1420,7 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
       for (auto& j : J) {
         spans.push_back({j.in.base, j.in.off, j.in.off + j.s});
         spans.push_back({j.out.base, j.out.off, j.out.off + j.s});
+        if (j.use_add) spans.push_back({j.add.base, j.add.off, j.add.off + j.s});
         if (j.model >= 0) {
           spans.push_back({j.x.base, j.x.off, j.x.off + j.s});
           if (j.model >= (int)h->models.size() || h->models[j.model].s != j.s) return fail("model");
@@ -1404,6 +1433,8 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
       SVAR_HIP(hipStreamSynchronize(st));
       for (auto& j : J) {
         spans.push_back({j.vec.base, j.vec.off, j.vec.off + (int64_t)j.len * j.s});
+        spans.push_back({j.src.base, j.src.off, j.src.off + (int64_t)j.len * j.s});
+        spans.push_back({j.sub.base, j.sub.off, j.sub.off + (int64_t)j.len * j.s});
         if (j.model < 0 || j.model >= (int)h->models.size() || h->models[j.model].kind != MK_BAND ||
             !h->models[j.model].wd || j.s > SWEEP_MAXS || j.len < 1)
           return fail("sweep job");

@@ -75,12 +75,17 @@ struct MJob {
   Operand in, x, out;
   int32_t model, mi, trans, s;
   double alpha;
+  Operand add;        // use_add: out also receives + add (band and dense models)
+  int32_t use_add, pad2;
 };
 enum ModelKind { MK_BAND = 0, MK_DENSE = 1, MK_L96 = 2 };
 // one whole L_M(k) sweep segment: blocks vec.off + [0, len) s, in place
 struct SJob {
   Operand vec;
   int32_t model, trans, s, len;
+  // sources of the sweep's input (base -1: none): the input is src - sub (src none: vec
+  // itself, in place), so a copy or a difference before the sweep needs no launch of its own
+  Operand src, sub;
 };
 constexpr int SWEEP_MAXS = 8192;  // LDS holds two state vectors (128 KB)
 constexpr int SWEEP_R = 8;        // outputs per thread of the fused sweep
