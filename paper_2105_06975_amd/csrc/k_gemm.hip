@@ -394,17 +394,142 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
   }
 }
 
+// The same product with the matrix rows staged in LDS as well (16 lanes per 128-byte row run,
+// stride 17): used when a matrix's rows are not 4-element aligned (n not a multiple of 4), where
+// the register path above would fall back to single-element loads spread over 16 rows.
+template <int CT, typename CS, typename AT>
+__global__ __launch_bounds__(256, 2) void k_gemm_tiled_lds(const GemmProb* __restrict__ probs,
+                                                    const GemmTask* __restrict__ tasks,
+                                                    double* __restrict__ ws, Bases b,
+                                                    const int* __restrict__ skip) {
+  constexpr int KT = 16, MT = 128, NT = 16 * CT, AS = KT + 1;
+  typedef typename mfma_of<AT>::acc_t acc_t;
+  typedef typename gptr_of<CS>::type cptr;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  AT* As = (AT*)lds_raw;             // [2][MT * AS]
+  AT* Xs = As + 2 * MT * AS;         // [2][NT * AS]
+  if (skip && *skip) return;
+  const GemmTask t = tasks[blockIdx.x];
+  const GemmProb P = probs[t.prob];
+  const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, q = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // loader role: k offset kl, row / column rsub + 16 j
+  const int kl = tid & 15, rsub = tid >> 4;
+  cptr arow[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int row = t.row0 + rsub + 16 * j;
+    arow[j] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
+  }
+  const double* X = opnd(b, P.X);
+  gdp xcol[CT];
+#pragma unroll
+  for (int j = 0; j < CT; ++j) {
+    const int c = t.col0 + rsub + 16 * j;
+    const bool ok = c < P.ncols;
+    const int cc = ok ? c : 0;
+    const int co = cc / P.per, ci = cc - co * P.per;
+    xcol[j] = (gdp)(ok ? X + co * P.xo + ci * P.xi : P.zeros);
+  }
+  acc_t acc[2][CT];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = acc_t{};
+  const int nst = (t.k1 - t.k0 + KT - 1) / KT;
+  CS ra[8];
+  double rx[CT];
+  bool okk = false;
+  auto gload = [&](int s) {
+    const int k = t.k0 + s * KT + kl;
+    okk = k < t.k1;
+    const int kc = okk ? k : t.k0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ra[j] = arow[j][kc];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) rx[j] = xcol[j][kc];
+  };
+  auto sstore = [&](int buf) {
+    AT* a = As + buf * MT * AS;
+    AT* x = Xs + buf * NT * AS;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[(rsub + 16 * j) * AS + kl] = okk ? to_acc(ra[j], AT()) : AT(0);
+#pragma unroll
+    for (int j = 0; j < CT; ++j) x[(rsub + 16 * j) * AS + kl] = okk ? to_acc(rx[j], AT()) : AT(0);
+  };
+  if (nst > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nst) gload(s + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    const AT* a = As + buf * MT * AS + (wave * 32 + r16) * AS;
+    const AT* x = Xs + buf * NT * AS + r16 * AS;
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) {
+      const int kk = 4 * sub + q;
+      AT av[2], bv[CT];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) av[rt] = a[rt * 16 * AS + kk];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) bv[ct] = x[ct * 16 * AS + kk];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma_of<AT>::op(av[rt], bv[ct], acc[rt][ct]);
+      // keep each sub-step's LDS reads next to its MFMAs (fewer live registers: two waves
+      // per SIMD fit, which hides the LDS latency and the stage barrier)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (s + 1 < nst) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int c = t.col0 + ct * 16 + r16;
+    if (c >= P.ncols) continue;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = t.row0 + wave * 32 + rt * 16 + mfma_of<AT>::row(q, e);
+        if (r >= P.n) continue;
+        const double v = (double)acc[rt][ct][e];
+        if (P.splits > 1)
+          ws[P.ws_off + ((int64_t)t.split * P.ncols + c) * P.n + r] = v;
+        else
+          gemm_store(P, b, r, c, v);
+      }
+  }
+}
+
 template <int CT, typename CS, typename AT>
 static void launch_tiled_t(const GemmPlanDev& g, Bases b, double* ws, const int* skip,
                            hipStream_t st) {
-  const size_t lds = (size_t)2 * (16 * CT) * 17 * sizeof(AT);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_gemm_tiled<CT, CS, AT>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr = true;
+  if (g.direct) {
+    const size_t lds = (size_t)2 * (16 * CT) * 17 * sizeof(AT);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)k_gemm_tiled<CT, CS, AT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_gemm_tiled<CT, CS, AT>), dim3(g.ntask), dim3(256), lds, st, g.probs,
+                       g.tasks, ws, b, skip);
+    return;
   }
-  hipLaunchKernelGGL((k_gemm_tiled<CT, CS, AT>), dim3(g.ntask), dim3(256), lds, st, g.probs,
+  const size_t lds = (size_t)2 * (128 + 16 * CT) * 17 * sizeof(AT);
+  static bool attr_lds = false;
+  if (!attr_lds) {
+    (void)hipFuncSetAttribute((const void*)k_gemm_tiled_lds<CT, CS, AT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_lds = true;
+  }
+  hipLaunchKernelGGL((k_gemm_tiled_lds<CT, CS, AT>), dim3(g.ntask), dim3(256), lds, st, g.probs,
                      g.tasks, ws, b, skip);
 }
 template <int CT>

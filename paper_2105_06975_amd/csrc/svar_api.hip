@@ -83,51 +83,81 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
                             int64_t& ws, int& maxct, int target) {
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
-  // Column tile 16 ct (ct in 4..9) and split-K chunk, chosen together so that the tasks fill
-  // whole rounds of the `target` resident workgroups.  Estimated time = rounds x longest chunk
-  // (16-wide stages) x (ct + 2) (the MFMAs and panel loads grow with ct, the matrix-row loads
-  // and the barrier do not) + one stage per split (the partials' write and fixed-order
-  // reduce).  One chunk length serves all problems.  C2's D product (4096 x 520) on 512
-  // slots: ct = 9, 32 x 4 tiles x 4 splits = 512 tasks in one round (576 computed columns);
-  // ct = 7 would leave 480 tasks of 86 stages.
+  // Column tile 16 ct and split-K chunk per problem.
+  // One or two problems per launch (the single-window products): ct in 4..9 and one chunk
+  // length chosen together so that the tasks fill whole rounds of the `target` resident
+  // workgroups.  Estimated time = rounds x longest chunk (16-wide stages) x (ct + 2) (the MFMAs
+  // and panel loads grow with ct, the matrix-row loads and the barrier do not) + one stage per
+  // split (the partials' write and fixed-order reduce).  C2's D product (4096 x 520) on 512
+  // slots: ct = 9, 32 x 4 tiles x 4 splits = 512 tasks in one round.
+  // Many problems (a batch of uneven windows): the tile with the fewest padded columns
+  // (ct 4..8, ties wider) and splits in proportion to each problem's share of the work, at
+  // least 256 k per task.  A common short chunk there multiplies the tasks and the partial
+  // tiles written for the reduce (64 C4 windows: 58 000 tasks against 3 300, +40 % GEMM time).
   const int rows = 128;
-  int maxst = 1;
-  for (auto& p : probs) maxst = std::max(maxst, (p.n + 15) / 16);
-  const int umin = std::min(maxst, 8);
-  const int ctmax = std::min(9, std::max(2, (maxcols + 15) / 16));
-  int bestU = maxst, bestct = ctmax;
-  double bestcost = 1e300;
-  for (int ct = std::min(4, ctmax); ct <= ctmax; ++ct) {
-    const int cwt = 16 * ct;
-    for (int U = maxst; U >= umin; --U) {
-      int64_t ntask = 0;
-      int longest = 0, maxS = 1;
-      for (auto& p : probs) {
-        const int st = (p.n + 15) / 16, S = (st + U - 1) / U, ch = (st + S - 1) / S;
-        ntask += (int64_t)((p.n + rows - 1) / rows) * ((p.ncols + cwt - 1) / cwt) * S;
-        longest = std::max(longest, ch);
-        maxS = std::max(maxS, S);
-      }
-      const double cost =
-          ((double)((ntask + target - 1) / target) * longest + maxS) * (ct + 2);
-      if (cost < bestcost) {
-        bestcost = cost;
-        bestU = U;
-        bestct = ct;
+  const int np = (int)probs.size();
+  std::vector<int> chunk(np), nsplit(np);
+  if (np <= 2) {
+    int maxst = 1;
+    for (auto& p : probs) maxst = std::max(maxst, (p.n + 15) / 16);
+    const int umin = std::min(maxst, 8);
+    const int ctmax = std::min(9, std::max(2, (maxcols + 15) / 16));
+    int bestU = maxst, bestct = ctmax;
+    double bestcost = 1e300;
+    for (int ct = std::min(4, ctmax); ct <= ctmax; ++ct) {
+      const int cwt = 16 * ct;
+      for (int U = maxst; U >= umin; --U) {
+        int64_t ntask = 0;
+        int longest = 0, maxS = 1;
+        for (auto& p : probs) {
+          const int st = (p.n + 15) / 16, S = (st + U - 1) / U, ch = (st + S - 1) / S;
+          ntask += (int64_t)((p.n + rows - 1) / rows) * ((p.ncols + cwt - 1) / cwt) * S;
+          longest = std::max(longest, ch);
+          maxS = std::max(maxS, S);
+        }
+        const double cost =
+            ((double)((ntask + target - 1) / target) * longest + maxS) * (ct + 2);
+        if (cost < bestcost) {
+          bestcost = cost;
+          bestU = U;
+          bestct = ct;
+        }
       }
     }
+    maxct = bestct;
+    for (int pi = 0; pi < np; ++pi) {
+      const int st = (probs[pi].n + 15) / 16, S = (st + bestU - 1) / bestU;
+      chunk[pi] = 16 * ((st + S - 1) / S);
+    }
+  } else {
+    int best = 8, bestpad = 1 << 30;
+    for (int ct = 8; ct >= 4; --ct) {
+      const int pad = (maxcols + 16 * ct - 1) / (16 * ct) * ct;
+      if (pad < bestpad) {
+        bestpad = pad;
+        best = ct;
+      }
+    }
+    maxct = std::min(best, (maxcols + 15) / 16);
+    const int cwt = maxct * 16;
+    double total_work = 0.0;
+    for (auto& p : probs) total_work += (double)p.n * p.n * p.ncols;
+    for (int pi = 0; pi < np; ++pi) {
+      const GemmProb& p = probs[pi];
+      const int rt = (p.n + rows - 1) / rows, cg = (p.ncols + cwt - 1) / cwt;
+      const double share = total_work > 0 ? (double)p.n * p.n * p.ncols / total_work : 1.0;
+      const int want = (int)std::ceil(target * share / (double)(rt * cg));
+      const int S = std::max(1, std::min(want, std::max(1, p.n / 256)));
+      chunk[pi] = ((p.n + S - 1) / S + 63) / 64 * 64;
+    }
   }
-  maxct = bestct;
   const int cw = maxct * 16;
   ws = 0;
   std::vector<std::vector<GemmTask>> groups;
-  for (int pi = 0; pi < (int)probs.size(); ++pi) {
+  for (int pi = 0; pi < np; ++pi) {
     GemmProb& p = probs[pi];
     const int rt = (p.n + rows - 1) / rows, cg = (p.ncols + cw - 1) / cw;
-    const int st = (p.n + 15) / 16;
-    const int S = (st + bestU - 1) / bestU;
-    const int chunk = 16 * ((st + S - 1) / S);
-    p.splits = (p.n + chunk - 1) / chunk;
+    p.splits = (p.n + chunk[pi] - 1) / chunk[pi];
     p.ws_off = 0;
     if (p.splits > 1) {
       p.ws_off = ws;
@@ -140,8 +170,8 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
           GemmTask t;
           t.prob = pi;
           t.row0 = r * rows;
-          t.k0 = sp * chunk;
-          t.k1 = std::min(p.n, (sp + 1) * chunk);
+          t.k0 = sp * chunk[pi];
+          t.k1 = std::min(p.n, (sp + 1) * chunk[pi]);
           t.col0 = c * cw;
           t.split = sp;
           grp.push_back(t);
@@ -231,6 +261,10 @@ static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector
   if (maxcols < 32) tiled = 0;  // the tiled kernel needs two or more 16-column tiles
   g.tiled = tiled;
   g.target = target;
+  g.direct = 1;
+  const size_t esz = dtype == DT_F64 ? 8 : (dtype == DT_F32 ? 4 : 2);
+  for (auto& p : probs)
+    if ((p.n & 3) != 0 || ((uintptr_t)p.C & (4 * esz - 1)) != 0) g.direct = 0;
   g.hprobs = probs;
   if (g.tiled)
     plan_gemm_tiled(probs, tasks, ws, maxct, target);

@@ -143,6 +143,7 @@ struct GemmPlanDev {
   int64_t ws_elems = 0;
   int dtype = DT_F64;
   int tiled = 0;                  // 1: LDS-tiled kernel (128-row tiles), 0: k-split kernel
+  int direct = 0;                 // tiled: every matrix 4-element aligned (rows read to registers)
   int target = 512;               // workgroups the planner aims for
   std::vector<GemmProb> hprobs;   // host copy of the problems (autotuning re-plans them)
   std::string key;                // shape key of the launch (autotuning cache)
