@@ -3,7 +3,8 @@ columns, i.e. several right-hand sides) and the learned correction at the benchm
 
 * A v and P^{-1} v for 12 right-hand sides of small uneven windows (tile rows past n, ragged
   column groups) against the oracle, element by element, with float64 matrices and with
-  float32 / bfloat16 copies;
+  float32 / bfloat16 copies; five windows per launch (the many-problem plan, with and without
+  rows that are not 4-element aligned);
 * A v at the full C2 size for 3 right-hand sides (195-column panels) against the oracle;
 * the learned correction inside P_I at the full C2 size, sampled: three time blocks of one
   right-hand side against the oracle's network on the same blocks.
@@ -59,6 +60,30 @@ def test_many_rhs_small_windows(sv, ptype):
             assert rel(ya[a:a + win.n], orc.apply_A(v)) < 1e-12, (w, r)
             ref = orc.apply_PI_inv(v) if ptype == "PI" else orc.apply_PD_inv(v)
             assert rel(yp[a:a + win.n], ref) < 1e-10, (w, r)
+
+
+def test_many_windows_tiled_plans(sv):
+    """Five uneven windows x 12 rhs: every covariance launch holds five problems (the
+    share-based split plan), with 4-aligned and unaligned rows mixed (the LDS-staged kernel)
+    and, for the last three windows alone, aligned rows only (the register path)."""
+    shapes = [(122, 10, 45), (98, 11, 37), (152, 12, 64), (200, 10, 80), (136, 11, 52)]
+    wins = [wl.make_small_window(s=s, N=N, p=p, seed=40 + i) for i, (s, N, p) in
+            enumerate(shapes)]
+    nrhs = 12
+    for sub in (wins, wins[2:]):
+        h = sv.Handle(sub, sv.Precond(type="PI", k=3, rhat="RR"))
+        V = np.concatenate([wl.random_vectors(w, nrhs, seed=60 + i).ravel()
+                            for i, w in enumerate(sub)])
+        ya = host(h.apply_A(dev(V), nrhs))
+        yp = host(h.apply_P(dev(V), nrhs))
+        off = h.offsets(nrhs)
+        for w, win in enumerate(sub):
+            orc = so.SaddleOracle(win, k=3, rhat="RR")
+            for r in (0, 5, nrhs - 1):
+                a = off[w] + r * win.n
+                v = V[a:a + win.n]
+                assert rel(ya[a:a + win.n], orc.apply_A(v)) < 1e-12, (len(sub), w, r)
+                assert rel(yp[a:a + win.n], orc.apply_PI_inv(v)) < 1e-10, (len(sub), w, r)
 
 
 def test_many_rhs_low_precision_products(sv):
