@@ -146,9 +146,9 @@ def gemm_flops(win, iters, applies_a64):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are "
-                                   "not part of this build (see DESIGN.md for the sharding "
-                                   "design)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no "
+                                   "multi-GPU path (independent windows would be placed on "
+                                   "different GPUs with no communication)"}))
         sys.exit(2)
     import torch
 
