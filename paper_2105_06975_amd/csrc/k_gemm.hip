@@ -354,6 +354,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
     if (s + 1 < nst) gload(s + 1);
     __builtin_amdgcn_sched_barrier(0);
     const AT* x = Xs + buf * NT * AS + r16 * AS + 4 * q;
+    // raised wave priority while this wave issues its MFMAs, so that the other wave of the
+    // SIMD, busy with its stores and the barrier, does not take issue slots from them
+    // (C2 D product 337 -> 333 us)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int sub = 0; sub < 4; ++sub) {
       AT bv[CT];
@@ -368,6 +372,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
       // per SIMD fit, which hides the LDS latency and the stage barrier)
       __builtin_amdgcn_sched_barrier(0);
     }
+    __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
     if (s + 1 < nst) {
       sstore(buf ^ 1);
