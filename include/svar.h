@@ -163,6 +163,20 @@ typedef struct svar_solve_opts {
      harvest then records every preconditioner input (the block's first vector and its
      normalised products); no graph replay in block mode. */
   int32_t block;
+  /* MINRES stopping rule: 0 (default) the relative residual in the two norm, §7 -- the
+     residual rhs - A x is carried along by the recurrence of A w (w the MINRES search
+     directions, A w formed from the A v of each Lanczos step) and checked every iteration;
+     1: the P^{-1}-norm estimate phibar <= rtol ||rhs||_{P^{-1}} of Paige-Saunders.  Either way
+     the true residual is recomputed at return and a system whose ||rhs - A x||_2 exceeds
+     rtol ||rhs||_2 reports SVAR_E_NOCONV.  Ignored by FGMRES. */
+  int32_t minres_norm;
+  /* residual history (nullable): DEVICE buffer of nsys * history_len doubles, nsys = windows x
+     nrhs in packed order; entry [sys * history_len + t] receives the solver's residual-norm
+     estimate (absolute, two norm; for MINRES with minres_norm = 1 the P^{-1}-norm estimate)
+     after iteration t + 1, counting across restart and refinement cycles.  Entries after a
+     system's last iteration are set to NaN.  Iterations beyond history_len are not recorded. */
+  double* history;
+  int32_t history_len;
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */

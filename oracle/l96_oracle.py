@@ -104,30 +104,73 @@ class L96Tangent:
         return x
 
 
-def gauss_newton(win, n_outer, *, k=3, rhat="RR", prec="PI", rtol=1e-12):
+def forecast_fn(win, traj):
+    """The nonlinear model of one observation interval, y = M_i(x_{i-1}) (§2.1): RK4 for a
+    Lorenz-96 window, the linear map M for the other model kinds."""
+    from oracle import svar_oracle as so
+    m = win.model
+    if m["kind"] == "l96":
+        T = L96Tangent(m["F"], m["dt"], m["nsteps"], traj)
+        return lambda i, x: T.forecast(x)
+    ops = so.ModelOps(win)
+    return lambda i, x: ops.M(i, x)
+
+
+def gn_rhs(x, xb, y, idx, forecast):
+    """Right-hand side (b; d; 0) of the saddle system linearised about x = (x_0..x_N) (§2.1,
+    incremental form): b_0 = x_b - x_0, b_i = M_i(x_{i-1}) - x_i, d_i = y_i - H x_i (H picks
+    the observed points idx)."""
+    nb, s = x.shape
+    b = np.zeros((nb, s))
+    b[0] = xb - x[0]
+    for i in range(1, nb):
+        b[i] = forecast(i, x[i - 1]) - x[i]
+    d = np.concatenate([y[i] - x[i][idx] for i in range(nb)])
+    return np.concatenate([b.ravel(), d, np.zeros(nb * s)])
+
+
+def cost(win, x, xb, y, idx, forecast):
+    """The weak-constraint 4D-Var cost of eq. CostFn at the trajectory x (dense inverses:
+    small windows only): 1/2 |x_0 - x_b|^2_{B^-1} + 1/2 sum_i |x_i - M_i(x_{i-1})|^2_{Q_i^-1}
+    + 1/2 sum_i |y_i - H x_i|^2_{R_i^-1}."""
+    nb = x.shape[0]
+
+    def wnorm(C, v):
+        return float(v @ np.linalg.solve(C, v))
+    D = [float(win.d_scale[i]) * np.asarray(win.dmats[int(win.d_index[i])]) for i in range(nb)]
+    R = [np.asarray(win.rmats[int(win.r_index[i])]) for i in range(nb)]
+    J = wnorm(D[0], x[0] - xb)
+    for i in range(1, nb):
+        J += wnorm(D[i], x[i] - forecast(i, x[i - 1]))
+    for i in range(nb):
+        J += wnorm(R[i], y[i] - x[i][idx])
+    return 0.5 * J
+
+
+def gauss_newton(win, n_outer, *, k=3, rhat="RR", prec="PI", rtol=1e-12, x0=None,
+                 rhs_fn=None):
     """Oracle outer loop (§2.1): linearise about x^(l), solve the saddle system for the
-    increment with the oracle FGMRES, x^(l+1) = x^(l) + dx.  Returns the list of iterates."""
+    increment with the oracle FGMRES, x^(l+1) = x^(l) + dx.  The window needs meta["xb"],
+    meta["y"] and meta["obs_idx"]; x0 defaults to model["traj"] (Lorenz-96) and must be given
+    for the linear kinds.  rhs_fn replaces gn_rhs (tests plant mistakes through it).
+    Returns the list of iterates."""
     import copy
 
     from oracle import svar_oracle as so
     s, nb = win.s, win.N + 1
     m = win.model
-    x = np.array(m["traj"], dtype=np.float64)
+    x = np.array(m["traj"] if x0 is None else x0, dtype=np.float64).reshape(nb, s)
     xb = np.asarray(win.meta["xb"])
     y = np.asarray(win.meta["y"])
     idx = np.asarray(win.meta["obs_idx"])
+    rhs_fn = gn_rhs if rhs_fn is None else rhs_fn
     out = [x.copy()]
     for _ in range(n_outer):
         w = copy.copy(win)
-        w.model = dict(m, traj=x.copy())
+        if m["kind"] == "l96":
+            w.model = dict(m, traj=x.copy())
         orc = so.SaddleOracle(w, k=k, rhat=rhat)
-        T = orc.model.l96
-        b = np.zeros((nb, s))
-        b[0] = xb - x[0]
-        for i in range(1, nb):
-            b[i] = T.forecast(x[i - 1]) - x[i]
-        d = np.concatenate([y[i] - x[i][idx] for i in range(nb)])
-        rhs = np.concatenate([b.ravel(), d, np.zeros(nb * s)])
+        rhs = rhs_fn(x, xb, y, idx, forecast_fn(w, x))
         sol = so.solve(orc, rhs, prec=prec, rtol=rtol, maxit=orc.n)
         x = x + sol["x"][-nb * s:].reshape(nb, s)
         out.append(x.copy())

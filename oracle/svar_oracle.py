@@ -394,13 +394,19 @@ def fgmres(apply_A, apply_Pinv, rhs, rtol: float, maxit: int):
     return x, iters, hist
 
 
-def minres(apply_A, apply_Minv, rhs, rtol: float, maxit: int):
+def minres(apply_A, apply_Minv, rhs, rtol: float, maxit: int, norm: str = "P"):
     """Preconditioned MINRES (Paige-Saunders) for symmetric A and SPD preconditioner M.
 
     The Lanczos process runs in the M^{-1} inner product; the tridiagonal least-squares
-    problem is solved by Givens rotations.  Stops when the M^{-1}-norm residual estimate
-    phibar <= rtol * beta_1.  Returns (x, iters, hist) with hist the estimate / beta_1.
+    problem is solved by Givens rotations.  norm="P": stop when the M^{-1}-norm residual
+    estimate phibar <= rtol * beta_1 (hist: the estimate / beta_1).  norm="2": stop when the
+    true residual ||rhs - A x||_2 <= rtol ||rhs||_2, recomputed from x after every iteration
+    (§7 asks for a residual criterion in the two norm; hist: that relative residual).
+    Returns (x, iters, hist).
     """
+    if norm not in ("P", "2"):
+        raise ValueError(norm)
+    nrhs = float(np.linalg.norm(rhs))
     n = rhs.size
     x = np.zeros(n)
     r_prev = np.zeros(n)
@@ -442,20 +448,27 @@ def minres(apply_A, apply_Minv, rhs, rtol: float, maxit: int):
         w_new = (v - eps_old * w_old - delta * w) / gamma
         w_old, w = w, w_new
         x = x + phi * w
-        hist.append(phibar / beta1)
-        if phibar <= rtol * beta1 or beta == 0.0:
+        if norm == "P":
+            hist.append(phibar / beta1)
+            stop = phibar <= rtol * beta1
+        else:
+            rel2 = float(np.linalg.norm(rhs - apply_A(x))) / nrhs
+            hist.append(rel2)
+            stop = rel2 <= rtol
+        if stop or beta == 0.0:
             iters = k
             break
     return x, iters, hist
 
 
-def solve(orc: SaddleOracle, rhs, *, prec="PI", method="FGMRES", rtol=1e-6, maxit=1000):
+def solve(orc: SaddleOracle, rhs, *, prec="PI", method="FGMRES", rtol=1e-6, maxit=1000,
+          minres_norm="2"):
     A = orc.apply_A
     P = lambda v: orc.apply_P_inv(v, prec)  # noqa: E731
     if method == "FGMRES":
         x, it, hist = fgmres(A, P, rhs, rtol, maxit)
     elif method == "MINRES":
-        x, it, hist = minres(A, P, rhs, rtol, maxit)
+        x, it, hist = minres(A, P, rhs, rtol, maxit, norm=minres_norm)
     else:
         raise ValueError(method)
     res = rhs - A(x)

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
                                                  const double* __restrict__ sums,
                                                  KHess* __restrict__ hs, int m, int finalize_only,
                                                  int* __restrict__ net_off, double drop,
-                                                 int patience) {
+                                                 int patience, HistArg hist) {
   __shared__ double red[NT / 64];
   __shared__ double col[1];
   extern __shared__ double dyn[];  // 3 j + 1 doubles
@@ -369,6 +369,10 @@ __global__ __launch_bounds__(NT) void k_fg_small(KState* __restrict__ st, KGloba
         }
       }
       S.iters = j;
+      if (hist.h) {
+        const int t = hist.it0[blockIdx.x] + j - 1;
+        if (t < hist.len) hist.h[(int64_t)blockIdx.x * hist.len + t] = S.est;
+      }
       bool fin = isfinite(S.est) && isfinite(rho);
       if (!fin) {
         S.status = SVAR_E_BREAKDOWN;
@@ -575,10 +579,10 @@ void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const doubl
 }
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
               int finalize_only, int jmax, int* net_off, double drop, int patience,
-              hipStream_t st) {
+              HistArg hist, hipStream_t st) {
   hipLaunchKernelGGL(k_fg_small, dim3(p.nsys), dim3(NT), (size_t)(3 * jmax + 4) * sizeof(double),
                      st, stt, gl, sums, hs, m, finalize_only, net_off, drop,
-                     patience < 1 ? 1 : patience);
+                     patience < 1 ? 1 : patience, hist);
 }
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
@@ -969,7 +973,7 @@ __global__ __launch_bounds__(NT) void k_bk_hess(KState* __restrict__ st, KGlobal
                                                 const KBlock* __restrict__ kbs,
                                                 KHess* __restrict__ hs, int m, int j, int b,
                                                 int* __restrict__ net_off, double drop,
-                                                int patience) {
+                                                int patience, HistArg hist) {
   extern __shared__ double sm[];  // cs[j], sn[j], block cs/sn [2B], columns [b][j + b + 1]
   __shared__ int nused_s;
   if (gl->all_done) return;
@@ -1051,6 +1055,10 @@ __global__ __launch_bounds__(NT) void k_bk_hess(KState* __restrict__ st, KGlobal
         }
       }
       S.iters = c + 1;
+      if (hist.h) {
+        const int t = hist.it0[blockIdx.x] + c;
+        if (t < hist.len) hist.h[(int64_t)blockIdx.x * hist.len + t] = S.est;
+      }
       used = i + 1;
       if (!(isfinite(S.est) && isfinite(rho))) {
         S.status = SVAR_E_BREAKDOWN;
@@ -1141,14 +1149,14 @@ void kb_trsm(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double
 }
 void kb_hess(int B, const KPlan& p, KState* stt, KGlobal* gl, const double* S1, const double* S2,
              int SLB, const KBlock* kb, KHess* hs, int m, int j, int b, int* net_off,
-             double drop, int patience, hipStream_t st) {
+             double drop, int patience, HistArg hist, hipStream_t st) {
   const size_t lds = (size_t)(2 * j + 2 * B + b * (j + b + 1)) * sizeof(double);
   if (B == 4)
     hipLaunchKernelGGL(k_bk_hess<4>, dim3(p.nsys), dim3(NT), lds, st, stt, gl, S1, S2, SLB, kb, hs,
-                       m, j, b, net_off, drop, patience < 1 ? 1 : patience);
+                       m, j, b, net_off, drop, patience < 1 ? 1 : patience, hist);
   else
     hipLaunchKernelGGL(k_bk_hess<KB_MAX>, dim3(p.nsys), dim3(NT), lds, st, stt, gl, S1, S2, SLB,
-                       kb, hs, m, j, b, net_off, drop, patience < 1 ? 1 : patience);
+                       kb, hs, m, j, b, net_off, drop, patience < 1 ? 1 : patience, hist);
 }
 
 int kr_resident_tasks() {

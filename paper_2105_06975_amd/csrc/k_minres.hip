@@ -2,9 +2,15 @@
 // definite, so MINRES applies).  Lanczos in the P^{-1} inner product with the three-term
 // recurrence; the tridiagonal least-squares problem is updated by one Givens rotation per
 // step; x is updated with the last two search directions.  Many systems run in lock step,
-// each with its own scalars; stopping test: P^{-1}-norm residual estimate <= rtol * beta_1.
+// each with its own scalars.  Stopping test (§7: a residual criterion in the two norm): the
+// residual r = rhs - A x is carried along with x.  Since x_k = x_{k-1} + phi_k w_k and
+// w_k = (v_k - eps w_{k-2} - delta w_{k-1}) / gamma, A w_k follows the same recurrence from the
+// product A v_k that the Lanczos step forms anyway, and r_k = r_{k-1} - phi_k A w_k; the
+// iteration stops when ||r_k||_2 <= rtol ||rhs||_2.  Optionally the Paige-Saunders estimate of
+// the P^{-1}-norm residual (phibar <= rtol * beta_1) is the test instead.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 #include "mem.h"
 #include "minres.h"
@@ -14,9 +20,11 @@ namespace svar {
 static constexpr int NT = 256;
 
 struct MState {
-  int32_t done, iters, status, pad;
+  int32_t done, iters, status, pad;  // pad: the step just taken met the stopping test
   double beta, beta_old, beta1, phibar, c, s, dbar, eps;
   double alpha, eps_old, delta, gamma, phi, tol;
+  double tol2;   // rtol ||rhs||_2 (two-norm test)
+  double res2;   // ||r_k||_2 of the carried residual
 };
 
 __device__ __forceinline__ double wsum(double v) {
@@ -48,8 +56,9 @@ __global__ __launch_bounds__(NT) void k_mr_dot(const KTask* __restrict__ tasks,
 }
 
 // beta_1 = sqrt(r^T P^{-1} r) from sysv; initial QR state
-__global__ void k_mr_init(MState* __restrict__ st, const double* __restrict__ sysv, double rtol,
-                          int nsys, KGlobal* __restrict__ gl) {
+__global__ void k_mr_init(MState* __restrict__ st, const double* __restrict__ sysv,
+                          const double* __restrict__ rhs2, double rtol, int nsys,
+                          KGlobal* __restrict__ gl) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int rem = 0;
   for (int i = 0; i < nsys; ++i) {
@@ -61,6 +70,8 @@ __global__ void k_mr_init(MState* __restrict__ st, const double* __restrict__ sy
     S.c = -1.0;
     S.s = 0.0;
     S.tol = rtol * S.beta1;
+    S.res2 = sqrt(fmax(rhs2[i], 0.0));
+    S.tol2 = rtol * S.res2;
     S.done = (S.beta1 > 0.0) ? 0 : 1;
     if (!isfinite(b2) || b2 < 0.0) {
       S.done = 1;
@@ -93,7 +104,8 @@ __global__ __launch_bounds__(NT) void k_mr_y1(const KTask* __restrict__ tasks,
                                               const KGlobal* __restrict__ gl, double* __restrict__ y,
                                               const double* __restrict__ rp,
                                               const double* __restrict__ v, int first,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ part,
+                                              double* __restrict__ av) {
   if (gl->all_done) return;
   const KTask t = tasks[blockIdx.x];
   const MState S = st[t.sys];
@@ -102,6 +114,7 @@ __global__ __launch_bounds__(NT) void k_mr_y1(const KTask* __restrict__ tasks,
   double acc = 0.0;
   for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) {
     double yy = y[e];
+    if (av) av[e] = yy;  // A v, kept for the residual recurrence
     if (!first) yy -= f * rp[e];
     y[e] = yy;
     acc += v[e] * yy;
@@ -129,7 +142,8 @@ __global__ __launch_bounds__(NT) void k_mr_y2(const KTask* __restrict__ tasks,
 
 // new beta from sysv = r^T P^{-1} r; Givens update of the tridiagonal QR
 __global__ void k_mr_scalar(MState* __restrict__ st, const double* __restrict__ sysv, int nsys,
-                            KGlobal* __restrict__ gl) {
+                            KGlobal* __restrict__ gl, int pnorm, double* __restrict__ hist,
+                            int hlen) {
   if (gl->all_done) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nsys) return;
@@ -156,12 +170,33 @@ __global__ void k_mr_scalar(MState* __restrict__ st, const double* __restrict__ 
   if (!isfinite(S.phibar) || !isfinite(b2) || b2 < 0.0) {
     S.status = SVAR_E_BREAKDOWN;
     stop = true;
-  } else if (S.phibar <= S.tol || beta == 0.0) {
+  } else if ((pnorm && S.phibar <= S.tol) || beta == 0.0) {
     stop = true;
   }
   // the x update of this step still runs (k_mr_w reads done only through `pending`)
   S.pad = stop ? 1 : 0;
   st[i] = S;
+  if (hist && pnorm && S.iters <= hlen) hist[(int64_t)i * hlen + S.iters - 1] = S.phibar;
+}
+
+// two-norm test on the carried residual (sysv = ||r_k||^2 per system)
+__global__ void k_mr_check(MState* __restrict__ st, const double* __restrict__ sysv, int nsys,
+                           const KGlobal* __restrict__ gl, double* __restrict__ hist, int hlen) {
+  if (gl->all_done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsys) return;
+  MState S = st[i];
+  if (S.done) return;
+  const double r2 = sysv[i];
+  S.res2 = r2 > 0.0 ? sqrt(r2) : 0.0;
+  if (!isfinite(r2)) {
+    S.status = SVAR_E_BREAKDOWN;
+    S.pad = 1;
+  } else if (S.res2 <= S.tol2) {
+    S.pad = 1;
+  }
+  st[i] = S;
+  if (hist && S.iters <= hlen) hist[(int64_t)i * hlen + S.iters - 1] = S.res2;
 }
 
 // w_new = (v - eps_old w_older - delta w_old) / gamma ; x += phi w_new; retire finished systems
@@ -172,18 +207,37 @@ __global__ __launch_bounds__(NT) void k_mr_w(const KTask* __restrict__ tasks,
                                              const double* __restrict__ wolder,
                                              const double* __restrict__ wold,
                                              double* __restrict__ wnew, double* __restrict__ x,
-                                             int first) {
+                                             int first, const double* __restrict__ av,
+                                             const double* __restrict__ awolder,
+                                             const double* __restrict__ awold,
+                                             double* __restrict__ awnew, double* __restrict__ res,
+                                             double* __restrict__ part) {
   if (gl->all_done) return;
   const KTask t = tasks[blockIdx.x];
   const MState S = st[t.sys];
   if (S.done) return;
   const double ig = 1.0 / S.gamma;
+  double acc = 0.0;
   for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) {
     const double a = first ? 0.0 : wolder[e];
     const double b = first ? 0.0 : wold[e];
     const double wn = (v[e] - S.eps_old * a - S.delta * b) * ig;
     wnew[e] = wn;
     x[e] += S.phi * wn;
+    if (av) {
+      // A w_k by the same recurrence, and the residual r_k = r_{k-1} - phi_k A w_k
+      const double aa = first ? 0.0 : awolder[e];
+      const double ab = first ? 0.0 : awold[e];
+      const double awn = (av[e] - S.eps_old * aa - S.delta * ab) * ig;
+      awnew[e] = awn;
+      const double r = res[e] - S.phi * awn;
+      res[e] = r;
+      acc += r * r;
+    }
+  }
+  if (av) {
+    acc = bsum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
   }
 }
 
@@ -209,10 +263,16 @@ int solve_minres(svar_handle* h, const svar_solve_opts* o, int nrhs, const doubl
   std::vector<void*> tmp;
   double *R0 = nullptr, *R1 = nullptr, *R2 = nullptr, *W0 = nullptr, *W1 = nullptr, *W2 = nullptr,
          *v = nullptr;
+  // two-norm test: A v, A w (three generations) and the carried residual
+  const bool two = o->minres_norm == 0;
+  double *AV = nullptr, *AW0 = nullptr, *AW1 = nullptr, *AW2 = nullptr, *RES = nullptr;
   MState* ms = nullptr;
   int rc = SVAR_OK;
   for (double** p : {&R0, &R1, &R2, &W0, &W1, &W2, &v})
     if (rc == SVAR_OK) rc = dalloc(tmp, p, (size_t)n);
+  if (two)
+    for (double** p : {&AV, &AW0, &AW1, &AW2, &RES})
+      if (rc == SVAR_OK) rc = dalloc(tmp, p, (size_t)n);
   if (rc == SVAR_OK) rc = dalloc(tmp, &ms, (size_t)nsys);
   if (rc != SVAR_OK) {
     free_all(tmp);
@@ -224,8 +284,17 @@ int solve_minres(svar_handle* h, const svar_solve_opts* o, int nrhs, const doubl
   std::vector<double> rhs2;
   if (rc == SVAR_OK) rc = sys_norm2(h, rhs, rhs2, st);
   int iters_done = 0;
+  double* hist = (o->history && o->history_len > 0) ? o->history : nullptr;
+  const int hlen = hist ? o->history_len : 0;
   if (rc == SVAR_OK) {
     launch_fill(x, n, 0.0, st);
+    if (hist)
+      launch_fill(hist, (int64_t)nsys * hlen, std::numeric_limits<double>::quiet_NaN(), st);
+    // the first steps read the older search directions scaled by zero: keep them finite
+    for (double* p : {W0, W1, W2, AW0, AW1, AW2})
+      if (p) launch_fill(p, n, 0.0, st);
+    if (two)
+      (void)hipMemcpyAsync(RES, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
     // r = rhs, y = P^{-1} r, beta_1^2 = r^T y
     double* r_prev = R0;
     double* r = R1;
@@ -234,7 +303,10 @@ int solve_minres(svar_handle* h, const svar_solve_opts* o, int nrhs, const doubl
     rc = run_program(h, *PP, r, y, st, nullptr);
     hipLaunchKernelGGL(k_mr_dot, dim3(K.plan.ntask), dim3(NT), 0, st, K.plan.tasks, r, y, K.npart);
     kr_seg_sum(K.plan, K.npart, K.sysv, st);
-    hipLaunchKernelGGL(k_mr_init, dim3(1), dim3(64), 0, st, ms, K.sysv, o->rtol, nsys, K.gl);
+    // rhs norms for the two-norm test (the host copy rhs2 is uploaded into K.tol_rel)
+    (void)hipMemcpyAsync(K.tol_rel, rhs2.data(), nsys * sizeof(double), hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(k_mr_init, dim3(1), dim3(64), 0, st, ms, K.sysv, K.tol_rel, o->rtol, nsys,
+                       K.gl);
     double* wolder = W0;
     double* wold = W1;
     double* wnew = W2;
@@ -244,7 +316,7 @@ int solve_minres(svar_handle* h, const svar_solve_opts* o, int nrhs, const doubl
       rc = run_program(h, *PA, v, y, st, skip);  // y = A v
       if (rc != SVAR_OK) break;
       hipLaunchKernelGGL(k_mr_y1, dim3(K.plan.ntask), dim3(NT), 0, st, K.plan.tasks, ms, K.gl, y,
-                         r_prev, v, k == 1 ? 1 : 0, K.npart);
+                         r_prev, v, k == 1 ? 1 : 0, K.npart, AV);
       kr_seg_sum(K.plan, K.npart, K.sysv, st);
       hipLaunchKernelGGL(k_mr_y2, dim3(K.plan.ntask), dim3(NT), 0, st, K.plan.tasks, K.plan.sys, ms,
                          K.gl, K.sysv, y, r);
@@ -259,14 +331,24 @@ int solve_minres(svar_handle* h, const svar_solve_opts* o, int nrhs, const doubl
                          K.npart);
       kr_seg_sum(K.plan, K.npart, K.sysv, st);
       hipLaunchKernelGGL(k_mr_scalar, dim3((nsys + 63) / 64), dim3(64), 0, st, ms, K.sysv, nsys,
-                         K.gl);
+                         K.gl, two ? 0 : 1, hist, hlen);
       hipLaunchKernelGGL(k_mr_w, dim3(K.plan.ntask), dim3(NT), 0, st, K.plan.tasks, K.plan.sys, ms,
-                         K.gl, v, wolder, wold, wnew, x, k == 1 ? 1 : 0);
+                         K.gl, v, wolder, wold, wnew, x, k == 1 ? 1 : 0, AV, AW0, AW1, AW2, RES,
+                         K.npart);
+      if (two) {
+        kr_seg_sum(K.plan, K.npart, K.sysv, st);
+        hipLaunchKernelGGL(k_mr_check, dim3((nsys + 63) / 64), dim3(64), 0, st, ms, K.sysv, nsys,
+                           K.gl, hist, hlen);
+      }
       hipLaunchKernelGGL(k_mr_retire, dim3(1), dim3(64), 0, st, ms, nsys, K.gl);
       double* t0 = wolder;
       wolder = wold;
       wold = wnew;
       wnew = t0;
+      double* a0 = AW0;
+      AW0 = AW1;
+      AW1 = AW2;
+      AW2 = a0;
       iters_done = k;
       if (k % 8 == 0 || k == o->maxit) {
         if (hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st) !=
@@ -301,9 +383,14 @@ int solve_minres(svar_handle* h, const svar_solve_opts* o, int nrhs, const doubl
       I.iters = hs[i].iters;
       I.outer = 1;
       I.relres_true = nb > 0 ? std::sqrt(r2[i]) / nb : 0.0;
-      I.relres_est = hs[i].beta1 > 0 ? hs[i].phibar / hs[i].beta1 : 0.0;
+      I.relres_est = two ? (nb > 0 ? hs[i].res2 / nb : 0.0)
+                         : (hs[i].beta1 > 0 ? hs[i].phibar / hs[i].beta1 : 0.0);
       I.status = hs[i].status;
       if (I.status == SVAR_OK && !hs[i].done && hs[i].pad == 0) I.status = SVAR_E_NOCONV;
+      // rtol is a two-norm tolerance whatever the stopping rule: a P^{-1}-norm stop with a
+      // larger true residual, or a carried residual that drifted from the true one, is not OK
+      if (I.status == SVAR_OK && !(I.relres_true <= o->rtol))
+        I.status = std::isfinite(I.relres_true) ? SVAR_E_NOCONV : SVAR_E_BREAKDOWN;
       const int it = hs[i].iters;
       I.n_M = (int64_t)std::llround((PA->cnt[0] + PP->cnt[0]) * sc * it + PA->cnt[0] * sc);
       I.n_MT = (int64_t)std::llround((PA->cnt[1] + PP->cnt[1]) * sc * it + PA->cnt[1] * sc);

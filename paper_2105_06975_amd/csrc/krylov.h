@@ -47,6 +47,13 @@ struct KBlock {
   double R[KB_MAX * KB_MAX];    // product of the rounds' factors
   int32_t blen, pad;            // leading columns that passed both Cholesky rounds
 };
+// residual history of a solve (see svar_solve_opts.history): h[sys * len + it0[sys] + t]
+// receives the residual estimate after step t of the current cycle; h == nullptr: off
+struct HistArg {
+  double* h = nullptr;
+  int len = 0, pad = 0;
+  const int* it0 = nullptr;  // device, per system: iterations done in earlier cycles
+};
 struct KPlan {
   KTask* tasks = nullptr;
   KSys* sys = nullptr;
@@ -66,7 +73,7 @@ void kr_reduce(const KPlan& p, const KState* stt, const KGlobal* gl, const doubl
                double* sums, int m, int jmax, hipStream_t st);
 void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHess* hs, int m,
               int finalize_only, int jmax, int* net_off, double drop, int patience,
-              hipStream_t st);
+              HistArg hist, hipStream_t st);
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
                hipStream_t st);
@@ -93,7 +100,7 @@ void kb_trsm(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double
              int j, int b, const KBlock* kb, hipStream_t st);
 void kb_hess(int B, const KPlan& p, KState* stt, KGlobal* gl, const double* S1, const double* S2,
              int SLB, const KBlock* kb, KHess* hs, int m, int j, int b, int* net_off,
-             double drop, int patience, hipStream_t st);
+             double drop, int patience, HistArg hist, hipStream_t st);
 // workgroups of the Gram-Schmidt passes resident on the current device at once (both passes:
 // the smaller of the two), 0 if the runtime cannot tell
 int kr_resident_tasks();

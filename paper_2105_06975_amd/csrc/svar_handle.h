@@ -122,7 +122,7 @@ struct svar_handle {
     hipGraphExec_t exec = nullptr;
     hipStream_t ps = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    int nrhs = -1, m = -1, gen = -1, patience = 0;
+    int nrhs = -1, m = -1, gen = -1, kgen = -1, patience = 0;
     const void* pa = nullptr;
     const void* pp = nullptr;
     const int* net_off = nullptr;
@@ -130,6 +130,7 @@ struct svar_handle {
     double drop = 0.0;
   } graph;
   // Krylov workspace (grown on demand)
+  int kry_gen = 0;  // bumped whenever the Krylov workspace below is (re)allocated
   struct Kry {
     int nrhs = -1, m = 0;
     int64_t ntot = 0;
@@ -145,6 +146,7 @@ struct svar_handle {
     svar::KGlobal* gl_host = nullptr;  // pinned, two slots (lagged convergence checks)
     hipEvent_t gl_ev[2] = {nullptr, nullptr};
     int* net_off = nullptr;            // per system: learned correction switched off
+    int* it0 = nullptr;                // per system: iterations of earlier cycles (history)
     // block (s-step) mode, allocated on first use: partial and reduced sums of the two
     // projections (stride slb per task / system), Gram partials and sums, per-system blocks
     double *bpart = nullptr, *bs1 = nullptr, *bs2 = nullptr, *gpart = nullptr, *gsum = nullptr;

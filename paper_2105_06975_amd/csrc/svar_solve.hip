@@ -65,6 +65,8 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   auto& K = h->kry;
   if (K.nrhs == nrhs && K.m >= m) return SVAR_OK;
   SVAR_HIP(hipStreamSynchronize(st));
+  // captured step graphs hold the old buffers' addresses: key them on this generation
+  ++h->kry_gen;
   free_all(K.allocs);
   {
     KGlobal* keep = K.gl_host;
@@ -113,6 +115,7 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   SVAR_TRY(dalloc(A, &K.tol_rel, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.st, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.net_off, (size_t)nsys));
+  SVAR_TRY(dalloc(A, &K.it0, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.gl, 1));
   // Hessenberg storage per system
   const size_t per = (size_t)(m + 1) * m + m + m + (m + 1) + m + (m + 1) + m;
@@ -168,7 +171,7 @@ struct Harvest {
 // device's j gives the same results, which lets a captured chunk use jl = m throughout).
 static int fg_step(svar_handle* h, int m, const Program& PA, const Program& PP, int jl,
                    bool scale, int* net_off, double drop, int patience, Harvest& hv,
-                   hipStream_t st) {
+                   HistArg hist, hipStream_t st) {
   auto& K = h->kry;
   const int* skip = &K.gl->all_done;
   if (scale) kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
@@ -183,7 +186,7 @@ static int fg_step(svar_handle* h, int m, const Program& PA, const Program& PP, 
   kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ldv, m, 1, K.part, st);
   timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
   kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, jl, st);
-  kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, jl, net_off, drop, patience, st);
+  kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 0, jl, net_off, drop, patience, hist, st);
   timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
   kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ldv, K.npart, jl, st);
   timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
@@ -202,7 +205,7 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
   bool same_bufs = true;
   for (int i = 0; i < 6; ++i) same_bufs = same_bufs && G.bufs[i] == bufs[i];
   if (G.exec && same_bufs && G.nrhs == nrhs && G.m == m && G.pa == &PA && G.pp == &PP &&
-      G.gen == h->prog_gen && G.net_off == net_off && G.drop == drop &&
+      G.gen == h->prog_gen && G.kgen == h->kry_gen && G.net_off == net_off && G.drop == drop &&
       G.patience == patience) {
     *out = G.exec;
     return SVAR_OK;
@@ -222,7 +225,7 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
   SVAR_HIP(hipStreamBeginCapture(G.ps, hipStreamCaptureModeThreadLocal));
   int rc = SVAR_OK;
   for (int i = 0; i < GRAPH_STEPS && rc == SVAR_OK; ++i)
-    rc = fg_step(h, m, PA, PP, m, true, net_off, drop, patience, none, G.ps);
+    rc = fg_step(h, m, PA, PP, m, true, net_off, drop, patience, none, HistArg(), G.ps);
   hipError_t ce = hipStreamEndCapture(G.ps, &graph);
   if (rc != SVAR_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -244,6 +247,7 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
   G.pa = &PA;
   G.pp = &PP;
   G.gen = h->prog_gen;
+  G.kgen = h->kry_gen;
   G.net_off = net_off;
   G.drop = drop;
   G.patience = patience;
@@ -254,7 +258,7 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
 
 static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
                         const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
-                        double drop, int patience, Harvest& hv, bool use_graph,
+                        double drop, int patience, Harvest& hv, bool use_graph, HistArg hist,
                         hipStream_t st) {
   int* net_off = h->net_off ? h->kry.net_off : nullptr;
   auto& K = h->kry;
@@ -263,7 +267,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
   kr_nrm2_part(K.plan, K.r, K.npart, st);
   kr_start(K.plan, K.npart, K.r, K.u, K.st, K.tol_rel, K.gl, st);
   const int check_every = GRAPH_STEPS;
-  const bool graph = use_graph && !hv.buf && !timing_any(h);
+  const bool graph = use_graph && !hv.buf && !hist.h && !timing_any(h);
   // Convergence checks: the device flag is copied to the host every check_every steps.  Read
   // at once, the copy drains the queue and the device idles while the host enqueues the next
   // steps; so the host reads each copy one checkpoint later, with the next steps already
@@ -285,7 +289,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
       SVAR_HIP(hipStreamWaitEvent(st, h->graph.ev_out, 0));
       done_steps = GRAPH_STEPS;
     } else {
-      SVAR_TRY(fg_step(h, m, PA, PP, j, j > 0, net_off, drop, patience, hv, st));
+      SVAR_TRY(fg_step(h, m, PA, PP, j, j > 0, net_off, drop, patience, hv, hist, st));
     }
     j += done_steps;
     if (j % check_every == 0 || j == m) {
@@ -316,7 +320,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
     kr_scale(K.plan, K.npart, K.u, K.st, K.gl, st);
     kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ldv, m, 0, K.part, st);
     kr_reduce(K.plan, K.st, K.gl, K.part, K.sums, m, m, st);
-    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, net_off, drop, patience, st);
+    kr_small(K.plan, K.st, K.gl, K.sums, K.hs, m, 1, m, net_off, drop, patience, hist, st);
   }
   kr_solve_y(K.plan, K.st, K.hs, m, st);
   kr_xupdate(K.plan, K.st, K.hs, K.Z, K.ldv, x, m, st);
@@ -351,7 +355,7 @@ static int ensure_block(svar_handle* h) {
 // V[0..m], Z[0..m-1]; the host reads the all-done flag after every block.
 static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Program& PP,
                        const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
-                       double drop, int patience, Harvest& hv, hipStream_t st) {
+                       double drop, int patience, Harvest& hv, HistArg hist, hipStream_t st) {
   int* net_off = h->net_off ? h->kry.net_off : nullptr;
   SVAR_TRY(ensure_block(h));
   auto& K = h->kry;
@@ -397,7 +401,7 @@ static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Pr
       kb_trsm(B, K.plan, K.st, K.gl, K.V, K.ldv, j, b, K.kb, st);
     }
     kb_hess(B, K.plan, K.st, K.gl, K.bs1, K.bs2, SLB, K.kb, K.hs, m, j, b, net_off, drop,
-            patience, st);
+            patience, hist, st);
     j += b;
     SVAR_HIP(hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
     SVAR_HIP(hipStreamSynchronize(st));
@@ -462,6 +466,14 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     hv.cap = o->harvest_cap;
     hv.len = state_total(h, nrhs);
   }
+  HistArg hist;
+  if (o->history && o->history_len > 0) {
+    hist.h = o->history;
+    hist.len = o->history_len;
+    hist.it0 = K.it0;
+    launch_fill(o->history, (int64_t)nsys * o->history_len,
+                std::numeric_limits<double>::quiet_NaN(), st);
+  }
   std::vector<double> rhs2;
   SVAR_TRY(sys_norm2(h, rhs, rhs2, st));
   std::vector<int> iters(nsys, 0), status(nsys, SVAR_OK), cycles(nsys, 0), fallbacks(nsys, 0);
@@ -507,11 +519,13 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     const int m = std::min(cyc, o->maxit - used);
     if (m < 1) break;
     std::vector<KState> ks;
+    if (hist.h)
+      SVAR_HIP(hipMemcpyAsync(K.it0, iters.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
     {
       const int rc = blk ? block_cycle(h, m, blk, *Ain, *Pin, tol, x, ks, drop,
-                                       o->fallback_patience, hv, st)
+                                       o->fallback_patience, hv, hist, st)
                          : fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
-                                        o->fallback_patience, hv, o->use_graph != 0, st);
+                                        o->fallback_patience, hv, o->use_graph != 0, hist, st);
       if (rc != SVAR_OK) {
         h->net_off = nullptr;
         return rc;

@@ -61,7 +61,8 @@ class SolveOpts(C.Structure):
                 ("restart", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("max_outer", C.c_int32), ("fallback_drop", C.c_double),
                 ("harvest", C.c_void_p), ("harvest_cap", C.c_int32),
-                ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("block", C.c_int32)]
+                ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("block", C.c_int32),
+                ("minres_norm", C.c_int32), ("history", C.c_void_p), ("history_len", C.c_int32)]
 
 
 class NetDesc(C.Structure):
@@ -299,20 +300,25 @@ class Handle:
     def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
               precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
               check=False, fallback_drop=1e-3, fallback_patience=3, harvest=None,
-              graph=False, block=0):
+              graph=False, block=0, minres_norm="2", history=None):
         """Solve A x = rhs; returns (x, [info dicts], status).
 
         harvest: optional float64 device tensor of shape (cap, state_len): receives the state
         component of the preconditioner input of each FGMRES step.
         block: s-step FGMRES with blocks of this many columns (2..8; 0 = one at a time).
+        minres_norm: MINRES stopping rule, "2" (two-norm residual) or "P" (P^{-1}-norm estimate).
+        history: optional float64 device tensor (nsys, len): residual-norm estimate per iteration.
         """
         import torch
         x = torch.empty_like(rhs) if x is None else x
         hv, cap = (None, 0) if harvest is None else (C.c_void_p(harvest.data_ptr()),
                                                      int(harvest.shape[0]))
+        hp, hl = (None, 0) if history is None else (C.c_void_p(history.data_ptr()),
+                                                    int(history.shape[-1]))
         o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
                       float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap,
-                      int(fallback_patience), 1 if graph else 0, int(block))
+                      int(fallback_patience), 1 if graph else 0, int(block),
+                      {"2": 0, "P": 1}[minres_norm], hp, hl)
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))

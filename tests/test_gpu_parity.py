@@ -233,10 +233,41 @@ def test_minres_pd(sv):
     x, info, rc = h.solve(dev(rhs), method="MINRES", rtol=1e-13, maxit=4 * win.n)
     assert rc == sv.OK
     assert rel(host(x), x_ref) < 1e-9
+    # two-norm stop (default): the carried residual agrees with the oracle's recomputed one
     ref = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-8, maxit=4 * win.n)
-    x8, info8, _ = h.solve(dev(rhs), method="MINRES", rtol=1e-8, maxit=4 * win.n)
+    hist = torch.zeros((1, 4 * win.n), dtype=torch.float64, device="cuda")
+    x8, info8, rc8 = h.solve(dev(rhs), method="MINRES", rtol=1e-8, maxit=4 * win.n,
+                             history=hist)
+    assert rc8 == sv.OK
     assert abs(info8[0]["iters"] - ref["iters"]) <= 2
-    assert info8[0]["relres_est"] <= 1e-8 and ref["hist"][-1] <= 1e-8
+    assert info8[0]["relres_true"] <= 1e-8 and ref["relres_true"] <= 1e-8
+    hh = host(hist)[0]
+    it = info8[0]["iters"]
+    nb = np.linalg.norm(rhs)
+    assert np.all(np.isfinite(hh[:it])) and np.all(np.isnan(hh[it:]))
+    assert hh[it - 1] <= 1e-8 * nb
+    # the carried residual tracks the recomputed one over the first steps (oracle history;
+    # later on the two Lanczos runs drift apart by rounding, as any two MINRES runs do)
+    m = min(it, ref["iters"], 30)
+    assert np.allclose(hh[:m] / nb, np.array(ref["hist"][1:m + 1]), rtol=1e-6, atol=1e-12)
+
+
+def test_minres_pnorm_stop_reports_two_norm(sv):
+    """With the P^{-1}-norm stopping rule MINRES stops where the oracle's does, with a true
+    two-norm residual above rtol: the status says so (rtol is a two-norm tolerance)."""
+    win = tiny(seed=0)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    rhs = win.rhs[0]
+    ref = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-6, maxit=4 * win.n,
+                   minres_norm="P")
+    assert ref["relres_true"] > 1e-6
+    h = sv.Handle([win], sv.Precond(type="PD", k=2, rhat="RR"))
+    x, info, rc = h.solve(dev(rhs), method="MINRES", rtol=1e-6, maxit=4 * win.n,
+                          minres_norm="P")
+    assert rc == sv.E_NOCONV and info[0]["status"] == sv.E_NOCONV
+    assert abs(info[0]["iters"] - ref["iters"]) <= 2
+    assert info[0]["relres_est"] <= 1e-6 < info[0]["relres_true"]
+    assert abs(info[0]["relres_true"] - ref["relres_true"]) <= 0.05 * ref["relres_true"]
 
 
 def test_batched_systems_and_restarts(sv):
@@ -399,3 +430,27 @@ def test_c2_solve_true_residual(sv, c2):
     rr = np.linalg.norm(rhs - orc.apply_A(host(x))) / np.linalg.norm(rhs)
     assert rr <= 1e-6
     assert abs(rr - info[0]["relres_true"]) <= 1e-9
+
+
+def test_fgmres_history_across_restarts(sv):
+    """svar_solve_opts.history: the residual estimate after every FGMRES step, counted across
+    restart cycles.  The first cycle matches the oracle FGMRES's estimates; every cycle's
+    estimates are non-increasing (P4); entries past the last step are NaN."""
+    win = wl.make_config_window("c1", seed=0)
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    rhs = win.rhs[0]
+    ref = so.solve(orc, rhs, prec="PI", rtol=1e-8, maxit=win.n)
+    h = sv.Handle([win], sv.Precond(type="PI", k=3, rhat="RR"))
+    L, m = 400, 30
+    hist = torch.zeros((1, L), dtype=torch.float64, device="cuda")
+    x, info, rc = h.solve(dev(rhs), rtol=1e-8, maxit=L, restart=m, max_outer=100,
+                          history=hist)
+    assert rc == sv.OK
+    it = info[0]["iters"]
+    hh = host(hist)[0] / np.linalg.norm(rhs)
+    assert np.all(np.isfinite(hh[:it])) and np.all(np.isnan(hh[it:]))
+    assert np.allclose(hh[:m], np.array(ref["hist"][1:m + 1]), rtol=1e-6, atol=1e-13)
+    for c0 in range(0, it, m):
+        cyc = hh[c0:min(c0 + m, it)]
+        assert np.all(np.diff(cyc) <= 1e-12 * cyc[0])
+    assert hh[it - 1] <= 1e-8 * (1 + 1e-9)

@@ -112,9 +112,32 @@ def test_minres_pd_matches_dense():
     orc = so.SaddleOracle(win, k=2, rhat="RR")
     rhs = win.rhs[0]
     x_ref = np.linalg.solve(orc.A_dense(), rhs)
-    out = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-14, maxit=4 * orc.n)
+    out = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-14, maxit=4 * orc.n,
+                   minres_norm="P")
     assert np.linalg.norm(out["x"] - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    # MINRES minimises the residual in the P^{-1} norm: that estimate never increases
     assert np.all(np.diff(np.array(out["hist"])) <= 1e-12)
+
+
+def test_minres_two_norm_stop():
+    """§7's two-norm criterion: MINRES returns at the first iterate whose true relative
+    residual is <= rtol (one iteration fewer is still above it).  The P^{-1}-norm estimate
+    stops earlier on the same instance with a true residual above rtol, so the two rules
+    are different readings and the two-norm one is the contract."""
+    win = tiny(seed=0, s=10, N=4, p=5)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    rhs = win.rhs[0]
+    out = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-6, maxit=4 * orc.n)
+    assert out["relres_true"] <= 1e-6
+    assert abs(out["hist"][-1] - out["relres_true"]) <= 1e-12
+    short = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-6, maxit=out["iters"] - 1)
+    assert short["relres_true"] > 1e-6
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    kappa = np.linalg.cond(orc.A_dense())
+    assert np.linalg.norm(out["x"] - x_ref) <= 2 * kappa * 1e-6 * np.linalg.norm(x_ref)
+    pn = so.solve(orc, rhs, prec="PD", method="MINRES", rtol=1e-6, maxit=4 * orc.n,
+                  minres_norm="P")
+    assert pn["iters"] < out["iters"] and pn["relres_true"] > 1e-6
 
 
 # ------------------------------------------------------------------ preconditioners
@@ -243,7 +266,8 @@ def test_remark1_minres_rate():
     ev = np.sort(np.linalg.eigvals(PDi @ orc.A_dense()).real)
     negs, poss = ev[ev < 0], ev[ev > 0]
     mu1, mu2, mu3, mu4 = th.stretch_intervals((negs.min(), negs.max()), (poss.min(), poss.max()))
-    out = so.solve(orc, win.rhs[0], prec="PD", method="MINRES", rtol=1e-14, maxit=60)
+    out = so.solve(orc, win.rhs[0], prec="PD", method="MINRES", rtol=1e-14, maxit=60,
+                   minres_norm="P")
     h = out["hist"]
     for ell in range(1, len(h) // 2):
         assert h[2 * ell] <= th.remark1_minres_bound(mu1, mu2, mu3, mu4, ell, 1.0) * (1 + 1e-6) + 1e-12
