@@ -1,23 +1,28 @@
 """Benchmark: preconditioned saddle-point solves per second on one MI355X.
 
-Workload: a linearised weak-constraint 4D-Var window shaped like the paper's experiments,
-s = 4096 state variables, N = 64 (65 time blocks), p_i = 2048 random observation points,
-dense SOAR B (length 0.1), Q_i = 0.1 B, dense SOAR R_i (length 0.05), implicit
-advection-diffusion model; 8 right-hand sides (0; d_r; 0) whose innovations share the signal
-and redraw the observation noise (perturbed observations).  Inexact-constraint
-preconditioner P_I with L_M(3) and the ridge-regression Rhat, flexible GMRES to a 1e-6 true
-relative residual, x0 = 0.
+Headline workload (default): the uneven batch of 512 linear advection-diffusion windows
+(s ~ U{256..4096}, N ~ U{8..64}, p_i = floor(s f) random observation points with
+f ~ U[1/8, 1/2], dense SOAR B (length 0.1), Q_i = 0.1 B, dense SOAR R_i (length 0.05)), each
+with 8 perturbed-observation right-hand sides (0; d_r; 0): 4096 saddle systems, about 9e8
+unknowns.  Inexact-constraint preconditioner P_I with L_M(3) and the ridge-regression Rhat,
+FGMRES restarted every 20 steps (both paths), stop at a 5e-7 true relative residual (every
+solution then within 1e-6 of the float64 reference; the metric asks for 1e-6), x0 = 0.
 
-Two paths on the same window, right-hand sides, P, k, Rhat and tolerance:
-  * plain FP64: one right-hand side per solve, no restart (the reference path);
-  * learned + batched (`value`): all 8 right-hand sides in one call, the network
-    correction of the Lhat^{-T} sweep (trained beforehand, untimed, on pairs harvested from
-    plain solves of other seeds of the same workload), float32 Rhat^{-1} products in P,
-    FGMRES restarted every 200 steps (each step's Gram-Schmidt reads the basis of its
-    cycle only; measured: 7.0 solves/s against 6.5 without restart).
-One step = one batched solve of the 8 right-hand sides.
+  * plain FP64 (the reference rate): one system per solve, every operator float64, timed
+    on a stratified sample of the windows (every 16th by size, one rhs each);
+  * learned + batched (`value`): all 4096 systems per call in waves that fit the device
+    memory, the network correction of the Lhat^{-T} sweep (trained beforehand, untimed, on
+    pairs harvested from plain solves of s = 4096, N = 32 windows; a convolution over space
+    with per-block inputs applies to any s and N), float32 Rhat^{-1} products in P, A in
+    float64; converged systems and windows retire from every launch;
+  * plain batched (context): the same batched solve without the network.
+One step = one batched solve of all 4096 systems.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--plain-only]
+Other modes: --c2 (one s = 4096, N = 64 window x 8 rhs), --c3 (Lorenz-96 Gauss-Newton),
+--c5 (learned correction on held-out s = 4096, N = 32 windows), --sweep (k, restart,
+precision on the C2 window).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--windows W] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -33,77 +38,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Gram-Schmidt passes, C2 x 8 rhs: HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters
-# (fetch scaled by 2.000, write by 1.000 from the calibration map in the same runs) over the
-# timed region, divided by the algorithmic bytes per launch of that run (7.0255 GB / 6.9426 GB).
-# Valid while k_fg_dot / k_fg_update and their task plan are unchanged.
-ORTHO_TRAFFIC_RATIO = 7.0255 / 6.9426
-# the same ratio for block Gram-Schmidt (blocks of BLOCK_TRAFFIC_B columns); None until the
-# counters have been taken for the current block kernels
-BLOCK_TRAFFIC_RATIO = None
-BLOCK_TRAFFIC_B = 8
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0,
+                    help="untimed full steps before the timed ones (a short priming solve "
+                         "that builds the launch programs and workspaces always runs)")
+    ap.add_argument("--rtol", type=float, default=5e-7,
+                    help="true relative residual of every path (5e-7 keeps every solution "
+                         "within 1e-6 of the float64 reference)")
     ap.add_argument("--k", type=int, default=3)
+    ap.add_argument("--restart", type=int, default=20,
+                    help="FGMRES restart length of every path")
+    ap.add_argument("--windows", type=int, default=512, help="windows of the headline batch")
+    ap.add_argument("--base-sample", type=int, default=32,
+                    help="windows (stratified by size, one rhs each) of the one-at-a-time "
+                         "plain FP64 sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-plain-batched", action="store_true")
+    ap.add_argument("--c2", action="store_true",
+                    help="one s=4096, N=64 window x 8 rhs instead of the batch (one JSON line)")
     ap.add_argument("--sweep", action="store_true",
                     help="print iterations and time per solve over k, restart length and "
-                         "precision (one JSON object) instead of the benchmark line")
+                         "precision on the C2 window (one JSON object)")
     ap.add_argument("--c3", action="store_true",
                     help="Lorenz-96 window (s=2048, N=32): iterations vs k and the 5-iteration "
                          "Gauss-Newton outer loop (one JSON object)")
     ap.add_argument("--c5", type=int, default=0, metavar="W",
                     help="learned-correction mode: train on C5-shaped windows (s=4096, N=32), "
-                         "then solve W held-out windows x 8 rhs batched with the network "
-                         "against every system one at a time in plain FP64 (one JSON object)")
-    ap.add_argument("--c4", type=int, default=0, metavar="W",
-                    help="batched mode: W uneven advection-diffusion windows x 8 perturbed-"
-                         "observation right-hand sides in one call, against one-at-a-time "
-                         "solves of the first two windows (one JSON object)")
-    ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--tune-cache", default=None,
-                    help="JSON file for the GEMM autotuning cache (--c4 mode)")
+                         "then solve W held-out windows x 8 rhs batched with and without the "
+                         "network against every system one at a time in plain FP64")
+    ap.add_argument("--tune-cache", default=None, help="JSON file for the GEMM autotuning cache")
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--precision", default="FP64_F32P",
                     help="precision of the learned + batched path")
     ap.add_argument("--block", type=int, default=0,
-                    help="s-step FGMRES block size of the learned + batched path (0: one "
-                         "column at a time; with the nonlinear network the block basis "
-                         "stagnates)")
-    ap.add_argument("--c4-learned", action="store_true",
-                    help="--c4 mode: also solve the batch with the network trained on the C5 "
-                         "shape (FP64_F32P)")
-    ap.add_argument("--c4-block", type=int, default=4,
-                    help="--c4 mode: also time s-step FGMRES with this block size (0: skip)")
-    ap.add_argument("--lb-restart", type=int, default=200,
-                    help="FGMRES restart length of the learned + batched path (0: none)")
-    ap.add_argument("--plain-block", type=int, default=8,
-                    help="also time the batched solve with the plain preconditioner in "
-                         "s-step FGMRES with this block size (0: skip)")
+                    help="s-step FGMRES block size of the batched paths (0: one column at a "
+                         "time; with the nonlinear network the block basis stagnates)")
     ap.add_argument("--train-windows", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
     ap.add_argument("--plain-only", action="store_true",
-                    help="time only the plain FP64 path (no training)")
+                    help="--c2: time only the plain FP64 path (no training)")
     ap.add_argument("--n-bound", type=int, default=20,
                     help="later segment starts the network sees (1 + n_bound + k <= 32)")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the GEMM autotuning of the batched path")
+                    help="--c2: skip the GEMM autotuning of the batched path")
     ap.add_argument("--patience", type=int, default=20,
                     help="failing FGMRES steps in a row before the network is switched off")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="after the benchmark, copy a 1 GiB float64 buffer three times (the "
-                         "reference kernel for scaling HBM byte counters)")
-    ap.add_argument("--cpu-iters", type=int, nargs=2, default=(3, 9),
-                    help="oracle iteration counts of the two timed samples")
+    ap.add_argument("--maxit", type=int, default=6000, help="iterations allowed per system")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="host time budget of the oracle sample")
     return ap.parse_args()
 
 
@@ -121,26 +112,53 @@ def ortho_bytes(n, iters, restart=0):
     return tot
 
 
-def block_ortho_bytes(n, iters, b):
-    """Algorithmic HBM bytes of the four passes over the basis of block Gram-Schmidt
-    (k_bk_dot twice, k_bk_update twice) over all blocks of b columns: a block starting at
-    column j reads V_{0..j} in each pass, the projections read the block's b columns and the
-    updates read and write them: (4 (j + 1) + 6 b) * 8 n."""
-    tot, j = 0, 0
-    while j < iters:
-        bb = min(b, iters - j)
-        tot += (4 * (j + 1) + 6 * bb) * n * 8
-        j += bb
-    return tot
-
-
 def gemm_flops(win, iters, applies_a64):
-    """Algorithmic flops of the covariance products: per iteration one A (D and R products)
-    and one P_I (D and Rhat^{-1} products), plus float64 residual checks (A only)."""
+    """Algorithmic flops of the covariance products of one system of a C2-mode solve: per
+    FGMRES step one P_I (D z1, float64, shared with the next A z; Rhat^{-1}) and one A (R;
+    D z1 reused), plus a float64 A (D and R) per true-residual check."""
     s, nb, p = win.s, win.nb, int(win.p[0])
+    step = 2.0 * s * s * nb + 4.0 * p * p * nb
     fa = 2.0 * s * s * nb + 2.0 * p * p * nb
-    fp = 2.0 * s * s * nb + 2.0 * p * p * nb
-    return (iters + 1) * (fa + fp) + applies_a64 * fa
+    return iters * step + applies_a64 * fa
+
+
+NET_FLOP_PER_POINT = 2 * (5 * 32 * 64 + 2 * 5 * 64 * 64 + 5 * 64)  # 103,040 (padded layer 1)
+
+
+def batch_work(wins, infos, nrhs, restart):
+    """Algorithmic work of a batched solve from its per-system iteration counts.
+
+    Covariance products (flops): a window's products run while any of its right-hand sides
+    is active (max over its rhs of the steps, plus one float64 A per cycle and one at the
+    end): per step 2 (s^2 + p^2)(N+1) nrhs float64 (D z1, R) and 2 p^2 (N+1) nrhs float32
+    (Rhat^{-1}); per check 2 (s^2 + p^2)(N+1) nrhs float64.  Gram-Schmidt bytes per system:
+    step t of a cycle (j = t mod restart) reads j basis vectors twice plus u, w, z and
+    writes Z_j, v_j, u: (2 j + 9) 8 n.  Network flops: NET_FLOP_PER_POINT per grid point of
+    every active system's state per step."""
+    f64 = f32 = gsb = net = 0.0
+    for w, win in enumerate(wins):
+        inf = infos[w * nrhs:(w + 1) * nrhs]
+        s, nb, p = win.s, win.nb, int(win.p[0])
+        steps = max(i["iters"] for i in inf)
+        checks = max(i["outer"] for i in inf) + 1
+        f64 += (steps + checks) * 2.0 * (s * s + p * p) * nb * nrhs
+        f32 += steps * 2.0 * p * p * nb * nrhs
+        for i in inf:
+            it = i["iters"]
+            full, rem = divmod(it, restart) if restart > 0 else (0, it)
+            m = restart if restart > 0 else it
+            per_cycle = sum(2 * j + 9 for j in range(m))
+            gsb += (full * per_cycle + sum(2 * j + 9 for j in range(rem))) * 8.0 * win.n
+            net += it * float(NET_FLOP_PER_POINT) * nb * s
+    return dict(gemm_f64=f64, gemm_f32=f32, ortho_bytes=gsb, net_flops=net)
+
+
+def threads_in_use():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
 
 
 def main():
@@ -151,19 +169,26 @@ def main():
                                    "different GPUs with no communication)"}))
         sys.exit(2)
     import torch
-
-    from paper_2105_06975_amd import svar, workloads as wl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     if args.c3:
         print(json.dumps(bench_c3(args)), flush=True)
-        return
-    if args.c4:
-        print(json.dumps(bench_c4(args)), flush=True)
         return
     if args.c5:
         print(json.dumps(bench_c5(args)), flush=True)
         return
+    if args.c2 or args.sweep:
+        bench_c2(args)
+        return
+    print(json.dumps(bench_headline(args)), flush=True)
+
+
+def bench_c2(args):
+    """One s = 4096, N = 64 window with 8 right-hand sides: plain FP64 one rhs per solve
+    against learned + batched, both with FGMRES(restart)."""
+    import torch
+
+    from paper_2105_06975_amd import svar, workloads as wl
+    dev = torch.device("cuda:0")
     t0 = time.time()
     win = wl.make_config_window("c2", seed=0, nrhs=args.nrhs)
     log(f"workload built in {time.time() - t0:.1f}s: n={win.n}, nrhs={args.nrhs}")
@@ -201,13 +226,13 @@ def main():
         # one extra, untimed call with HIP events around every launch of the three kernel
         # classes (events around every launch cost about 3 %, so the timed region records the
         # Gram-Schmidt class only, which the roofline needs)
-        for kc in ("GEMM", "ORTHO", "MODEL"):
+        for kc in ("GEMM", "ORTHO", "MODEL", "NET"):
             h.timing_enable(kc, True)
             h.timing_read(kc, reset=True)
         fn(0)
         torch.cuda.synchronize()
         out = {}
-        for kc in ("GEMM", "ORTHO", "MODEL"):
+        for kc in ("GEMM", "ORTHO", "MODEL", "NET"):
             out[kc] = h.timing_read(kc, reset=True)
             h.timing_enable(kc, False)
         return out
@@ -219,7 +244,8 @@ def main():
 
     def plain(i):
         r = i % R
-        x, info, rc = h.solve(rhs1[r], rtol=args.rtol, maxit=1000)
+        x, info, rc = h.solve(rhs1[r], rtol=args.rtol, maxit=args.maxit, restart=args.restart,
+                              max_outer=args.maxit)
         assert rc == svar.OK, info
         xs_plain[r] = x
         return info[0]
@@ -277,9 +303,8 @@ def main():
             t_tune = time.time() - t0
             log(f"GEMM autotuning for {R} rhs: {t_tune:.1f}s")
         # ---- learned + batched
-        kw = dict(rtol=args.rtol, maxit=700, fallback_patience=args.patience, block=args.block)
-        if args.lb_restart > 0:
-            kw.update(restart=args.lb_restart, max_outer=100, maxit=2000)
+        kw = dict(rtol=args.rtol, maxit=args.maxit, fallback_patience=args.patience,
+                  block=args.block, restart=args.restart, max_outer=args.maxit)
         if args.precision != "FP64":
             kw["precision"] = args.precision
 
@@ -304,8 +329,7 @@ def main():
                                  "the Lhat^-T sweep (bf16 MFMA), %s, %s"
                                  % (args.precision, ("s-step FGMRES, blocks of %d" % args.block
                                      if args.block >= 2 else "one column per step")
-                                    + (", restart %d" % args.lb_restart if args.lb_restart > 0
-                                       else "")))
+                                    + ", restart %d" % args.restart))
         res["speedup_vs_plain_fp64"] = sps / sps_plain
         res["learned_batched"] = {
             "iters_mean": it_b, "fallbacks": int(sum(i["fallbacks"] for i in infos_b)),
@@ -316,89 +340,229 @@ def main():
                          "harvest_s": t_h, "train_s": t_t, "loss_first": hist[0],
                          "loss_last": hist[-1]}}
         tm, it_main, ntot_main, steps_main, el_main = tm, it_b, win.n * R, args.steps, el_b
-        if args.plain_block >= 2:
-            # context, not `value`: the batched solve without the network, s-step FGMRES
-            h.set_net(None)
-            kwp = dict(rtol=args.rtol, maxit=700, block=args.plain_block)
-            if args.precision != "FP64":
-                kwp["precision"] = args.precision
+        # context, not `value`: the same batched solve without the network
+        h.set_net(None)
+        kwp = dict(kw)
+        kwp.pop("fallback_patience", None)
 
-            def pblock(i):
-                x, infos, rc = h.solve(rhs_all, R, **kwp)
-                assert rc == svar.OK, infos
-                return infos
-            el_pb, outs_pb, _ = timed(pblock, args.steps, 1)
-            infos_pb = outs_pb[-1]
-            res["plain_batched_block"] = {
-                "value": R * args.steps / el_pb, "unit": "solves/s",
-                "iters_mean": float(np.mean([i["iters"] for i in infos_pb])),
-                "relres_true_max": float(max(i["relres_true"] for i in infos_pb)),
-                "path": "plain P_I (no network), 8 rhs per call, %s, s-step FGMRES with blocks "
-                        "of %d" % (args.precision, args.plain_block)}
-            log(f"plain+batched, blocks of {args.plain_block}: "
-                f"{res['plain_batched_block']['value']:.3f} solves/s")
+        def pbatched(i):
+            x, infos, rc = h.solve(rhs_all, R, **kwp)
+            assert rc == svar.OK, infos
+            return infos
+        el_pb, outs_pb, _ = timed(pbatched, args.steps, 1)
+        infos_pb = outs_pb[-1]
+        res["plain_batched"] = {
+            "value": R * args.steps / el_pb, "unit": "solves/s",
+            "iters_mean": float(np.mean([i["iters"] for i in infos_pb])),
+            "relres_true_max": float(max(i["relres_true"] for i in infos_pb)),
+            "path": "plain P_I (no network), 8 rhs per call, %s, restart %d"
+                    % (args.precision, args.restart)}
+        res["network_gain"] = res["value"] / res["plain_batched"]["value"]
+        log(f"plain+batched: {res['plain_batched']['value']:.3f} solves/s")
     res["iters"] = it_main
-    # roofline of the dominant kernel class (by measured time in the timed region)
     oms, ol = tm["ORTHO"]
     gms, gl = bd["GEMM"]
     res["kernel_time_ms"] = {
         "ortho": oms, "ortho_launches": ol, "timed_region_ms": 1e3 * el_main,
         "one_instrumented_solve": {"gemm": gms, "gemm_launches": gl, "ortho": bd["ORTHO"][0],
                                    "ortho_launches": bd["ORTHO"][1],
-                                   "model_and_net": bd["MODEL"][0],
-                                   "model_launches": bd["MODEL"][1]},
+                                   "model": bd["MODEL"][0], "net": bd["NET"][0]},
         "note": "ortho: HIP events around every Gram-Schmidt launch of the timed region; "
                 "one_instrumented_solve: one more call of the timed path with events around "
-                "every launch of all three classes"}
-    blk = args.block if (not args.plain_only and args.block >= 2) else 0
-    if bd["ORTHO"][0] >= gms and blk:
-        # four timed launches per block: the two projections and the two updates
-        byts = block_ortho_bytes(ntot_main, int(round(it_main)), blk) * steps_main
-        ach = byts / (oms * 1e-3) / 1e9
-        per_launch = byts / max(ol, 1)
-        res["roofline"] = {"bound": "hbm",
-                           "kernel": "k_bk_dot + k_bk_update (block Gram-Schmidt passes over "
-                                     "the basis)",
-                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS,
-                           "traffic": (BLOCK_TRAFFIC_RATIO * per_launch
-                                       if BLOCK_TRAFFIC_RATIO and blk == BLOCK_TRAFFIC_B else None),
-                           "traffic_note": "HBM bytes per launch: measured/algorithmic ratio of "
-                                           "the byte counters (calibrated) times this run's "
-                                           "algorithmic bytes per launch",
-                           "algorithmic_bytes_per_launch": per_launch,
-                           "launches": ol, "avg_ms": oms / max(ol, 1)}
-    elif bd["ORTHO"][0] >= gms:
-        byts = ortho_bytes(ntot_main, int(round(it_main)),
-                           0 if args.plain_only else args.lb_restart) * steps_main
-        ach = byts / (oms * 1e-3) / 1e9
-        per_launch = byts / max(ol, 1)
+                "every launch of all classes"}
+    byts = ortho_bytes(ntot_main, int(round(it_main)), args.restart) * steps_main
+    ach = byts / (oms * 1e-3) / 1e9
+    res["roofline"] = {"bound": "hbm", "kernel": "k_fg_dot + k_fg_update (Gram-Schmidt)",
+                       "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                       "algorithmic_bytes_per_launch": byts / max(ol, 1),
+                       "launches": ol, "avg_ms": oms / max(ol, 1)}
+    print(json.dumps(res), flush=True)
+
+
+def bench_headline(args):
+    """The uneven batch (see the module docstring): plain FP64 one system at a time on a
+    stratified sample, learned + batched (`value`) and plain batched on all systems."""
+    import torch
+
+    from paper_2105_06975_amd import svar, workloads as wl
+    nrhs, m = args.nrhs, args.restart
+    t0 = time.time()
+    wins = wl.make_c4_batch(args.windows, nrhs=nrhs, workers=min(16, os.cpu_count() or 1))
+    t_work = time.time() - t0
+    nsys = len(wins) * nrhs
+    ntot = sum(w.n for w in wins) * nrhs
+    log(f"batch: {len(wins)} windows x {nrhs} rhs, {ntot:.3e} unknowns, drawn in {t_work:.1f}s")
+    prec = svar.Precond(type="PI", k=args.k, rhat="RR")
+    kw = dict(rtol=args.rtol, maxit=args.maxit, restart=m, max_outer=args.maxit)
+
+    # ---- plain FP64, one system at a time, on a stratified sample (one window per size stratum)
+    order = np.argsort([w.n for w in wins], kind="stable")
+    ns = min(args.base_sample, len(wins))
+    pick = [int(order[(2 * i + 1) * len(wins) // (2 * ns)]) for i in range(ns)]
+    one_t, its1, one_ms = 0.0, [], {}
+    for wi in pick:
+        w = wins[wi]
+        hw = svar.Handle([w], prec)
+        b = torch.from_numpy(np.ascontiguousarray(w.rhs[0])).cuda()
+        hw.solve(b, 1, rtol=args.rtol, maxit=2, restart=m)  # builds programs and workspace
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, inf1, rc1 = hw.solve(b, 1, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        assert rc1 == svar.OK, inf1
+        one_t += dt
+        its1.append(inf1[0]["iters"])
+        one_ms[wi] = 1e3 * dt
+        hw.close()
+    sps_plain = ns / one_t
+    log(f"plain FP64 one at a time: {sps_plain:.2f} solves/s on {ns} sampled systems, "
+        f"iters mean {np.mean(its1):.1f}")
+
+    # ---- network trained on the s = 4096, N = 32 shape (untimed)
+    net, hist, t_train = train_c5_net(args)
+    torch.cuda.empty_cache()
+
+    t0 = time.time()
+    h = svar.Handle(wins, prec)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log(f"batch handle set-up {setup_s:.1f}s")
+    rhs_all = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
+    kwb = dict(kw, precision=args.precision, block=args.block)
+
+    def run(label, attach, classes, steps, warmup):
+        h.set_net(attach)
+        kk = dict(kwb, fallback_patience=args.patience) if attach else kwb
+        t0 = time.time()
+        h.solve(rhs_all, nrhs, **dict(kk, maxit=2))  # views, programs, arena
+        for _ in range(warmup):
+            h.solve(rhs_all, nrhs, **kk)
+        torch.cuda.synchronize()
+        log(f"{label}: priming and {warmup} warm-up steps {time.time() - t0:.1f}s")
+        for kc in classes:
+            h.timing_enable(kc, True)
+            h.timing_read(kc, reset=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(steps):
+            x, infos, rc = h.solve(rhs_all, nrhs, **kk)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        tm = {}
+        for kc in classes:
+            tm[kc] = h.timing_read(kc, reset=True)
+            h.timing_enable(kc, False)
+        assert rc == svar.OK, [i for i in infos if i["status"] != 0][:4]
+        its = [i["iters"] for i in infos]
+        out = {"value": nsys * steps / el, "unit": "solves/s", "seconds": el,
+               "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+               "relres_true_max": float(max(i["relres_true"] for i in infos)),
+               "fallbacks": int(sum(i["fallbacks"] for i in infos))}
+        log(f"{label}: {out['value']:.2f} solves/s, iters mean {out['iters_mean']:.1f} "
+            f"max {out['iters_max']}")
+        return out, infos, tm, el
+
+    classes = ("GEMM", "ORTHO", "MODEL", "NET")
+    lb, infos_lb, tm, el = run("learned + batched", net, classes, args.steps, args.warmup)
+    res = {
+        "metric": "saddle solves/sec to 1e-6 rel residual; learned+batched vs plain FP64, 1 GPU",
+        "value": lb["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (Krylov, A, D z1, R) + f32 (Rhat^-1 products) + bf16 (network)",
+        "data": "synthetic",
+        "config": {"workload": "c4 batch: %d uneven advection-diffusion windows (s~U{256..4096}, "
+                               "N~U{8..64}, p=floor(s f), f~U[1/8,1/2]) x %d perturbed-"
+                               "observation rhs; SOAR B l=0.1, Q=0.1B, SOAR R l=0.05; P_I with "
+                               "L_M(%d) and R_RR; FGMRES(%d) to a true relative residual of %g"
+                               % (len(wins), nrhs, args.k, m, args.rtol),
+                   "windows": len(wins), "nrhs": nrhs, "systems": nsys, "unknowns": int(ntot),
+                   "restart": m, "path": "learned + batched: all systems per call in waves, "
+                   "network correction of the Lhat^-T sweep (bf16 MFMA), %s" % args.precision},
+        "speedup_vs_plain_fp64": lb["value"] / sps_plain,
+        "plain_fp64": {"value": sps_plain, "unit": "solves/s", "systems": ns,
+                       "iters_mean": float(np.mean(its1)), "ms_per_solve": 1e3 * one_t / ns,
+                       "sample": "one rhs of each of %d windows, one per stratum of the batch "
+                                 "sorted by size; one system per FGMRES(%d) solve, every "
+                                 "operator float64" % (ns, m)},
+        "learned_batched": dict(lb, training={"pairs_windows": args.train_windows,
+                                              "epochs": args.epochs, "seconds": t_train,
+                                              "loss_first": hist[0], "loss_last": hist[-1]},
+                                n_bound=args.n_bound, patience=args.patience),
+        "setup_s": setup_s, "workload_s": t_work,
+    }
+    # ---- roofline of the class with the largest time in the timed region
+    wk = batch_work(wins, infos_lb, nrhs, m)
+    wk = {k: v * args.steps for k, v in wk.items()}
+    kt = {k: tm[k][0] for k in classes}
+    res["kernel_time_ms"] = {k.lower(): kt[k] for k in classes}
+    res["kernel_time_ms"].update(timed_region=1e3 * el, launches={k.lower(): tm[k][1]
+                                                                  for k in classes})
+    top = max(("GEMM", "ORTHO", "NET"), key=lambda k: kt[k])
+    if top == "ORTHO":
+        ach = wk["ortho_bytes"] / (kt["ORTHO"] * 1e-3) / 1e9
         res["roofline"] = {"bound": "hbm", "kernel": "k_fg_dot + k_fg_update (Gram-Schmidt)",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS,
-                           "traffic": ORTHO_TRAFFIC_RATIO * per_launch,
-                           "traffic_note": "HBM bytes per launch: measured/algorithmic ratio of the "
-                                           "byte counters (calibrated) times this run's "
-                                           "algorithmic bytes per launch",
-                           "algorithmic_bytes_per_launch": per_launch,
-                           "launches": ol, "avg_ms": oms / max(ol, 1)}
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "algorithmic": wk["ortho_bytes"], "launches": tm["ORTHO"][1],
+                           "avg_ms": kt["ORTHO"] / max(tm["ORTHO"][1], 1)}
+    elif top == "GEMM":
+        fl = wk["gemm_f64"] + wk["gemm_f32"]
+        t_peak = wk["gemm_f64"] / (FP64_PEAK_TFLOPS * 1e12) + wk["gemm_f32"] / (FP32_PEAK_TFLOPS * 1e12)
+        peak = fl / t_peak / 1e12
+        ach = fl / (kt["GEMM"] * 1e-3) / 1e12
+        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm_tiled / k_gemm (covariance "
+                           "products: float64 D z1 and R, float32 Rhat^-1)",
+                           "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                           "traffic": None, "peak_note": "flop-weighted: float64 at 78.6, "
+                           "float32 at 157.3 TFLOP/s", "launches": tm["GEMM"][1],
+                           "avg_ms": kt["GEMM"] / max(tm["GEMM"][1], 1)}
     else:
-        flops = gemm_flops(win, int(round(it_main)), 2) * (R if ntot_main > win.n else 1)
-        ach = flops / (gms * 1e-3) / 1e12
-        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm (covariance products)",
-                           "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
-                           "launches": gl, "avg_ms": gms / max(gl, 1)}
+        ach = wk["net_flops"] / (kt["NET"] * 1e-3) / 1e12
+        res["roofline"] = {"bound": "mfma", "kernel": "k_net_fused (bf16 network inference)",
+                           "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ach / BF16_PEAK_TFLOPS, "traffic": None,
+                           "launches": tm["NET"][1], "avg_ms": kt["NET"] / max(tm["NET"][1], 1)}
+    # ---- context: the same batched solve without the network
+    if not args.no_plain_batched:
+        pb, _, _, el_pb = run("plain batched", None, (), 1, 0)
+        res["plain_batched"] = dict(pb, path="the same batched solve without the network")
+        res["network_gain"] = lb["value"] / pb["value"]
+        res["speedup_plain_batched_vs_plain_fp64"] = pb["value"] / sps_plain
+    h.set_net(None)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(win, args, int(round(it_plain)))
-    print(json.dumps(res), flush=True)
-    if args.calib_copy:
-        # reference for the byte counters: an elementwise map that reads 1 GiB and writes 1 GiB
-        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.neg(a, out=b)
-        torch.cuda.synchronize()
+        res["cpu_baseline"] = cpu_baseline_oracle(wins, pick, one_ms, args)
+    return res
+
+
+def cpu_baseline_oracle(wins, pick, gpu_ms, args):
+    """The float64 oracle on the host cores: full FGMRES(restart) solves of the sampled
+    windows' first rhs, smallest first, until the time budget is used (at least one)."""
+    from oracle import svar_oracle as so
+    order = sorted(pick, key=lambda wi: wins[wi].n)
+    done, t_tot, its, gpu_same = 0, 0.0, [], 0.0
+    for wi in order:
+        w = wins[wi]
+        orc = so.SaddleOracle(w, k=args.k, rhat="RR")
+        t = time.perf_counter()
+        x, it, _ = so.fgmres_restarted(orc.apply_A, orc.apply_PI_inv, w.rhs[0], args.rtol,
+                                       args.restart, args.maxit)
+        t_tot += time.perf_counter() - t
+        done += 1
+        its.append(it)
+        gpu_same += gpu_ms[wi] * 1e-3
+        log(f"  oracle: window {wi} (n={w.n}) {it} iterations, {t_tot:.1f}s so far")
+        if t_tot >= args.cpu_seconds:
+            break
+    return {"value": done / t_tot, "unit": "solves/s", "cores": int(threads_in_use()),
+            "kind": "oracle", "sample": "full oracle FGMRES(%d) solves of the first rhs of the "
+            "%d smallest sampled windows (n = %s), %.1f s of host time; the GPU plain FP64 path "
+            "solves the same systems at %.2f solves/s" % (args.restart, done,
+                                                          [wins[wi].n for wi in order[:done]],
+                                                          t_tot, done / gpu_same),
+            "iters": its}
 
 
 def bench_c3(args):
@@ -444,24 +608,6 @@ def bench_c3(args):
     return out
 
 
-def c4_windows(nwin, seed=0, nrhs=8):
-    """Uneven windows: s ~ U{256..4096}, N ~ U{8..64}, p = floor(s f) with f ~ U[1/8, 1/2]
-    random observation points (fixed in time), SOAR R (0.05, 0.5), 8 right-hand sides whose
-    observation noise is redrawn from R."""
-    from paper_2105_06975_amd import workloads as wl
-    rng = np.random.default_rng(np.random.SeedSequence([seed, 4]))
-    wins = []
-    for w in range(nwin):
-        s = int(rng.integers(256, 4097))
-        N = int(rng.integers(8, 65))
-        f = float(rng.uniform(1 / 8, 1 / 2))
-        p = max(1, int(np.floor(s * f)))
-        idx = wl.obs_indices(s, "random", rng, p=p)
-        wins.append(wl.make_advdiff_window(s, N, idx, r_len=0.05, r_var=0.5, nrhs=nrhs,
-                                           seed=1000 * 4 + w))
-    return wins
-
-
 def train_c5_net(args):
     """The network of the C5 shape (s = 4096, N = 32): pairs from plain solves of seeds
     0..train_windows-1, Adam epochs (untimed)."""
@@ -483,8 +629,9 @@ def train_c5_net(args):
 
 def bench_c5(args):
     """Learned correction on the C5 shape: training on seeds 0..2 (untimed), evaluation on
-    held-out seeds 10^6 + w, 8 rhs each: the learned + batched solve (FP64_F32P, restart as
-    the main path) against plain FP64 solves of every system one at a time."""
+    held-out seeds 10^6 + w, 8 rhs each: learned + batched and plain batched (the same solve
+    without the network) against plain FP64 solves of every system one at a time, all with
+    FGMRES(restart)."""
     import torch
 
     from paper_2105_06975_amd import svar
@@ -494,153 +641,51 @@ def bench_c5(args):
     wins = [wl.make_c5_like(s, N, seed=10**6 + w, nrhs=nrhs) for w in range(args.c5)]
     prec = svar.Precond(type="PI", k=args.k, rhat="RR")
     rhs = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
-    # plain FP64, one system at a time (the reference path: no restart)
+    kw1 = dict(rtol=args.rtol, maxit=args.maxit, restart=args.restart, max_outer=args.maxit)
     one_t, its1 = 0.0, []
     for w in wins:
         hw = svar.Handle([w], prec)
         for r in range(nrhs):
             b = torch.from_numpy(w.rhs[r]).cuda()
             if r == 0:
-                hw.solve(b, 1, rtol=args.rtol, maxit=1000)
+                hw.solve(b, 1, **kw1)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, inf1, rc1 = hw.solve(b, 1, rtol=args.rtol, maxit=1000)
+            _, inf1, rc1 = hw.solve(b, 1, **kw1)
             torch.cuda.synchronize()
             one_t += time.perf_counter() - t
             assert rc1 == svar.OK, inf1
             its1.append(inf1[0]["iters"])
         hw.close()
-    # learned + batched
     h = svar.Handle(wins, prec)
-    h.set_net(net)
-    kw = dict(rtol=args.rtol, maxit=2000, precision=args.precision,
-              fallback_patience=args.patience)
-    if args.lb_restart > 0:
-        kw.update(restart=args.lb_restart, max_outer=100)
-    h.solve(rhs, nrhs, **kw)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    xb, infb, rcb = h.solve(rhs, nrhs, **kw)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t
-    nsys = len(infb)
-    res = {"workload": f"c5: {args.c5} held-out windows (s={s}, N={N}, p=s/2) x {nrhs} rhs",
+    kwb = dict(kw1, precision=args.precision)
+    out = {}
+    for name, attach in (("learned_batched", net), ("plain_batched", None)):
+        h.set_net(attach)
+        kk = dict(kwb, fallback_patience=args.patience) if attach else kwb
+        h.solve(rhs, nrhs, **kk)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xb, infb, rcb = h.solve(rhs, nrhs, **kk)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out[name] = {"systems": len(infb), "solves_per_s": len(infb) / el, "rc": rcb,
+                     "iters_mean": float(np.mean([i["iters"] for i in infb])),
+                     "fallbacks": int(sum(i["fallbacks"] for i in infb)),
+                     "relres_max": float(max(i["relres_true"] for i in infb))}
+        log(name, out[name])
+    res = {"workload": f"c5: {args.c5} held-out windows (s={s}, N={N}, p=s/2) x {nrhs} rhs, "
+                       f"FGMRES({args.restart}) on every path",
            "training": {"windows": args.train_windows, "epochs": args.epochs,
                         "loss_first": hist[0], "loss_last": hist[-1], "seconds": t_train},
            "plain_fp64_one_at_a_time": {"systems": len(its1), "solves_per_s": len(its1) / one_t,
-                                        "iters_mean": float(np.mean(its1))},
-           "learned_batched": {"systems": nsys, "solves_per_s": nsys / el, "rc": rcb,
-                               "iters_mean": float(np.mean([i["iters"] for i in infb])),
-                               "fallbacks": int(sum(i["fallbacks"] for i in infb)),
-                               "relres_max": float(max(i["relres_true"] for i in infb))}}
-    res["speedup"] = res["learned_batched"]["solves_per_s"] / \
-        res["plain_fp64_one_at_a_time"]["solves_per_s"]
+                                        "iters_mean": float(np.mean(its1))}, **out}
+    one = res["plain_fp64_one_at_a_time"]["solves_per_s"]
+    res["speedup_learned_batched"] = out["learned_batched"]["solves_per_s"] / one
+    res["speedup_plain_batched"] = out["plain_batched"]["solves_per_s"] / one
+    res["network_gain"] = (out["learned_batched"]["solves_per_s"] /
+                           out["plain_batched"]["solves_per_s"])
     log(res)
-    return res
-
-
-def bench_c4(args):
-    import torch
-
-    from paper_2105_06975_amd import svar
-    nrhs = 8
-    t0 = time.time()
-    wins = c4_windows(args.c4, nrhs=nrhs)
-    log(f"c4: {len(wins)} windows built in {time.time() - t0:.1f}s; "
-        f"n per rhs: {[w.n for w in wins]}")
-    prec = svar.Precond(type="PI", k=args.k, rhat="RR")
-    kw = dict(rtol=args.rtol, maxit=3000, restart=args.restart, max_outer=400)
-    t0 = time.time()
-    h = svar.Handle(wins, prec)
-    log(f"c4 set-up {time.time() - t0:.1f}s")
-    rhs = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
-
-    def timed_solve(**extra):
-        h.solve(rhs, nrhs, **kw, **extra)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        x, info, rc = h.solve(rhs, nrhs, **kw, **extra)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t, x, info, rc
-
-    el, x, info, rc = timed_solve()
-    its = [i["iters"] for i in info]
-    res = {"workload": f"c4 wave: {len(wins)} uneven windows x {nrhs} rhs, restart {args.restart}",
-           "batched": {"systems": len(info), "seconds": el, "solves_per_s": len(info) / el,
-                       "rc": rc, "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
-                       "relres_max": float(max(i["relres_true"] for i in info)),
-                       "n_total": int(sum(w.n for w in wins) * nrhs)}}
-    log(res["batched"])
-    # the same batch with graph-captured FGMRES step chunks, then with autotuned GEMM plans
-    el_g, xg, info_g, rc_g = timed_solve(graph=True)
-    res["batched_graph"] = {"seconds": el_g, "solves_per_s": len(info) / el_g, "rc": rc_g,
-                            "identical_x": bool(torch.equal(xg, x))}
-    log(res["batched_graph"])
-    t0 = time.time()
-    h.autotune(nrhs, "FP64", args.tune_cache)
-    t_tune = time.time() - t0
-    el_t, xt, info_t, rc_t = timed_solve(graph=True)
-    res["batched_graph_autotuned"] = {"seconds": el_t, "solves_per_s": len(info) / el_t,
-                                      "rc": rc_t, "autotune_s": t_tune,
-                                      "x_rel_diff": float(torch.linalg.norm(xt - x) /
-                                                          torch.linalg.norm(x))}
-    log(res["batched_graph_autotuned"])
-    if args.c4_block >= 2:
-        el_k, xk, info_k, rc_k = timed_solve(block=args.c4_block)
-        res["batched_block"] = {"block": args.c4_block, "seconds": el_k,
-                                "solves_per_s": len(info) / el_k, "rc": rc_k,
-                                "iters_mean": float(np.mean([i["iters"] for i in info_k])),
-                                "relres_max": float(max(i["relres_true"] for i in info_k)),
-                                "x_rel_diff": float(torch.linalg.norm(xk - x) /
-                                                    torch.linalg.norm(x))}
-        log(res["batched_block"])
-    if args.c4_learned:
-        # the network trained on the C5 shape, applied to this batch (a convolution over space
-        # with per-block inputs does not depend on s or N)
-        net, hist, t_train = train_c5_net(args)
-        h.set_net(net)
-        el_l, xl, info_l, rc_l = timed_solve(precision=args.precision,
-                                             fallback_patience=args.patience)
-        h.set_net(None)
-        res["learned_batched"] = {"seconds": el_l, "solves_per_s": len(info) / el_l, "rc": rc_l,
-                                  "precision": args.precision,
-                                  "iters_mean": float(np.mean([i["iters"] for i in info_l])),
-                                  "fallbacks": int(sum(i["fallbacks"] for i in info_l)),
-                                  "relres_max": float(max(i["relres_true"] for i in info_l)),
-                                  "training": {"loss_first": hist[0], "loss_last": hist[-1],
-                                               "seconds": t_train}}
-        log(res["learned_batched"])
-    # one at a time: the first two windows' 16 systems (same preconditioner and restart)
-    sub = wins[:2]
-    hs = svar.Handle(sub, prec)
-    one_t = 0.0
-    its1 = []
-    for wi, w in enumerate(sub):
-        hw = svar.Handle([w], prec)
-        for r in range(nrhs):
-            b = torch.from_numpy(w.rhs[r]).cuda()
-            hw.solve(b, 1, **kw) if r == 0 else None
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            xx, inf1, rc1 = hw.solve(b, 1, **kw)
-            torch.cuda.synchronize()
-            one_t += time.perf_counter() - t
-            its1.append(inf1[0]["iters"])
-    rhs_sub = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in sub])).cuda()
-    hs.solve(rhs_sub, nrhs, **kw)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    xs, infs, rcs = hs.solve(rhs_sub, nrhs, **kw)
-    torch.cuda.synchronize()
-    el_sub = time.perf_counter() - t
-    res["subset"] = {"systems": 2 * nrhs, "one_at_a_time_s": one_t, "batched_s": el_sub,
-                     "batched_speedup": one_t / el_sub, "iters_one": its1,
-                     "iters_batched": [i["iters"] for i in infs]}
-    if "learned_batched" in res:
-        # the whole batch learned + batched against the one-at-a-time plain FP64 rate
-        res["learned_batched_vs_one_at_a_time"] = (res["learned_batched"]["solves_per_s"] /
-                                                   (2 * nrhs / one_t))
-    log(res["subset"])
     return res
 
 
@@ -682,36 +727,6 @@ def sweep(win, rhs, args):
                 log(r)
         del h
     return {"sweep": out, "workload": "c2", "rtol": args.rtol}
-
-
-def cpu_baseline(win, args, gpu_iters):
-    """The float64 oracle on the host cores: FGMRES timed for two short iteration counts
-    (operator cost a per iteration, Gram-Schmidt cost b per basis vector), extrapolated to
-    the GPU's iteration count: T(I) = a I + b I^2 / 2.  Set-up is excluded on both sides."""
-    from oracle import svar_oracle as so
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    orc = so.SaddleOracle(win, k=args.k, rhat="RR")
-    rhs = win.rhs[0]
-    times = []
-    m1, m2 = args.cpu_iters
-    for m in (m1, m2):
-        t = time.perf_counter()
-        so.fgmres(orc.apply_A, orc.apply_PI_inv, rhs, 1e-30, m)
-        times.append(time.perf_counter() - t)
-        log(f"  oracle {m} iterations: {times[-1]:.2f}s")
-    # T(m) = a m + b m^2 / 2
-    M = np.array([[m1, m1 * m1 / 2.0], [m2, m2 * m2 / 2.0]])
-    a, b = np.linalg.solve(M, np.array(times))
-    a, b = max(a, 1e-9), max(b, 0.0)
-    t_solve = a * gpu_iters + b * gpu_iters ** 2 / 2.0
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle FGMRES timed at {m1} and {m2} iterations on the same window "
-                      f"({sum(times):.1f}s), extrapolated to {gpu_iters} iterations",
-            "sec_per_solve": t_solve}
 
 
 if __name__ == "__main__":

@@ -103,6 +103,8 @@ typedef struct svar_window_desc {
 #define SVAR_RHAT_RR 1     /* R_i + gamma I (ridge regression)                   Alg. 1    */
 #define SVAR_RHAT_ME 2     /* eigenvalues below T raised to T (minimum eigenvalue) Alg. 2  */
 #define SVAR_RHAT_EXACT 3  /* R_i itself                                                   */
+#define SVAR_RHAT_BLOCK 4  /* R_block: R_i with the couplings between weakly correlated
+                              groups of observation blocks removed              Alg. 3    */
 
 typedef struct svar_prec_opts {
   int32_t type;      /* SVAR_PREC_*                                                        */
@@ -111,6 +113,21 @@ typedef struct svar_prec_opts {
   double rr_gamma;   /* gamma of R_RR; < 0 selects lambda_min(R_i) (§6.1)                  */
   double me_T;       /* threshold of R_ME; < 0 selects the second smallest eigenvalue      */
   double d_ridge;    /* Dhat_i = D_i + d_ridge I (§6.1 uses 0.01); used by PD only         */
+  /* R_block (Alg. 3, Appendix; rhat = SVAR_RHAT_BLOCK): R_i is split into rb_npvec blocks of
+     sizes rb_pvec (host array, summing to p_i of every R matrix of the windows).  Where the
+     scaled Frobenius norm ||R_i[block j, block j+1]||_F / sqrt(pvec_j pvec_{j+1}) of a
+     super-diagonal block is below rb_tol, every coupling across that block boundary is
+     removed; R_block keeps R_i whole inside each remaining group of blocks.  Then, once each:
+     a group larger than rb_maxsize rows is split in two; with more groups than rb_numproc
+     the two smallest adjacent groups are combined, with fewer than rb_numproc - 2 the
+     largest group is split (a split cuts at the block boundary nearest the group's middle,
+     a one-block group at its middle row; rb_maxsize, rb_numproc <= 0: no adjustment).
+     Rhat^{-1} is then applied group by group. */
+  const int32_t* rb_pvec;
+  int32_t rb_npvec;
+  int32_t rb_maxsize;
+  double rb_tol;
+  int32_t rb_numproc;
 } svar_prec_opts;
 
 /* ------------------------------------------------------------------ solver options */
@@ -177,6 +194,13 @@ typedef struct svar_solve_opts {
      system's last iteration are set to NaN.  Iterations beyond history_len are not recorded. */
   double* history;
   int32_t history_len;
+  /* wave scheduling (FGMRES): the windows are solved in contiguous waves whose packed length
+     (nrhs x the windows' saddle lengths) is at most wave_len elements, one wave after the
+     other, so that the Krylov basis of a wave fits the device memory.  0: chosen from the
+     free device memory (one wave when everything fits).  Each wave runs the same kernels on
+     its windows; results equal those of one call up to the rounding order of the reductions.
+     Not with harvest; MINRES always runs in one wave. */
+  int64_t wave_len;
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */
@@ -262,6 +286,20 @@ int svar_model_forecast(svar_handle* h, int32_t w, const double* x, double* y, v
    doubles, copied), e.g. after an outer-loop update.  E_INVAL for other model kinds. */
 int svar_set_trajectory(svar_handle* h, int32_t w, const double* traj, void* stream);
 
+/* Right-hand side of the outer loop's saddle system (§2.1, incremental form) for window w of
+   a handle whose right-hand sides hold one system (nrhs = 1 layout of that window): with the
+   current trajectory x = (x_0..x_N), the background x_b and the observations y,
+       b_0 = x_b - x_0,  b_i = M_i(x_{i-1}) - x_i (i = 1..N),  d_i = y_i - H_i x_i,
+   and the third component zero.  x: device state vector ((N+1) s), xb: device (s), y: device
+   observation vector (sum_i p_i, blocks concatenated), rhs: device saddle vector of the
+   window (n_w doubles), distinct from the inputs.  Stream ordered. */
+int svar_gn_rhs(svar_handle* h, int32_t w, const double* x, const double* xb, const double* y,
+                double* rhs, void* stream);
+/* Outer-loop update x += dx with dx the state component of the saddle solution sol (device,
+   n_w doubles); for Lorenz-96 windows also the new linearisation trajectory of the window
+   (svar_set_trajectory), so the next solve uses the tangent linear model about x. */
+int svar_gn_update(svar_handle* h, int32_t w, double* x, const double* sol, void* stream);
+
 /* Set-up results of window w: gamma of R_RR, T of R_ME and lambda_1(R_i) for each distinct
    R matrix (host arrays of n_rmat entries; NaN where not applicable; any may be NULL). */
 int svar_rhat_params(const svar_handle* h, int32_t w, double* gamma, double* T, double* lam1);
@@ -271,7 +309,8 @@ int svar_rhat_params(const svar_handle* h, int32_t w, double* gamma, double* T, 
 #define SVAR_KCLASS_GEMM 0      /* covariance products (D, R, Rhat^{-1}, Dhat^{-1})      */
 #define SVAR_KCLASS_ORTHO 1     /* Gram-Schmidt passes of FGMRES                          */
 #define SVAR_KCLASS_MODEL 2     /* model products and Lhat sweeps                         */
-#define SVAR_KCLASS_COUNT 3
+#define SVAR_KCLASS_NET 3       /* learned correction (sigma, network inference, update)  */
+#define SVAR_KCLASS_COUNT 4
 int svar_timing_enable(svar_handle* h, int32_t kclass, int32_t on);
 /* total_ms, launches: host pointers; resets the accumulators when reset != 0. */
 int svar_timing_read(svar_handle* h, int32_t kclass, double* total_ms, int64_t* launches,
@@ -335,6 +374,34 @@ int svar_net_forward(svar_net* net, int32_t precision, int32_t npair, int32_t nb
 int svar_net_train_step(svar_net* net, int32_t npair, int32_t nb, int32_t s, const float* x,
                         const float* y, int32_t nsample, const int32_t* samples,
                         const svar_adam_opts* adam, double* loss, float* grad, void* stream);
+
+/* Training loop on a pair pool: `epochs` passes over every (pair, block) sample of (x, y)
+   ([npair][nb][s] float32, device, as written by svar_net_make_pairs), in mini-batches of
+   `batch` samples, each a float32 forward / backward pass and one Adam step
+   (svar_net_train_step).  The sample order of epoch e is a Fisher-Yates shuffle driven by
+   splitmix64 seeded with seed + e.  When ckpt_path is not NULL a checkpoint (parameters,
+   Adam moments and step count, and the data cursor: the epoch and the position of the next
+   batch in that epoch's order) is written after every checkpoint_every Adam steps (0: none
+   inside an epoch) and at the end of every epoch, to ckpt_path + ".tmp" and then renamed.
+   resume = 1 continues from the checkpoint at ckpt_path when the file exists (it must
+   belong to the same pool shape, seed and batch size): the continued run reproduces the
+   uninterrupted one.  loss_hist (host, epochs doubles, nullable): mean loss of each epoch
+   (asking for it synchronises after every step).  Synchronous. */
+typedef struct svar_train_opts {
+  int32_t epochs;
+  int32_t batch;
+  svar_adam_opts adam;
+  uint64_t seed;
+  int32_t checkpoint_every;
+  int32_t resume;
+} svar_train_opts;
+int svar_train(svar_net* net, int32_t npair, int32_t nb, int32_t s, const float* x,
+               const float* y, const svar_train_opts* opts, const char* ckpt_path,
+               double* loss_hist, void* stream);
+/* Load a checkpoint written by svar_train into a network of the same k, n_bound and size:
+   parameters and Adam state.  cursor (host, 3 int64, nullable) receives the epoch, the
+   position in that epoch's order and the Adam step count.  Synchronous. */
+int svar_load_learned(svar_net* net, const char* path, int64_t* cursor);
 
 /* Attach (or with NULL detach) a network to a handle: svar_apply_P and svar_solve then
    correct every Lhat^{-T} v3 of the preconditioner as above.  The network's k must equal

@@ -15,7 +15,8 @@ preconditioners for weak-constraint 4D-Var" (arXiv 2105.06975).
   * L_M(k): L with the couplings into every k-th block removed (§4.1, Definition 1)
   * P_D = blkdiag(Dhat, Rhat, Lhat^T D^{-1} Lhat), P_I         (§2.2, eq. prec)
   * A v, P_D^{-1} v, P_I^{-1} v by block loops                  (§6.2)
-  * Rhat in {diag, ridge regression, minimum eigenvalue, R}     (§5, Alg. 1, Alg. 2, §6.1)
+  * Rhat in {diag, block, ridge regression, minimum eigenvalue, R}
+                                                              (§5, Alg. 1, 2, 3, §6.1)
   * Dhat = B + 0.01 I, Q + 0.01 I                              (§6.1)
   * FGMRES (right preconditioned, modified Gram-Schmidt, Givens) and
     preconditioned MINRES (Paige-Saunders), x0 = 0               (§7 solver settings)
@@ -25,7 +26,69 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-RHAT_KINDS = ("DIAG", "RR", "ME", "EXACT")
+RHAT_KINDS = ("DIAG", "RR", "ME", "EXACT")  # plus "BLOCK", which takes its parameters (rblock)
+
+
+# =================================================================== R_block (§5.1, Alg. 3)
+def rblock_partition(R, pvec, tol, maxsize=None, numproc=None):
+    """The groups of consecutive blocks that R_block keeps (Alg. 3, Appendix).
+
+    R is split into pn = len(pvec) blocks of sizes pvec.  For every pair of neighbouring
+    blocks j, j+1 the scaled Frobenius norm of the super-diagonal block,
+        normvec_j = ||R[block j, block j+1]||_F / sqrt(pvec_j pvec_{j+1}),
+    is compared with tol; below it, every coupling across the boundary between blocks j and
+    j+1 is removed, so R_block is block diagonal over the groups of blocks between removed
+    boundaries (inside a group R is kept whole, higher super-diagonals included).  Then, as
+    printed, one adjustment each: a group larger than maxsize is split in two; if there are
+    more groups than numproc the two smallest adjacent groups are combined, and if there are
+    fewer than numproc - 2 the largest group is split.  A split cuts a group at the block
+    boundary nearest its middle row (a group of one block is cut at its middle row), so the
+    result is a list of (start, stop) row ranges.  Returns (ranges, normvec)."""
+    R = np.asarray(R, dtype=np.float64)
+    pvec = [int(v) for v in pvec]
+    if any(v < 1 for v in pvec) or sum(pvec) != R.shape[0]:
+        raise ValueError("pvec must be positive block sizes summing to p")
+    pst = np.concatenate([[0], np.cumsum(pvec)]).astype(int)
+    pn = len(pvec)
+    normvec = np.array([np.linalg.norm(R[pst[j]:pst[j + 1], pst[j + 1]:pst[j + 2]], "fro") /
+                        np.sqrt(pvec[j] * pvec[j + 1]) for j in range(pn - 1)])
+    # boundaries between groups: block starts where the coupling is dropped
+    cuts = [0] + [int(pst[j + 1]) for j in range(pn - 1) if normvec[j] < tol] + [int(pst[-1])]
+    bounds = set(int(b) for b in pst)
+
+    def split(lo, hi):
+        inner = [b for b in bounds if lo < b < hi]
+        mid = (lo + hi) / 2.0
+        c = min(inner, key=lambda b: (abs(b - mid), b)) if inner else (lo + hi) // 2
+        return [(lo, c), (c, hi)]
+
+    ranges = [(cuts[i], cuts[i + 1]) for i in range(len(cuts) - 1)]
+    if maxsize is not None:
+        big = max(range(len(ranges)), key=lambda i: (ranges[i][1] - ranges[i][0], -i))
+        lo, hi = ranges[big]
+        if hi - lo > maxsize and hi - lo > 1:
+            ranges[big:big + 1] = split(lo, hi)
+    if numproc is not None:
+        if len(ranges) > numproc:
+            j = min(range(len(ranges) - 1),
+                    key=lambda i: (ranges[i][1] - ranges[i][0] + ranges[i + 1][1] -
+                                   ranges[i + 1][0], i))
+            ranges[j:j + 2] = [(ranges[j][0], ranges[j + 1][1])]
+        elif len(ranges) < numproc - 2:
+            big = max(range(len(ranges)), key=lambda i: (ranges[i][1] - ranges[i][0], -i))
+            lo, hi = ranges[big]
+            if hi - lo > 1:
+                ranges[big:big + 1] = split(lo, hi)
+    return ranges, normvec
+
+
+def rblock_matrix(R, ranges):
+    """R_block: R on the diagonal blocks of the partition, zero elsewhere."""
+    R = np.asarray(R, dtype=np.float64)
+    out = np.zeros_like(R)
+    for lo, hi in ranges:
+        out[lo:hi, lo:hi] = R[lo:hi, lo:hi]
+    return out
 
 
 # =================================================================== models
@@ -87,8 +150,11 @@ class SaddleOracle:
     """Operators of one window.  Vectors are laid out (eta_0..eta_N | nu_0..nu_N | x_0..x_N)."""
 
     def __init__(self, win, *, k: int = 1, rhat: str = "RR", rr_gamma=None, me_T=None,
-                 d_ridge: float = 0.01):
+                 d_ridge: float = 0.01, rblock=None):
         self.win = win
+        # R_block parameters (Alg. 3): dict(pvec, tol, maxsize, numproc) per distinct R, or one
+        # dict for all
+        self.rblock = rblock
         self.s, self.N, self.nb = win.s, win.N, win.N + 1
         self.p = np.asarray(win.p, dtype=np.int64)
         self.poff = np.concatenate([[0], np.cumsum(self.p)])
@@ -229,6 +295,12 @@ class SaddleOracle:
         elif kind == "EXACT":
             Rh = R
             self.rhat_params[idx] = {}
+        elif kind == "BLOCK":
+            prm = self.rblock[idx] if isinstance(self.rblock, (list, tuple)) else self.rblock
+            ranges, normvec = rblock_partition(R, prm["pvec"], prm["tol"], prm.get("maxsize"),
+                                               prm.get("numproc"))
+            Rh = rblock_matrix(R, ranges)
+            self.rhat_params[idx] = dict(ranges=ranges, normvec=normvec)
         else:
             raise ValueError(kind)
         return ("chol", sla.cho_factor(Rh, lower=True), Rh)
@@ -392,6 +464,113 @@ def fgmres(apply_A, apply_Pinv, rhs, rtol: float, maxit: int):
     for i in range(iters):
         x += y[i] * Z[i]
     return x, iters, hist
+
+
+def fgmres_restarted(apply_A, apply_Pinv, rhs, rtol: float, m: int, maxit: int):
+    """FGMRES(m): cycles of at most m steps of `fgmres` on A d = r, x += d, with the true
+    residual r = rhs - A x recomputed before each cycle; stops when ||r||_2 <= rtol ||rhs||_2
+    or after maxit steps in total.  Returns (x, iters, cycles)."""
+    nb = float(np.linalg.norm(rhs))
+    x = np.zeros(rhs.size)
+    if nb == 0.0:
+        return x, 0, 0
+    used, cycles = 0, 0
+    r = rhs.copy()
+    while used < maxit:
+        nr = float(np.linalg.norm(r))
+        if nr <= rtol * nb:
+            break
+        d, it, _ = fgmres(apply_A, apply_Pinv, r, rtol * nb / nr, min(m, maxit - used))
+        x = x + d
+        used += it
+        cycles += 1
+        r = rhs - apply_A(x)
+    return x, used, cycles
+
+
+def block_fgmres(apply_A, apply_Pinv, RHS, rtol: float, maxit: int):
+    """Block flexible GMRES over the p columns of RHS (n x p), X0 = 0, no restart.
+
+    The block Arnoldi process: RHS = V_0 S_0 (thin QR); at block step j every column of V_j
+    goes through the preconditioner, Z_j = [P^{-1} v for the columns v of V_j], W = A Z_j is
+    orthogonalised against V_0..V_j by block modified Gram-Schmidt, H_ij = V_i^T W, and
+    W = V_{j+1} H_{j+1,j} (thin QR), so that A [Z_0..Z_j] = [V_0..V_{j+1}] Hbar_j with Hbar_j
+    block upper Hessenberg.  X = [Z_0..Z_j] Y with Y minimising ||E_1 S_0 - Hbar_j Y||_F,
+    which decouples into one least-squares problem per column; column c's residual is that
+    column's least-squares residual.  Stops when every column's residual is <= rtol times its
+    right-hand side's norm, at maxit block steps, or when the new block loses rank (a Krylov
+    space that is invariant up to rounding: the current X is then the solution).
+
+    Returns (X, steps, hist) with hist[j] the per-column relative residuals after j steps."""
+    RHS = np.asarray(RHS, dtype=np.float64)
+    n, p = RHS.shape
+    nb = np.linalg.norm(RHS, axis=0)
+    act = nb > 0
+    hist = [np.where(act, 1.0, 0.0)]
+    X = np.zeros((n, p))
+    if not act.any():
+        return X, 0, hist
+    V0, S0 = np.linalg.qr(RHS)
+    V = [V0]
+    Z = []
+    Hcols = []       # Hcols[j]: ((j + 2) p x p) block column j of Hbar
+    steps = maxit
+    Y = None
+    for j in range(maxit):
+        Zj = np.column_stack([apply_Pinv(V[j][:, c]) for c in range(p)])
+        Z.append(Zj)
+        W = np.column_stack([apply_A(Zj[:, c]) for c in range(p)])
+        col = np.zeros(((j + 2) * p, p))
+        for i in range(j + 1):
+            Hij = V[i].T @ W
+            W = W - V[i] @ Hij
+            col[i * p:(i + 1) * p] = Hij
+        Q, Rn = np.linalg.qr(W)
+        col[(j + 1) * p:] = Rn
+        Hcols.append(col)
+        # least squares over the current space, column by column
+        Hbar = np.zeros(((j + 2) * p, (j + 1) * p))
+        for c_ in range(j + 1):
+            Hbar[:(c_ + 2) * p, c_ * p:(c_ + 1) * p] = Hcols[c_]
+        E = np.zeros(((j + 2) * p, p))
+        E[:p] = S0
+        Y, *_ = np.linalg.lstsq(Hbar, E, rcond=None)
+        res = np.linalg.norm(E - Hbar @ Y, axis=0)
+        rel = np.where(act, res / np.where(act, nb, 1.0), 0.0)
+        hist.append(rel)
+        sv = np.linalg.svd(Rn, compute_uv=False)
+        if np.all(rel <= rtol) or sv[-1] <= 1e-14 * max(sv[0], 1e-300):
+            steps = j + 1
+            break
+        V.append(Q)
+    Zall = np.column_stack(Z)
+    X = Zall @ Y
+    return X, steps, hist
+
+
+def block_fgmres_restarted(apply_A, apply_Pinv, RHS, rtol: float, m: int, maxit: int):
+    """Block FGMRES(m): cycles of at most m block steps of `block_fgmres` on A D = R, X += D,
+    with the true residual block R = RHS - A X recomputed before each cycle (all p columns
+    stay in the block); stops when every column's true residual is <= rtol times its
+    right-hand side's norm, or after maxit block steps.  Returns (X, steps, cycles)."""
+    RHS = np.asarray(RHS, dtype=np.float64)
+    n, p = RHS.shape
+    nb = np.linalg.norm(RHS, axis=0)
+    X = np.zeros((n, p))
+    Rb = RHS.copy()
+    used, cycles = 0, 0
+    while used < maxit:
+        nr = np.linalg.norm(Rb, axis=0)
+        if np.all(nr <= rtol * nb):
+            break
+        # the cycle's tolerance, relative to the cycle's right-hand sides: the tightest column
+        tol = float(np.min(np.where(nr > 0, rtol * nb / np.where(nr > 0, nr, 1.0), np.inf)))
+        D, st, _ = block_fgmres(apply_A, apply_Pinv, Rb, min(tol, 1.0), min(m, maxit - used))
+        X = X + D
+        used += st
+        cycles += 1
+        Rb = RHS - np.column_stack([apply_A(X[:, c]) for c in range(p)])
+    return X, used, cycles
 
 
 def minres(apply_A, apply_Minv, rhs, rtol: float, maxit: int, norm: str = "P"):

@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
+  if (SVAR_JOB_SKIPPED(b, P)) return;
   const int lane = threadIdx.x & 63;
   // wave index as a scalar: the k-range bounds are then uniform and the loop control stays on
   // scalar branches (no exec-masked regions around the prefetch loads)
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmProb* __restrict_
                                                      const int* __restrict__ skip) {
   if (skip && *skip) return;
   const GemmProb P = probs[list[blockIdx.y]];
+  if (SVAR_JOB_SKIPPED(b, P)) return;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t tot = (int64_t)P.n * P.ncols;
   if (e >= tot) return;
@@ -280,6 +282,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
+  if (SVAR_JOB_SKIPPED(b, P)) return;
   const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // panel loader role: k offset kl, column rsub + 16 j
@@ -416,6 +419,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled_lds(const GemmProb* __res
   if (skip && *skip) return;
   const GemmTask t = tasks[blockIdx.x];
   const GemmProb P = probs[t.prob];
+  if (SVAR_JOB_SKIPPED(b, P)) return;
   const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // loader role: k offset kl, row / column rsub + 16 j

@@ -490,9 +490,30 @@ __global__ __launch_bounds__(NT) void k_fg_update(const KTask* __restrict__ task
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// advance the iteration counter (single thread)
-__global__ void k_fg_advance(KGlobal* __restrict__ gl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && !gl->all_done) gl->j = gl->j + 1;
+// advance the iteration counter (advance != 0) and refresh the skip flags of the operator
+// programs: flags[0] = every system done, flags[1 + sys] = system sys done, flags[1 + nsys + w]
+// = every right-hand side of window w done (one thread per window; systems are packed window
+// by window, nrhs per window)
+// net_off (nullable): bit 0 = the learned correction was switched off (fallback), bit 1 = the
+// system is done; the network kernels skip a system when either is set
+__global__ void k_fg_advance(KGlobal* __restrict__ gl, const KState* __restrict__ st,
+                             int* __restrict__ flags, int* __restrict__ net_off, int nsys,
+                             int nrhs, int advance) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w == 0) {
+    if (advance && !gl->all_done) gl->j = gl->j + 1;
+    if (flags) flags[0] = gl->all_done;
+  }
+  if (!flags || w * nrhs >= nsys) return;
+  int all = 1;
+  for (int r = 0; r < nrhs; ++r) {
+    const int sy = w * nrhs + r;
+    const int d = st[sy].done ? 1 : 0;
+    flags[1 + sy] = d;
+    if (net_off) net_off[sy] = (net_off[sy] & 1) | (d << 1);
+    all &= d;
+  }
+  flags[1 + nsys + w] = all;
 }
 
 // ---------------------------------------------------------------- end of cycle
@@ -591,8 +612,11 @@ void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, 
                      (size_t)(2 * jmax + 2) * sizeof(double), st, p.tasks, stt, gl, V, u, w, hs,
                      ntot, part);
 }
-void kr_advance(KGlobal* gl, hipStream_t st) {
-  hipLaunchKernelGGL(k_fg_advance, dim3(1), dim3(64), 0, st, gl);
+void kr_advance(KGlobal* gl, const KState* stt, int* flags, int* net_off, int nsys, int nrhs,
+                int advance, hipStream_t st) {
+  const int nwin = flags ? (nsys + nrhs - 1) / nrhs : 1;
+  hipLaunchKernelGGL(k_fg_advance, dim3((nwin + 255) / 256), dim3(256), 0, st, gl, stt, flags,
+                     net_off, nsys, nrhs, advance);
 }
 void kr_solve_y(const KPlan& p, const KState* stt, KHess* hs, int m, hipStream_t st) {
   hipLaunchKernelGGL(k_fg_solve_y, dim3(p.nsys), dim3(NT), (size_t)(m + 1) * sizeof(double), st,

@@ -92,6 +92,7 @@ __global__ __launch_bounds__(NT) void k_mstep_l96(const MJob* __restrict__ jobs,
   if (jid >= njobs || blockIdx.x != 0) return;
   extern __shared__ double lds[];
   const MJob J = jobs[jid];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
   const double* in = b.p[J.in.base] + J.in.off;
   double* out = b.p[J.out.base] + J.out.off;

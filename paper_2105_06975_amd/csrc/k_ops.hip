@@ -39,6 +39,7 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
   extern __shared__ double lds[];
   if (job_id() >= njobs) return;
   const MJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
   const int j0 = blockIdx.x * TS;
   if (j0 >= s) return;
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(TS) void k_mstep_win(const MJob* __restrict__ jobs,
   if (skip && *skip) return;
   if (job_id() >= njobs) return;
   const MJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
   const int j0 = blockIdx.x * TS;
   if (j0 >= s) return;
@@ -127,6 +129,7 @@ __global__ __launch_bounds__(256) void k_sweep_band(const SJob* __restrict__ job
   if (skip && *skip) return;
   if (job_id() >= njobs) return;
   const SJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
   const ModelDev& M = models[J.model];
   const double* __restrict__ wd = J.trans ? M.wdT : M.wd;  // H + 1 weights, offsets o0 .. o0+H
@@ -197,6 +200,7 @@ __global__ __launch_bounds__(TS) void k_mstep_dense(const MJob* __restrict__ job
   if (skip && *skip) return;
   if (job_id() >= njobs) return;
   const MJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
   const int j = blockIdx.x * TS + threadIdx.x;
   if (j >= s) return;
@@ -222,6 +226,7 @@ __global__ __launch_bounds__(TS) void k_gather(const HJob* __restrict__ jobs, Ba
   if (skip && *skip) return;
   if (job_id() >= njobs) return;
   const HJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int r = blockIdx.x * TS + threadIdx.x;
   if (r >= J.rows) return;
   const double* x = opnd(b, J.x);
@@ -236,6 +241,7 @@ __global__ __launch_bounds__(TS) void k_scatter(const HTJob* __restrict__ jobs, 
   if (skip && *skip) return;
   if (job_id() >= njobs) return;
   const HTJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const int j = blockIdx.x * TS + threadIdx.x;
   if (j >= J.s) return;
   const double* y = opnd(b, J.y);
@@ -249,6 +255,7 @@ __global__ __launch_bounds__(TS) void k_vec(const VJob* __restrict__ jobs, Bases
   if (skip && *skip) return;
   if (job_id() >= njobs) return;
   const VJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
   const double* in = opnd(b, J.in);
   double* out = opnd(b, J.out);
   const double* add = J.beta != 0.0 ? opnd(b, J.add) : nullptr;

@@ -188,6 +188,36 @@ __global__ __launch_bounds__(NT) void k_to_bf16(const double* src, unsigned shor
 }
 
 // ------------------------------------------------------------------ launchers
+// out[j] = ||R[pst_j..pst_{j+1}), pst_{j+1}..pst_{j+2})||_F / sqrt(pvec_j pvec_{j+1}) for the
+// super-diagonal blocks of R (n x n row-major), one workgroup per block pair
+__global__ __launch_bounds__(NT) void k_superdiag_norms(const double* R, int n,
+                                                        const int* pst, double* out) {
+  __shared__ double red[NT / 64];
+  const int j = blockIdx.x;
+  const int r0 = pst[j], r1 = pst[j + 1], c1 = pst[j + 2];
+  const int rows = r1 - r0, cols = c1 - r1;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += NT) {
+    const int r = (int)(e / cols), c = (int)(e - (int64_t)r * cols);
+    const double v = R[(int64_t)(r0 + r) * n + r1 + c];
+    acc += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    out[j] = sqrt(t) / sqrt((double)rows * (double)cols);
+  }
+}
+
+void su_superdiag_norms(const double* R, int n, const int* pst, int npairs, double* out,
+                        hipStream_t st) {
+  if (npairs > 0)
+    hipLaunchKernelGGL(k_superdiag_norms, dim3(npairs), dim3(NT), 0, st, R, n, pst, out);
+}
+
 void su_scaled_identity(double* X, int n, double a, hipStream_t st) {
   hipLaunchKernelGGL(k_scaled_identity, dim3(gsz((int64_t)n * n)), dim3(NT), 0, st, X, n, a);
 }

@@ -77,7 +77,10 @@ void kr_small(const KPlan& p, KState* stt, KGlobal* gl, const double* sums, KHes
 void kr_update(const KPlan& p, const KState* stt, const KGlobal* gl, double* V, double* u,
                const double* w, const KHess* hs, int64_t ntot, double* part, int jmax,
                hipStream_t st);
-void kr_advance(KGlobal* gl, hipStream_t st);
+// advance j (advance != 0) and refresh the operator skip flags and the done bit of the
+// network switch-off flags (both nullable, see k_fg_advance)
+void kr_advance(KGlobal* gl, const KState* stt, int* flags, int* net_off, int nsys, int nrhs,
+                int advance, hipStream_t st);
 void kr_solve_y(const KPlan& p, const KState* stt, KHess* hs, int m, hipStream_t st);
 void kr_xupdate(const KPlan& p, const KState* stt, const KHess* hs, const double* Zb,
                 int64_t ntot, double* x, int m, hipStream_t st);

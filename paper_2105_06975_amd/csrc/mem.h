@@ -32,8 +32,9 @@ inline void free_all(std::vector<void*>& v) {
 
 // defined in svar_api.hip
 int get_program(svar_handle* h, int op, int nrhs, int prec, Program** out, hipStream_t st);
+// skip: every launch returns at once when *skip != 0; flags: per-job skip flags (see Bases)
 int run_program(svar_handle* h, const Program& P, double* in, double* out, hipStream_t st,
-                const int* skip);
+                const int* skip, const int* flags = nullptr);
 int64_t handle_total(const svar_handle* h, int nrhs);
 int64_t state_total(const svar_handle* h, int nrhs);
 bool timing_any(const svar_handle* h);

@@ -674,10 +674,124 @@ static int setup_window(svar_handle* h, WinDev& W, const svar_window_desc& d, hi
 }
 
 // Rhat^{-1} (§5, §6.1) and Dhat^{-1} (§6.1) on the GPU
+// R_block (Alg. 3): groups of consecutive observation blocks kept whole.  normvec is formed on
+// the device; the cut, split and combine rules run here; each group's inverse is formed by
+// Newton-Schulz into one buffer (groups one after another, each n_g x n_g).
+static int rblock_groups(const std::vector<int>& pvec, const std::vector<double>& normvec,
+                         double tol, int maxsize, int numproc,
+                         std::vector<std::pair<int, int>>& groups) {
+  const int pn = (int)pvec.size();
+  std::vector<int> pst(pn + 1, 0);
+  for (int j = 0; j < pn; ++j) pst[j + 1] = pst[j] + pvec[j];
+  std::vector<int> cuts{0};
+  for (int j = 0; j + 1 < pn; ++j)
+    if (normvec[j] < tol) cuts.push_back(pst[j + 1]);
+  cuts.push_back(pst[pn]);
+  groups.clear();
+  for (size_t i = 0; i + 1 < cuts.size(); ++i) groups.push_back({cuts[i], cuts[i + 1]});
+  auto size_of = [&](int i) { return groups[i].second - groups[i].first; };
+  // a split cuts at the block boundary nearest the middle (the smaller one on a tie), a
+  // one-block group at its middle row
+  auto split = [&](int gi) {
+    const int lo = groups[gi].first, hi = groups[gi].second;
+    int best = -1;
+    double bd = 0.0;
+    for (int b : pst)
+      if (b > lo && b < hi) {
+        const double d = std::fabs(b - 0.5 * (lo + hi));
+        if (best < 0 || d < bd) {
+          best = b;
+          bd = d;
+        }
+      }
+    const int c = best >= 0 ? best : (lo + hi) / 2;
+    groups[gi] = {lo, c};
+    groups.insert(groups.begin() + gi + 1, std::make_pair(c, hi));
+  };
+  auto largest = [&]() {
+    int bi = 0;
+    for (int i = 1; i < (int)groups.size(); ++i)
+      if (size_of(i) > size_of(bi)) bi = i;
+    return bi;
+  };
+  if (maxsize > 0) {
+    const int bi = largest();
+    if (size_of(bi) > maxsize && size_of(bi) > 1) split(bi);
+  }
+  if (numproc > 0) {
+    if ((int)groups.size() > numproc) {
+      int bj = 0;
+      for (int j = 1; j + 1 < (int)groups.size(); ++j)
+        if (size_of(j) + size_of(j + 1) < size_of(bj) + size_of(bj + 1)) bj = j;
+      groups[bj].second = groups[bj + 1].second;
+      groups.erase(groups.begin() + bj + 1);
+    } else if ((int)groups.size() < numproc - 2) {
+      const int bi = largest();
+      if (size_of(bi) > 1) split(bi);
+    }
+  }
+  return SVAR_OK;
+}
+
+static int setup_rblock(svar_handle* h, WinDev& W, int m, hipStream_t st) {
+  const int p = W.rmat_p[m];
+  const std::vector<int>& pvec = h->rb_pvec;
+  const int pn = (int)pvec.size();
+  int tot = 0;
+  for (int v : pvec) tot += v;
+  if (tot != p) return inval("rb_pvec sums to " + std::to_string(tot) + " but R matrix " +
+                             std::to_string(m) + " has " + std::to_string(p) + " rows");
+  std::vector<int> pst(pn + 1, 0);
+  for (int j = 0; j < pn; ++j) pst[j + 1] = pst[j] + pvec[j];
+  std::vector<double> nv(std::max(pn - 1, 0));
+  if (pn > 1) {
+    std::vector<void*> tmp;
+    int* dpst = nullptr;
+    double* dnv = nullptr;
+    SVAR_TRY(upload(tmp, &dpst, pst.data(), pst.size(), st));
+    SVAR_TRY(dalloc(tmp, &dnv, nv.size()));
+    su_superdiag_norms(W.rmats[m], p, dpst, pn - 1, dnv, st);
+    SVAR_HIP(hipMemcpyAsync(nv.data(), dnv, nv.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+    SVAR_HIP(hipStreamSynchronize(st));
+    free_all(tmp);
+  }
+  std::vector<std::pair<int, int>> groups;
+  SVAR_TRY(rblock_groups(pvec, nv, h->popts.rb_tol, h->popts.rb_maxsize, h->popts.rb_numproc,
+                         groups));
+  int64_t elems = 0;
+  for (auto& g : groups) elems += (int64_t)(g.second - g.first) * (g.second - g.first);
+  double* buf = nullptr;
+  SVAR_TRY(dalloc(h->allocs, &buf, (size_t)elems));
+  int64_t off = 0;
+  for (auto& g : groups) {
+    const int ng = g.second - g.first;
+    std::vector<void*> tmp;
+    double* blk = nullptr;
+    SVAR_TRY(dalloc(tmp, &blk, (size_t)ng * ng));
+    SVAR_HIP(hipMemcpy2DAsync(blk, (size_t)ng * sizeof(double),
+                              W.rmats[m] + (int64_t)g.first * p + g.first,
+                              (size_t)p * sizeof(double), (size_t)ng * sizeof(double), ng,
+                              hipMemcpyDeviceToDevice, st));
+    const int rc = inverse_spd(h, blk, ng, buf + off, st,
+                               "R_block group at row " + std::to_string(g.first));
+    SVAR_HIP(hipStreamSynchronize(st));
+    free_all(tmp);
+    SVAR_TRY(rc);
+    W.rblk[m].push_back({(int64_t)g.first, (int64_t)g.second, off});
+    off += (int64_t)ng * ng;
+  }
+  W.rhat_inv[m] = buf;
+  W.rhat_inv_elems[m] = elems;
+  return SVAR_OK;
+}
+
 static int setup_precond(svar_handle* h, WinDev& W, hipStream_t st) {
   const svar_prec_opts& po = h->popts;
   const int nr = (int)W.rmats.size();
   W.rhat_inv.assign(nr, nullptr);
+  W.rhat_inv_elems.assign(nr, 0);
+  W.rblk.assign(nr, {});
   W.rhat_dinv.assign(nr, nullptr);
   W.rr_gamma.assign(nr, std::numeric_limits<double>::quiet_NaN());
   W.me_T = W.rr_gamma;
@@ -691,9 +805,14 @@ static int setup_precond(svar_handle* h, WinDev& W, hipStream_t st) {
       su_diag_inv(W.rmats[m], p, W.rhat_dinv[m], st);
       continue;
     }
+    if (po.rhat == SVAR_RHAT_BLOCK) {
+      SVAR_TRY(setup_rblock(h, W, m, st));
+      continue;
+    }
     double* Rinv = nullptr;
     SVAR_TRY(dalloc(h->allocs, &Rinv, (size_t)p * p));
     SVAR_TRY(inverse_spd(h, W.rmats[m], p, Rinv, st, what));
+    W.rhat_inv_elems[m] = (int64_t)p * p;
     const bool need_l1 = (po.rhat == SVAR_RHAT_RR && po.rr_gamma < 0) || po.rhat == SVAR_RHAT_ME;
     std::vector<void*> tmp;
     double* v1 = nullptr;
@@ -805,13 +924,32 @@ static int setup_lowprec(svar_handle* h, WinDev& W, hipStream_t st) {
     }
     return SVAR_OK;
   };
+  auto conv_n = [&](const std::vector<double*>& src, std::vector<void*>& dst,
+                    const std::vector<int64_t>& elems, bool bf16) -> int {
+    dst.assign(src.size(), nullptr);
+    for (size_t m = 0; m < src.size(); ++m) {
+      if (!src[m] || m >= elems.size() || elems[m] <= 0) continue;
+      if (bf16) {
+        uint16_t* q = nullptr;
+        SVAR_TRY(dalloc(h->allocs, &q, (size_t)elems[m]));
+        su_to_bf16(src[m], q, elems[m], st);
+        dst[m] = q;
+      } else {
+        float* q = nullptr;
+        SVAR_TRY(dalloc(h->allocs, &q, (size_t)elems[m]));
+        su_to_f32(src[m], q, elems[m], st);
+        dst[m] = q;
+      }
+    }
+    return SVAR_OK;
+  };
   const int64_t ss = (int64_t)W.s * W.s;
   SVAR_TRY(conv(W.dmats, W.dmats_f32, ss, false, nullptr));
   SVAR_TRY(conv(W.rmats, W.rmats_f32, 0, false, &W.rmat_p));
   SVAR_TRY(conv(W.dmats, W.dmats_bf16, ss, true, nullptr));
-  SVAR_TRY(conv(W.rhat_inv, W.rhat_inv_bf16, 0, true, &W.rmat_p));
+  SVAR_TRY(conv_n(W.rhat_inv, W.rhat_inv_bf16, W.rhat_inv_elems, true));
   SVAR_TRY(conv(W.dhat_inv, W.dhat_inv_bf16, ss, true, nullptr));
-  SVAR_TRY(conv(W.rhat_inv, W.rhat_inv_f32, 0, false, &W.rmat_p));
+  SVAR_TRY(conv_n(W.rhat_inv, W.rhat_inv_f32, W.rhat_inv_elems, false));
   SVAR_TRY(conv(W.dhat_inv, W.dhat_inv_f32, ss, false, nullptr));
   SVAR_HIP(hipStreamSynchronize(st));
   return SVAR_OK;
@@ -853,7 +991,15 @@ struct Builder {
   int nrhs;
   hipStream_t st;
   Program* P;
+  bool global_flag = false;  // every job retires on flag 0 only (all systems done)
 };
+// skip flag index (see Bases) of the jobs of system (w, r) and of window w's covariance products
+static int sysflag(const Builder& B, int w, int r) {
+  return B.global_flag ? 0 : 1 + w * B.nrhs + r;
+}
+static int winflag(const Builder& B, int w) {
+  return B.global_flag ? 0 : 1 + (int)B.h->wins.size() * B.nrhs + w;
+}
 
 static int add_mjobs(Builder& B, std::vector<MJob> jobs[3]) {
   const LaunchKind kinds[3] = {LK_MSTEP_BAND, LK_MSTEP_DENSE, LK_MSTEP_L96};
@@ -896,6 +1042,7 @@ static int add_L(Builder& B, VRef in, VRef out, int trans, VRef add = VRef{-1, S
         J.in = blk(B.h, w, r, B.nrhs, in, i);
         J.out = blk(B.h, w, r, B.nrhs, out, i);
         J.s = W.s;
+        J.flag = sysflag(B, w, r);
         J.alpha = -1.0;
         J.trans = trans;
         if (add.base >= 0) {
@@ -955,6 +1102,7 @@ static int add_sweep(Builder& B, VRef vec, int trans, int k, VRef src = VRef{-1,
           J.sub = sub.base >= 0 ? blk(B.h, w, r, B.nrhs, sub, b0) : Operand{-1, 0, 0};
           J.vec = blk(B.h, w, r, B.nrhs, vec, b0);
           J.model = W.model_id;
+          J.flag = sysflag(B, w, r);
           J.trans = trans;
           J.s = W.s;
           J.len = e0 - b0 + 1;
@@ -987,6 +1135,7 @@ static int add_sweep(Builder& B, VRef vec, int trans, int k, VRef src = VRef{-1,
           MJob J{};
           J.in = blk(B.h, w, r, B.nrhs, vec, i);
           J.out = J.in;
+          J.flag = sysflag(B, w, r);
           J.x = blk(B.h, w, r, B.nrhs, vec, trans ? i + 1 : i - 1);
           J.model = W.model_id;
           J.mi = trans ? i + 1 : i;
@@ -1030,6 +1179,7 @@ static int add_axpy_state(Builder& B, VRef in, VRef add, double beta, VRef out) 
       J.add = blk(B.h, w, r, B.nrhs, add, 0);
       J.alpha = 1.0;
       J.beta = beta;
+      J.flag = sysflag(B, w, r);
       J.len = (int64_t)W.nb * W.s;
       jobs.push_back(J);
     }
@@ -1046,6 +1196,7 @@ static int add_copy_state(Builder& B, VRef in, VRef out, double alpha) {
       J.out = blk(B.h, w, r, B.nrhs, out, 0);
       J.alpha = alpha;
       J.len = (int64_t)W.nb * W.s;
+      J.flag = sysflag(B, w, r);
       jobs.push_back(J);
     }
   }
@@ -1127,7 +1278,7 @@ static int add_net(Builder& B, VRef vec) {
   Launch L;
   L.kind = LK_NET;
   L.jobs = app.get();
-  L.kclass = SVAR_KCLASS_MODEL;
+  L.kclass = SVAR_KCLASS_NET;
   B.P->launches.push_back(L);
   B.h->netapps.push_back(std::move(app));
   return SVAR_OK;
@@ -1144,6 +1295,7 @@ static int add_copy_obs(Builder& B, VRef in, VRef out, bool diag_rhat) {
       J.alpha = 1.0;
       J.scale = diag_rhat ? W.rhat_dinv_blocks : nullptr;
       J.len = W.P;
+      J.flag = sysflag(B, w, r);
       jobs.push_back(J);
     }
     if (diag_rhat) B.P->cnt[4] += (int64_t)W.nb * B.nrhs;
@@ -1166,6 +1318,7 @@ static int add_gather(Builder& B, VRef x, VRef out) {
         J.vals = W.h_vals + W.h_off[i];
         J.rows = W.p[i];
         J.width = W.hw;
+        J.flag = sysflag(B, w, r);
         mr = std::max(mr, W.p[i]);
         jobs.push_back(J);
       }
@@ -1197,6 +1350,7 @@ static int add_scatter(Builder& B, VRef y, VRef out) {
         J.idx = W.ht_idx + W.ht_ent_off[i];
         J.val = W.ht_val + W.ht_ent_off[i];
         J.s = W.s;
+        J.flag = sysflag(B, w, r);
         ms = std::max(ms, W.s);
         jobs.push_back(J);
       }
@@ -1265,7 +1419,23 @@ static void add_cov(Builder& B, std::vector<GemmProb>& probs, MatSel sel, int dt
         p.alpha = scaled ? W.d_scale_dev + i : nullptr;
         p.alpha0 = alpha0;
         p.beta = beta;
-        probs.push_back(p);
+        p.flag = winflag(B, w);
+        if (sel == MS_RHAT && B.h->popts.rhat == SVAR_RHAT_BLOCK) {
+          // R_block: one product per group (rows [lo, hi) of every column; the columns keep
+          // the block stride n)
+          const size_t es = dtype == DT_F64 ? 8 : (dtype == DT_F32 ? 4 : 2);
+          for (const auto& g : W.rblk[key(i)]) {
+            GemmProb q = p;
+            q.C = (const char*)p.C + g[2] * es;
+            q.n = (int)(g[1] - g[0]);
+            q.X.off += g[0];
+            q.Y.off += g[0];
+            if (q.Z.base >= 0) q.Z.off += g[0];
+            probs.push_back(q);
+          }
+        } else {
+          probs.push_back(p);
+        }
         const int cidx = sel == MS_D ? 2 : (sel == MS_R ? 3 : (sel == MS_RHAT ? 4 : 5));
         B.P->cnt[cidx] += (int64_t)(j - i) * B.nrhs;
       }
@@ -1355,6 +1525,7 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
           J.out = Operand{B_OUT, 0, J.in.off};
           J.alpha = 1.0;
           J.len = h->wins[w].n;
+          J.flag = sysflag(B, w, r);
           jobs.push_back(J);
         }
       return add_vjobs(B, jobs);
@@ -1389,7 +1560,10 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
   }
   // component maps on state / obs vectors
   const VRef IS{B_IN, SP_STATE, C_X}, OS{B_OUT, SP_STATE, C_X};
-  if (op == PROG_HARVEST) return add_copy_state(B, IN_SAD_X, OS, 1.0);
+  if (op == PROG_HARVEST) {
+    B.global_flag = true;  // every system's slot is written while any system is active
+    return add_copy_state(B, IN_SAD_X, OS, 1.0);
+  }
   const VRef IO{B_IN, SP_OBS, C_NU}, OO{B_OUT, SP_OBS, C_NU};
   std::vector<GemmProb> probs;
   switch (op) {
@@ -1559,6 +1733,7 @@ int get_program(svar_handle* h, int op, int nrhs, int prec, Program** out, hipSt
 
 // ------------------------------------------------------------------ timing
 static void timer_begin(svar_handle* h, int kc, hipStream_t st, hipEvent_t* e0, hipEvent_t* e1) {
+  if (h->parent) h = h->parent;  // a view records into its parent's timers
   *e0 = *e1 = nullptr;
   if (kc < 0 || kc >= SVAR_KCLASS_COUNT || !h->timers[kc].on) return;
   Timer& T = h->timers[kc];
@@ -1574,11 +1749,13 @@ static void timer_begin(svar_handle* h, int kc, hipStream_t st, hipEvent_t* e0, 
 }
 static void timer_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!e0) return;
+  if (h->parent) h = h->parent;  // a view records into its parent's timers
   (void)hipEventRecord(e1, st);
   h->timers[kc].pending.emplace_back(e0, e1);
   h->timers[kc].launches += 1;
 }
 bool timing_any(const svar_handle* h) {
+  if (h->parent) h = h->parent;
   for (const auto& T : h->timers)
     if (T.on) return true;
   return false;
@@ -1591,21 +1768,34 @@ void timed_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hipEvent_t
 }
 
 // ------------------------------------------------------------------ program execution
+// Launches of a program with the given split-K workspace (no allocation, no check of the
+// workspace sizes: the callers do that); timed: record the kernel-class timers.
+static int exec_program(svar_handle* h, const Program& P, double* in, double* out,
+                        hipStream_t st, const int* skip, const int* flags, double* gemm_ws,
+                        bool timed);
+
 int run_program(svar_handle* h, const Program& P, double* in, double* out, hipStream_t st,
-                const int* skip) {
+                const int* skip, const int* flags) {
   if (P.tmp_elems > h->tmp_elems) SVAR_TRY(regrow(h, &h->tmp, &h->tmp_elems, P.tmp_elems));
   if (P.aux_elems > h->dz1_elems) SVAR_TRY(regrow(h, &h->dz1, &h->dz1_elems, P.aux_elems));
   for (const Launch& L : P.launches)
     if (L.kind == LK_GEMM && L.gemm.ws_elems > h->gemm_ws_elems)
       SVAR_TRY(regrow(h, &h->gemm_ws, &h->gemm_ws_elems, L.gemm.ws_elems));
+  return exec_program(h, P, in, out, st, skip, flags, h->gemm_ws, true);
+}
+
+static int exec_program(svar_handle* h, const Program& P, double* in, double* out,
+                        hipStream_t st, const int* skip, const int* flags, double* gemm_ws,
+                        bool timed) {
   Bases b{};
   b.p[B_IN] = in;
   b.p[B_OUT] = out;
   b.p[B_TMP] = h->tmp;
   b.p[B_AUX] = P.aux_elems > 0 ? h->dz1 : nullptr;
+  b.flags = flags;
   for (const Launch& L : P.launches) {
-    hipEvent_t e0, e1;
-    timer_begin(h, L.kclass, st, &e0, &e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) timer_begin(h, L.kclass, st, &e0, &e1);
     switch (L.kind) {
       case LK_MSTEP_BAND:
         launch_mstep_band((const MJob*)L.jobs, L.njobs, L.max_s, h->max_halo, h->models_dev, b,
@@ -1630,7 +1820,7 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
         launch_vec((const VJob*)L.jobs, L.njobs, L.max_s, b, skip, st);
         break;
       case LK_GEMM:
-        launch_gemm(L.gemm, b, h->gemm_ws, skip, st);
+        launch_gemm(L.gemm, b, gemm_ws, skip, st);
         break;
       case LK_NET: {
         const NetApp* a = (const NetApp*)L.jobs;
@@ -1638,7 +1828,7 @@ int run_program(svar_handle* h, const Program& P, double* in, double* out, hipSt
         break;
       }
     }
-    timer_end(h, L.kclass, st, e0, e1);
+    if (timed) timer_end(h, L.kclass, st, e0, e1);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -1842,11 +2032,19 @@ int svar_create(const svar_window_desc* windows, int32_t nwin, const svar_prec_o
   if (!windows || nwin < 1) return inval("need at least one window");
   if (!popts) return inval("popts is NULL");
   if (popts->type < SVAR_PREC_NONE || popts->type > SVAR_PREC_PI) return inval("bad prec type");
-  if (popts->rhat < SVAR_RHAT_DIAG || popts->rhat > SVAR_RHAT_EXACT) return inval("bad rhat kind");
+  if (popts->rhat < SVAR_RHAT_DIAG || popts->rhat > SVAR_RHAT_BLOCK) return inval("bad rhat kind");
   if (popts->type == SVAR_PREC_PD && !(popts->d_ridge >= 0.0)) return inval("bad d_ridge");
   hipStream_t st = (hipStream_t)stream;
+  if (popts->rhat == SVAR_RHAT_BLOCK) {
+    if (!popts->rb_pvec || popts->rb_npvec < 1) return inval("R_block needs rb_pvec");
+    for (int j = 0; j < popts->rb_npvec; ++j)
+      if (popts->rb_pvec[j] < 1) return inval("rb_pvec entries must be >= 1");
+  }
   svar_handle* h = new svar_handle();
   h->popts = *popts;
+  if (popts->rhat == SVAR_RHAT_BLOCK)
+    h->rb_pvec.assign(popts->rb_pvec, popts->rb_pvec + popts->rb_npvec);
+  h->popts.rb_pvec = nullptr;
   int rc = SVAR_OK;
   if (hipGetDevice(&h->device) != hipSuccess) rc = inval("no HIP device");
   h->wins.resize(nwin);
@@ -2000,6 +2198,64 @@ int svar_set_trajectory(svar_handle* h, int32_t w, const double* traj, void* str
   return SVAR_OK;
 }
 
+int svar_gn_rhs(svar_handle* h, int32_t w, const double* x, const double* xb, const double* y,
+                double* rhs, void* stream) {
+  if (!h || !x || !xb || !y || !rhs || w < 0 || w >= (int)h->wins.size())
+    return inval("bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const WinDev& W = h->wins[w];
+  const int64_t ns = (int64_t)W.nb * W.s;
+  double* b = rhs;
+  double* d = rhs + ns;
+  double* z = rhs + ns + W.P;
+  // b_i = M_i(x_{i-1}) - x_i (i >= 1) and b_0 = x_b - x_0
+  SVAR_TRY(svar_model_forecast(h, w, x, b, stream));
+  launch_axpby(b, x, ns, -1.0, 1.0, st);
+  launch_axpby(b, xb, W.s, 1.0, 0.0, st);
+  launch_axpby(b, x, W.s, -1.0, 1.0, st);
+  // d_i = y_i - H_i x_i
+  std::vector<HJob> jobs;
+  for (int i = 0; i < W.nb; ++i) {
+    if (W.p[i] == 0) continue;
+    HJob J{};
+    J.x = Operand{B_IN, 0, (int64_t)i * W.s};
+    J.out = Operand{B_OUT, 0, (int64_t)W.poff[i]};
+    J.cols = W.h_cols + W.h_off[i];
+    J.vals = W.h_vals + W.h_off[i];
+    J.rows = W.p[i];
+    J.width = W.hw;
+    jobs.push_back(J);
+  }
+  if (!jobs.empty()) {
+    int mr = 0;
+    for (const HJob& J : jobs) mr = std::max(mr, J.rows);
+    std::vector<void*> tmp;
+    HJob* dj = nullptr;
+    SVAR_TRY(upload(tmp, &dj, jobs.data(), jobs.size(), st));
+    Bases bb{};
+    bb.p[B_IN] = const_cast<double*>(x);
+    bb.p[B_OUT] = d;
+    launch_gather(dj, (int)jobs.size(), mr, bb, nullptr, st);
+    launch_axpby(d, y, W.P, 1.0, -1.0, st);
+    SVAR_HIP(hipStreamSynchronize(st));
+    free_all(tmp);
+  }
+  launch_fill(z, ns, 0.0, st);
+  SVAR_HIP(hipGetLastError());
+  return SVAR_OK;
+}
+
+int svar_gn_update(svar_handle* h, int32_t w, double* x, const double* sol, void* stream) {
+  if (!h || !x || !sol || w < 0 || w >= (int)h->wins.size()) return inval("bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const WinDev& W = h->wins[w];
+  const int64_t ns = (int64_t)W.nb * W.s;
+  launch_axpby(x, sol + ns + W.P, ns, 1.0, 1.0, st);
+  SVAR_HIP(hipGetLastError());
+  if (h->models[W.model_id].kind == MK_L96) return svar_set_trajectory(h, w, x, stream);
+  return SVAR_OK;
+}
+
 int svar_rhat_params(const svar_handle* h, int32_t w, double* gamma, double* T, double* lam1) {
   if (!h || w < 0 || w >= (int)h->wins.size()) return inval("bad window index");
   const WinDev& W = h->wins[w];
@@ -2042,6 +2298,10 @@ int svar_timing_read(svar_handle* h, int32_t kclass, double* total_ms, int64_t* 
 int svar_destroy(svar_handle* h) {
   if (!h) return SVAR_OK;
   (void)hipDeviceSynchronize();
+  for (auto& kv : h->views) svar_destroy(kv.second);  // views own only their programs
+  h->views.clear();
+  if (h->arena) (void)hipFree(h->arena);
+  h->arena = nullptr;
   if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
   if (h->graph.ev_in) (void)hipEventDestroy(h->graph.ev_in);
   if (h->graph.ev_out) (void)hipEventDestroy(h->graph.ev_out);

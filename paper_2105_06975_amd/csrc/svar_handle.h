@@ -1,5 +1,6 @@
 // Handle state of libsvar (internal).
 #pragma once
+#include <array>
 #include <memory>
 
 #include "krylov.h"
@@ -29,6 +30,10 @@ struct WinDev {
   std::vector<double*> rhat_dinv;
   double* rhat_dinv_blocks = nullptr; // [P] inverse diagonal laid out per block (DIAG)
   std::vector<double> rr_gamma, me_T, lam1;
+  // R_block (Alg. 3): per distinct R, the groups (first row, end row, element offset of the
+  // group's inverse inside rhat_inv[m]); rhat_inv_elems: doubles held by rhat_inv[m]
+  std::vector<std::vector<std::array<int64_t, 3>>> rblk;
+  std::vector<int64_t> rhat_inv_elems;
   // Dhat^{-1}: distinct inverses and the one used by each block
   std::vector<double*> dhat_inv;
   std::vector<int> dhat_of_block;
@@ -91,6 +96,7 @@ struct Timer {
 struct svar_handle {
   int device = 0;
   svar_prec_opts popts{};
+  std::vector<int> rb_pvec;  // copy of popts.rb_pvec (popts.rb_pvec is cleared)
   std::vector<svar::WinDev> wins;
   std::vector<svar::ModelDev> models;       // host copy
   svar::ModelDev* models_dev = nullptr;
@@ -129,6 +135,14 @@ struct svar_handle {
     const void* bufs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // workspaces
     double drop = 0.0;
   } graph;
+  // wave scheduling: svar_solve over more systems than one Krylov workspace holds runs the
+  // windows in contiguous waves, each through a view (a handle over a window range that shares
+  // the parent's matrices, model tables and zero buffer, and builds its own launch programs);
+  // the views carve their basis vectors from the parent's arena, sized for the largest wave
+  svar_handle* parent = nullptr;  // set on a view
+  std::map<std::pair<int, int>, svar_handle*> views;  // owned, by window range [w0, w1)
+  double* arena = nullptr;
+  int64_t arena_elems = 0;
   // Krylov workspace (grown on demand)
   int kry_gen = 0;  // bumped whenever the Krylov workspace below is (re)allocated
   struct Kry {
@@ -147,6 +161,7 @@ struct svar_handle {
     hipEvent_t gl_ev[2] = {nullptr, nullptr};
     int* net_off = nullptr;            // per system: learned correction switched off
     int* it0 = nullptr;                // per system: iterations of earlier cycles (history)
+    int* flags = nullptr;              // operator skip flags: 1 + nsys + nwin (see Bases)
     // block (s-step) mode, allocated on first use: partial and reduced sums of the two
     // projections (stride slb per task / system), Gram partials and sums, per-system blocks
     double *bpart = nullptr, *bs1 = nullptr, *bs2 = nullptr, *gpart = nullptr, *gsum = nullptr;

@@ -39,9 +39,15 @@ inline int inval_msg(const std::string& m) {
 // passed by value; job tables store (base, offset) pairs so that they can be built once
 // per (operation, nrhs) and reused for any caller pointers.
 enum BaseId { B_IN = 0, B_OUT = 1, B_TMP = 2, B_AUX = 3 };
+// flags (nullable): per-job skip flags of a solve.  Every job carries the index of the flag
+// that retires it: 1 + sys for the jobs of one system (window w, rhs r: sys = w nrhs + r),
+// 1 + nsys + w for the covariance products of window w (all its right-hand sides at once);
+// a nonzero flag makes the job return at once (the system has converged this cycle).
 struct Bases {
   double* p[4];
+  const int* flags;
 };
+#define SVAR_JOB_SKIPPED(b, J) ((b).flags && (b).flags[(J).flag])
 struct Operand {
   int32_t base;  // BaseId, or -1 for "none"
   int32_t pad;
@@ -60,7 +66,7 @@ struct GemmProb {
   const double* alpha;  // [per] device, or nullptr
   double alpha0, beta;
   int64_t ws_off;       // element offset of the split-K partials (splits > 1)
-  int32_t dtype, pad;
+  int32_t dtype, flag;  // flag: skip flag index (see Bases)
   const double* zeros;  // >= n zeros: stands in for rows / columns past the edge
 };
 struct GemmTask {
@@ -76,7 +82,7 @@ struct MJob {
   int32_t model, mi, trans, s;
   double alpha;
   Operand add;        // use_add: out also receives + add (band and dense models)
-  int32_t use_add, pad2;
+  int32_t use_add, flag;
 };
 enum ModelKind { MK_BAND = 0, MK_DENSE = 1, MK_L96 = 2 };
 // one whole L_M(k) sweep segment: blocks vec.off + [0, len) s, in place
@@ -86,6 +92,7 @@ struct SJob {
   // sources of the sweep's input (base -1: none): the input is src - sub (src none: vec
   // itself, in place), so a copy or a difference before the sweep needs no launch of its own
   Operand src, sub;
+  int32_t flag, pad;
 };
 constexpr int SWEEP_MAXS = 8192;  // LDS holds two state vectors (128 KB)
 constexpr int SWEEP_R = 8;        // outputs per thread of the fused sweep
@@ -113,13 +120,14 @@ struct HJob {            // gather: out[r] = sum_w vals[r*w+e] * x[cols[r*w+e]]
   const int32_t* cols;
   const double* vals;
   int32_t rows, width;
+  int32_t flag, pad;
 };
 struct HTJob {           // scatter-add: out[j] += sum_{e in ptr[j]..ptr[j+1]} val[e] * y[idx[e]]
   Operand y, out;
   const int32_t* ptr;
   const int32_t* idx;
   const double* val;
-  int32_t s, pad;
+  int32_t s, flag;
 };
 struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha) + beta * add[j], j < len
   Operand in, out;
@@ -128,6 +136,7 @@ struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha) + beta *
   int64_t len;
   Operand add;            // read only when beta != 0
   double beta;
+  int32_t flag, pad;
 };
 
 // ------------------------------------------------------------------ launch programs

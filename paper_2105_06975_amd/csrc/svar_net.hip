@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -379,6 +381,169 @@ int svar_net_train_step(svar_net* n, int32_t npair, int32_t nb, int32_t s, const
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return inv(std::string("network kernels failed: ") + hipGetErrorString(e));
+  return SVAR_OK;
+}
+
+// ------------------------------------------------------------------ training driver
+namespace {
+
+// splitmix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number generators"): the
+// sample order of epoch e is a Fisher-Yates shuffle driven by the generator seeded with
+// seed + e, so any epoch's order can be rebuilt when training resumes
+uint64_t splitmix64(uint64_t& st) {
+  uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void epoch_order(int64_t nsamp, uint64_t seed, int64_t epoch, std::vector<int64_t>& ord) {
+  ord.resize(nsamp);
+  for (int64_t i = 0; i < nsamp; ++i) ord[i] = i;
+  uint64_t st = seed + (uint64_t)epoch;
+  for (int64_t i = nsamp - 1; i > 0; --i) {
+    const int64_t j = (int64_t)(splitmix64(st) % (uint64_t)(i + 1));
+    std::swap(ord[i], ord[j]);
+  }
+}
+
+// checkpoint file: this header, then theta, m, v (nparams float32 each), little endian
+struct CkptHeader {
+  char magic[8];        // "SVARNET1"
+  int32_t k, n_bound, precision, cin;
+  int64_t nparams;
+  int64_t adam_t;       // Adam steps taken
+  int64_t epoch, pos;   // data cursor: next batch starts at sample pos of epoch's order
+  uint64_t seed;
+  int32_t npair, nb, s, batch;
+};
+
+int write_ckpt(const svar_net* n, const char* path, int64_t epoch, int64_t pos, uint64_t seed,
+               int npair, int nb, int s, int batch) {
+  CkptHeader H{};
+  std::memcpy(H.magic, "SVARNET1", 8);
+  H.k = n->d.k;
+  H.n_bound = n->d.n_bound;
+  H.precision = n->d.precision;
+  H.cin = n->L.cin;
+  H.nparams = n->L.n;
+  H.adam_t = n->t;
+  H.epoch = epoch;
+  H.pos = pos;
+  H.seed = seed;
+  H.npair = npair;
+  H.nb = nb;
+  H.s = s;
+  H.batch = batch;
+  std::vector<float> buf((size_t)3 * n->L.n);
+  const size_t b = (size_t)n->L.n * sizeof(float);
+  SVAR_HIP(hipDeviceSynchronize());
+  SVAR_HIP(hipMemcpy(buf.data(), n->theta, b, hipMemcpyDeviceToHost));
+  SVAR_HIP(hipMemcpy(buf.data() + n->L.n, n->m, b, hipMemcpyDeviceToHost));
+  SVAR_HIP(hipMemcpy(buf.data() + 2 * n->L.n, n->v, b, hipMemcpyDeviceToHost));
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return inv(std::string("cannot open ") + tmp + " for writing");
+  const bool ok = std::fwrite(&H, sizeof(H), 1, f) == 1 &&
+                  std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed) return inv(std::string("writing ") + tmp + " failed");
+  if (std::rename(tmp.c_str(), path) != 0) return inv(std::string("cannot rename to ") + path);
+  return SVAR_OK;
+}
+
+int read_ckpt(svar_net* n, const char* path, CkptHeader* out) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return inv(std::string("cannot open ") + path);
+  CkptHeader H{};
+  std::vector<float> buf;
+  bool ok = std::fread(&H, sizeof(H), 1, f) == 1 && std::memcmp(H.magic, "SVARNET1", 8) == 0;
+  if (ok && (H.k != n->d.k || H.n_bound != n->d.n_bound || H.nparams != n->L.n)) {
+    std::fclose(f);
+    return inv("checkpoint was written for another network shape (k, n_bound or size)");
+  }
+  if (ok) {
+    buf.resize((size_t)3 * H.nparams);
+    ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  }
+  std::fclose(f);
+  if (!ok) return inv(std::string(path) + " is not a network checkpoint");
+  const size_t b = (size_t)n->L.n * sizeof(float);
+  SVAR_HIP(hipMemcpy(n->theta, buf.data(), b, hipMemcpyHostToDevice));
+  SVAR_HIP(hipMemcpy(n->m, buf.data() + n->L.n, b, hipMemcpyHostToDevice));
+  SVAR_HIP(hipMemcpy(n->v, buf.data() + 2 * n->L.n, b, hipMemcpyHostToDevice));
+  n->t = H.adam_t;
+  net_pack(n->theta, n->L, n->W, nullptr);
+  SVAR_HIP(hipDeviceSynchronize());
+  if (out) *out = H;
+  return SVAR_OK;
+}
+
+}  // namespace
+
+int svar_train(svar_net* n, int32_t npair, int32_t nb, int32_t s, const float* x, const float* y,
+               const svar_train_opts* o, const char* ckpt_path, double* loss_hist,
+               void* stream) {
+  if (!n || !x || !y || !o) return inv("bad arguments");
+  SVAR_TRY(check_shape(npair, nb, s));
+  if (o->epochs < 1 || o->batch < 1) return inv("need epochs >= 1 and batch >= 1");
+  if (o->resume && !ckpt_path) return inv("resume needs a checkpoint path");
+  const int64_t nsamp = (int64_t)npair * nb;
+  if (nsamp > ((int64_t)1 << 31) - 1) return inv("too many samples");
+  int64_t epoch = 0, pos = 0;
+  if (o->resume) {
+    FILE* f = std::fopen(ckpt_path, "rb");
+    if (f) {
+      std::fclose(f);
+      CkptHeader H{};
+      SVAR_TRY(read_ckpt(n, ckpt_path, &H));
+      if (H.npair != npair || H.nb != nb || H.s != s || H.seed != o->seed ||
+          H.batch != o->batch)
+        return inv("checkpoint belongs to another pool, seed or batch size");
+      epoch = H.epoch;
+      pos = H.pos;
+    }
+  }
+  std::vector<int64_t> ord;
+  std::vector<int32_t> smp;
+  int64_t steps = 0;
+  for (; epoch < o->epochs; ++epoch, pos = 0) {
+    epoch_order(nsamp, o->seed, epoch, ord);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (; pos < nsamp; pos += o->batch) {
+      const int64_t e = std::min<int64_t>(nsamp, pos + o->batch);
+      smp.resize(2 * (e - pos));
+      for (int64_t q = pos; q < e; ++q) {
+        smp[2 * (q - pos)] = (int32_t)(ord[q] / nb);
+        smp[2 * (q - pos) + 1] = (int32_t)(ord[q] % nb);
+      }
+      double loss = 0.0;
+      SVAR_TRY(svar_net_train_step(n, npair, nb, s, x, y, (int32_t)(e - pos), smp.data(),
+                                   &o->adam, loss_hist ? &loss : nullptr, nullptr, stream));
+      tot += loss * (double)(e - pos);
+      cnt += e - pos;
+      ++steps;
+      if (ckpt_path && o->checkpoint_every > 0 && steps % o->checkpoint_every == 0)
+        SVAR_TRY(write_ckpt(n, ckpt_path, epoch, e, o->seed, npair, nb, s, o->batch));
+    }
+    if (loss_hist) loss_hist[epoch] = cnt > 0 ? tot / (double)cnt : 0.0;
+    if (ckpt_path)
+      SVAR_TRY(write_ckpt(n, ckpt_path, epoch + 1, 0, o->seed, npair, nb, s, o->batch));
+  }
+  SVAR_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return SVAR_OK;
+}
+
+int svar_load_learned(svar_net* n, const char* path, int64_t* cursor) {
+  if (!n || !path) return inv("bad arguments");
+  CkptHeader H{};
+  SVAR_TRY(read_ckpt(n, path, &H));
+  if (cursor) {
+    cursor[0] = H.epoch;
+    cursor[1] = H.pos;
+    cursor[2] = H.adam_t;
+  }
   return SVAR_OK;
 }
 

@@ -61,6 +61,14 @@ static void gs_tasks(const std::vector<int64_t>& ns, int resident, std::vector<K
   }
 }
 
+// basis stride: ntot rounded to 4 KB plus 12.5 KB, so that consecutive basis vectors do not
+// start at the same offset modulo large powers of two (they are read side by side)
+static int64_t kry_ldv(int64_t ntot) { return (ntot + 511) / 512 * 512 + 1600; }
+// elements of the basis and work vectors of a Krylov workspace of m slots
+static int64_t kry_big_elems(int64_t ntot, int m) {
+  return 2 * (int64_t)m * kry_ldv(ntot) + 5 * ((ntot + 63) / 64 * 64);
+}
+
 int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   auto& K = h->kry;
   if (K.nrhs == nrhs && K.m >= m) return SVAR_OK;
@@ -88,9 +96,7 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   K.nrhs = nrhs;
   K.m = m;
   K.ntot = ntot;
-  // basis stride: ntot rounded to 4 KB plus 12.5 KB, so that consecutive basis vectors do not
-  // start at the same offset modulo large powers of two (they are read side by side)
-  K.ldv = (ntot + 511) / 512 * 512 + 1600;
+  K.ldv = kry_ldv(ntot);
   const int SL = 2 * m + 2;
   auto& A = K.allocs;
   SVAR_TRY(dalloc(A, &K.plan.tasks, tasks.size()));
@@ -101,13 +107,24 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
                           st));
   K.plan.ntask = (int)tasks.size();
   K.plan.nsys = nsys;
-  SVAR_TRY(dalloc(A, &K.V, (size_t)m * K.ldv));
-  SVAR_TRY(dalloc(A, &K.Z, (size_t)m * K.ldv));
-  SVAR_TRY(dalloc(A, &K.u, (size_t)ntot));
-  SVAR_TRY(dalloc(A, &K.w, (size_t)ntot));
-  SVAR_TRY(dalloc(A, &K.z, (size_t)ntot));
-  SVAR_TRY(dalloc(A, &K.r, (size_t)ntot));
-  SVAR_TRY(dalloc(A, &K.xs, (size_t)ntot));
+  // basis V, Z (m slots of ldv) and the work vectors u, w, z, r, xs in one block: the handle's
+  // own allocation, or for a wave's view a carve of the parent's arena
+  const int64_t nt64 = (ntot + 63) / 64 * 64;
+  double* big = nullptr;
+  if (h->parent) {
+    if (h->parent->arena_elems < kry_big_elems(ntot, m))
+      return inval_msg("wave arena smaller than the wave's Krylov workspace");
+    big = h->parent->arena;
+  } else {
+    SVAR_TRY(dalloc(A, &big, (size_t)kry_big_elems(ntot, m)));
+  }
+  K.V = big;
+  K.Z = K.V + (int64_t)m * K.ldv;
+  K.u = K.Z + (int64_t)m * K.ldv;
+  K.w = K.u + nt64;
+  K.z = K.w + nt64;
+  K.r = K.z + nt64;
+  K.xs = K.r + nt64;
   SVAR_TRY(dalloc(A, &K.part, (size_t)K.plan.ntask * SL));
   SVAR_TRY(dalloc(A, &K.npart, (size_t)K.plan.ntask));
   SVAR_TRY(dalloc(A, &K.sums, (size_t)nsys * SL));
@@ -116,6 +133,7 @@ int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st) {
   SVAR_TRY(dalloc(A, &K.st, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.net_off, (size_t)nsys));
   SVAR_TRY(dalloc(A, &K.it0, (size_t)nsys));
+  SVAR_TRY(dalloc(A, &K.flags, (size_t)(1 + nsys + nw)));
   SVAR_TRY(dalloc(A, &K.gl, 1));
   // Hessenberg storage per system
   const size_t per = (size_t)(m + 1) * m + m + m + (m + 1) + m + (m + 1) + m;
@@ -179,8 +197,8 @@ static int fg_step(svar_handle* h, int m, const Program& PA, const Program& PP, 
     SVAR_TRY(run_program(h, *hv.prog, K.u, hv.buf + (int64_t)hv.count * hv.len, st, skip));
     ++hv.count;
   }
-  SVAR_TRY(run_program(h, PP, K.u, K.z, st, skip));
-  SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip));
+  SVAR_TRY(run_program(h, PP, K.u, K.z, st, skip, K.flags));
+  SVAR_TRY(run_program(h, PA, K.z, K.w, st, skip, K.flags));
   hipEvent_t e0, e1;
   timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
   kr_dot(K.plan, K.st, K.gl, K.V, K.u, K.w, K.z, K.Z, K.ldv, m, 1, K.part, st);
@@ -190,7 +208,7 @@ static int fg_step(svar_handle* h, int m, const Program& PA, const Program& PP, 
   timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
   kr_update(K.plan, K.st, K.gl, K.V, K.u, K.w, K.hs, K.ldv, K.npart, jl, st);
   timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
-  kr_advance(K.gl, st);
+  kr_advance(K.gl, K.st, K.flags, net_off, K.plan.nsys, K.nrhs, 1, st);
   return SVAR_OK;
 }
 
@@ -266,6 +284,8 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
                           hipMemcpyHostToDevice, st));
   kr_nrm2_part(K.plan, K.r, K.npart, st);
   kr_start(K.plan, K.npart, K.r, K.u, K.st, K.tol_rel, K.gl, st);
+  // skip flags of the systems that are inactive in this cycle
+  kr_advance(K.gl, K.st, K.flags, net_off, K.plan.nsys, K.nrhs, 0, st);
   const int check_every = GRAPH_STEPS;
   const bool graph = use_graph && !hv.buf && !hist.h && !timing_any(h);
   // Convergence checks: the device flag is copied to the host every check_every steps.  Read
@@ -366,6 +386,7 @@ static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Pr
                           hipMemcpyHostToDevice, st));
   kr_nrm2_part(K.plan, K.r, K.npart, st);
   kr_start(K.plan, K.npart, K.r, K.V, K.st, K.tol_rel, K.gl, st);
+  kr_advance(K.gl, K.st, K.flags, net_off, K.plan.nsys, K.nrhs, 0, st);
   int j = 0;
   while (j < m) {
     const int b = std::min(s, m - j);
@@ -377,8 +398,8 @@ static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Pr
         SVAR_TRY(run_program(h, *hv.prog, in, hv.buf + (int64_t)hv.count * hv.len, st, skip));
         ++hv.count;
       }
-      SVAR_TRY(run_program(h, PP, in, zo, st, skip));
-      SVAR_TRY(run_program(h, PA, zo, wo, st, skip));
+      SVAR_TRY(run_program(h, PP, in, zo, st, skip, K.flags));
+      SVAR_TRY(run_program(h, PA, zo, wo, st, skip, K.flags));
       kr_nrm2_part(K.plan, wo, K.npart, st);
       kb_scale(K.plan, K.npart, wo, K.st, K.gl, K.kb, i, st);
     }
@@ -402,6 +423,7 @@ static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Pr
     }
     kb_hess(B, K.plan, K.st, K.gl, K.bs1, K.bs2, SLB, K.kb, K.hs, m, j, b, net_off, drop,
             patience, hist, st);
+    kr_advance(K.gl, K.st, K.flags, net_off, K.plan.nsys, K.nrhs, 0, st);
     j += b;
     SVAR_HIP(hipMemcpyAsync(K.gl_host, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
     SVAR_HIP(hipStreamSynchronize(st));
@@ -455,7 +477,7 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   // learned correction: per-system switch-off flags, cleared for this solve
   const double drop = o->fallback_drop;
   h->net_off = nullptr;
-  if (h->net && drop > 0.0) {
+  if (h->net) {  // fallback bits (drop > 0) and done bits, see k_fg_advance
     net_fill_int(K.net_off, nsys, 0, st);
     h->net_off = K.net_off;
   }
@@ -585,6 +607,120 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   return rc;
 }
 
+// ------------------------------------------------------------------ wave scheduling
+// A view over windows [w0, w1) of h: shares the matrices, model tables and zero buffer, and
+// builds its own launch programs (created on first use, owned by h).
+static int get_view(svar_handle* h, int w0, int w1, svar_handle** out) {
+  auto it = h->views.find({w0, w1});
+  if (it != h->views.end()) {
+    *out = it->second;
+    return SVAR_OK;
+  }
+  svar_handle* v = new svar_handle();
+  v->device = h->device;
+  v->popts = h->popts;
+  v->wins.assign(h->wins.begin() + w0, h->wins.begin() + w1);
+  v->models = h->models;
+  v->models_dev = h->models_dev;
+  v->max_halo = h->max_halo;
+  v->band_window = h->band_window;
+  v->zeros = h->zeros;
+  v->zeros_elems = h->zeros_elems;
+  v->net = h->net;
+  v->tune = h->tune;
+  v->parent = h;
+  h->views[{w0, w1}] = v;
+  *out = v;
+  return SVAR_OK;
+}
+
+// Contiguous waves of windows whose packed length stays within the limit (opts.wave_len, or
+// what the free device memory holds at (2 m + 8) doubles per element: the basis, work vectors
+// and the views' own buffers).  One wave when everything fits.
+static int plan_waves(svar_handle* h, const svar_solve_opts* o, int nrhs, int m,
+                      std::vector<std::pair<int, int>>& waves) {
+  const int nw = (int)h->wins.size();
+  int64_t limit = o->wave_len;
+  if (limit <= 0) {
+    size_t fr = 0, tot = 0;
+    SVAR_HIP(hipMemGetInfo(&fr, &tot));
+    // memory this handle already holds for Krylov vectors is available to the solve
+    int64_t held = h->arena_elems;
+    if (h->kry.nrhs > 0) held += kry_big_elems(h->kry.ntot, h->kry.m);
+    const double avail = 0.85 * ((double)fr + 8.0 * (double)held);
+    limit = (int64_t)(avail / (8.0 * (2.0 * m + 8.0)));
+  }
+  waves.clear();
+  int w0 = 0;
+  int64_t acc = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int64_t len = (int64_t)nrhs * h->wins[w].n;
+    if (w > w0 && acc + len > limit) {
+      waves.push_back({w0, w});
+      w0 = w;
+      acc = 0;
+    }
+    acc += len;
+  }
+  waves.push_back({w0, nw});
+  return SVAR_OK;
+}
+
+static int solve_waves(svar_handle* h, const svar_solve_opts* o, int nrhs, const double* rhs,
+                       double* x, svar_solve_info* info, hipStream_t st, int m,
+                       const std::vector<std::pair<int, int>>& waves) {
+  if (o->harvest && o->harvest_cap > 0)
+    return inval_msg("harvesting needs one wave (raise wave_len)");
+  std::vector<int64_t> off(h->wins.size() + 1);
+  SVAR_TRY(svar_offsets(h, nrhs, off.data()));
+  // the arena holds the largest wave's basis and work vectors
+  int64_t need = 0;
+  for (const auto& wv : waves) need = std::max(need, kry_big_elems(off[wv.second] - off[wv.first], m));
+  if (need > h->arena_elems) {
+    SVAR_HIP(hipStreamSynchronize(st));
+    for (auto& kv : h->views) {  // their carves point into the old arena
+      free_all(kv.second->kry.allocs);
+      kv.second->kry.nrhs = -1;
+      ++kv.second->kry_gen;
+    }
+    if (h->arena) (void)hipFree(h->arena);
+    h->arena = nullptr;
+    h->arena_elems = 0;
+    // the handle's own single-wave workspace is not needed while solving in waves
+    free_all(h->kry.allocs);
+    h->kry.nrhs = -1;
+    ++h->kry_gen;
+    if (hipMalloc((void**)&h->arena, (size_t)need * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      h->arena = nullptr;
+      set_error("device allocation of the wave arena failed (" + std::to_string(need) +
+                " doubles)");
+      return SVAR_E_NOMEM;
+    }
+    h->arena_elems = need;
+  }
+  int rc = SVAR_OK;
+  std::string first_err;
+  for (const auto& wv : waves) {
+    svar_handle* v = nullptr;
+    SVAR_TRY(get_view(h, wv.first, wv.second, &v));
+    if (v->net != h->net) SVAR_TRY(svar_set_net(v, h->net));
+    svar_solve_opts ow = *o;
+    ow.wave_len = 0;
+    if (o->history && o->history_len > 0)
+      ow.history = o->history + (int64_t)wv.first * nrhs * o->history_len;
+    const int64_t b = off[wv.first];
+    const int r = solve_fgmres(v, &ow, nrhs, rhs + b, x + b, info + (int64_t)wv.first * nrhs, st);
+    if (r != SVAR_OK && r != SVAR_E_NOCONV && r != SVAR_E_BREAKDOWN) return r;
+    if (r != SVAR_OK && rc == SVAR_OK) {
+      rc = r;
+      first_err = svar_last_error();
+    }
+  }
+  if (rc != SVAR_OK) set_error(first_err);
+  return rc;
+}
+
 }  // namespace svar
 
 using namespace svar;
@@ -595,7 +731,18 @@ extern "C" int svar_solve(svar_handle* h, const svar_solve_opts* o, int32_t nrhs
   if (!(o->rtol > 0.0) || o->maxit < 1) return inval_msg("need rtol > 0 and maxit >= 1");
   if (!prec_valid(o->precision)) return inval_msg("bad precision");
   hipStream_t st = (hipStream_t)stream;
-  if (o->method == SVAR_METHOD_FGMRES) return solve_fgmres(h, o, nrhs, rhs, x, info, st);
+  if (o->wave_len < 0) return inval_msg("wave_len must be >= 0");
+  if (o->method == SVAR_METHOD_FGMRES) {
+    // basis slots of one cycle, as in solve_fgmres
+    const int blk = o->block >= 2 ? std::min((int)o->block, KB_MAX) : 0;
+    const int cap = blk ? KB_MAX_CYCLE : KR_MAX_CYCLE;
+    int cyc = o->restart > 0 ? std::min(o->restart, o->maxit) : o->maxit;
+    cyc = std::min(cyc, cap);
+    std::vector<std::pair<int, int>> waves;
+    if (h->wins.size() > 1) SVAR_TRY(plan_waves(h, o, nrhs, blk ? cyc + 1 : cyc, waves));
+    if (waves.size() > 1) return solve_waves(h, o, nrhs, rhs, x, info, st, blk ? cyc + 1 : cyc, waves);
+    return solve_fgmres(h, o, nrhs, rhs, x, info, st);
+  }
   if (o->method == SVAR_METHOD_MINRES) {
     if (h->popts.type == SVAR_PREC_PI)
       return inval_msg("MINRES needs a symmetric positive definite preconditioner (P_D)");

@@ -4,8 +4,8 @@
 trajectory x^(l), solves the saddle system for the increment and sets x^(l+1) = x^(l) + dx.
 With x = (x_0..x_N), the right-hand side (b; d; 0) has
     b_0 = x_b - x_0,   b_i = M_i(x_{i-1}) - x_i  (i = 1..N),   d_i = y_i - H_i x_i.
-The model forecast, H and the solve run in the HIP library; this module only assembles the
-right-hand side from their outputs.
+The right-hand side (svar_gn_rhs), the solve and the update x += dx (svar_gn_update) run in
+the HIP library; this module is the loop.
 """
 from __future__ import annotations
 
@@ -29,15 +29,11 @@ def gauss_newton(handle, win, *, n_outer: int = 5, x0=None, solve_kw: Optional[d
     xb = torch.from_numpy(np.asarray(win.meta["xb"], dtype=np.float64)).to(dev)
     y = torch.from_numpy(np.asarray(win.meta["y"], dtype=np.float64).reshape(-1)).to(dev)
     hist = []
+    handle.set_trajectory(x, w)
     for _ in range(n_outer):
-        handle.set_trajectory(x, w)
-        fc = handle.model_forecast(x, w)
-        b = fc - x
-        b[:s] = xb - x[:s]
-        d = y - handle.apply_op("H", x)
-        rhs = torch.cat([b, d, torch.zeros(nb * s, dtype=torch.float64, device=dev)])
+        rhs = handle.gn_rhs(x, xb, y, w)
         dx, info, rc = handle.solve(rhs, **kw)
-        x = x + dx[-nb * s:]
+        handle.gn_update(x, dx, w)
         rec = dict(info[0])
         rec.update(rc=rc, norm_dx=float(dx[-nb * s:].norm()), norm_rhs=float(rhs.norm()))
         hist.append(rec)

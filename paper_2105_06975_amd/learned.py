@@ -46,22 +46,11 @@ def harvest_pairs(windows: Sequence, k: int, rtol: float = 1e-6, maxit: int = 10
 
 
 def train(net: "sv.Net", x, y, epochs: int = 10, batch: int = 64, lr: float = 1e-3,
-          seed: int = 0, log=None):
-    """Adam epochs over every (pair, block) sample in random order; returns the mean loss of
-    each epoch."""
-    npair, nb, s = x.shape
-    rng = np.random.default_rng(seed)
-    allp = np.stack(np.meshgrid(np.arange(npair), np.arange(nb), indexing="ij"), -1).reshape(-1, 2)
-    hist = []
-    for ep in range(epochs):
-        perm = rng.permutation(allp.shape[0])
-        tot, cnt = 0.0, 0
-        for b0 in range(0, perm.size, batch):
-            idx = allp[perm[b0:b0 + batch]]
-            loss, _ = net.train_step(x, y, idx, adam=dict(lr=lr), want_loss=True)
-            tot += loss * len(idx)
-            cnt += len(idx)
-        hist.append(tot / cnt)
-        if log:
-            log(f"epoch {ep} loss {hist[-1]:.5f}")
-    return hist
+          seed: int = 0, log=None, ckpt=None):
+    """Adam epochs over every (pair, block) sample in a shuffled order (svar_train: the loop
+    runs in the library); returns the mean loss of each epoch."""
+    hist = net.train(x, y, epochs=epochs, batch=batch, lr=lr, seed=seed, ckpt=ckpt)
+    if log:
+        for ep, v in enumerate(hist):
+            log(f"epoch {ep} loss {v:.5f}")
+    return list(hist)

@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOTSPD", 3: "E_NOCONV", 4: "E_BREAKDOWN",
           6: "E_NOMEM"}
 MODEL = {"dense": 0, "band": 1, "tridiag_inv": 2, "l96": 3}
 PREC = {"NONE": 0, "PD": 1, "PI": 2}
-RHAT = {"DIAG": 0, "RR": 1, "ME": 2, "EXACT": 3}
+RHAT = {"DIAG": 0, "RR": 1, "ME": 2, "EXACT": 3, "BLOCK": 4}
 METHOD = {"FGMRES": 0, "MINRES": 1}
 PRECISION = {"FP64": 0, "MIXED_FP32": 1, "MIXED_BF16P": 2, "FP64_F32P": 3, "FP64_BF16P": 4}
 OPS = {"L": 0, "LT": 1, "LHAT_INV": 2, "LHAT_INVT": 3, "D": 4, "DHAT_INV": 5, "R": 6,
@@ -31,7 +31,7 @@ OP_SPACES = {"L": ("state", "state"), "LT": ("state", "state"), "LHAT_INV": ("st
              "LHAT_INVT": ("state", "state"), "D": ("state", "state"),
              "DHAT_INV": ("state", "state"), "R": ("obs", "obs"), "RHAT_INV": ("obs", "obs"),
              "H": ("state", "obs"), "HT": ("obs", "state")}
-KCLASS = {"GEMM": 0, "ORTHO": 1, "MODEL": 2}
+KCLASS = {"GEMM": 0, "ORTHO": 1, "MODEL": 2, "NET": 3}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -53,7 +53,9 @@ class WindowDesc(C.Structure):
 
 class PrecOpts(C.Structure):
     _fields_ = [("type", C.c_int32), ("k", C.c_int32), ("rhat", C.c_int32),
-                ("rr_gamma", C.c_double), ("me_T", C.c_double), ("d_ridge", C.c_double)]
+                ("rr_gamma", C.c_double), ("me_T", C.c_double), ("d_ridge", C.c_double),
+                ("rb_pvec", C.POINTER(C.c_int32)), ("rb_npvec", C.c_int32),
+                ("rb_maxsize", C.c_int32), ("rb_tol", C.c_double), ("rb_numproc", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -62,7 +64,8 @@ class SolveOpts(C.Structure):
                 ("max_outer", C.c_int32), ("fallback_drop", C.c_double),
                 ("harvest", C.c_void_p), ("harvest_cap", C.c_int32),
                 ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("block", C.c_int32),
-                ("minres_norm", C.c_int32), ("history", C.c_void_p), ("history_len", C.c_int32)]
+                ("minres_norm", C.c_int32), ("history", C.c_void_p), ("history_len", C.c_int32),
+                ("wave_len", C.c_int64)]
 
 
 class NetDesc(C.Structure):
@@ -73,6 +76,11 @@ class NetDesc(C.Structure):
 class AdamOpts(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("adam", AdamOpts),
+                ("seed", C.c_uint64), ("checkpoint_every", C.c_int32), ("resume", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -106,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svar_rhat_params.argtypes = [vp, C.c_int32, _dp, _dp, _dp]
     lib.svar_model_forecast.argtypes = [vp, C.c_int32, vp, vp, vp]
     lib.svar_set_trajectory.argtypes = [vp, C.c_int32, vp, vp]
+    lib.svar_gn_rhs.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
+    lib.svar_gn_update.argtypes = [vp, C.c_int32, vp, vp, vp]
     lib.svar_timing_enable.argtypes = [vp, C.c_int32, C.c_int32]
     lib.svar_timing_read.argtypes = [vp, C.c_int32, _dp, C.POINTER(C.c_int64), C.c_int32]
     lib.svar_net_create.argtypes = [C.POINTER(NetDesc), C.POINTER(vp)]
@@ -118,6 +128,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svar_net_forward.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
     lib.svar_net_train_step.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_int32,
                                         _ip, C.POINTER(AdamOpts), _dp, C.POINTER(C.c_float), vp]
+    lib.svar_train.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp,
+                               C.POINTER(TrainOpts), C.c_char_p, _dp, vp]
+    lib.svar_load_learned.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64)]
     lib.svar_set_net.argtypes = [vp, vp]
     lib.svar_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p, vp]
     lib.svar_autotune_load.argtypes = [vp, C.c_char_p]
@@ -224,6 +237,10 @@ class Precond:
     rr_gamma: float = -1.0
     me_T: float = -1.0
     d_ridge: float = 0.01
+    rb_pvec: Optional[Sequence[int]] = None   # R_block (Alg. 3): block sizes of R_i
+    rb_tol: float = 0.0
+    rb_maxsize: int = 0
+    rb_numproc: int = 0
 
 
 class Handle:
@@ -233,8 +250,12 @@ class Handle:
         self.windows = list(windows)
         keep = _Keep()
         descs = (WindowDesc * len(self.windows))(*[window_desc(w, keep) for w in self.windows])
+        pv = np.ascontiguousarray(prec.rb_pvec if prec.rb_pvec is not None else [],
+                                  dtype=np.int32)
         po = PrecOpts(PREC[prec.type], int(prec.k), RHAT[prec.rhat], float(prec.rr_gamma),
-                      float(prec.me_T), float(prec.d_ridge))
+                      float(prec.me_T), float(prec.d_ridge),
+                      _ptr(pv, C.c_int32) if pv.size else None, int(pv.size),
+                      int(prec.rb_maxsize), float(prec.rb_tol), int(prec.rb_numproc))
         self.prec = prec
         h = C.c_void_p()
         _check(lib().svar_create(descs, len(self.windows), C.byref(po), C.byref(h), _stream(stream)))
@@ -300,7 +321,7 @@ class Handle:
     def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
               precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
               check=False, fallback_drop=1e-3, fallback_patience=3, harvest=None,
-              graph=False, block=0, minres_norm="2", history=None):
+              graph=False, block=0, minres_norm="2", history=None, wave_len=0):
         """Solve A x = rhs; returns (x, [info dicts], status).
 
         harvest: optional float64 device tensor of shape (cap, state_len): receives the state
@@ -308,6 +329,8 @@ class Handle:
         block: s-step FGMRES with blocks of this many columns (2..8; 0 = one at a time).
         minres_norm: MINRES stopping rule, "2" (two-norm residual) or "P" (P^{-1}-norm estimate).
         history: optional float64 device tensor (nsys, len): residual-norm estimate per iteration.
+        wave_len: FGMRES over windows in contiguous waves of at most this packed length (0: from
+        the free device memory).
         """
         import torch
         x = torch.empty_like(rhs) if x is None else x
@@ -318,7 +341,7 @@ class Handle:
         o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
                       float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap,
                       int(fallback_patience), 1 if graph else 0, int(block),
-                      {"2": 0, "P": 1}[minres_norm], hp, hl)
+                      {"2": 0, "P": 1}[minres_norm], hp, hl, int(wave_len))
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
@@ -340,6 +363,19 @@ class Handle:
         """Attach a Net (or None): the preconditioner then corrects its Lhat^{-T} output."""
         _check(lib().svar_set_net(self._h, None if net is None else net._n))
         self._net = net
+
+    def gn_rhs(self, x, xb, y, w: int = 0, out=None, stream=None):
+        """(b; d; 0) of the outer loop about trajectory x (svar_gn_rhs)."""
+        import torch
+        win = self.windows[w]
+        out = torch.empty(win.n, dtype=torch.float64, device=x.device) if out is None else out
+        _check(lib().svar_gn_rhs(self._h, w, _vp(x), _vp(xb), _vp(y), _vp(out), _stream(stream)))
+        return out
+
+    def gn_update(self, x, sol, w: int = 0, stream=None):
+        """x += state component of sol, and the new trajectory (svar_gn_update); in place."""
+        _check(lib().svar_gn_update(self._h, w, _vp(x), _vp(sol), _stream(stream)))
+        return x
 
     def model_forecast(self, x, w: int = 0, out=None, stream=None):
         """y_0 = x_0, y_i = M_i(x_{i-1}): one observation interval of the model of window w."""
@@ -430,6 +466,29 @@ class Net:
             None if ao is None else C.byref(ao), C.byref(loss) if want_loss else None,
             None if grad is None else _ptr(grad, C.c_float), _stream(stream)))
         return (loss.value if want_loss else None), grad
+
+
+    def train(self, x, y, epochs: int = 3, batch: int = 64, lr: float = 1e-3, seed: int = 0,
+              ckpt=None, checkpoint_every: int = 0, resume: bool = False, beta1=0.9,
+              beta2=0.999, eps=1e-8, stream=None):
+        """svar_train: the Adam epoch loop over every (pair, block) sample of the pool (x, y),
+        with an optional checkpoint file; returns the mean loss of each epoch."""
+        npair, nb, s = x.shape
+        o = TrainOpts(int(epochs), int(batch), AdamOpts(float(lr), float(beta1), float(beta2),
+                                                        float(eps)),
+                      int(seed), int(checkpoint_every), 1 if resume else 0)
+        hist = np.zeros(int(epochs))
+        _check(lib().svar_train(self._n, npair, nb, s, _vp(x), _vp(y), C.byref(o),
+                                None if ckpt is None else str(ckpt).encode(),
+                                _ptr(hist, C.c_double), _stream(stream)))
+        return hist
+
+    def load(self, path):
+        """svar_load_learned: parameters and Adam state from a checkpoint; returns the data
+        cursor (epoch, position, Adam steps)."""
+        cur = np.zeros(3, dtype=np.int64)
+        _check(lib().svar_load_learned(self._n, str(path).encode(), _ptr(cur, C.c_int64)))
+        return tuple(int(c) for c in cur)
 
 
 def make_pairs(chat, cexact, stream=None):

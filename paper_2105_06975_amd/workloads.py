@@ -121,6 +121,67 @@ def _spd_sqrt_factor(C: np.ndarray) -> np.ndarray:
         return V * np.sqrt(np.clip(lam, 0.0, None))
 
 
+# ---------------------------------------------------------------- the paper's own covariances
+def modified_soar_row(s: int, L: float, maxval: int, sigma: float) -> np.ndarray:
+    """First row of the circulant B / Q of §6.1 (eq. SOAR): entry i (circular index distance
+    d = min(i, s - i)) is sigma (1 + r) e^{-r} with r = 2 |sin(d theta / 2)| / L and
+    theta = pi / maxval for d <= maxval, zero beyond (maxval fixes the nonzeros per row).
+    The printed bracketing puts the exponential inside the factor; the standard SOAR form
+    (1 + r) e^{-r} is taken."""
+    i = np.arange(s)
+    d = np.minimum(i, s - i)
+    r = 2.0 * np.abs(np.sin(d * (np.pi / maxval) / 2.0)) / L
+    c = sigma * (1.0 + r) * np.exp(-r)
+    c[d > maxval] = 0.0
+    return c
+
+
+def modified_soar_matrix(s: int, L: float, maxval: int, sigma: float,
+                         rng: np.random.Generator) -> np.ndarray:
+    """The circulant B or Q of §6.1 (B: L = 0.6, maxval = 100, sigma = 0.4; Q: 0.5, 120, 0.2):
+    when its smallest eigenvalue is negative, |lambda_min| + psi (psi ~ U[0, 0.5]) is added
+    to the diagonal."""
+    c = modified_soar_row(s, L, maxval, sigma)
+    idx = (np.arange(s)[None, :] - np.arange(s)[:, None]) % s
+    C = c[idx]
+    lam_min = float(np.min(np.fft.fft(c).real))  # eigenvalues of a symmetric circulant
+    if lam_min < 0:
+        C = C + (abs(lam_min) + rng.uniform(0.0, 0.5)) * np.eye(s)
+    return C
+
+
+def block_obs_covariance(pvec, pcorr, rng: np.random.Generator, density: float = 0.5,
+                         lam_min: float = 0.41) -> np.ndarray:
+    """An inter-channel observation-error covariance with block structure (§6.1): diagonal
+    blocks are the Hadamard product of a sparse random matrix (entries U(0, 1), the given
+    density) and a SOAR matrix of the block (eq. SOAR with L = 0.6, maxval = the block size,
+    sigma = 1); the off-diagonal block (k, l), k < l, is a sparse random matrix with entries in
+    (0, pcorr_m) (m runs over the pairs k < l in row order; pcorr_m = 0: uncorrelated).  The
+    diagonal blocks and the upper half are added and symmetrised, and the matrix is shifted by
+    a multiple of I so that its smallest eigenvalue is lam_min (0.41 in the paper)."""
+    pvec = [int(v) for v in pvec]
+    p = sum(pvec)
+    pst = np.concatenate([[0], np.cumsum(pvec)])
+    A = np.zeros((p, p))
+    m = 0
+    for k, nk in enumerate(pvec):
+        c = modified_soar_row(nk, 0.6, max(1, nk), 1.0)
+        idx = (np.arange(nk)[None, :] - np.arange(nk)[:, None]) % nk
+        mask = rng.uniform(size=(nk, nk)) < density
+        A[pst[k]:pst[k + 1], pst[k]:pst[k + 1]] = c[idx] * mask * rng.uniform(size=(nk, nk))
+        for l_ in range(k + 1, len(pvec)):
+            nl = pvec[l_]
+            pc = float(pcorr[m])
+            m += 1
+            if pc > 0:
+                mask = rng.uniform(size=(nk, nl)) < density
+                A[pst[k]:pst[k + 1], pst[l_]:pst[l_ + 1]] = mask * rng.uniform(0.0, pc,
+                                                                               size=(nk, nl))
+    R = np.triu(A) + np.triu(A, 1).T
+    lam = np.linalg.eigvalsh(R)
+    return R + (lam_min - lam[0]) * np.eye(p)
+
+
 # ---------------------------------------------------------------- windows
 def advdiff_coeffs(courant: float, nu: float) -> tuple[float, float, float]:
     return (-(courant + nu), 1.0 + courant + 2.0 * nu, -nu)
@@ -202,6 +263,74 @@ def draw_rhs(win: Window, nrhs: int, rng_sig: np.random.Generator,
         out[:, off: off + pi] = hx[None, :] + noise.T
         off += pi
     return out
+
+
+def soar_circulant(s: int, length: float, var: float) -> np.ndarray:
+    """The SOAR matrix of the uniform periodic grid of s points (chordal distance): circulant,
+    built from its first row (entry (i, j) depends on (j - i) mod s only)."""
+    d = np.arange(s, dtype=np.float64) / s
+    r = (np.sin(np.pi * d) / np.pi) / length
+    c = var * (1.0 + r) * np.exp(-r)
+    idx = (np.arange(s)[None, :] - np.arange(s)[:, None]) % s
+    return c[idx]
+
+
+def circulant_sqrt_apply(first_row: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """C^{1/2} xi for a symmetric circulant C given by its first row (columns of xi), through
+    the FFT: C = F^* diag(lambda) F with lambda = fft(first_row) (real, clipped at 0)."""
+    lam = np.clip(np.fft.fft(first_row).real, 0.0, None)
+    return np.fft.ifft(np.sqrt(lam)[:, None] * np.fft.fft(xi, axis=0), axis=0).real
+
+
+def make_c4_window(w: int, *, seed: int = 0, nrhs: int = 8, r_len: float = 0.05,
+                   r_var: float = 0.5) -> Window:
+    """Window w of the uneven batch: s ~ U{256..4096}, N ~ U{8..64}, p = floor(s f) with
+    f ~ U[1/8, 1/2] random observation points (fixed in time), SOAR B (0.1, 1) on the grid,
+    Q = 0.1 B, SOAR R (r_len, r_var) on the observed points, implicit advection-diffusion,
+    nrhs perturbed-observation right-hand sides (observation noise redrawn from R).
+
+    The same recipe as make_advdiff_window, except that the grid SOAR B is built as the
+    circulant matrix it is and the smooth signal B^{1/2} xi is drawn through the FFT (the
+    batch holds 512 windows with s up to 4096)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4, w]))
+    s = int(rng.integers(256, 4097))
+    N = int(rng.integers(8, 65))
+    f = float(rng.uniform(1 / 8, 1 / 2))
+    p = max(1, int(np.floor(s * f)))
+    idx = obs_indices(s, "random", rng, p=p)
+    ss = np.random.SeedSequence([seed, 4000 + w])
+    rng_sig, rng_obs = [np.random.default_rng(c) for c in ss.spawn(2)]
+    B = soar_circulant(s, 0.1, 1.0)
+    grid = np.arange(s, dtype=np.float64) / s
+    R, shift = recondition(soar_matrix(grid[idx], r_len, r_var))
+    nb = N + 1
+    a, b, c = advdiff_coeffs(0.5, 0.1)
+    win = Window(
+        s=s, N=N, p=np.full(nb, p, dtype=np.int32), dmats=[B], d_index=np.zeros(nb, np.int32),
+        d_scale=np.array([1.0] + [0.1] * N), rmats=[R], r_index=np.zeros(nb, np.int32),
+        h_width=1, h_cols=[idx.reshape(p, 1).copy() for _ in range(nb)],
+        h_vals=[np.ones((p, 1)) for _ in range(nb)],
+        model=dict(kind="tridiag_inv", a=a, b=b, c=c),
+        meta=dict(r_shift=shift, seed=seed, r_len=r_len, b_len=0.1, q_scale=0.1,
+                  config="c4", index=w),
+    )
+    sig = circulant_sqrt_apply(B[0], rng_sig.standard_normal((s, nb)))
+    FR = _spd_sqrt_factor(R)
+    rhs = np.zeros((nrhs, win.n))
+    off = nb * s
+    for i in range(nb):
+        noise = FR @ rng_obs.standard_normal((p, nrhs))
+        rhs[:, off:off + p] = sig[idx, i][None, :] + noise.T
+        off += p
+    win.rhs = rhs
+    return win
+
+
+def make_c4_batch(nwin: int = 512, *, seed: int = 0, nrhs: int = 8, workers: int = 8) -> list:
+    """The uneven batch of nwin windows (make_c4_window), drawn in parallel threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        return list(ex.map(lambda w: make_c4_window(w, seed=seed, nrhs=nrhs), range(nwin)))
 
 
 def make_config_window(name: str, *, seed: int = 0, nrhs: int = 1, r_len: Optional[float] = None,

@@ -46,9 +46,10 @@ def test_binding_struct_sizes_match_header_layout():
 #include <stdio.h>
 #include "svar.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(svar_model_desc), sizeof(svar_window_desc),
-         sizeof(svar_prec_opts), sizeof(svar_solve_opts), sizeof(svar_solve_info),
-         sizeof(svar_net_desc), sizeof(svar_adam_opts));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(svar_model_desc),
+         sizeof(svar_window_desc), sizeof(svar_prec_opts), sizeof(svar_solve_opts),
+         sizeof(svar_solve_info), sizeof(svar_net_desc), sizeof(svar_adam_opts),
+         sizeof(svar_train_opts));
   return 0;
 }
 '''
@@ -61,7 +62,7 @@ int main(void) {
     assert sizes == [ctypes.sizeof(sv.ModelDesc), ctypes.sizeof(sv.WindowDesc),
                      ctypes.sizeof(sv.PrecOpts), ctypes.sizeof(sv.SolveOpts),
                      ctypes.sizeof(sv.SolveInfo), ctypes.sizeof(sv.NetDesc),
-                     ctypes.sizeof(sv.AdamOpts)]
+                     ctypes.sizeof(sv.AdamOpts), ctypes.sizeof(sv.TrainOpts)]
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libsvar.so not built")
@@ -82,3 +83,5 @@ def test_errors_without_device_calls():
     assert lib.svar_net_nparams(None) == -1
     assert lib.svar_set_net(None, None) == sv.E_INVAL
     assert lib.svar_destroy(None) == sv.OK
+    assert lib.svar_train(None, 1, 1, 1, None, None, None, None, None, None) == sv.E_INVAL
+    assert lib.svar_load_learned(None, b"x", None) == sv.E_INVAL

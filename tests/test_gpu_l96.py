@@ -76,15 +76,25 @@ def test_c3_shape_operator_parity_and_solve(sv):
     V = wl.random_vectors(win, 1, seed=5)[0]
     assert rel(host(h.apply_A(dev(V))), orc.apply_A(V)) < 1e-12
     assert rel(host(h.apply_P(dev(V))), orc.apply_P_inv(V, "PI")) < 1e-10
-    # the tangent maps expand strongly over 0.2 time units (Prop. 2 does not apply) and the
-    # system needs thousands of iterations for 1e-6; here 200 iterations with the exact L
-    # (k = N+1) must not increase the residual (FGMRES minimises it over a growing space),
-    # and the library's reported true residual must equal the one the oracle's own A gives
-    # for the returned x
+    # the tangent maps expand by about 3.5 over each 0.2-time-unit interval (Prop. 2 does not
+    # apply) and B's fine-grid spectrum makes the window hard: the solve needs thousands of
+    # iterations for 1e-6 (the oracle's FGMRES is still at 0.977 after 200).  Parity over the
+    # first 20 iterations with the exact L (k = N+1; the oracle needs about 2.6 s per
+    # iteration here): the GPU's residual history follows the oracle FGMRES's (the two
+    # orthogonalisations differ only by rounding), and the residual falls.
     h = sv.Handle([win], sv.Precond(type="PI", k=win.N + 1, rhat="RR"))
+    orc33 = so.SaddleOracle(win, k=win.N + 1, rhat="RR")
     rhs = win.rhs[0]
-    x, info, rc = h.solve(dev(rhs), rtol=1e-6, maxit=200)
-    assert rc in (sv.OK, sv.E_NOCONV)
+    it = 20
+    _, _, ref_hist = so.fgmres(orc33.apply_A, orc33.apply_PI_inv, rhs, 1e-30, it)
+    hist = torch.zeros((1, it), dtype=torch.float64, device="cuda")
+    x, info, rc = h.solve(dev(rhs), rtol=1e-6, maxit=it, history=hist)
+    assert rc in (sv.OK, sv.E_NOCONV) and info[0]["iters"] == it
+    hh = host(hist)[0] / np.linalg.norm(rhs)
+    ref = np.array(ref_hist[1:it + 1])
+    print(f"C3 k=N+1: relres after {it} iterations GPU {hh[-1]:.4e} oracle {ref[-1]:.4e}")
+    assert np.allclose(hh, ref, rtol=1e-6)
+    assert hh[-1] < hh[0] and np.all(np.diff(hh) <= 1e-15)
     rr = np.linalg.norm(rhs - orc.apply_A(host(x))) / np.linalg.norm(rhs)
-    assert rr <= 1.0 + 1e-12
     assert abs(rr - info[0]["relres_true"]) <= 1e-10
+    assert abs(rr - hh[-1]) <= 1e-3 * hh[-1]

@@ -273,3 +273,39 @@ def test_training_gain_on_held_out_windows(sv):
         assert el <= max(10 * ep, 1e-6)
         gains.append(ip[0]["iters"] - il[0]["iters"])
     assert min(gains) > 0
+
+
+def test_train_loop_checkpoint_and_resume(sv, tmp_path):
+    """svar_train: two epochs in one call equal one epoch, a checkpoint, and a resumed call
+    for the second epoch (bitwise: the sample order of each epoch is rebuilt from the seed and
+    the Adam moments and step count come back from the file); svar_load_learned restores the
+    parameters and reports the data cursor."""
+    rng = np.random.default_rng(31)
+    npair, nb, s = 3, 5, 100
+    x = torch.from_numpy(f32(rng.standard_normal((npair, nb, s))).astype(np.float32)).cuda()
+    y = torch.from_numpy(f32(0.1 * rng.standard_normal((npair, nb, s))).astype(np.float32)).cuda()
+    theta0 = theta_random(7, scale=0.5)
+    a = sv.Net(K, S, "FP32")
+    a.set_params(theta0)
+    ha = a.train(x, y, epochs=2, batch=4, lr=1e-3, seed=5, ckpt=tmp_path / "a.ckpt")
+    pa = a.get_params()
+    b = sv.Net(K, S, "FP32")
+    b.set_params(theta0)
+    hb1 = b.train(x, y, epochs=1, batch=4, lr=1e-3, seed=5, ckpt=tmp_path / "b.ckpt")
+    c = sv.Net(K, S, "FP32")
+    c.set_params(np.zeros_like(theta0))
+    hc = c.train(x, y, epochs=2, batch=4, lr=1e-3, seed=5, ckpt=tmp_path / "b.ckpt", resume=True)
+    pc = c.get_params()
+    assert np.array_equal(pa, pc)
+    assert hb1[0] == ha[0] and hc[1] == ha[1]
+    assert ha[1] < ha[0]
+    d = sv.Net(K, S, "FP32")
+    cur = d.load(tmp_path / "a.ckpt")
+    steps_per_epoch = -(-npair * nb // 4)
+    assert cur == (2, 0, 2 * steps_per_epoch)
+    assert np.array_equal(d.get_params(), pa)
+    e = sv.Net(K, S + 1, "FP32")
+    with pytest.raises(sv.SvarError, match="another network shape"):
+        e.load(tmp_path / "a.ckpt")
+    for n in (a, b, c, d, e):
+        n.close()

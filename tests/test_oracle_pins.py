@@ -96,6 +96,35 @@ def test_fgmres_matches_dense_lu(prec, k, rhat):
     assert abs(h[-1] - out["relres_true"]) <= 1e-11
 
 
+def test_restarted_fgmres():
+    """FGMRES(m): with m at least the unrestarted iteration count it is one cycle of the plain
+    method (same iterate); with a short m it still reaches the dense LU solution, the true
+    residual never grows from one cycle to the next (each cycle minimises over a space that
+    contains the zero correction), and it needs at least as many steps as the unrestarted one."""
+    win = tiny(seed=4)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    rhs = win.rhs[0]
+    A, P = orc.apply_A, orc.apply_PI_inv
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    x0, it0, _ = so.fgmres(A, P, rhs, 1e-12, orc.n)
+    x1, it1, c1 = so.fgmres_restarted(A, P, rhs, 1e-12, it0 + 5, orc.n)
+    assert c1 == 1 and it1 == it0 and np.allclose(x1, x0, rtol=0, atol=1e-14 * np.abs(x0).max())
+    m = max(2, it0 // 4)
+    res = []
+    x2, it2, c2 = so.fgmres_restarted(A, P, rhs, 1e-12, m, 50 * orc.n)
+    assert c2 > 1 and it2 >= it0
+    assert np.linalg.norm(x2 - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+    # residual after each cycle: replay cycle by cycle
+    x = np.zeros_like(rhs)
+    r = rhs.copy()
+    for _ in range(c2):
+        d, _, _ = so.fgmres(A, P, r, 1e-12 * np.linalg.norm(rhs) / np.linalg.norm(r), m)
+        x = x + d
+        r = rhs - A(x)
+        res.append(np.linalg.norm(r))
+    assert np.all(np.diff(res) <= 1e-12 * np.linalg.norm(rhs))
+
+
 def test_primal_normal_equations_equivalence():
     """P2: the saddle solution equals the primal weak-constraint solution."""
     win = tiny(seed=5)
@@ -333,3 +362,181 @@ def test_golden_prop1_counts_table_sizes():
     assert th.prop1_unit_eigs(5, 3, 500) == 4 * 500
     assert th.prop1_unit_eigs(15, 16, 2500) == 16 * 2500  # k = N+1: L_M = L
     assert th.prop2_bound(3, 5) == pytest.approx(1 + 3 + math.sqrt(3))
+
+
+# ------------------------------------------------------------------ block FGMRES over rhs
+def _block_case(seed=4, p=4):
+    win = tiny(seed=seed)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    rng = np.random.default_rng(seed)
+    B = np.zeros((orc.n, p))
+    B[: orc.n - orc.nb * orc.s] = rng.standard_normal((orc.n - orc.nb * orc.s, p))
+    return orc, B
+
+
+def test_block_fgmres_one_column_is_fgmres():
+    """With one right-hand side block FGMRES is FGMRES: the same iterate and history."""
+    orc, B = _block_case(p=1)
+    A, P = orc.apply_A, orc.apply_PI_inv
+    X, st, hist = so.block_fgmres(A, P, B, 1e-10, orc.n)
+    x, it, h1 = so.fgmres(A, P, B[:, 0], 1e-10, orc.n)
+    assert st == it
+    assert np.allclose(X[:, 0], x, rtol=0, atol=1e-10 * np.abs(x).max())
+    assert np.allclose([hh[0] for hh in hist], h1, rtol=1e-8, atol=1e-14)
+
+
+def test_block_fgmres_reaches_dense_solution_and_beats_columns():
+    """Every column reaches the dense LU solution; each column's residual never grows; and
+    after j block steps a column's residual is at most that of j single-column FGMRES steps
+    (the block Krylov space contains the column's own Krylov space for a linear P)."""
+    orc, B = _block_case(p=4)
+    A, P = orc.apply_A, orc.apply_PI_inv
+    Ad = orc.A_dense()
+    X, st, hist = so.block_fgmres(A, P, B, 1e-12, orc.n)
+    H = np.array(hist)
+    for c in range(B.shape[1]):
+        xr = np.linalg.solve(Ad, B[:, c])
+        assert np.linalg.norm(X[:, c] - xr) <= 1e-9 * np.linalg.norm(xr)
+        assert np.all(np.diff(H[:, c]) <= 1e-13)
+        _, it, h1 = so.fgmres(A, P, B[:, c], 1e-12, orc.n)
+        assert st <= it
+        for j in range(1, min(st, it) + 1):
+            assert H[j, c] <= h1[j] * (1 + 1e-8) + 1e-14
+    # the estimate is the true residual at the end
+    R = B - Ad @ X
+    rr = np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.allclose(rr, H[-1], rtol=1e-6, atol=1e-13)
+
+
+def test_block_fgmres_dependent_columns():
+    """Two equal right-hand sides (a rank-deficient block) still give both solutions."""
+    orc, B = _block_case(p=3)
+    B[:, 2] = B[:, 0]
+    X, st, _ = so.block_fgmres(orc.apply_A, orc.apply_PI_inv, B, 1e-11, orc.n)
+    Ad = orc.A_dense()
+    for c in range(3):
+        xr = np.linalg.solve(Ad, B[:, c])
+        assert np.linalg.norm(X[:, c] - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+def test_block_fgmres_restarted():
+    orc, B = _block_case(p=4)
+    A, P = orc.apply_A, orc.apply_PI_inv
+    X0, st0, _ = so.block_fgmres(A, P, B, 1e-11, orc.n)
+    X1, st1, c1 = so.block_fgmres_restarted(A, P, B, 1e-11, st0 + 3, 10 * orc.n)
+    assert c1 == 1 and st1 == st0 and np.allclose(X1, X0, rtol=0, atol=1e-12 * np.abs(X0).max())
+    m = max(2, st0 // 3)
+    X2, st2, c2 = so.block_fgmres_restarted(A, P, B, 1e-11, m, 50 * orc.n)
+    assert c2 > 1
+    Ad = orc.A_dense()
+    rr = np.linalg.norm(B - Ad @ X2, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.all(rr <= 1e-11 * (1 + 1e-6))
+
+
+# ------------------------------------------------------------------ R_block (Alg. 3)
+def _coupled_blocks(pvec, strong, seed=0):
+    """SPD matrix with blocks of sizes pvec: diagonal blocks dense, neighbour couplings of
+    scaled Frobenius norm about 0.3 where strong[j], 1e-3 otherwise, nothing further out."""
+    rng = np.random.default_rng(seed)
+    p = sum(pvec)
+    pst = np.concatenate([[0], np.cumsum(pvec)])
+    R = np.zeros((p, p))
+    for k, n in enumerate(pvec):
+        G = rng.standard_normal((n, n))
+        R[pst[k]:pst[k + 1], pst[k]:pst[k + 1]] = G @ G.T / n + np.eye(n)
+    for j in range(len(pvec) - 1):
+        a, b = pvec[j], pvec[j + 1]
+        C = rng.uniform(0.2, 0.4, size=(a, b)) * (1.0 if strong[j] else 1e-3 / 0.3)
+        R[pst[j]:pst[j + 1], pst[j + 1]:pst[j + 2]] = C
+        R[pst[j + 1]:pst[j + 2], pst[j]:pst[j + 1]] = C.T
+    lam = np.linalg.eigvalsh(R)
+    return R + max(0.0, 0.5 - lam[0]) * np.eye(p), pst
+
+
+def test_rblock_retains_the_strong_couplings():
+    """Alg. 3 on a hand-built matrix whose retained blocks are known: couplings 0-1 and 2-3
+    strong, 1-2 and 3-4 weak, so R_block = blkdiag(R[blocks 0-1], R[blocks 2-3], R[block 4]);
+    the scaled norms are those of the super-diagonal blocks; within a kept group the higher
+    super-diagonals survive (blocks 2-3 of a strong pair plus their whole square)."""
+    pvec = [3, 2, 4, 3, 2]
+    R, pst = _coupled_blocks(pvec, [True, False, True, False], seed=1)
+    ranges, nv = so.rblock_partition(R, pvec, tol=0.05)
+    assert ranges == [(0, 5), (5, 12), (12, 14)]
+    for j in range(4):
+        blk = R[pst[j]:pst[j + 1], pst[j + 1]:pst[j + 2]]
+        assert abs(nv[j] - np.sqrt(np.sum(blk ** 2) / (pvec[j] * pvec[j + 1]))) < 1e-15
+    Rb = so.rblock_matrix(R, ranges)
+    assert np.array_equal(Rb[0:5, 0:5], R[0:5, 0:5]) and np.all(Rb[0:5, 5:] == 0)
+    assert np.array_equal(Rb[5:12, 5:12], R[5:12, 5:12]) and np.all(Rb[5:12, 12:] == 0)
+    # tol above every norm: block diagonal over pvec; below every norm: R itself
+    r_all, _ = so.rblock_partition(R, pvec, tol=10.0)
+    assert r_all == [(0, 3), (3, 5), (5, 9), (9, 12), (12, 14)]
+    r_none, _ = so.rblock_partition(R, pvec, tol=0.0)
+    assert r_none == [(0, 14)] and np.array_equal(so.rblock_matrix(R, r_none), R)
+
+
+def test_rblock_size_and_processor_adjustments():
+    pvec = [3, 2, 4, 3, 2]
+    R, _ = _coupled_blocks(pvec, [True, False, True, False], seed=1)
+    # the largest group (5..12, 7 rows) exceeds maxsize 6: cut at the block boundary nearest
+    # its middle (row 9)
+    r, _ = so.rblock_partition(R, pvec, tol=0.05, maxsize=6)
+    assert r == [(0, 5), (5, 9), (9, 12), (12, 14)]
+    # more groups than processors: the two smallest adjacent groups (5+... -> 7 + 2) combine
+    r, _ = so.rblock_partition(R, pvec, tol=0.05, numproc=2)
+    assert r == [(0, 5), (5, 14)]
+    # fewer than numproc - 2 groups: the largest is split
+    r, _ = so.rblock_partition(R, pvec, tol=0.05, numproc=6)
+    assert r == [(0, 5), (5, 9), (9, 12), (12, 14)]
+
+
+def test_rblock_two_groups_mirror_eigenvalues():
+    """With two groups R_block is the block-Jacobi part of R, and the eigenvalues of
+    R_block^{-1} R come in pairs 1 +- sigma_k (sigma_k the singular values of the scaled
+    coupling R11^{-1/2} R12 R22^{-1/2}), the rest equal to 1: sorted eigenvalues e satisfy
+    e + reversed(e) = 2."""
+    pvec = [4, 5]
+    R, _ = _coupled_blocks(pvec, [True], seed=3)
+    Rb = so.rblock_matrix(R, [(0, 4), (4, 9)])
+    e = np.sort(np.linalg.eigvals(np.linalg.solve(Rb, R)).real)
+    assert np.allclose(e + e[::-1], 2.0, atol=1e-12)
+    R11, R22, R12 = R[:4, :4], R[4:, 4:], R[:4, 4:]
+    w1, V1 = np.linalg.eigh(R11)
+    w2, V2 = np.linalg.eigh(R22)
+    Ch = (V1 / np.sqrt(w1)) @ V1.T @ R12 @ (V2 / np.sqrt(w2)) @ V2.T
+    sig = np.linalg.svd(Ch, compute_uv=False)
+    assert np.allclose(np.sort(np.concatenate([1 + sig, 1 - sig, [1.0]])), e, atol=1e-12)
+
+
+def test_rblock_in_the_preconditioner():
+    """R_block as Rhat: P_I with it is symmetric (P3) and FGMRES reaches the dense solution."""
+    from paper_2105_06975_amd import workloads as wl2
+    win = tiny(seed=8, s=16, N=3, p=9)
+    pvec = [3, 2, 4]
+    R = wl2.block_obs_covariance(pvec, [0.6, 0.0, 0.05], np.random.default_rng(2))
+    win.rmats = [R]
+    orc = so.SaddleOracle(win, k=2, rhat="BLOCK", rblock=dict(pvec=pvec, tol=0.05))
+    ranges = orc.rhat_params[0]["ranges"]
+    assert ranges[0][0] == 0 and ranges[-1][1] == 9
+    Pd = orc.operator_dense(lambda v: orc.apply_PI_inv(v))
+    assert np.allclose(Pd, Pd.T, atol=1e-12 * np.abs(Pd).max())
+    rhs = win.rhs[0]
+    out = so.solve(orc, rhs, prec="PI", rtol=1e-12, maxit=orc.n)
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    assert np.linalg.norm(out["x"] - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+
+
+def test_paper_covariance_generators():
+    """eq. SOAR rows: maxval nonzeros either side of the diagonal, symmetric, sigma on the
+    diagonal; the circulant B made positive definite; the block R_i has lambda_min = 0.41
+    and zero coupling where pcorr is zero."""
+    from paper_2105_06975_amd import workloads as wl2
+    c = wl2.modified_soar_row(500, 0.6, 100, 0.4)
+    assert c[0] == 0.4 and np.count_nonzero(c) == 201 and np.allclose(c[1:], c[1:][::-1])
+    B = wl2.modified_soar_matrix(500, 0.6, 100, 0.4, np.random.default_rng(0))
+    assert np.linalg.eigvalsh(B)[0] > 0 and np.allclose(B, B.T)
+    pvec = [5, 7, 4]
+    R = wl2.block_obs_covariance(pvec, [0.3, 0.0, 0.2], np.random.default_rng(1))
+    assert np.allclose(R, R.T) and abs(np.linalg.eigvalsh(R)[0] - 0.41) < 1e-12
+    shift = R[0, 0] - R[0, 0]  # off-diagonal entries are untouched by the shift
+    assert shift == 0 and np.all(R[0:5, 12:16] == 0)
