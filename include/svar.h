@@ -254,6 +254,17 @@ int svar_apply_A_prec(svar_handle* h, int32_t precision, int32_t nrhs, const dou
 int svar_apply_P_prec(svar_handle* h, int32_t precision, int32_t nrhs, const double* v, double* z,
                       void* stream);
 
+/* y = A v like svar_apply_A, for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation): it allocates nothing
+   and builds nothing.  The launch program of this nrhs must already exist (an earlier
+   svar_apply_A call with the same handle and nrhs builds it; otherwise SVAR_E_INVAL).  The
+   split-K partial sums of the covariance products go to a static device array of the library
+   (8 Mi doubles = 64 MiB per GPU, held until the process ends) instead of the handle's
+   workspace; a program that needs more returns SVAR_E_INVAL.  Every call on one GPU shares
+   that array: calls that overlap on one GPU (several streams or threads) race.  Results are
+   bitwise those of svar_apply_A; no kernel-class timing is recorded. */
+int svar_apply_A_noalloc(svar_handle* h, int32_t nrhs, const double* v, double* y, void* stream);
+
 /* Component maps, for checking each step on its own.  Vectors of the "state" space hold
    (N+1) s entries per (window, rhs); those of the "obs" space hold sum_i p_i entries; packed
    window by window and rhs by rhs like saddle vectors. */

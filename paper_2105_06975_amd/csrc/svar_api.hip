@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
 
 #include "setup.h"
@@ -1952,6 +1953,29 @@ int64_t state_total(const svar_handle* h, int nrhs) { return total_len(h, nrhs, 
 // ====================================================================== C ABI
 using namespace svar;
 
+// ------------------------------------------------------------------ allocation-free A v
+// The split-K partial sums of svar_apply_A_noalloc live in this file-scope device array (one
+// copy per GPU, held until the process ends).  Host code never passes the array's name to a
+// kernel: svar_create looks up its device address once per device (with that device current)
+// and the entry point uses that address.
+#define SVAR_NOALLOC_SCRATCH_ELEMS ((int64_t)1 << 23)  // 8 Mi doubles = 64 MiB per GPU
+static __device__ __align__(256) double scratch[SVAR_NOALLOC_SCRATCH_ELEMS];
+static std::mutex g_scratch_mu;
+static constexpr int SCRATCH_MAX_DEV = 64;
+static double* g_scratch_dev[SCRATCH_MAX_DEV] = {};
+
+// device address of `scratch` on device dev (the current device), looked up on first use
+static int scratch_setup(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV) return inval("device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return SVAR_OK;
+  void* p = nullptr;
+  SVAR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return inval("no device address for the scratch array");
+  g_scratch_dev[dev] = (double*)p;
+  return SVAR_OK;
+}
+
 extern "C" {
 
 const char* svar_last_error(void) { return g_err.c_str(); }
@@ -2047,6 +2071,7 @@ int svar_create(const svar_window_desc* windows, int32_t nwin, const svar_prec_o
   h->popts.rb_pvec = nullptr;
   int rc = SVAR_OK;
   if (hipGetDevice(&h->device) != hipSuccess) rc = inval("no HIP device");
+  if (rc == SVAR_OK) rc = scratch_setup(h->device);  // svar_apply_A_noalloc's scratch
   h->wins.resize(nwin);
   // the zero buffer that GEMM plans read past matrix edges is sized once for the largest
   // order (later growth would leave earlier plans pointing at a freed buffer)
@@ -2085,6 +2110,31 @@ int svar_offsets(const svar_handle* h, int32_t nrhs, int64_t* off) {
   if (!h || !off || nrhs < 1) return inval("bad arguments");
   for (int w = 0; w <= (int)h->wins.size(); ++w) off[w] = win_base(h, w, nrhs, SP_SADDLE);
   return SVAR_OK;
+}
+
+int svar_apply_A_noalloc(svar_handle* h, int32_t nrhs, const double* v, double* y, void* stream) {
+  if (!h || !v || !y || nrhs < 1) return inval("bad arguments");
+  double* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (h->device >= 0 && h->device < SCRATCH_MAX_DEV) ws = g_scratch_dev[h->device];
+  }
+  if (!ws) return inval("scratch address of the handle's device was not set up");
+  auto it = h->progs.find(ProgKey{PROG_A, nrhs, PV_F64});
+  if (it == h->progs.end())
+    return inval("no launch program for this nrhs yet: call svar_apply_A once with the same "
+                 "nrhs first (this entry point builds nothing and allocates nothing)");
+  const Program& P = it->second;
+  if (P.tmp_elems > 0 || P.aux_elems > 0) return inval("program needs handle workspaces");
+  for (const Launch& L : P.launches) {
+    if (L.kind == LK_NET) return inval("program holds a network application");
+    if (L.kind == LK_GEMM && L.gemm.ws_elems > SVAR_NOALLOC_SCRATCH_ELEMS)
+      return inval("split-K partials of " + std::to_string(L.gemm.ws_elems) +
+                   " doubles exceed the scratch array of " +
+                   std::to_string(SVAR_NOALLOC_SCRATCH_ELEMS) + " doubles");
+  }
+  return exec_program(h, P, const_cast<double*>(v), y, (hipStream_t)stream, nullptr, nullptr,
+                      ws, false);
 }
 
 int svar_apply_A(svar_handle* h, int32_t nrhs, const double* v, double* y, void* stream) {

@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svar_system_size.argtypes = [vp, C.c_int32]
     lib.svar_system_size.restype = C.c_int64
     lib.svar_offsets.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
-    for f in (lib.svar_apply_A, lib.svar_apply_P):
+    for f in (lib.svar_apply_A, lib.svar_apply_P, lib.svar_apply_A_noalloc):
         f.argtypes = [vp, C.c_int32, vp, vp, vp]
     lib.svar_apply_op.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     for f in (lib.svar_apply_A_prec, lib.svar_apply_P_prec):
@@ -298,6 +298,12 @@ class Handle:
         else:
             _check(lib().svar_apply_A_prec(self._h, PRECISION[precision], nrhs, _vp(v), _vp(out),
                                            _stream(stream)))
+        return out
+
+    def apply_A_noalloc(self, v, out, nrhs: int = 1, stream=None):
+        """y = A v into the caller's `out` without any device allocation (the launch program
+        of this nrhs must exist: an earlier apply_A with the same nrhs builds it)."""
+        _check(lib().svar_apply_A_noalloc(self._h, nrhs, _vp(v), _vp(out), _stream(stream)))
         return out
 
     def apply_P(self, v, nrhs: int = 1, out=None, stream=None, precision: str = "FP64"):
