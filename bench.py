@@ -70,6 +70,11 @@ def parse():
     ap.add_argument("--c3", action="store_true",
                     help="Lorenz-96 window (s=2048, N=32): iterations vs k and the 5-iteration "
                          "Gauss-Newton outer loop (one JSON object)")
+    ap.add_argument("--replay", choices=["A", "B"], default=None,
+                    help="the paper's experiments on their own recipes: A = Lorenz-96 (s=2500, "
+                         "N=15, dt=1e-4), B = heat equation (s=10000, N=5); iterations for "
+                         "P_D (MINRES) and P_I (FGMRES) over k and Rhat (one JSON object)")
+    ap.add_argument("--replay-s", type=int, default=0, help="--replay: state size override")
     ap.add_argument("--c5", type=int, default=0, metavar="W",
                     help="learned-correction mode: train on C5-shaped windows (s=4096, N=32), "
                          "then solve W held-out windows x 8 rhs batched with and without the "
@@ -175,6 +180,9 @@ def main():
         return
     if args.c5:
         print(json.dumps(bench_c5(args)), flush=True)
+        return
+    if args.replay:
+        print(json.dumps(bench_replay(args)), flush=True)
         return
     if args.c2 or args.sweep:
         bench_c2(args)
@@ -563,6 +571,64 @@ def cpu_baseline_oracle(wins, pick, gpu_ms, args):
                                                           [wins[wi].n for wi in order[:done]],
                                                           t_tot, done / gpu_same),
             "iters": its}
+
+
+# the paper's iteration counts for Experiment A (s = 2500), derived from Tables 4 and 5 as the
+# R_i product totals / 16 (one R_i product per block per iteration), by k
+PAPER_EXPA = {"PD": {"DIAG": {1: 1406, 2: 1148, 3: 1043, 4: 823, 7: 736, 10: 595, 16: 220},
+                     "BLOCK": {1: 669, 2: 515, 3: 471, 4: 414, 7: 380, 10: 301, 16: 86}},
+              "PI": {"DIAG": {1: 539, 2: 443, 3: 394, 4: 379, 7: 329, 10: 315, 16: 274},
+                     "BLOCK": {1: 209, 2: 169, 3: 150, 4: 146, 7: 125, 10: 119, 16: 103}}}
+
+
+def bench_replay(args):
+    """Iterations of the paper's two experiments on this library: P_D with MINRES (two-norm
+    stop) and P_I with unrestarted FGMRES, rtol 1e-6, over k (Definition 1; k = N + 1 is L) and
+    the Rhat kinds, the component product counts per solve, and the time per solve.  The
+    instances are seeded draws of the paper's recipe (its own random data are not published),
+    so the paper's counts are context for the trends, not targets."""
+    import torch
+
+    from paper_2105_06975_amd import svar, workloads as wl
+    t0 = time.time()
+    if args.replay == "A":
+        win = wl.make_expA_window(s=args.replay_s or 2500, N=15)
+        ks = [1, 2, 3, 4, 7, 10, 16]
+    else:
+        win = wl.make_expB_window(s=args.replay_s or 10000, N=5)
+        ks = [1, 2, 3, 4, 5, 6]
+    log(f"replay {args.replay}: n = {win.n}, drawn in {time.time() - t0:.1f}s")
+    rhs = torch.from_numpy(np.ascontiguousarray(win.rhs[0])).cuda()
+    pvec = win.meta["pvec"]
+    rows = []
+    for ptype in ("PD", "PI"):
+        for rh in ("DIAG", "BLOCK", "RR", "ME", "EXACT"):
+            for k in ks:
+                prec = svar.Precond(type=ptype, k=k, rhat=rh, rb_pvec=pvec, rb_tol=0.05)
+                h = svar.Handle([win], prec)
+                kw = dict(rtol=1e-6, maxit=3000)
+                if ptype == "PD":
+                    kw["method"] = "MINRES"
+                h.solve(rhs, **dict(kw, maxit=2))
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                x, info, rc = h.solve(rhs, **kw)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+                i0 = info[0]
+                row = dict(prec=ptype, rhat=rh, k=k, iters=i0["iters"], rc=rc,
+                           relres=i0["relres_true"], ms=1e3 * el, n_R=i0["n_R"], n_D=i0["n_D"],
+                           n_M=i0["n_M"] + i0["n_MT"], n_Rhat_inv=i0["n_Rhat_inv"],
+                           n_Dhat_inv=i0["n_Dhat_inv"])
+                if args.replay == "A" and rh in ("DIAG", "BLOCK") and k in PAPER_EXPA[ptype][rh]:
+                    row["paper_iters"] = PAPER_EXPA[ptype][rh][k]
+                rows.append(row)
+                log(row)
+                h.close()
+    return {"replay": args.replay, "n": int(win.n), "s": win.s, "N": win.N,
+            "recipe": "Lorenz-96, dt 1e-4, one RK4 step per subwindow" if args.replay == "A"
+            else "heat equation, forward Euler r = 0.4, Dirichlet",
+            "rows": rows}
 
 
 def bench_c3(args):

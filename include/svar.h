@@ -55,14 +55,18 @@ extern "C" {
                                             diffusion step)                                 */
 #define SVAR_MODEL_L96_TLM 3             /* tangent linear of nsteps RK4 steps of Lorenz-96
                                             about a stored trajectory (see fields)          */
+#define SVAR_MODEL_BAND_DIRICHLET 4      /* (M x)_j = sum_t w_t x_{j + off_t}, all i, with
+                                            x_m = 0 outside 0..s-1 (homogeneous Dirichlet
+                                            boundaries; e.g. the explicit heat-equation step
+                                            of §7.2: offsets -1, 0, 1, weights r, 1 - 2r, r)  */
 
 typedef struct svar_model_desc {
   int32_t kind;
   /* DENSE: dense[i-1] points to M_i (s x s, row-major), i = 1..N */
   const double* const* dense;
-  /* CIRC_BAND */
+  /* CIRC_BAND (offsets taken modulo s) and BAND_DIRICHLET (|offsets| < s) */
   int32_t ntaps;
-  const int32_t* offsets;   /* [ntaps], any integers (taken modulo s) */
+  const int32_t* offsets;   /* [ntaps] */
   const double* weights;    /* [ntaps] */
   /* PERIODIC_TRIDIAG_INV: a, b, c as above; |b| > |a| + |c| required */
   double tri_a, tri_b, tri_c;
@@ -128,7 +132,12 @@ typedef struct svar_prec_opts {
   int32_t rb_maxsize;
   double rb_tol;
   int32_t rb_numproc;
+  int32_t lhat;      /* SVAR_LHAT_*: the approximation of L in both preconditioners          */
 } svar_prec_opts;
+
+#define SVAR_LHAT_LM 0   /* L_M(k) of Definition 1 (k above)                                  */
+#define SVAR_LHAT_LI 1   /* L_I: every -M_i replaced by -I (§2.2); its inverse is the running
+                            sum over the time blocks (k is not used)                          */
 
 /* ------------------------------------------------------------------ solver options */
 #define SVAR_METHOD_FGMRES 0  /* right-preconditioned flexible GMRES                    */
@@ -431,6 +440,19 @@ int svar_autotune(svar_handle* h, int32_t nrhs, int32_t precision, const char* c
                   void* stream);
 /* Load the choices of a cache written by svar_autotune (unknown shapes keep the default). */
 int svar_autotune_load(svar_handle* h, const char* cache_path);
+
+/* Spectral diagnostics (Theorem 1, Propositions 1-4): nsteps steps of the Lanczos process for
+   the eigenvalues of M^{-1} K on window w, in the M inner product, from the caller's start
+   vector (device, the operator's space of window w, length: SPEC_PD_A n_w, SPEC_RHAT_R
+   sum_i p_i, SPEC_LML (N+1) s).  ritz (host, nsteps doubles) receives the eigenvalues of the
+   Lanczos tridiagonal in ascending order and *nritz their number (fewer than nsteps when the
+   Krylov space becomes invariant).  The extreme Ritz values approach the extreme eigenvalues
+   first; without re-orthogonalisation converged values can repeat.  Synchronous. */
+#define SVAR_SPEC_PD_A 0    /* P_D^{-1} A, K = A, M = P_D (needs a P_D handle)                  */
+#define SVAR_SPEC_RHAT_R 1  /* Rhat^{-1} R over all observation blocks, K = R, M = Rhat       */
+#define SVAR_SPEC_LML 2     /* Lhat^{-T} L^T L Lhat^{-1} (Lhat = L_M(k) or L_I), M = I          */
+int svar_spectrum(svar_handle* h, int32_t which, int32_t w, int32_t nsteps, const double* start,
+                  double* ritz, int32_t* nritz, void* stream);
 
 const char* svar_last_error(void);
 

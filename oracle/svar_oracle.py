@@ -118,6 +118,21 @@ class ModelOps:
                 for j in range(s):
                     Mb[j, (j + off) % s] += w
             self.mats = [Mb] * self.N
+        elif self.kind == "band_dirichlet":
+            # (M x)_j = sum_t w_t x_{j + o_t}, entries outside the grid zero (Dirichlet), sparse
+            import scipy.sparse as sp
+            s = self.s
+            rows, cols, vals = [], [], []
+            for off, w in zip(m["offsets"], m["weights"]):
+                j = np.arange(s)
+                ok = (j + off >= 0) & (j + off < s)
+                rows.append(j[ok])
+                cols.append(j[ok] + off)
+                vals.append(np.full(int(ok.sum()), float(w)))
+            Mb = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows),
+                                                       np.concatenate(cols))), shape=(s, s))
+            self.mats = [Mb] * self.N
+            self.sparse = True
         elif self.kind == "l96":
             from oracle.l96_oracle import L96Tangent
             self.l96 = L96Tangent(m["F"], m["dt"], m["nsteps"], np.asarray(m["traj"]))
@@ -150,8 +165,12 @@ class SaddleOracle:
     """Operators of one window.  Vectors are laid out (eta_0..eta_N | nu_0..nu_N | x_0..x_N)."""
 
     def __init__(self, win, *, k: int = 1, rhat: str = "RR", rr_gamma=None, me_T=None,
-                 d_ridge: float = 0.01, rblock=None):
+                 d_ridge: float = 0.01, rblock=None, lhat: str = "LM"):
         self.win = win
+        # Lhat: "LM" = L_M(k) (Definition 1), "LI" = L_I, the -I subdiagonal (§2.2)
+        if lhat not in ("LM", "LI"):
+            raise ValueError(lhat)
+        self.lhat = lhat
         # R_block parameters (Alg. 3): dict(pvec, tol, maxsize, numproc) per distinct R, or one
         # dict for all
         self.rblock = rblock
@@ -252,6 +271,28 @@ class SaddleOracle:
                 w[i] = v[i] + self.model.MT(i + 1, w[i + 1])
         return w
 
+    def LI_inv(self, v):
+        """L_I^{-1} v (§2.2: L with every M_i replaced by I): z_i = v_i + z_{i-1}, the running
+        sum over the time blocks."""
+        return np.cumsum(v, axis=0)
+
+    def LI_invT(self, v):
+        """L_I^{-T} v: w_i = v_i + w_{i+1}, the running sum from the last block backwards."""
+        return np.cumsum(v[::-1], axis=0)[::-1]
+
+    def Lhat_inv(self, v):
+        return self.LI_inv(v) if self.lhat == "LI" else self.LM_inv(v)
+
+    def Lhat_invT(self, v):
+        return self.LI_invT(v) if self.lhat == "LI" else self.LM_invT(v)
+
+    def LI_dense(self):
+        s, nb = self.s, self.nb
+        Li = np.eye(nb * s)
+        for i in range(1, nb):
+            Li[i * s:(i + 1) * s, (i - 1) * s: i * s] = -np.eye(s)
+        return Li
+
     # ---------------------------------------------------------- covariance products
     def D_apply(self, x):
         return np.stack([self.D_block(i) @ x[i] for i in range(self.nb)])
@@ -334,14 +375,14 @@ class SaddleOracle:
     def apply_PD_inv(self, v):
         """(Dhat^{-1} v1, Rhat^{-1} v2, Lhat^{-1} D Lhat^{-T} v3)."""
         v1, v2, v3 = self.split(v)
-        z3 = self.LM_inv(self.D_apply(self.LM_invT(v3)))
+        z3 = self.Lhat_inv(self.D_apply(self.Lhat_invT(v3)))
         return self.join(self.Dhat_inv(v1), self.Rhat_inv(v2), z3)
 
     def apply_PI_inv(self, v):
         """(c1 = Lhat^{-T} v3, Rhat^{-1} v2, Lhat^{-1}(v1 - D c1))."""
         v1, v2, v3 = self.split(v)
-        c1 = self.LM_invT(v3)
-        z3 = self.LM_inv(v1 - self.D_apply(c1))
+        c1 = self.Lhat_invT(v3)
+        z3 = self.Lhat_inv(v1 - self.D_apply(c1))
         return self.join(c1, self.Rhat_inv(v2), z3)
 
     def apply_P_inv(self, v, prec: str):

@@ -9,79 +9,65 @@
 // with y1..y4 the nonlinear stage states.  The adjoint runs the same chain backwards with
 //   (J(y)^T l)_m = y_{m-2} l_{m-1} - y_{m+1} l_{m+2} + (y_{m+2} - y_{m-1}) l_{m+1} - l_m,
 // recomputing the stage states of each step from x_{i-1}.
-// One workgroup per block product; the state (s <= 2048) lives in LDS.
 #include "svar_impl.h"
 
 namespace svar {
 
 static constexpr int NT = 256;
-static constexpr int MAXS = 2048;
-static constexpr int EPT = MAXS / NT;
 
 __device__ __forceinline__ int wrap(int j, int s) {
   j %= s;
   return j < 0 ? j + s : j;
 }
 
-// f(y)_j from an LDS copy of y
-__device__ __forceinline__ double l96_f(const double* y, int j, int s, double F) {
-  return (y[wrap(j + 1, s)] - y[wrap(j - 2, s)]) * y[wrap(j - 1, s)] - y[j] + F;
+// Tiled products: a workgroup owns TILE outputs [j0, j0 + TILE) of one block product and works
+// on a region of the ring that extends the tile by the dependence radius of the chain, so any s
+// (and several workgroups per product) works.  f and J at point j read j-2 .. j+1, J^T at
+// point m reads m-2 .. m+2.  Region indices i map to ring points (j0 - left + i) mod s; values
+// near the region's edges become invalid stage by stage (their neighbours are missing) but
+// never reach the tile, whose distance to the edges is the chain's radius:
+//   tangent of ns steps: left 8 ns, right 4 ns;
+//   adjoint: the cotangent needs 8 ns on both sides, and the nonlinear stage states it uses
+//   are recomputed forward from x_{i-1} over that range plus 8 ns left, 4 ns right.
+static constexpr int TILE = 256;
+static constexpr int L96_MAX_STEPS = 32;  // region <= TILE + 28 * 32 points (LDS below)
+static constexpr int REG_MAX = TILE + 28 * L96_MAX_STEPS + 8;
+// LDS arrays of the adjoint, each of its region length: x, ys, k, ks, the 4 stage states Ys,
+// lam, the 4 stage cotangents ld, as (ADJ_ARRAYS * REG_MAX doubles = 130 KB at 32 steps)
+static constexpr int ADJ_ARRAYS = 14;
+
+// stage value of f or J v at region index i from LDS copies (i - 2 .. i + 1 in range)
+__device__ __forceinline__ double reg_f(const double* y, int i, double F) {
+  return (y[i + 1] - y[i - 2]) * y[i - 1] - y[i] + F;
 }
-__device__ __forceinline__ double l96_jv(const double* y, const double* d, int j, int s) {
-  return (d[wrap(j + 1, s)] - d[wrap(j - 2, s)]) * y[wrap(j - 1, s)] +
-         (y[wrap(j + 1, s)] - y[wrap(j - 2, s)]) * d[wrap(j - 1, s)] - d[j];
+__device__ __forceinline__ double reg_jv(const double* y, const double* d, int i) {
+  return (d[i + 1] - d[i - 2]) * y[i - 1] + (y[i + 1] - y[i - 2]) * d[i - 1] - d[i];
 }
-__device__ __forceinline__ double l96_jtv(const double* y, const double* l, int m, int s) {
-  return y[wrap(m - 2, s)] * l[wrap(m - 1, s)] - y[wrap(m + 1, s)] * l[wrap(m + 2, s)] +
-         (y[wrap(m + 2, s)] - y[wrap(m - 1, s)]) * l[wrap(m + 1, s)] - l[m];
+__device__ __forceinline__ double reg_jtv(const double* y, const double* l, int m) {
+  return y[m - 2] * l[m - 1] - y[m + 1] * l[m + 2] + (y[m + 2] - y[m - 1]) * l[m + 1] - l[m];
 }
 
-// one nonlinear RK4 step on registers x[] (elements j = tid + q NT), stage states written to
-// Ys[0..3] (LDS) when Ys != nullptr; scratch ys is an LDS array of s doubles
-__device__ void rk4_step(double* x, int s, double F, double h, double* ys, double* Ys) {
-  double ks[EPT], k[EPT];
-  // stage 1
-  __syncthreads();
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    if (j < s) {
-      ys[j] = x[q];
-      if (Ys) Ys[j] = x[q];
-    }
-  }
-  __syncthreads();
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    if (j < s) {
-      k[q] = l96_f(ys, j, s, F);
-      ks[q] = k[q];
-    }
-  }
-  const double c[3] = {0.5 * h, 0.5 * h, h};
-  const double wgt[3] = {2.0, 2.0, 1.0};
-  for (int st = 0; st < 3; ++st) {
+// one nonlinear RK4 step over the region (x in place); stage states to Ys[0..3] when given
+__device__ void reg_rk4(double* x, double* ys, double* k, double* ks, double* Ys, int R,
+                        double F, double h) {
+  const double c[4] = {0.0, 0.5 * h, 0.5 * h, h};
+  const double wgt[4] = {1.0, 2.0, 2.0, 1.0};
+  for (int st = 0; st < 4; ++st) {
     __syncthreads();
-    for (int q = 0; q < EPT; ++q) {
-      const int j = threadIdx.x + q * NT;
-      if (j < s) {
-        const double v = x[q] + c[st] * k[q];
-        ys[j] = v;
-        if (Ys) Ys[(st + 1) * s + j] = v;
-      }
+    for (int i = threadIdx.x; i < R; i += NT) {
+      const double v = x[i] + (st ? c[st] * k[i] : 0.0);
+      ys[i] = v;
+      if (Ys) Ys[st * R + i] = v;
     }
     __syncthreads();
-    for (int q = 0; q < EPT; ++q) {
-      const int j = threadIdx.x + q * NT;
-      if (j < s) {
-        k[q] = l96_f(ys, j, s, F);
-        ks[q] += wgt[st] * k[q];
-      }
+    for (int i = threadIdx.x; i < R; i += NT) {
+      const double kv = (i >= 2 && i + 1 < R) ? reg_f(ys, i, F) : 0.0;
+      k[i] = kv;
+      ks[i] = (st ? ks[i] : 0.0) + wgt[st] * kv;
     }
   }
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    if (j < s) x[q] += h / 6.0 * ks[q];
-  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += NT) x[i] += h / 6.0 * ks[i];
 }
 
 __global__ __launch_bounds__(NT) void k_mstep_l96(const MJob* __restrict__ jobs,
@@ -89,15 +75,18 @@ __global__ __launch_bounds__(NT) void k_mstep_l96(const MJob* __restrict__ jobs,
                                                   const int* __restrict__ skip, int njobs) {
   if (skip && *skip) return;
   const int jid = blockIdx.y + 65535 * blockIdx.z;
-  if (jid >= njobs || blockIdx.x != 0) return;
+  if (jid >= njobs) return;
   extern __shared__ double lds[];
   const MJob J = jobs[jid];
   if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
+  const int j0 = blockIdx.x * TILE;
+  if (j0 >= s) return;
+  const int tlen = min(TILE, s - j0);
   const double* in = b.p[J.in.base] + J.in.off;
   double* out = b.p[J.out.base] + J.out.off;
   if (J.model < 0) {
-    for (int j = threadIdx.x; j < s; j += NT) out[j] = in[j];
+    for (int t = threadIdx.x; t < tlen; t += NT) out[j0 + t] = in[j0 + t];
     return;
   }
   const ModelDev& M = models[J.model];
@@ -105,130 +94,148 @@ __global__ __launch_bounds__(NT) void k_mstep_l96(const MJob* __restrict__ jobs,
   const int ns = M.nsteps;
   const double* x0 = M.traj + (size_t)(J.mi - 1) * s;
   const double* xin = b.p[J.x.base] + J.x.off;
-  double* ys = lds;           // s
-  double* as = lds + s;       // s
-  double* Ys = lds + 2 * s;   // 4 s (adjoint only)
-  double x[EPT], d[EPT];
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    x[q] = j < s ? x0[j] : 0.0;
-    d[q] = j < s ? xin[j] : 0.0;
-  }
   if (!J.trans) {
+    const int left = 8 * ns + 2, R = TILE + 12 * ns + 4;
+    double* x = lds;          // nonlinear state
+    double* d = x + R;        // tangent
+    double* ys = d + R;
+    double* as = ys + R;
+    double* k = as + R;
+    double* dk = k + R;
+    double* ks = dk + R;
+    double* dks = ks + R;
+    for (int i = threadIdx.x; i < R; i += NT) {
+      const int g = wrap(j0 - left + i, s);
+      x[i] = x0[g];
+      d[i] = xin[g];
+    }
+    const double c[4] = {0.0, 0.5 * h, 0.5 * h, h};
+    const double wgt[4] = {1.0, 2.0, 2.0, 1.0};
     for (int n = 0; n < ns; ++n) {
-      double k[EPT], dk[EPT], ks[EPT], dks[EPT];
-      const double c[4] = {0.0, 0.5 * h, 0.5 * h, h};
-      const double wgt[4] = {1.0, 2.0, 2.0, 1.0};
-      for (int q = 0; q < EPT; ++q) {
-        k[q] = 0.0;
-        dk[q] = 0.0;
-        ks[q] = 0.0;
-        dks[q] = 0.0;
-      }
       for (int st = 0; st < 4; ++st) {
         __syncthreads();
-        for (int q = 0; q < EPT; ++q) {
-          const int j = threadIdx.x + q * NT;
-          if (j < s) {
-            ys[j] = x[q] + c[st] * k[q];
-            as[j] = d[q] + c[st] * dk[q];
-          }
+        for (int i = threadIdx.x; i < R; i += NT) {
+          ys[i] = x[i] + (st ? c[st] * k[i] : 0.0);
+          as[i] = d[i] + (st ? c[st] * dk[i] : 0.0);
         }
         __syncthreads();
-        for (int q = 0; q < EPT; ++q) {
-          const int j = threadIdx.x + q * NT;
-          if (j < s) {
-            k[q] = l96_f(ys, j, s, F);
-            dk[q] = l96_jv(ys, as, j, s);
-            ks[q] += wgt[st] * k[q];
-            dks[q] += wgt[st] * dk[q];
-          }
+        for (int i = threadIdx.x; i < R; i += NT) {
+          const bool ok = i >= 2 && i + 1 < R;
+          const double kv = ok ? reg_f(ys, i, F) : 0.0;
+          const double dv = ok ? reg_jv(ys, as, i) : 0.0;
+          k[i] = kv;
+          dk[i] = dv;
+          ks[i] = (st ? ks[i] : 0.0) + wgt[st] * kv;
+          dks[i] = (st ? dks[i] : 0.0) + wgt[st] * dv;
         }
       }
-      for (int q = 0; q < EPT; ++q) {
-        x[q] += h / 6.0 * ks[q];
-        d[q] += h / 6.0 * dks[q];
+      __syncthreads();
+      for (int i = threadIdx.x; i < R; i += NT) {
+        x[i] += h / 6.0 * ks[i];
+        d[i] += h / 6.0 * dks[i];
       }
     }
-  } else {
-    // reverse over the steps; the stage states of step n are recomputed from x_{i-1}
-    for (int n = ns - 1; n >= 0; --n) {
-      double xs[EPT];
-      for (int q = 0; q < EPT; ++q) xs[q] = x[q];
-      for (int m = 0; m < n; ++m) rk4_step(xs, s, F, h, ys, nullptr);
-      rk4_step(xs, s, F, h, ys, Ys);  // Ys[0..3] = stage states of step n
-      double lam[EPT], ld[4][EPT];
-      const double wl[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0};
-      for (int q = 0; q < EPT; ++q) {
-        lam[q] = d[q];
-        for (int st = 0; st < 4; ++st) ld[st][q] = wl[st] * d[q];
+    __syncthreads();
+    for (int t = threadIdx.x; t < tlen; t += NT)
+      out[j0 + t] = in[j0 + t] + J.alpha * d[left + t];
+    return;
+  }
+  // adjoint: before step n (taken in reverse) the cotangent must be valid 8 (n + 1) points
+  // around the tile and the stage states of step n 2 points further; stage 3 of step n is
+  // valid from 8 n + 6 to R - 4 n - 3, so the tile starts at 16 ns + 4 and the region ends
+  // 12 ns + 4 points after it (both with a little slack)
+  const int left = 16 * ns + 4, R = TILE + 28 * ns + 8;
+  double* x = lds;
+  double* ys = x + R;
+  double* k = ys + R;
+  double* ks = k + R;
+  double* Ys = ks + R;       // 4 R
+  double* lam = Ys + 4 * R;  // cotangent after the current step (region indices)
+  double* ld = lam + R;      // 4 R: stage cotangents
+  double* as = ld + 4 * R;
+  for (int i = threadIdx.x; i < R; i += NT) lam[i] = xin[wrap(j0 - left + i, s)];
+  const double wl[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0};
+  const double back[4] = {0.0, 0.5 * h, 0.5 * h, h};
+  for (int n = ns - 1; n >= 0; --n) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += NT) x[i] = x0[wrap(j0 - left + i, s)];
+    for (int m = 0; m < n; ++m) reg_rk4(x, ys, k, ks, nullptr, R, F, h);
+    reg_rk4(x, ys, k, ks, Ys, R, F, h);  // Ys[0..3]: stage states of step n
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += NT)
+      for (int st = 0; st < 4; ++st) ld[st * R + i] = wl[st] * lam[i];
+    for (int st = 3; st >= 0; --st) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < R; i += NT) as[i] = ld[st * R + i];
+      __syncthreads();
+      for (int i = threadIdx.x; i < R; i += NT) {
+        const double la = (i >= 2 && i + 2 < R) ? reg_jtv(Ys + st * R, as, i) : 0.0;
+        lam[i] += la;
+        if (st > 0) ld[(st - 1) * R + i] += back[st] * la;
       }
-      const double back[4] = {0.0, 0.5 * h, 0.5 * h, h};  // a_st = d + back[st] d_{st-1}
-      for (int st = 3; st >= 0; --st) {
-        __syncthreads();
-        for (int q = 0; q < EPT; ++q) {
-          const int j = threadIdx.x + q * NT;
-          if (j < s) as[j] = ld[st][q];
-        }
-        __syncthreads();
-        for (int q = 0; q < EPT; ++q) {
-          const int j = threadIdx.x + q * NT;
-          if (j < s) {
-            const double la = l96_jtv(Ys + st * s, as, j, s);
-            lam[q] += la;
-            if (st > 0) ld[st - 1][q] += back[st] * la;
-          }
-        }
-      }
-      for (int q = 0; q < EPT; ++q) d[q] = lam[q];
     }
   }
   __syncthreads();
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    if (j < s) out[j] = in[j] + J.alpha * d[q];
-  }
+  for (int t = threadIdx.x; t < tlen; t += NT)
+    out[j0 + t] = in[j0 + t] + J.alpha * lam[left + t];
 }
 
-// y_0 = x_0, y_i = nonlinear model over one observation interval from x_{i-1} (i = 1..N);
-// one workgroup per block, the state in registers and an LDS copy for the neighbours.
+// y_0 = x_0, y_i = nonlinear model over one observation interval from x_{i-1} (i = 1..N); a
+// workgroup per (tile, block), the region extended by 8 ns left and 4 ns right.
 __global__ __launch_bounds__(NT) void k_l96_forecast(const double* __restrict__ x,
                                                      double* __restrict__ y, int s, int N, double F,
                                                      double h, int nsteps) {
-  __shared__ double ys[MAXS];
-  const int i = blockIdx.x;
-  if (i > N) return;
-  double xr[EPT];
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    xr[q] = j < s ? x[(size_t)(i > 0 ? i - 1 : 0) * s + j] : 0.0;
+  extern __shared__ double lds[];
+  const int i = blockIdx.y;
+  const int j0 = blockIdx.x * TILE;
+  if (i > N || j0 >= s) return;
+  const int tlen = min(TILE, s - j0);
+  if (i == 0) {
+    for (int t = threadIdx.x; t < tlen; t += NT) y[j0 + t] = x[j0 + t];
+    return;
   }
-  if (i > 0)
-    for (int n = 0; n < nsteps; ++n) rk4_step(xr, s, F, h, ys, nullptr);
-  for (int q = 0; q < EPT; ++q) {
-    const int j = threadIdx.x + q * NT;
-    if (j < s) y[(size_t)i * s + j] = xr[q];
-  }
+  const int left = 8 * nsteps + 2, R = TILE + 12 * nsteps + 4;
+  double* xr = lds;
+  double* ys = xr + R;
+  double* k = ys + R;
+  double* ks = k + R;
+  const double* xp = x + (size_t)(i - 1) * s;
+  for (int q = threadIdx.x; q < R; q += NT) xr[q] = xp[wrap(j0 - left + q, s)];
+  for (int n = 0; n < nsteps; ++n) reg_rk4(xr, ys, k, ks, nullptr, R, F, h);
+  __syncthreads();
+  for (int t = threadIdx.x; t < tlen; t += NT) y[(size_t)i * s + j0 + t] = xr[left + t];
 }
 
 void launch_l96_forecast(const double* x, double* y, int s, int N, double F, double h, int nsteps,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_l96_forecast, dim3(N + 1), dim3(NT), 0, st, x, y, s, N, F, h, nsteps);
+  const size_t sh = (size_t)4 * (TILE + 12 * nsteps + 4) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_l96_forecast,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(4 * (TILE + 12 * L96_MAX_STEPS + 4) * sizeof(double)));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_l96_forecast, dim3((s + TILE - 1) / TILE, N + 1), dim3(NT), sh, st, x, y,
+                     s, N, F, h, nsteps);
 }
 
-void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
-                      const int* skip, hipStream_t st) {
+void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, int max_steps,
+                      const ModelDev* models, Bases b, const int* skip, hipStream_t st) {
   if (njobs == 0) return;
-  (void)max_s;
+  // LDS for the largest step count of the launch's models (the adjoint's ADJ_ARRAYS arrays of
+  // TILE + 28 ns + 8 points; the tangent needs 8 of TILE + 12 ns + 4)
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_mstep_l96, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(6 * MAXS * sizeof(double)));
+                              (int)(ADJ_ARRAYS * REG_MAX * sizeof(double)));
     attr = true;
   }
-  const dim3 grid = njobs <= 65535 ? dim3(1, njobs, 1) : dim3(1, 65535, (njobs + 65534) / 65535);
-  hipLaunchKernelGGL(k_mstep_l96, grid, dim3(NT), (size_t)6 * MAXS * sizeof(double), st, jobs,
-                     models, b, skip, njobs);
+  const int ns = max_steps < 1 ? 1 : (max_steps > L96_MAX_STEPS ? L96_MAX_STEPS : max_steps);
+  const size_t sh = (size_t)ADJ_ARRAYS * (TILE + 28 * ns + 8) * sizeof(double);
+  const unsigned gx = (unsigned)((max_s + TILE - 1) / TILE);
+  const dim3 grid = njobs <= 65535 ? dim3(gx, njobs, 1) : dim3(gx, 65535, (njobs + 65534) / 65535);
+  hipLaunchKernelGGL(k_mstep_l96, grid, dim3(NT), sh, st, jobs, models, b, skip, njobs);
 }
 
 }  // namespace svar

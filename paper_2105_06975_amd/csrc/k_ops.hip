@@ -58,10 +58,10 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
   const int span = TS + omax - omin;
   const double* x = opnd(b, J.x);
   for (int t = threadIdx.x; t < span; t += TS) {
-    int g = j0 + omin + t;
-    g %= s;
+    const int gu = j0 + omin + t;
+    int g = gu % s;
     if (g < 0) g += s;
-    lds[t] = x[g];
+    lds[t] = (M.nonperiodic && (gu < 0 || gu >= s)) ? 0.0 : x[g];
   }
   __syncthreads();
   if (j >= s) return;
@@ -266,6 +266,29 @@ __global__ __launch_bounds__(TS) void k_vec(const VJob* __restrict__ jobs, Bases
   }
 }
 
+// L_I^{-1}, L_I^{-T} (§2.2): z_i = v_i + z_{i-1} (forward) or w_i = v_i + w_{i+1}
+// (backward) over the len time blocks of one system, one thread per spatial point (the
+// accesses of a block are coalesced), input src - sub (src none: vec in place)
+__global__ __launch_bounds__(TS) void k_prefix(const SJob* __restrict__ jobs, Bases b,
+                                               const int* __restrict__ skip, int njobs) {
+  if (skip && *skip) return;
+  if (job_id() >= njobs) return;
+  const SJob J = jobs[job_id()];
+  if (SVAR_JOB_SKIPPED(b, J)) return;
+  const int j = blockIdx.x * TS + threadIdx.x;
+  if (j >= J.s) return;
+  double* vec = opnd(b, J.vec);
+  const double* src = J.src.base >= 0 ? opnd(b, J.src) : vec;
+  const double* sub = J.sub.base >= 0 ? opnd(b, J.sub) : nullptr;
+  double acc = 0.0;
+  for (int t = 0; t < J.len; ++t) {
+    const int i = J.trans ? J.len - 1 - t : t;
+    const int64_t e = (int64_t)i * J.s + j;
+    acc += sub ? src[e] - sub[e] : src[e];
+    vec[e] = acc;
+  }
+}
+
 __global__ void k_fill(double* x, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -313,6 +336,10 @@ void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* 
   if (njobs == 0) return;
   hipLaunchKernelGGL(k_mstep_dense, jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs, models, b,
                      skip, njobs);
+}
+void launch_prefix(const SJob* jobs, int njobs, int max_s, Bases b, const int* skip,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_prefix, jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
 }
 void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
                    hipStream_t st) {

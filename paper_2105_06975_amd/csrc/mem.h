@@ -41,6 +41,8 @@ bool timing_any(const svar_handle* h);
 void timed_begin(svar_handle* h, int kc, hipStream_t st, hipEvent_t* e0, hipEvent_t* e1);
 void timed_end(svar_handle* h, int kc, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 int ensure_krylov(svar_handle* h, int nrhs, int m, hipStream_t st);
+// a handle over windows [w0, w1) of h sharing its matrices (created on first use, owned by h)
+int get_view(svar_handle* h, int w0, int w1, svar_handle** out);
 int sys_norm2(svar_handle* h, const double* x, std::vector<double>& out, hipStream_t st);
 
 }  // namespace svar

@@ -474,7 +474,39 @@ static int setup_model(svar_handle* h, WinDev& W, const svar_model_desc& md, hip
   const int s = W.s;
   std::vector<int32_t> off;
   std::vector<double> wts;
-  if (md.kind == SVAR_MODEL_CIRC_BAND || md.kind == SVAR_MODEL_PERIODIC_TRIDIAG_INV) {
+  if (md.kind == SVAR_MODEL_BAND_DIRICHLET) {
+    // a non-periodic band: the per-step model kernel with zero boundary values (no tap window,
+    // so neither the windowed nor the fused sweep kernel, which wrap around the ring)
+    M.kind = MK_BAND;
+    M.nonperiodic = 1;
+    if (md.ntaps < 1 || !md.offsets || !md.weights) return inval("band model needs taps");
+    for (int t = 0; t < md.ntaps; ++t) {
+      if (md.offsets[t] <= -s || md.offsets[t] >= s) return inval("band offset beyond the grid");
+      off.push_back(md.offsets[t]);
+      wts.push_back(md.weights[t]);
+    }
+    M.ntap = (int)off.size();
+    std::vector<int32_t> offT(off.size());
+    for (size_t t = 0; t < off.size(); ++t) offT[t] = -off[t];
+    auto mm = std::minmax_element(off.begin(), off.end());
+    M.omin = *mm.first;
+    M.omax = *mm.second;
+    M.ominT = -M.omax;
+    M.omaxT = -M.omin;
+    const int halo = M.omax - M.omin;
+    if ((256 + halo) * 8 > 64 * 1024) return inval("band model too wide for the LDS tile");
+    h->max_halo = std::max(h->max_halo, halo);
+    int32_t *doff = nullptr, *doffT = nullptr;
+    double* dw = nullptr;
+    SVAR_TRY(upload(h->allocs, &doff, off.data(), off.size(), st));
+    SVAR_TRY(upload(h->allocs, &doffT, offT.data(), offT.size(), st));
+    SVAR_TRY(upload(h->allocs, &dw, wts.data(), wts.size(), st));
+    M.off = doff;
+    M.offT = doffT;
+    M.w = dw;
+    M.wT = dw;
+    h->band_window = false;
+  } else if (md.kind == SVAR_MODEL_CIRC_BAND || md.kind == SVAR_MODEL_PERIODIC_TRIDIAG_INV) {
     M.kind = MK_BAND;
     if (md.kind == SVAR_MODEL_CIRC_BAND) {
       if (md.ntaps < 1 || !md.offsets || !md.weights) return inval("band model needs taps");
@@ -567,7 +599,9 @@ static int setup_model(svar_handle* h, WinDev& W, const svar_model_desc& md, hip
   } else if (md.kind == SVAR_MODEL_L96_TLM) {
     M.kind = MK_L96;
     if (!md.l96_traj || md.l96_nsteps < 1 || !(md.l96_dt > 0)) return inval("bad Lorenz-96 model");
-    if (s < 4 || s > 2048) return inval("Lorenz-96 tangent model needs 4 <= s <= 2048");
+    if (s < 4) return inval("Lorenz-96 tangent model needs s >= 4");
+    if (md.l96_nsteps > 32) return inval("Lorenz-96 tangent model takes at most 32 RK4 steps per interval");
+    h->l96_max_steps = std::max(h->l96_max_steps, md.l96_nsteps);
     double* tr = nullptr;
     SVAR_TRY(upload(h->allocs, &tr, md.l96_traj, (size_t)(W.N + 1) * s, st));
     M.traj = tr;
@@ -1079,6 +1113,37 @@ static bool sweep_fusable(const Builder& B, int k) {
 // vec = L_M(k)^{-1} (src - sub) (trans: L_M(k)^{-T}); src / sub NONE_REF: in place on vec
 static int add_sweep(Builder& B, VRef vec, int trans, int k, VRef src = VRef{-1, SP_STATE, 0},
                      VRef sub = VRef{-1, SP_STATE, 0}) {
+  if (B.h->popts.lhat == SVAR_LHAT_LI) {
+    // L_I (§2.2): block running sums, one job per system, no model products
+    std::vector<SJob> jobs;
+    int ms = 0;
+    for (int w = 0; w < (int)B.h->wins.size(); ++w) {
+      const WinDev& W = B.h->wins[w];
+      for (int r = 0; r < B.nrhs; ++r) {
+        SJob J{};
+        J.vec = blk(B.h, w, r, B.nrhs, vec, 0);
+        J.src = src.base >= 0 ? blk(B.h, w, r, B.nrhs, src, 0) : Operand{-1, 0, 0};
+        J.sub = sub.base >= 0 ? blk(B.h, w, r, B.nrhs, sub, 0) : Operand{-1, 0, 0};
+        J.model = -1;
+        J.trans = trans;
+        J.s = W.s;
+        J.len = W.nb;
+        J.flag = sysflag(B, w, r);
+        ms = std::max(ms, W.s);
+        jobs.push_back(J);
+      }
+    }
+    Launch L;
+    L.kind = LK_PREFIX;
+    L.njobs = (int)jobs.size();
+    L.max_s = ms;
+    L.kclass = SVAR_KCLASS_MODEL;
+    SJob* d = nullptr;
+    SVAR_TRY(upload(B.h->allocs, &d, jobs.data(), jobs.size(), B.st));
+    L.jobs = d;
+    B.P->launches.push_back(L);
+    return SVAR_OK;
+  }
   // band models with s <= SWEEP_MAXS: one fused launch, one workgroup per segment and rhs
   std::vector<SJob> fused;
   const bool outplace = src.base >= 0 || sub.base >= 0;
@@ -1648,6 +1713,16 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
             !h->models[j.model].wd || j.s > SWEEP_MAXS || j.len < 1)
           return fail("sweep job");
       }
+    } else if (L.kind == LK_PREFIX) {
+      std::vector<SJob> J(L.njobs);
+      SVAR_HIP(hipMemcpyAsync(J.data(), L.jobs, J.size() * sizeof(SJob), hipMemcpyDeviceToHost, st));
+      SVAR_HIP(hipStreamSynchronize(st));
+      for (auto& j : J) {
+        spans.push_back({j.vec.base, j.vec.off, j.vec.off + (int64_t)j.len * j.s});
+        spans.push_back({j.src.base, j.src.off, j.src.off + (int64_t)j.len * j.s});
+        spans.push_back({j.sub.base, j.sub.off, j.sub.off + (int64_t)j.len * j.s});
+        if (j.len < 1 || j.s < 1 || j.s > L.max_s) return fail("running-sum job");
+      }
     } else if (L.kind == LK_GATHER) {
       std::vector<HJob> J(L.njobs);
       SVAR_HIP(hipMemcpyAsync(J.data(), L.jobs, J.size() * sizeof(HJob), hipMemcpyDeviceToHost, st));
@@ -1808,8 +1883,12 @@ static int exec_program(svar_handle* h, const Program& P, double* in, double* ou
       case LK_SWEEP_BAND:
         launch_sweep_band((const SJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);
         break;
+      case LK_PREFIX:
+        launch_prefix((const SJob*)L.jobs, L.njobs, L.max_s, b, skip, st);
+        break;
       case LK_MSTEP_L96:
-        launch_mstep_l96((const MJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);
+        launch_mstep_l96((const MJob*)L.jobs, L.njobs, L.max_s, h->l96_max_steps, h->models_dev,
+                         b, skip, st);
         break;
       case LK_GATHER:
         launch_gather((const HJob*)L.jobs, L.njobs, L.max_s, b, skip, st);
@@ -2058,6 +2137,7 @@ int svar_create(const svar_window_desc* windows, int32_t nwin, const svar_prec_o
   if (popts->type < SVAR_PREC_NONE || popts->type > SVAR_PREC_PI) return inval("bad prec type");
   if (popts->rhat < SVAR_RHAT_DIAG || popts->rhat > SVAR_RHAT_BLOCK) return inval("bad rhat kind");
   if (popts->type == SVAR_PREC_PD && !(popts->d_ridge >= 0.0)) return inval("bad d_ridge");
+  if (popts->lhat != SVAR_LHAT_LM && popts->lhat != SVAR_LHAT_LI) return inval("bad lhat kind");
   hipStream_t st = (hipStream_t)stream;
   if (popts->rhat == SVAR_RHAT_BLOCK) {
     if (!popts->rb_pvec || popts->rb_npvec < 1) return inval("R_block needs rb_pvec");

@@ -101,6 +101,7 @@ struct svar_handle {
   std::vector<svar::ModelDev> models;       // host copy
   svar::ModelDev* models_dev = nullptr;
   int max_halo = 0;
+  int l96_max_steps = 0;  // largest RK4 step count of the Lorenz-96 models (LDS of their kernel)
   bool band_window = true;  // every band model has a dense tap window (windowed M-step kernel)
   std::vector<void*> allocs;                // every device allocation owned by the handle
   std::map<svar::ProgKey, svar::Program> progs;

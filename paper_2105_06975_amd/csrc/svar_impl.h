@@ -111,7 +111,8 @@ struct ModelDev {
   // Lorenz-96 tangent linear model
   const double* traj;    // [N+1][s]
   double F, dt;
-  int32_t nsteps, pad;
+  int32_t nsteps;
+  int32_t nonperiodic;   // band models: values outside 0..s-1 are zero (Dirichlet boundaries)
 };
 
 // ------------------------------------------------------------------ H
@@ -141,7 +142,7 @@ struct VJob {            // out[j] = in[j] * (scale ? scale[j] : alpha) + beta *
 
 // ------------------------------------------------------------------ launch programs
 enum LaunchKind { LK_MSTEP_BAND, LK_MSTEP_DENSE, LK_MSTEP_L96, LK_GATHER, LK_SCATTER, LK_VEC,
-                  LK_GEMM, LK_SWEEP_BAND, LK_NET };
+                  LK_GEMM, LK_SWEEP_BAND, LK_NET, LK_PREFIX };
 struct GemmPlanDev {
   GemmProb* probs = nullptr;   // device
   GemmTask* tasks = nullptr;   // device
@@ -182,8 +183,12 @@ void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* 
                         Bases b, const int* skip, hipStream_t st);
 void launch_sweep_band(const SJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
                        const int* skip, hipStream_t st);
-void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
-                      Bases b, const int* skip, hipStream_t st);
+// L_I^{-1} (trans = 0: running sum over the len blocks) or L_I^{-T} (trans = 1: from the last
+// block backwards) of each job's vector, input src - sub as for the sweeps
+void launch_prefix(const SJob* jobs, int njobs, int max_s, Bases b, const int* skip,
+                   hipStream_t st);
+void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, int max_steps,
+                      const ModelDev* models, Bases b, const int* skip, hipStream_t st);
 void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
                    hipStream_t st);
 void launch_scatter(const HTJob* jobs, int njobs, int max_s, Bases b, const int* skip,

@@ -610,7 +610,7 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
 // ------------------------------------------------------------------ wave scheduling
 // A view over windows [w0, w1) of h: shares the matrices, model tables and zero buffer, and
 // builds its own launch programs (created on first use, owned by h).
-static int get_view(svar_handle* h, int w0, int w1, svar_handle** out) {
+int get_view(svar_handle* h, int w0, int w1, svar_handle** out) {
   auto it = h->views.find({w0, w1});
   if (it != h->views.end()) {
     *out = it->second;
@@ -623,6 +623,7 @@ static int get_view(svar_handle* h, int w0, int w1, svar_handle** out) {
   v->models = h->models;
   v->models_dev = h->models_dev;
   v->max_halo = h->max_halo;
+  v->l96_max_steps = h->l96_max_steps;
   v->band_window = h->band_window;
   v->zeros = h->zeros;
   v->zeros_elems = h->zeros_elems;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsvar.so")
 OK, E_INVAL, E_NOTSPD, E_NOCONV, E_BREAKDOWN, E_HIP, E_NOMEM = range(7)
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOTSPD", 3: "E_NOCONV", 4: "E_BREAKDOWN", 5: "E_HIP",
           6: "E_NOMEM"}
-MODEL = {"dense": 0, "band": 1, "tridiag_inv": 2, "l96": 3}
+MODEL = {"dense": 0, "band": 1, "tridiag_inv": 2, "l96": 3, "band_dirichlet": 4}
 PREC = {"NONE": 0, "PD": 1, "PI": 2}
 RHAT = {"DIAG": 0, "RR": 1, "ME": 2, "EXACT": 3, "BLOCK": 4}
 METHOD = {"FGMRES": 0, "MINRES": 1}
@@ -55,7 +55,8 @@ class PrecOpts(C.Structure):
     _fields_ = [("type", C.c_int32), ("k", C.c_int32), ("rhat", C.c_int32),
                 ("rr_gamma", C.c_double), ("me_T", C.c_double), ("d_ridge", C.c_double),
                 ("rb_pvec", C.POINTER(C.c_int32)), ("rb_npvec", C.c_int32),
-                ("rb_maxsize", C.c_int32), ("rb_tol", C.c_double), ("rb_numproc", C.c_int32)]
+                ("rb_maxsize", C.c_int32), ("rb_tol", C.c_double), ("rb_numproc", C.c_int32),
+                ("lhat", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -132,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                C.POINTER(TrainOpts), C.c_char_p, _dp, vp]
     lib.svar_load_learned.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64)]
     lib.svar_set_net.argtypes = [vp, vp]
+    lib.svar_spectrum.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, _dp, _ip, vp]
     lib.svar_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p, vp]
     lib.svar_autotune_load.argtypes = [vp, C.c_char_p]
     lib.svar_last_error.restype = C.c_char_p
@@ -216,7 +218,7 @@ def window_desc(win, keep: _Keep) -> WindowDesc:
     md.kind = MODEL[m["kind"]]
     if m["kind"] == "tridiag_inv":
         md.tri_a, md.tri_b, md.tri_c = float(m["a"]), float(m["b"]), float(m["c"])
-    elif m["kind"] == "band":
+    elif m["kind"] in ("band", "band_dirichlet"):
         md.ntaps = len(m["offsets"])
         md.offsets = _ptr(keep.arr(m["offsets"], np.int32), C.c_int32)
         md.weights = _ptr(keep.arr(m["weights"], np.float64), C.c_double)
@@ -241,6 +243,7 @@ class Precond:
     rb_tol: float = 0.0
     rb_maxsize: int = 0
     rb_numproc: int = 0
+    lhat: str = "LM"                          # "LM": L_M(k), "LI": L_I (§2.2)
 
 
 class Handle:
@@ -255,7 +258,8 @@ class Handle:
         po = PrecOpts(PREC[prec.type], int(prec.k), RHAT[prec.rhat], float(prec.rr_gamma),
                       float(prec.me_T), float(prec.d_ridge),
                       _ptr(pv, C.c_int32) if pv.size else None, int(pv.size),
-                      int(prec.rb_maxsize), float(prec.rb_tol), int(prec.rb_numproc))
+                      int(prec.rb_maxsize), float(prec.rb_tol), int(prec.rb_numproc),
+                      {"LM": 0, "LI": 1}[prec.lhat])
         self.prec = prec
         h = C.c_void_p()
         _check(lib().svar_create(descs, len(self.windows), C.byref(po), C.byref(h), _stream(stream)))
@@ -355,6 +359,23 @@ class Handle:
         if rc not in (OK, E_NOCONV, E_BREAKDOWN) or (check and rc != OK):
             _check(rc)
         return x, [i.as_dict() for i in infos], rc
+
+    def spectrum(self, which: str, nsteps: int, w: int = 0, start=None, seed: int = 0,
+                 stream=None):
+        """Lanczos Ritz values of M^{-1} K (svar_spectrum): which = "PD_A" (P_D^{-1} A),
+        "RHAT_R" (Rhat^{-1} R) or "LML" (Lhat^{-T} L^T L Lhat^{-1}); start defaults to a seeded
+        standard-normal vector of the operator's space.  Returns the ascending Ritz values."""
+        import torch
+        win = self.windows[w]
+        n = {"PD_A": win.n, "RHAT_R": win.P, "LML": win.nb * win.s}[which]
+        if start is None:
+            start = torch.from_numpy(np.random.default_rng(seed).standard_normal(n)).cuda()
+        ritz = np.zeros(int(nsteps))
+        cnt = C.c_int32(0)
+        _check(lib().svar_spectrum(self._h, {"PD_A": 0, "RHAT_R": 1, "LML": 2}[which], w,
+                                   int(nsteps), _vp(start), _ptr(ritz, C.c_double),
+                                   C.byref(cnt), _stream(stream)))
+        return ritz[:cnt.value]
 
     def autotune(self, nrhs: int = 1, precision: str = "FP64", cache_path=None, stream=None):
         """Time the GEMM plan candidates of this handle's A and P programs (svar_autotune)."""

@@ -460,6 +460,126 @@ def make_l96_window(s: int = 2048, N: int = 32, *, F: float = 8.0, dt: float = 0
     return win
 
 
+# ---------------------------------------------------------------- the paper's experiments (§7)
+def paper_block_R(p: int, rng: np.random.Generator, block: int = 25,
+                  coupling: float = 0.4) -> tuple[np.ndarray, list]:
+    """R_i of §6.1 for the replays: blocks of `block` observations (pvec), neighbouring blocks
+    coupled with pcorr = coupling for a random half of the neighbour pairs and uncorrelated
+    otherwise (the paper does not print its pvec / pcorr), lambda_min = 0.41."""
+    nblk = max(1, p // block)
+    pvec = [block] * nblk
+    pvec[-1] += p - block * nblk
+    pcorr = []
+    for k in range(nblk):
+        for l_ in range(k + 1, nblk):
+            pcorr.append(coupling if (l_ == k + 1 and rng.uniform() < 0.5) else 0.0)
+    return block_obs_covariance(pvec, pcorr, rng), pvec
+
+
+def _paper_D(s, rng):
+    B = modified_soar_matrix(s, 0.6, 100, 0.4, rng)
+    Q = modified_soar_matrix(s, 0.5, 120, 0.2, rng)
+    return B, Q
+
+
+def make_expA_window(s: int = 2500, N: int = 15, *, dt: float = 1e-4, nsteps: int = 1,
+                     seed: int = 0, spinup: int = 2000) -> Window:
+    """Experiment A (§7.1, Table 1): Lorenz-96 (F = 8, RK4) with s points, N = 15 subwindows,
+    time step 1e-4 (one RK4 step per subwindow: the paper gives the step, not the steps per
+    subwindow), observations of every second variable, D from the modified SOAR B and Q of
+    eq. SOAR, block R_i (§6.1).  Truth: a spun-up nature run with model error Q^{1/2} eta;
+    background x_b = x_0^t + B^{1/2} eps; first guess a free run from x_b (the single outer
+    loop is linearised about it); right-hand side b_0 = x_b - x_0 (= 0), b_i = 0, d_i = y_i -
+    H x_i."""
+    ss = np.random.SeedSequence([seed, 71])
+    rng_m, rng_i, rng_b, rng_q, rng_o, rng_r = [np.random.default_rng(c) for c in ss.spawn(6)]
+    B, Q = _paper_D(s, rng_m)
+    FB, FQ = _spd_sqrt_factor(B), _spd_sqrt_factor(Q)
+    idx = np.arange(0, s, 2, dtype=np.int32)
+    p = idx.size
+    R, pvec = paper_block_R(p, rng_r)
+    FR = _spd_sqrt_factor(R)
+    x = 8.0 + 0.01 * rng_i.standard_normal(s)
+    x = _l96_run(x, 8.0, 0.01, spinup)
+    truth = np.zeros((N + 1, s))
+    truth[0] = x
+    for i in range(1, N + 1):
+        truth[i] = _l96_run(truth[i - 1], 8.0, dt, nsteps) + FQ @ rng_q.standard_normal(s)
+    xb = truth[0] + FB @ rng_b.standard_normal(s)
+    y = np.stack([truth[i][idx] + FR @ rng_o.standard_normal(p) for i in range(N + 1)])
+    guess = np.zeros((N + 1, s))
+    guess[0] = xb
+    for i in range(1, N + 1):
+        guess[i] = _l96_run(guess[i - 1], 8.0, dt, nsteps)
+    nb = N + 1
+    win = Window(
+        s=s, N=N, p=np.full(nb, p, dtype=np.int32), dmats=[B, Q],
+        d_index=np.array([0] + [1] * N, dtype=np.int32), d_scale=np.ones(nb),
+        rmats=[R], r_index=np.zeros(nb, np.int32), h_width=1,
+        h_cols=[idx.reshape(p, 1).copy() for _ in range(nb)],
+        h_vals=[np.ones((p, 1)) for _ in range(nb)],
+        model=dict(kind="l96", F=8.0, dt=dt, nsteps=nsteps, traj=guess.copy()),
+        meta=dict(truth=truth, xb=xb, y=y, obs_idx=idx, pvec=pvec, seed=seed, config="expA"),
+    )
+    rhs = np.zeros((1, win.n))
+    off = nb * s
+    for i in range(nb):
+        rhs[0, off + i * p: off + (i + 1) * p] = y[i] - guess[i][idx]
+    win.rhs = rhs
+    return win
+
+
+def make_expB_window(s: int = 10000, N: int = 5, *, r: float = 0.4, seed: int = 0) -> Window:
+    """Experiment B (§7.2, Table 1): the heat equation u_t = u_xx on s interior points with
+    homogeneous Dirichlet boundaries, forward Euler with r = dt/dx^2 = 0.4 (M: weights r,
+    1 - 2r, r on offsets -1, 0, 1), N subwindows (N = 5: 750,000 = 2.5 * 50,000 * (N + 1)),
+    every fourth point observed, modified-SOAR D and block R_i.  Truth: a smooth initial
+    profile plus B^{1/2} noise, propagated by M with model error; first guess a free run from
+    x_b; right-hand side of the first outer loop (b = 0, d = y - H x)."""
+    ss = np.random.SeedSequence([seed, 72])
+    rng_m, rng_b, rng_q, rng_o, rng_r, rng_t = [np.random.default_rng(c) for c in ss.spawn(6)]
+    B, Q = _paper_D(s, rng_m)
+    FB, FQ = _spd_sqrt_factor(B), _spd_sqrt_factor(Q)
+    idx = np.arange(0, s, 4, dtype=np.int32)
+    p = idx.size
+    R, pvec = paper_block_R(p, rng_r)
+    FR = _spd_sqrt_factor(R)
+    offs, wts = [-1, 0, 1], [r, 1.0 - 2.0 * r, r]
+
+    def step(u):
+        v = (1.0 - 2.0 * r) * u
+        v[1:] += r * u[:-1]
+        v[:-1] += r * u[1:]
+        return v
+    grid = (np.arange(s) + 1.0) / (s + 1.0)
+    truth = np.zeros((N + 1, s))
+    truth[0] = np.sin(np.pi * grid) + FB @ rng_t.standard_normal(s)
+    for i in range(1, N + 1):
+        truth[i] = step(truth[i - 1]) + FQ @ rng_q.standard_normal(s)
+    xb = truth[0] + FB @ rng_b.standard_normal(s)
+    y = np.stack([truth[i][idx] + FR @ rng_o.standard_normal(p) for i in range(N + 1)])
+    guess = np.zeros((N + 1, s))
+    guess[0] = xb
+    for i in range(1, N + 1):
+        guess[i] = step(guess[i - 1])
+    nb = N + 1
+    win = Window(
+        s=s, N=N, p=np.full(nb, p, dtype=np.int32), dmats=[B, Q],
+        d_index=np.array([0] + [1] * N, dtype=np.int32), d_scale=np.ones(nb),
+        rmats=[R], r_index=np.zeros(nb, np.int32), h_width=1,
+        h_cols=[idx.reshape(p, 1).copy() for _ in range(nb)],
+        h_vals=[np.ones((p, 1)) for _ in range(nb)],
+        model=dict(kind="band_dirichlet", offsets=offs, weights=wts),
+        meta=dict(truth=truth, xb=xb, y=y, obs_idx=idx, pvec=pvec, seed=seed, config="expB"),
+    )
+    rhs = np.zeros((1, win.n))
+    off = nb * s
+    for i in range(nb):
+        rhs[0, off + i * p: off + (i + 1) * p] = y[i] - guess[i][idx]
+    win.rhs = rhs
+    return win
+
+
 def net_init(cin: int, C: int, seed: int = 0, width: int = 5) -> np.ndarray:
     """Seeded initial parameters of the correction network, flat, float32-representable.
 

@@ -53,6 +53,31 @@ def test_l96_blocks_and_forecast(sv):
         assert rel(fc[i], T.forecast(x[i - 1])) < 1e-13
 
 
+@pytest.mark.parametrize("s,nsteps,dt", [(2500, 1, 1e-4), (2500, 3, 0.025), (300, 32, 0.01)])
+def test_l96_tiled_products_any_size(sv, s, nsteps, dt):
+    """The tiled tangent and adjoint kernels beyond one workgroup per product: the paper's
+    s = 2500 with one RK4 step of 1e-4 per interval, several steps, and the largest step count
+    (32): L, L^T, the sweeps and the forecast against the oracle, and the dot test."""
+    win = wl.make_l96_window(s=s, N=3, nsteps=nsteps, dt=dt, spinup=100, seed=s + nsteps)
+    orc = so.SaddleOracle(win, k=2, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PI", k=2, rhat="RR"))
+    X = np.random.default_rng(9).standard_normal((2, win.nb * win.s))
+    outs = {}
+    for op, fn in {"L": orc.L_apply, "LT": orc.LT_apply, "LHAT_INV": orc.LM_inv,
+                   "LHAT_INVT": orc.LM_invT}.items():
+        out = host(h.apply_op(op, dev(X), 2)).reshape(2, -1)
+        outs[op] = out
+        for r in range(2):
+            assert rel(out[r], fn(X[r].reshape(win.nb, win.s)).ravel()) < 1e-12, op
+    # dot test of the GPU's own L and L^T
+    assert abs(X[1] @ outs["L"][0] - X[0] @ outs["LT"][1]) <= 1e-12 * np.abs(X[1] @ outs["L"][0])
+    x = win.model["traj"]
+    fc = host(h.model_forecast(dev(x))).reshape(win.nb, win.s)
+    T = orc.model.l96
+    for i in range(1, win.nb):
+        assert rel(fc[i], T.forecast(x[i - 1])) < 1e-13
+
+
 def test_gauss_newton_matches_oracle(sv):
     from paper_2105_06975_amd.gauss_newton import gauss_newton
     win = wl.make_l96_window(s=32, N=3, nsteps=2, spinup=200, seed=4)

@@ -513,3 +513,61 @@ def test_rhat_block(sv, adj):
             assert rc == sv.OK
             assert rel(host(x), np.linalg.solve(orc.A_dense(), rhs)) < 1e-9
         h.close()
+
+
+# ------------------------------------------------------------------ L_I (§2.2)
+@pytest.mark.parametrize("prec", ["PI", "PD"])
+def test_lhat_LI(sv, prec):
+    """L_I in both preconditioners: the running-sum sweeps against the oracle, P^{-1} v on
+    two uneven windows x 2 rhs, and a solve against the dense solution."""
+    wins = [tiny(seed=33, s=12, N=4, p=6), wl.make_small_window(s=70, N=6, p=20, seed=34)]
+    h = sv.Handle(wins, sv.Precond(type=prec, k=2, rhat="RR", lhat="LI"))
+    off = h.offsets(2)
+    Vs = [wl.random_vectors(w, 2, seed=35 + i) for i, w in enumerate(wins)]
+    Z = host(h.apply_P(dev(np.concatenate([v.ravel() for v in Vs])), 2))
+    for i, w in enumerate(wins):
+        orc = so.SaddleOracle(w, k=2, rhat="RR", lhat="LI")
+        z = Z[off[i]:off[i + 1]].reshape(2, -1)
+        for r in range(2):
+            ref = orc.apply_P_inv(Vs[i][r], prec)
+            assert rel(z[r], ref) < 1e-10
+            assert_blocks(w, z[r], ref, 1e-9, what=f"{prec} L_I")
+    w0 = wins[0]
+    h0 = sv.Handle([w0], sv.Precond(type=prec, k=2, rhat="RR", lhat="LI"))
+    orc0 = so.SaddleOracle(w0, k=2, rhat="RR", lhat="LI")
+    X = np.random.default_rng(36).standard_normal((2, w0.nb * w0.s))
+    for op, fn in (("LHAT_INV", orc0.LI_inv), ("LHAT_INVT", orc0.LI_invT)):
+        out = host(h0.apply_op(op, dev(X), 2)).reshape(2, -1)
+        for r in range(2):
+            assert rel(out[r], fn(X[r].reshape(w0.nb, w0.s)).ravel()) < 1e-14
+    rhs = w0.rhs[0]
+    x, info, rc = h0.solve(dev(rhs), rtol=1e-12, maxit=w0.n, max_outer=3)
+    assert rc == sv.OK
+    assert rel(host(x), np.linalg.solve(orc0.A_dense(), rhs)) < 1e-9
+    assert info[0]["n_M"] >= 0
+
+
+# ------------------------------------------------------------------ heat equation (§7.2)
+def test_dirichlet_band_model(sv):
+    """The explicit heat-equation step with Dirichlet boundaries (a non-periodic band): the
+    model products, the L_M(k) sweeps, A v, P^{-1} v and the forecast against the oracle's
+    sparse matrix, on a window of the paper's Experiment B recipe."""
+    win = wl.make_expB_window(s=300, N=5, seed=3)
+    for prec, k in (("PI", 3), ("PD", 2)):
+        orc = so.SaddleOracle(win, k=k, rhat="RR")
+        h = sv.Handle([win], sv.Precond(type=prec, k=k, rhat="RR"))
+        X = np.random.default_rng(4).standard_normal((2, win.nb * win.s))
+        for op, fn in {"L": orc.L_apply, "LT": orc.LT_apply, "LHAT_INV": orc.LM_inv,
+                       "LHAT_INVT": orc.LM_invT}.items():
+            out = host(h.apply_op(op, dev(X), 2)).reshape(2, -1)
+            for r in range(2):
+                ref = fn(X[r].reshape(win.nb, win.s)).ravel()
+                assert rel(out[r], ref) < 1e-13, op
+                assert_blocks(win, out[r], ref, 1e-12, space="state", what=op)
+        V = wl.random_vectors(win, 1, seed=5)[0]
+        assert rel(host(h.apply_A(dev(V))), orc.apply_A(V)) < 1e-12
+        assert rel(host(h.apply_P(dev(V))), orc.apply_P_inv(V, prec)) < 1e-10
+    x = win.meta["truth"]
+    fc = host(h.model_forecast(dev(x))).reshape(win.nb, win.s)
+    for i in range(1, win.nb):
+        assert rel(fc[i], orc.model.M(i, x[i - 1])) < 1e-14

@@ -540,3 +540,24 @@ def test_paper_covariance_generators():
     assert np.allclose(R, R.T) and abs(np.linalg.eigvalsh(R)[0] - 0.41) < 1e-12
     shift = R[0, 0] - R[0, 0]  # off-diagonal entries are untouched by the shift
     assert shift == 0 and np.all(R[0:5, 12:16] == 0)
+
+
+# ------------------------------------------------------------------ L_I (§2.2)
+def test_LI_sweeps_and_preconditioner():
+    """L_I's inverse is the block running sum (its transpose the reverse running sum):
+    checked against the assembled L_I, with the model ignored (L_I keeps no model
+    information); P_I and P_D with L_I are symmetric and FGMRES reaches the dense solution."""
+    win = tiny(seed=12)
+    orc = so.SaddleOracle(win, k=2, rhat="RR", lhat="LI")
+    Li = orc.LI_dense()
+    X = np.random.default_rng(3).standard_normal((orc.nb, orc.s))
+    assert np.allclose(Li @ orc.Lhat_inv(X).ravel(), X.ravel(), atol=1e-13)
+    assert np.allclose(Li.T @ orc.Lhat_invT(X).ravel(), X.ravel(), atol=1e-13)
+    assert np.allclose(orc.xspace_dense(orc.Lhat_inv), np.linalg.inv(Li), atol=1e-13)
+    for prec in ("PI", "PD"):
+        Pd = orc.operator_dense(lambda v: orc.apply_P_inv(v, prec))
+        assert np.allclose(Pd, Pd.T, atol=1e-11 * np.abs(Pd).max())
+    rhs = win.rhs[0]
+    out = so.solve(orc, rhs, prec="PI", rtol=1e-12, maxit=orc.n)
+    x_ref = np.linalg.solve(orc.A_dense(), rhs)
+    assert np.linalg.norm(out["x"] - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
