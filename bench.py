@@ -75,6 +75,10 @@ def parse():
                          "N=15, dt=1e-4), B = heat equation (s=10000, N=5); iterations for "
                          "P_D (MINRES) and P_I (FGMRES) over k and Rhat (one JSON object)")
     ap.add_argument("--replay-s", type=int, default=0, help="--replay: state size override")
+    ap.add_argument("--grid", action="store_true",
+                    help="the C2 window with R lengths 0.01, 0.05, 0.2: iterations and time of "
+                         "P_D (MINRES, float64) and P_I (FGMRES, float64 and bfloat16 P "
+                         "products) over k and Rhat (one JSON object)")
     ap.add_argument("--c5", type=int, default=0, metavar="W",
                     help="learned-correction mode: train on C5-shaped windows (s=4096, N=32), "
                          "then solve W held-out windows x 8 rhs batched with and without the "
@@ -86,6 +90,9 @@ def parse():
     ap.add_argument("--block", type=int, default=0,
                     help="s-step FGMRES block size of the batched paths (0: one column at a "
                          "time; with the nonlinear network the block basis stagnates)")
+    ap.add_argument("--block-rhs", type=int, default=0, choices=(0, 1),
+                    help="1: the batched paths run block FGMRES over the 8 right-hand sides of "
+                         "each window (one Krylov space per window)")
     ap.add_argument("--train-windows", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
@@ -168,6 +175,8 @@ def threads_in_use():
 
 def main():
     args = parse()
+    # the library reports long solves on stderr (at most one line every 20 s)
+    os.environ.setdefault("SVAR_PROGRESS", "1")
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no "
                                    "multi-GPU path (independent windows would be placed on "
@@ -183,6 +192,9 @@ def main():
         return
     if args.replay:
         print(json.dumps(bench_replay(args)), flush=True)
+        return
+    if args.grid:
+        print(json.dumps(bench_grid(args)), flush=True)
         return
     if args.c2 or args.sweep:
         bench_c2(args)
@@ -438,7 +450,7 @@ def bench_headline(args):
     setup_s = time.time() - t0
     log(f"batch handle set-up {setup_s:.1f}s")
     rhs_all = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
-    kwb = dict(kw, precision=args.precision, block=args.block)
+    kwb = dict(kw, precision=args.precision, block=args.block, block_rhs=bool(args.block_rhs))
 
     def run(label, attach, classes, steps, warmup):
         h.set_net(attach)
@@ -753,6 +765,42 @@ def bench_c5(args):
                            out["plain_batched"]["solves_per_s"])
     log(res)
     return res
+
+
+def bench_grid(args):
+    """The C2 window (s = 4096, N = 64, p = 2048) for R lengths 0.01, 0.05 and 0.2 (SOAR,
+    reconditioned to kappa <= 1724 where worse): iterations, true residual and time per solve
+    of P_D with MINRES (float64) and P_I with FGMRES (float64, and with bfloat16 copies of the
+    covariance matrices in P: FP64_BF16P) for k in {1, 3, N + 1} and every Rhat kind."""
+    import torch
+
+    from paper_2105_06975_amd import svar, workloads as wl
+    rows = []
+    for rl in (0.01, 0.05, 0.2):
+        win = wl.make_config_window("c2", seed=0, r_len=rl)
+        rhs = torch.from_numpy(np.ascontiguousarray(win.rhs[0])).cuda()
+        log(f"R length {rl}: recondition shift {win.meta['r_shift']:.3e}")
+        for ptype in ("PD", "PI"):
+            for rh in ("DIAG", "RR", "ME", "EXACT"):
+                for k in (1, 3, win.N + 1):
+                    h = svar.Handle([win], svar.Precond(type=ptype, k=k, rhat=rh))
+                    precs = ("FP64",) if ptype == "PD" else ("FP64", "FP64_BF16P")
+                    for pr in precs:
+                        kw = dict(rtol=args.rtol, maxit=3000, precision=pr)
+                        if ptype == "PD":
+                            kw["method"] = "MINRES"
+                        h.solve(rhs, **dict(kw, maxit=2))
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        _, info, rc = h.solve(rhs, **kw)
+                        torch.cuda.synchronize()
+                        row = dict(r_len=rl, prec=ptype, rhat=rh, k=k, precision=pr, rc=rc,
+                                   iters=info[0]["iters"], relres=info[0]["relres_true"],
+                                   ms=1e3 * (time.perf_counter() - t))
+                        rows.append(row)
+                        log(row)
+                    h.close()
+    return {"grid": rows, "workload": "c2 window, R length sweep", "rtol": args.rtol}
 
 
 def sweep(win, rhs, args):

@@ -165,7 +165,9 @@ typedef struct svar_solve_opts {
   /* learned path (a network attached with svar_set_net): a FGMRES step fails when the
      least-squares residual does not fall below (1 - fallback_drop) times the previous one;
      after fallback_patience failing steps in a row the system's later preconditioner
-     applications skip the network (the plain P).  fallback_drop <= 0 disables the check. */
+     applications skip the network (the plain P).  With block_rhs the test runs per window on
+     the two norm of its columns' residuals and switches the whole window.  fallback_drop <= 0
+     disables the check. */
   double fallback_drop;
   /* training-pair harvest: when non-NULL, the state component v3 of the preconditioner input
      of each FGMRES step j < harvest_cap is copied to harvest + j * state_len (device memory,
@@ -210,6 +212,18 @@ typedef struct svar_solve_opts {
      its windows; results equal those of one call up to the rounding order of the reductions.
      Not with harvest; MINRES always runs in one wave. */
   int64_t wave_len;
+  /* block FGMRES over the right-hand sides (FGMRES, nrhs <= 8, block < 2, no harvest): 1 runs
+     the nrhs systems of each window as one block -- the residuals are factorised R_0 = V_0 S_0,
+     every step applies P and A to the nrhs columns of the newest basis block, orthogonalises
+     the products against the basis (two block classical Gram-Schmidt passes) and within
+     themselves (two Cholesky QR rounds), and the shared block Hessenberg matrix gives each
+     column its own least-squares solution and residual estimate.  A window's cycle ends when
+     every column meets its tolerance (its systems all stop together), when the basis is full,
+     or when a new block loses rank (then the float64 restart continues).  Rank loss in the
+     starting block (zero or equal residuals) puts seeded random directions in the basis.
+     iters counts block steps (one P and one A product per system each).  Cycles hold at most
+     7424 / nrhs^2 - 1 block steps (115 for 8 columns).  0: one Krylov space per system. */
+  int32_t block_rhs;
 } svar_solve_opts;
 
 typedef struct svar_solve_info {   /* one per (window, right-hand side), packed order     */

@@ -104,6 +104,63 @@ void kb_trsm(int B, const KPlan& p, const KState* stt, const KGlobal* gl, double
 void kb_hess(int B, const KPlan& p, KState* stt, KGlobal* gl, const double* S1, const double* S2,
              int SLB, const KBlock* kb, KHess* hs, int m, int j, int b, int* net_off,
              double drop, int patience, HistArg hist, hipStream_t st);
+// FGMRES over the right-hand sides of a window as one block (k_bkr.hip); P <= KBR_MAX columns
+#define KBR_MAX 8
+// block steps per cycle: the Hessenberg step and the update keep P^2 (m + 1) doubles in LDS
+#define KBR_MAX_CYCLE(P) (7424 / ((P) * (P)) - 1)
+#define KBR_TASK 1024   // rows of a window per task of the block passes (256 threads x 4)
+struct KBRTask {        // rows [e0, e1) of window `win` (row offsets inside the window)
+  int32_t win, pad;
+  int64_t off, n;       // packed offset of the window's first column, rows per column
+  int64_t e0, e1;
+};
+struct KBRWin {         // per window, per cycle
+  int32_t task0, ntask;
+  int32_t done;         // the window's cycle has ended (converged, basis full, breakdown)
+  int32_t bad;          // non-finite Gram matrix: breakdown
+  int32_t steps;        // block steps taken in this cycle
+  int32_t zmask;        // columns of the current block deflated (numerically dependent)
+  int32_t rmask;        // deflated columns of the starting block replaced by random vectors
+  int32_t cut;          // a new block lost rank: the cycle ends after this step
+  int32_t stall, pad;   // learned path: consecutive steps that failed the decrease test
+  double prev;          // learned path: the block's residual norm after the previous step
+  double Fr[KBR_MAX * KBR_MAX];  // the current Cholesky QR round's factor (row major, upper)
+  double Ft[KBR_MAX * KBR_MAX];  // product of the rounds' factors
+};
+struct KBRHess {        // per window (device pointers), P = the block width
+  double* H;            // (m+1) P x m P, column major (column q at q (m+1) P)
+  double* cs;           // m P x P rotations: rotation k of column q at q P + k
+  double* sn;
+  double* G;            // (m+1) P x P right-hand sides of the least-squares problems
+  double* Y;            // m P x P solutions
+};
+struct KBRPlan {
+  KBRTask* tasks = nullptr;
+  int ntask = 0, nwin = 0;
+};
+// the block passes (see k_bkr.hip): SLP / SLS are the strides of the per-task partial sums
+// and the per-window sums
+void bkr_reset(const KBRPlan& p, KBRWin* wins, hipStream_t st);
+void bkr_dot(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64_t lda, int na,
+             const double* Wb, double* part, int SLP, hipStream_t st);
+void bkr_reduce(const KBRPlan& p, const KBRWin* wins, const double* part, int SLP, int nv,
+                double* sums, int SLS, hipStream_t st);
+void bkr_update(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64_t lda,
+                int na, double* Wb, const double* C, int SLS, double sgn, int final_x,
+                hipStream_t st);
+void bkr_chol(int P, const KBRPlan& p, KBRWin* wins, const double* G, int SLS, int round,
+              int start, hipStream_t st);
+void bkr_trsm(int P, const KBRPlan& p, const KBRWin* wins, double* Wb, hipStream_t st);
+void bkr_start(int P, const KBRPlan& p, KBRWin* wins, KBRHess* hs, KState* stt,
+               const double* tol_rel, const double* G0, int SLS, int m, KGlobal* gl,
+               hipStream_t st);
+void bkr_hess(int P, const KBRPlan& p, KBRWin* wins, KBRHess* hs, KState* stt, const double* C1,
+              const double* C2, int SLS, int j, int m, int* net_off, double drop, int patience,
+              HistArg hist, hipStream_t st);
+void bkr_solve_y(int P, const KBRPlan& p, const KBRWin* wins, const KBRHess* hs, int m,
+                 double* Yl, int SLS, hipStream_t st);
+void bkr_flags(int P, const KBRPlan& p, const KBRWin* wins, KGlobal* gl, int* flags,
+               int* net_off, hipStream_t st);
 // workgroups of the Gram-Schmidt passes resident on the current device at once (both passes:
 // the smaller of the two), 0 if the runtime cannot tell
 int kr_resident_tasks();

@@ -141,6 +141,7 @@ struct svar_handle {
   // the parent's matrices, model tables and zero buffer, and builds its own launch programs);
   // the views carve their basis vectors from the parent's arena, sized for the largest wave
   svar_handle* parent = nullptr;  // set on a view
+  int view_w0 = 0;                // a view's first window in its parent
   std::map<std::pair<int, int>, svar_handle*> views;  // owned, by window range [w0, w1)
   double* arena = nullptr;
   int64_t arena_elems = 0;
@@ -168,6 +169,15 @@ struct svar_handle {
     double *bpart = nullptr, *bs1 = nullptr, *bs2 = nullptr, *gpart = nullptr, *gsum = nullptr;
     svar::KBlock* kb = nullptr;
     int slb = 0;
+    // block FGMRES over the right-hand sides (allocated on first use): row tasks, per-window
+    // states and Hessenberg storage, partial sums (stride br_slp per task), per-window sums
+    // (stride br_sls): the two projections, the Gram matrices of the QR rounds, Y
+    svar::KBRPlan br;
+    svar::KBRWin* br_wins = nullptr;
+    svar::KBRHess* br_hs = nullptr;
+    double *br_part = nullptr, *br_c1 = nullptr, *br_c2 = nullptr, *br_g0 = nullptr;
+    double *br_g1 = nullptr, *br_yl = nullptr, *br_hbuf = nullptr;
+    int br_slp = 0, br_sls = 0;
     std::vector<void*> allocs;
   } kry;
 };

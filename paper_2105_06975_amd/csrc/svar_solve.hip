@@ -7,7 +7,11 @@
 // with the mixed precisions the inner operators use float32 / bfloat16 covariance products
 // while the Arnoldi basis, Hessenberg least squares and residual checks stay float64.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <limits>
 
 #include "mem.h"
@@ -274,6 +278,27 @@ static int step_graph(svar_handle* h, int nrhs, int m, const Program& PA, const 
   return SVAR_OK;
 }
 
+// Progress lines on stderr for long solves (environment SVAR_PROGRESS=1): at most one every
+// 20 s, from the convergence checks of the FGMRES cycles.
+static bool progress_on() {
+  static const int on = [] {
+    const char* e = std::getenv("SVAR_PROGRESS");
+    return e && e[0] == '1' ? 1 : 0;
+  }();
+  return on != 0;
+}
+static void progress_line(const svar_handle* h, int j, int remaining) {
+  using clk = std::chrono::steady_clock;
+  static clk::time_point last = clk::now();
+  const clk::time_point now = clk::now();
+  if (std::chrono::duration<double>(now - last).count() < 20.0) return;
+  last = now;
+  const int w0 = h->view_w0;
+  std::fprintf(stderr, "svar: windows %d..%d, cycle step %d, %d systems still iterating\n", w0,
+               w0 + (int)h->wins.size() - 1, j, remaining);
+  std::fflush(stderr);
+}
+
 static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, const Program& PP,
                         const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
                         double drop, int patience, Harvest& hv, bool use_graph, HistArg hist,
@@ -326,6 +351,7 @@ static int fgmres_cycle(svar_handle* h, int nrhs, int m, const Program& PA, cons
       }
       if (pend >= 0) {
         SVAR_HIP(hipEventSynchronize(K.gl_ev[pend]));
+        if (progress_on()) progress_line(h, j, K.gl_host[pend].remaining);
         if (K.gl_host[pend].all_done) {
           all_done = true;
           break;
@@ -443,6 +469,146 @@ static int block_cycle(svar_handle* h, int m, int s, const Program& PA, const Pr
   return SVAR_OK;
 }
 
+// Block FGMRES over the right-hand sides: tasks of KBR_TASK rows per window, per-window states
+// and Hessenberg storage for cycles of K.m - 1 block steps.
+static int ensure_br(svar_handle* h, hipStream_t st) {
+  auto& K = h->kry;
+  if (K.br_wins) return SVAR_OK;
+  const int P = K.nrhs, m = K.m - 1, nw = (int)h->wins.size();
+  std::vector<KBRTask> tasks;
+  std::vector<KBRWin> wins(nw);
+  int64_t off = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int64_t n = h->wins[w].n;
+    std::memset(&wins[w], 0, sizeof(KBRWin));
+    wins[w].task0 = (int)tasks.size();
+    for (int64_t e = 0; e < n; e += KBR_TASK) {
+      KBRTask t{};
+      t.win = w;
+      t.off = off;
+      t.n = n;
+      t.e0 = e;
+      t.e1 = std::min<int64_t>(n, e + KBR_TASK);
+      tasks.push_back(t);
+    }
+    wins[w].ntask = (int)tasks.size() - wins[w].task0;
+    off += (int64_t)P * n;
+  }
+  auto& A = K.allocs;
+  K.br_slp = std::max(m, 1) * P * P;
+  K.br_sls = K.br_slp;
+  SVAR_TRY(dalloc(A, &K.br.tasks, tasks.size()));
+  SVAR_TRY(dalloc(A, &K.br_wins, (size_t)nw));
+  SVAR_HIP(hipMemcpyAsync(K.br.tasks, tasks.data(), tasks.size() * sizeof(KBRTask),
+                          hipMemcpyHostToDevice, st));
+  SVAR_HIP(hipMemcpyAsync(K.br_wins, wins.data(), nw * sizeof(KBRWin), hipMemcpyHostToDevice, st));
+  K.br.ntask = (int)tasks.size();
+  K.br.nwin = nw;
+  SVAR_TRY(dalloc(A, &K.br_part, (size_t)K.br.ntask * K.br_slp));
+  for (double** b : {&K.br_c1, &K.br_c2, &K.br_g0, &K.br_g1, &K.br_yl})
+    SVAR_TRY(dalloc(A, b, (size_t)nw * K.br_sls));
+  const int64_t ld = (int64_t)(m + 1) * P, mp = (int64_t)m * P;
+  const int64_t per = ld * mp + 2 * mp * P + ld * P + mp * P;
+  SVAR_TRY(dalloc(A, &K.br_hbuf, (size_t)(per * nw)));
+  std::vector<KBRHess> hs(nw);
+  for (int w = 0; w < nw; ++w) {
+    double* q = K.br_hbuf + per * w;
+    hs[w].H = q;
+    q += ld * mp;
+    hs[w].cs = q;
+    q += mp * P;
+    hs[w].sn = q;
+    q += mp * P;
+    hs[w].G = q;
+    q += ld * P;
+    hs[w].Y = q;
+  }
+  SVAR_TRY(dalloc(A, &K.br_hs, (size_t)nw));
+  SVAR_HIP(hipMemcpyAsync(K.br_hs, hs.data(), nw * sizeof(KBRHess), hipMemcpyHostToDevice, st));
+  SVAR_HIP(hipStreamSynchronize(st));
+  return SVAR_OK;
+}
+
+// One cycle of at most m block steps over the right-hand sides of every window (basis slots
+// V[0..m], Z[0..m-1], each holding the whole batch): QR of the residual block, then per step
+// Z_j = P^{-1} V_j, W = A Z_j, two block Gram-Schmidt passes, two Cholesky QR rounds and the
+// Hessenberg step; the host reads the all-done flag every GRAPH_STEPS steps, one check late.
+static int br_cycle(svar_handle* h, int m, const Program& PA, const Program& PP,
+                    const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
+                    double drop, int patience, HistArg hist, hipStream_t st) {
+  int* net_off = h->net_off ? h->kry.net_off : nullptr;
+  SVAR_TRY(ensure_br(h, st));
+  auto& K = h->kry;
+  const int P = K.nrhs;
+  const KBRPlan& B = K.br;
+  const int SLP = K.br_slp, SLS = K.br_sls;
+  const int* skip = &K.gl->all_done;
+  SVAR_HIP(hipMemcpyAsync(K.tol_rel, tol_rel.data(), tol_rel.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+  bkr_reset(B, K.br_wins, st);
+  double* V0 = K.V;
+  SVAR_HIP(hipMemcpyAsync(V0, K.r, K.ntot * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double* gram[2] = {K.br_g0, K.br_g1};
+  auto qr = [&](double* Wb, int start) {
+    for (int round = 0; round < 2; ++round) {
+      bkr_dot(P, B, K.br_wins, Wb, K.ldv, 1, Wb, K.br_part, SLP, st);
+      bkr_reduce(B, K.br_wins, K.br_part, SLP, P * P, gram[round], SLS, st);
+      bkr_chol(P, B, K.br_wins, gram[round], SLS, round, start, st);
+      bkr_trsm(P, B, K.br_wins, Wb, st);
+    }
+  };
+  qr(V0, 1);
+  bkr_start(P, B, K.br_wins, K.br_hs, K.st, K.tol_rel, K.br_g0, SLS, m, K.gl, st);
+  bkr_flags(P, B, K.br_wins, K.gl, K.flags, net_off, st);
+  int pend = -1, slot = 0;
+  for (int j = 0; j < m; ++j) {
+    double* Vj = K.V + (int64_t)j * K.ldv;
+    double* Zj = K.Z + (int64_t)j * K.ldv;
+    double* Wn = K.V + (int64_t)(j + 1) * K.ldv;
+    SVAR_TRY(run_program(h, PP, Vj, Zj, st, skip, K.flags));
+    SVAR_TRY(run_program(h, PA, Zj, Wn, st, skip, K.flags));
+    double* C[2] = {K.br_c1, K.br_c2};
+    for (int pass = 0; pass < 2; ++pass) {
+      hipEvent_t e0, e1;
+      timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+      bkr_dot(P, B, K.br_wins, K.V, K.ldv, j + 1, Wn, K.br_part, SLP, st);
+      timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+      bkr_reduce(B, K.br_wins, K.br_part, SLP, (j + 1) * P * P, C[pass], SLS, st);
+      timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
+      bkr_update(P, B, K.br_wins, K.V, K.ldv, j + 1, Wn, C[pass], SLS, -1.0, 0, st);
+      timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
+    }
+    qr(Wn, 0);
+    bkr_hess(P, B, K.br_wins, K.br_hs, K.st, K.br_c1, K.br_c2, SLS, j, m, net_off, drop,
+             patience, hist, st);
+    bkr_flags(P, B, K.br_wins, K.gl, K.flags, net_off, st);
+    if ((j + 1) % GRAPH_STEPS == 0 && j + 1 < m) {
+      KGlobal* hb = K.gl_host + slot;
+      SVAR_HIP(hipMemcpyAsync(hb, K.gl, sizeof(KGlobal), hipMemcpyDeviceToHost, st));
+      SVAR_HIP(hipEventRecord(K.gl_ev[slot], st));
+      if (pend >= 0) {
+        SVAR_HIP(hipEventSynchronize(K.gl_ev[pend]));
+        if (progress_on()) progress_line(h, j + 1, K.gl_host[pend].remaining * P);
+        if (K.gl_host[pend].all_done) break;
+      }
+      pend = slot;
+      slot ^= 1;
+    }
+  }
+  bkr_solve_y(P, B, K.br_wins, K.br_hs, m, K.br_yl, SLS, st);
+  bkr_update(P, B, K.br_wins, K.Z, K.ldv, m, x, K.br_yl, SLS, 1.0, 1, st);
+  out.resize(K.plan.nsys);
+  SVAR_HIP(hipMemcpyAsync(out.data(), K.st, K.plan.nsys * sizeof(KState), hipMemcpyDeviceToHost,
+                          st));
+  SVAR_HIP(hipStreamSynchronize(st));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("Krylov kernel failed: ") + hipGetErrorString(e));
+    return SVAR_E_HIP;
+  }
+  return SVAR_OK;
+}
+
 static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, const double* rhs,
                         double* x, svar_solve_info* info, hipStream_t st) {
   const int nsys = (int)h->wins.size() * nrhs;
@@ -451,11 +617,15 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   // block mode (s-step) when block >= 2; its cycles hold at most KB_MAX_CYCLE
   // columns (LDS of the Hessenberg step) and use basis slots 0..m
   const int blk = o->block >= 2 ? std::min((int)o->block, KB_MAX) : 0;
-  const int cap = blk ? KB_MAX_CYCLE : KR_MAX_CYCLE;
+  const bool brhs = o->block_rhs != 0;
+  const int cap = brhs ? KBR_MAX_CYCLE(nrhs) : (blk ? KB_MAX_CYCLE : KR_MAX_CYCLE);
   int cyc = o->restart > 0 ? std::min(o->restart, o->maxit) : o->maxit;
   cyc = std::min(cyc, cap);
   if (cyc < 1) return inval_msg("maxit must be >= 1");
-  SVAR_TRY(ensure_krylov(h, nrhs, blk ? cyc + 1 : cyc, st));
+  // the workspace holds a full restart cycle even when maxit is smaller, so that a short first
+  // call builds what later calls with the same restart use
+  const int ws_m = o->restart > 0 ? std::min((int)o->restart, cap) : cyc;
+  SVAR_TRY(ensure_krylov(h, nrhs, (blk || brhs) ? ws_m + 1 : ws_m, st));
   auto& K = h->kry;
   // inner operators: FP64_F32P / FP64_BF16P keep A in float64 (no refinement needed: under flexible GMRES
   // the preconditioner's rounding changes only the convergence rate, not the attainable
@@ -544,10 +714,12 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     if (hist.h)
       SVAR_HIP(hipMemcpyAsync(K.it0, iters.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
     {
-      const int rc = blk ? block_cycle(h, m, blk, *Ain, *Pin, tol, x, ks, drop,
-                                       o->fallback_patience, hv, hist, st)
-                         : fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
-                                        o->fallback_patience, hv, o->use_graph != 0, hist, st);
+      const int rc = brhs  ? br_cycle(h, m, *Ain, *Pin, tol, x, ks, drop, o->fallback_patience,
+                                      hist, st)
+                     : blk ? block_cycle(h, m, blk, *Ain, *Pin, tol, x, ks, drop,
+                                         o->fallback_patience, hv, hist, st)
+                           : fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
+                                          o->fallback_patience, hv, o->use_graph != 0, hist, st);
       if (rc != SVAR_OK) {
         h->net_off = nullptr;
         return rc;
@@ -555,7 +727,9 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     }
     int jmax = 0;
     for (int i = 0; i < nsys; ++i) {
-      if (tol[i] >= 1.0) continue;
+      // a block over the right-hand sides carries a window's converged columns along: they
+      // take the window's steps (one P and one A product each)
+      if (tol[i] >= 1.0 && !(brhs && ks[i].iters > 0)) continue;
       iters[i] += ks[i].iters;
       cycles[i] += 1;
       fallbacks[i] = std::max(fallbacks[i], (int)ks[i].fallback);
@@ -630,6 +804,7 @@ int get_view(svar_handle* h, int w0, int w1, svar_handle** out) {
   v->net = h->net;
   v->tune = h->tune;
   v->parent = h;
+  v->view_w0 = w0;
   h->views[{w0, w1}] = v;
   *out = v;
   return SVAR_OK;
@@ -667,6 +842,35 @@ static int plan_waves(svar_handle* h, const svar_solve_opts* o, int nrhs, int m,
   return SVAR_OK;
 }
 
+// Views that the current wave plan does not use are destroyed (their launch programs and Krylov
+// buffers); with a single wave the arena goes too, since the handle then solves in its own
+// workspace and the plan counted the arena as free memory.
+static int drop_views(svar_handle* h, const std::vector<std::pair<int, int>>& waves,
+                      hipStream_t st) {
+  const bool single = waves.size() <= 1;
+  bool sync = false;
+  for (auto it = h->views.begin(); it != h->views.end();) {
+    const bool used = !single && std::find(waves.begin(), waves.end(), it->first) != waves.end();
+    if (used) {
+      ++it;
+      continue;
+    }
+    if (!sync) {
+      SVAR_HIP(hipStreamSynchronize(st));
+      sync = true;
+    }
+    svar_destroy(it->second);
+    it = h->views.erase(it);
+  }
+  if (single && h->arena) {
+    if (!sync) SVAR_HIP(hipStreamSynchronize(st));
+    (void)hipFree(h->arena);
+    h->arena = nullptr;
+    h->arena_elems = 0;
+  }
+  return SVAR_OK;
+}
+
 static int solve_waves(svar_handle* h, const svar_solve_opts* o, int nrhs, const double* rhs,
                        double* x, svar_solve_info* info, hipStream_t st, int m,
                        const std::vector<std::pair<int, int>>& waves) {
@@ -677,6 +881,12 @@ static int solve_waves(svar_handle* h, const svar_solve_opts* o, int nrhs, const
   // the arena holds the largest wave's basis and work vectors
   int64_t need = 0;
   for (const auto& wv : waves) need = std::max(need, kry_big_elems(off[wv.second] - off[wv.first], m));
+  if (h->kry.nrhs > 0) {  // the handle's own single-wave workspace is not needed in waves
+    SVAR_HIP(hipStreamSynchronize(st));
+    free_all(h->kry.allocs);
+    h->kry.nrhs = -1;
+    ++h->kry_gen;
+  }
   if (need > h->arena_elems) {
     SVAR_HIP(hipStreamSynchronize(st));
     for (auto& kv : h->views) {  // their carves point into the old arena
@@ -687,10 +897,6 @@ static int solve_waves(svar_handle* h, const svar_solve_opts* o, int nrhs, const
     if (h->arena) (void)hipFree(h->arena);
     h->arena = nullptr;
     h->arena_elems = 0;
-    // the handle's own single-wave workspace is not needed while solving in waves
-    free_all(h->kry.allocs);
-    h->kry.nrhs = -1;
-    ++h->kry_gen;
     if (hipMalloc((void**)&h->arena, (size_t)need * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
       h->arena = nullptr;
@@ -733,15 +939,23 @@ extern "C" int svar_solve(svar_handle* h, const svar_solve_opts* o, int32_t nrhs
   if (!prec_valid(o->precision)) return inval_msg("bad precision");
   hipStream_t st = (hipStream_t)stream;
   if (o->wave_len < 0) return inval_msg("wave_len must be >= 0");
+  if (o->block_rhs != 0) {
+    if (o->method != SVAR_METHOD_FGMRES) return inval_msg("block_rhs needs FGMRES");
+    if (nrhs > KBR_MAX) return inval_msg("block_rhs takes at most 8 right-hand sides");
+    if (o->block >= 2) return inval_msg("block_rhs and block (s-step) exclude each other");
+    if (o->harvest && o->harvest_cap > 0) return inval_msg("block_rhs does not harvest");
+  }
   if (o->method == SVAR_METHOD_FGMRES) {
     // basis slots of one cycle, as in solve_fgmres
     const int blk = o->block >= 2 ? std::min((int)o->block, KB_MAX) : 0;
-    const int cap = blk ? KB_MAX_CYCLE : KR_MAX_CYCLE;
-    int cyc = o->restart > 0 ? std::min(o->restart, o->maxit) : o->maxit;
-    cyc = std::min(cyc, cap);
+    const bool brhs = o->block_rhs != 0;
+    const int cap = brhs ? KBR_MAX_CYCLE(nrhs) : (blk ? KB_MAX_CYCLE : KR_MAX_CYCLE);
+    int cyc = o->restart > 0 ? std::min(o->restart, cap) : std::min(o->maxit, cap);
+    const int slots = (blk || brhs) ? cyc + 1 : cyc;
     std::vector<std::pair<int, int>> waves;
-    if (h->wins.size() > 1) SVAR_TRY(plan_waves(h, o, nrhs, blk ? cyc + 1 : cyc, waves));
-    if (waves.size() > 1) return solve_waves(h, o, nrhs, rhs, x, info, st, blk ? cyc + 1 : cyc, waves);
+    if (h->wins.size() > 1) SVAR_TRY(plan_waves(h, o, nrhs, slots, waves));
+    SVAR_TRY(drop_views(h, waves, st));
+    if (waves.size() > 1) return solve_waves(h, o, nrhs, rhs, x, info, st, slots, waves);
     return solve_fgmres(h, o, nrhs, rhs, x, info, st);
   }
   if (o->method == SVAR_METHOD_MINRES) {

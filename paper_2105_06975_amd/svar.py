@@ -66,7 +66,7 @@ class SolveOpts(C.Structure):
                 ("harvest", C.c_void_p), ("harvest_cap", C.c_int32),
                 ("fallback_patience", C.c_int32), ("use_graph", C.c_int32), ("block", C.c_int32),
                 ("minres_norm", C.c_int32), ("history", C.c_void_p), ("history_len", C.c_int32),
-                ("wave_len", C.c_int64)]
+                ("wave_len", C.c_int64), ("block_rhs", C.c_int32)]
 
 
 class NetDesc(C.Structure):
@@ -331,7 +331,8 @@ class Handle:
     def solve(self, rhs, nrhs: int = 1, *, method="FGMRES", rtol=1e-6, maxit=1000, restart=0,
               precision="FP64", inner_rtol=1e-4, max_outer=1, x=None, stream=None,
               check=False, fallback_drop=1e-3, fallback_patience=3, harvest=None,
-              graph=False, block=0, minres_norm="2", history=None, wave_len=0):
+              graph=False, block=0, minres_norm="2", history=None, wave_len=0,
+              block_rhs=False):
         """Solve A x = rhs; returns (x, [info dicts], status).
 
         harvest: optional float64 device tensor of shape (cap, state_len): receives the state
@@ -341,6 +342,7 @@ class Handle:
         history: optional float64 device tensor (nsys, len): residual-norm estimate per iteration.
         wave_len: FGMRES over windows in contiguous waves of at most this packed length (0: from
         the free device memory).
+        block_rhs: block FGMRES over the nrhs (<= 8) right-hand sides of each window.
         """
         import torch
         x = torch.empty_like(rhs) if x is None else x
@@ -351,7 +353,8 @@ class Handle:
         o = SolveOpts(METHOD[method], float(rtol), int(maxit), int(restart), PRECISION[precision],
                       float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap,
                       int(fallback_patience), 1 if graph else 0, int(block),
-                      {"2": 0, "P": 1}[minres_norm], hp, hl, int(wave_len))
+                      {"2": 0, "P": 1}[minres_norm], hp, hl, int(wave_len),
+                      1 if block_rhs else 0)
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))
