@@ -85,14 +85,16 @@ def parse():
                          "network against every system one at a time in plain FP64")
     ap.add_argument("--tune-cache", default=None, help="JSON file for the GEMM autotuning cache")
     ap.add_argument("--nrhs", type=int, default=8)
-    ap.add_argument("--precision", default="FP64_F32P",
-                    help="precision of the learned + batched path")
+    ap.add_argument("--precision", default="MIXED_F32",
+                    help="precision of the batched paths (MIXED_F32: float32 covariance "
+                         "products in A and P inside the float64 restart loop)")
     ap.add_argument("--block", type=int, default=0,
                     help="s-step FGMRES block size of the batched paths (0: one column at a "
                          "time; with the nonlinear network the block basis stagnates)")
-    ap.add_argument("--block-rhs", type=int, default=0, choices=(0, 1),
-                    help="1: the batched paths run block FGMRES over the 8 right-hand sides of "
-                         "each window (one Krylov space per window)")
+    ap.add_argument("--block-rhs", type=int, default=2, choices=(0, 1, 2),
+                    help="the batched paths run block FGMRES over the 8 right-hand sides of "
+                         "each window (one Krylov space per window) with 2 (1) or 1 (2) "
+                         "Gram-Schmidt passes per step; 0: one Krylov space per system")
     ap.add_argument("--train-windows", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
@@ -137,7 +139,7 @@ def gemm_flops(win, iters, applies_a64):
 NET_FLOP_PER_POINT = 2 * (5 * 32 * 64 + 2 * 5 * 64 * 64 + 5 * 64)  # 103,040 (padded layer 1)
 
 
-def batch_work(wins, infos, nrhs, restart):
+def batch_work(wins, infos, nrhs, restart, block_rhs=0, precision="FP64_F32P"):
     """Algorithmic work of a batched solve from its per-system iteration counts.
 
     Covariance products (flops): a window's products run while any of its right-hand sides
@@ -145,22 +147,36 @@ def batch_work(wins, infos, nrhs, restart):
     end): per step 2 (s^2 + p^2)(N+1) nrhs float64 (D z1, R) and 2 p^2 (N+1) nrhs float32
     (Rhat^{-1}); per check 2 (s^2 + p^2)(N+1) nrhs float64.  Gram-Schmidt bytes per system:
     step t of a cycle (j = t mod restart) reads j basis vectors twice plus u, w, z and
-    writes Z_j, v_j, u: (2 j + 9) 8 n.  Network flops: NET_FLOP_PER_POINT per grid point of
-    every active system's state per step."""
+    writes Z_j, v_j, u: (2 j + 9) 8 n.  Block mode over the rhs (block_rhs = 1: two passes,
+    2: one pass) per window and block step j: each pass reads the j + 1 basis blocks twice (the
+    projections and the update) and the new block three times (read twice, written once):
+    passes (2 j + 5) nrhs 8 n.  Network flops: NET_FLOP_PER_POINT per grid point of every
+    active system's state per step."""
     f64 = f32 = gsb = net = 0.0
     for w, win in enumerate(wins):
         inf = infos[w * nrhs:(w + 1) * nrhs]
         s, nb, p = win.s, win.nb, int(win.p[0])
         steps = max(i["iters"] for i in inf)
         checks = max(i["outer"] for i in inf) + 1
-        f64 += (steps + checks) * 2.0 * (s * s + p * p) * nb * nrhs
-        f32 += steps * 2.0 * p * p * nb * nrhs
+        if precision == "MIXED_F32":   # every inner product float32, the checks float64
+            f64 += checks * 2.0 * (s * s + p * p) * nb * nrhs
+            f32 += steps * 2.0 * (s * s + 2 * p * p) * nb * nrhs
+        else:
+            f64 += (steps + checks) * 2.0 * (s * s + p * p) * nb * nrhs
+            f32 += steps * 2.0 * p * p * nb * nrhs
+        if block_rhs:
+            passes = 2 if block_rhs == 1 else 1
+            full, rem = divmod(steps, restart) if restart > 0 else (0, steps)
+            m = restart if restart > 0 else steps
+            per = lambda J: sum(passes * (2 * j + 5) for j in range(J))
+            gsb += (full * per(m) + per(rem)) * nrhs * 8.0 * win.n
         for i in inf:
             it = i["iters"]
-            full, rem = divmod(it, restart) if restart > 0 else (0, it)
-            m = restart if restart > 0 else it
-            per_cycle = sum(2 * j + 9 for j in range(m))
-            gsb += (full * per_cycle + sum(2 * j + 9 for j in range(rem))) * 8.0 * win.n
+            if not block_rhs:
+                full, rem = divmod(it, restart) if restart > 0 else (0, it)
+                m = restart if restart > 0 else it
+                per_cycle = sum(2 * j + 9 for j in range(m))
+                gsb += (full * per_cycle + sum(2 * j + 9 for j in range(rem))) * 8.0 * win.n
             net += it * float(NET_FLOP_PER_POINT) * nb * s
     return dict(gemm_f64=f64, gemm_f32=f32, ortho_bytes=gsb, net_flops=net)
 
@@ -450,7 +466,7 @@ def bench_headline(args):
     setup_s = time.time() - t0
     log(f"batch handle set-up {setup_s:.1f}s")
     rhs_all = torch.from_numpy(np.concatenate([w.rhs.reshape(-1) for w in wins])).cuda()
-    kwb = dict(kw, precision=args.precision, block=args.block, block_rhs=bool(args.block_rhs))
+    kwb = dict(kw, precision=args.precision, block=args.block, block_rhs=args.block_rhs)
 
     def run(label, attach, classes, steps, warmup):
         h.set_net(attach)
@@ -491,16 +507,24 @@ def bench_headline(args):
         "value": lb["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (Krylov, A, D z1, R) + f32 (Rhat^-1 products) + bf16 (network)",
+        "dtype": {"MIXED_F32": "f64 (Krylov basis, least squares, restart residuals, model "
+                               "products, sweeps) + f32 (every covariance product, MFMA) + bf16 "
+                               "(network)",
+                  "FP64_F32P": "f64 (Krylov, A, D z1, R) + f32 (Rhat^-1 products) + bf16 "
+                               "(network)"}.get(args.precision, args.precision + " + bf16 (network)"),
         "data": "synthetic",
         "config": {"workload": "c4 batch: %d uneven advection-diffusion windows (s~U{256..4096}, "
                                "N~U{8..64}, p=floor(s f), f~U[1/8,1/2]) x %d perturbed-"
                                "observation rhs; SOAR B l=0.1, Q=0.1B, SOAR R l=0.05; P_I with "
-                               "L_M(%d) and R_RR; FGMRES(%d) to a true relative residual of %g"
-                               % (len(wins), nrhs, args.k, m, args.rtol),
+                               "L_M(%d) and R_RR; %sFGMRES(%d) to a true relative residual of %g"
+                               % (len(wins), nrhs, args.k, "block-over-rhs " if args.block_rhs
+                                  else "", m, args.rtol),
                    "windows": len(wins), "nrhs": nrhs, "systems": nsys, "unknowns": int(ntot),
                    "restart": m, "path": "learned + batched: all systems per call in waves, "
-                   "network correction of the Lhat^-T sweep (bf16 MFMA), %s" % args.precision},
+                   "%snetwork correction of the Lhat^-T sweep (bf16 MFMA), %s"
+                   % ("one block Krylov space per window over its %d rhs (block FGMRES, "
+                      "restart %d block steps), " % (nrhs, m) if args.block_rhs else "",
+                      args.precision)},
         "speedup_vs_plain_fp64": lb["value"] / sps_plain,
         "plain_fp64": {"value": sps_plain, "unit": "solves/s", "systems": ns,
                        "iters_mean": float(np.mean(its1)), "ms_per_solve": 1e3 * one_t / ns,
@@ -514,7 +538,7 @@ def bench_headline(args):
         "setup_s": setup_s, "workload_s": t_work,
     }
     # ---- roofline of the class with the largest time in the timed region
-    wk = batch_work(wins, infos_lb, nrhs, m)
+    wk = batch_work(wins, infos_lb, nrhs, m, args.block_rhs, args.precision)
     wk = {k: v * args.steps for k, v in wk.items()}
     kt = {k: tm[k][0] for k in classes}
     res["kernel_time_ms"] = {k.lower(): kt[k] for k in classes}
@@ -523,7 +547,9 @@ def bench_headline(args):
     top = max(("GEMM", "ORTHO", "NET"), key=lambda k: kt[k])
     if top == "ORTHO":
         ach = wk["ortho_bytes"] / (kt["ORTHO"] * 1e-3) / 1e9
-        res["roofline"] = {"bound": "hbm", "kernel": "k_fg_dot + k_fg_update (Gram-Schmidt)",
+        res["roofline"] = {"bound": "hbm", "kernel": ("k_bkr_dot + k_bkr_update (block "
+                                                      "Gram-Schmidt)" if args.block_rhs else
+                                                      "k_fg_dot + k_fg_update (Gram-Schmidt)"),
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
                            "algorithmic": wk["ortho_bytes"], "launches": tm["ORTHO"][1],
@@ -533,8 +559,11 @@ def bench_headline(args):
         t_peak = wk["gemm_f64"] / (FP64_PEAK_TFLOPS * 1e12) + wk["gemm_f32"] / (FP32_PEAK_TFLOPS * 1e12)
         peak = fl / t_peak / 1e12
         ach = fl / (kt["GEMM"] * 1e-3) / 1e12
-        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm_tiled / k_gemm (covariance "
-                           "products: float64 D z1 and R, float32 Rhat^-1)",
+        res["roofline"] = {"bound": "mfma", "kernel": "k_gemm_tiled / k_gemm / k_gemm_lp "
+                           "(covariance products: %s)" % (
+                               "float32 D z1, R and Rhat^-1; float64 A at the restarts"
+                               if args.precision == "MIXED_F32" else
+                               "float64 D z1 and R, float32 Rhat^-1"),
                            "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                            "traffic": None, "peak_note": "flop-weighted: float64 at 78.6, "
                            "float32 at 157.3 TFLOP/s", "launches": tm["GEMM"][1],

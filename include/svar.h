@@ -144,7 +144,7 @@ typedef struct svar_prec_opts {
 #define SVAR_METHOD_MINRES 1  /* preconditioned MINRES, needs SVAR_PREC_PD or NONE        */
 
 #define SVAR_PRECISION_FP64 0         /* every operator in float64                       */
-#define SVAR_PRECISION_MIXED_FP32 1   /* FP64 refinement; inner A and P in float32       */
+#define SVAR_PRECISION_MIXED_FP32 1   /* FP64 refinement; inner A float32, P float64     */
 #define SVAR_PRECISION_MIXED_BF16P 2  /* FP64 refinement; inner A float32, P covariance
                                          products bfloat16 with float32 accumulation      */
 #define SVAR_PRECISION_FP64_F32P 3    /* A in float64 (no refinement needed); P covariance
@@ -153,6 +153,10 @@ typedef struct svar_prec_opts {
                                          (it is shared with the next A z)                  */
 #define SVAR_PRECISION_FP64_BF16P 4   /* A in float64; P covariance products bfloat16 with
                                          float32 accumulation                              */
+#define SVAR_PRECISION_MIXED_F32 5    /* FP64 refinement; every inner covariance product
+                                         (A and P) float32 on the matrix cores with float32
+                                         accumulation; FGMRES with P_I forms D z1 once in
+                                         float32 and shares it with the next A z           */
 
 typedef struct svar_solve_opts {
   int32_t method;     /* SVAR_METHOD_*                                                      */
@@ -222,7 +226,10 @@ typedef struct svar_solve_opts {
      or when a new block loses rank (then the float64 restart continues).  Rank loss in the
      starting block (zero or equal residuals) puts seeded random directions in the basis.
      iters counts block steps (one P and one A product per system each).  Cycles hold at most
-     7424 / nrhs^2 - 1 block steps (115 for 8 columns).  0: one Krylov space per system. */
+     7424 / nrhs^2 - 1 block steps (115 for 8 columns).  2: the same with one Gram-Schmidt
+     pass per step (half the basis reads; the basis then loses orthogonality as classical
+     Gram-Schmidt does, which restart cycles of a few tens of blocks keep near rounding).
+     0: one Krylov space per system. */
   int32_t block_rhs;
 } svar_solve_opts;
 

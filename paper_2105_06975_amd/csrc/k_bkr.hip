@@ -3,7 +3,7 @@
 //
 // The P = nrhs residuals of window w form the block R_0 = V_0 S_0.  Block step j applies the
 // preconditioner to every column of V_j (Z_j; flexible, so a nonlinear correction may enter),
-// forms W = A Z_j, orthogonalises W against V_0..V_j by two passes of block classical
+// forms W = A Z_j, orthogonalises W against V_0..V_j by two passes (or one) of block classical
 // Gram-Schmidt (C = C_1 + C_2) and factorises it by two Cholesky QR rounds on the
 // column-normalised Gram matrix (W = V_{j+1} F, F = F_2 F_1 upper triangular).  The block
 // Hessenberg matrix Hbar holds C in rows 0..(j+1)P-1 and F below, so that
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(64) void k_bkr_hess(KBRWin* __restrict__ wins,
     for (int s = 0; s <= j; ++s)
       for (int r = 0; r < P; ++r) {
         const int64_t v = (int64_t)w * SLS + s * P * P + r * P + c;
-        col[s * P + r] = C1[v] + C2[v];
+        col[s * P + r] = C2 ? C1[v] + C2[v] : C1[v];
       }
     for (int r = 0; r <= c; ++r) col[(j + 1) * P + r] = W.Ft[r * P + c];
     // rotations of the earlier block columns, in order (each acts on rows row, row + 1)

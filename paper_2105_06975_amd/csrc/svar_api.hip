@@ -1540,28 +1540,33 @@ static int build_program(svar_handle* h, int op, int nrhs, int prec, Program& P,
   // for MIXED_BF16P (products with float32 accumulation)
   const VRef DZ1{B_AUX, SP_STATE, C_X};
   if (op == PROG_AD) {
-    // A z for z = P_I u just formed by PROG_PD: c1 = L z3 + D z1 with D z1 from the buffer
+    // A z for z = P_I u just formed by PROG_PD: c1 = L z3 + D z1 with D z1 from the buffer;
+    // R in float64 (PV_F64) or float32 (PV_F32)
+    const int dr = prec == PV_F32 ? DT_F32 : DT_F64;
     P.aux_elems = total_len(h, nrhs, SP_STATE);
     SVAR_TRY(add_L(B, IN_SAD_X, OUT_SAD_ETA, 0, DZ1));  // L z3 + D z1
     SVAR_TRY(add_L(B, IN_SAD_ETA, OUT_SAD_X, 1));
     SVAR_TRY(add_gather(B, IN_SAD_X, OUT_SAD_NU));
     SVAR_TRY(add_scatter(B, IN_SAD_NU, OUT_SAD_X));
     std::vector<GemmProb> probs;
-    add_cov(B, probs, MS_R, DT_F64, IN_SAD_NU, OUT_SAD_NU, OUT_SAD_NU, false, 1.0, 1.0);
-    SVAR_TRY(add_gemm(B, probs, DT_F64));
+    add_cov(B, probs, MS_R, dr, IN_SAD_NU, OUT_SAD_NU, OUT_SAD_NU, false, 1.0, 1.0);
+    SVAR_TRY(add_gemm(B, probs, dr));
     return SVAR_OK;
   }
   if (op == PROG_PD) {
-    // P_I with D z1 formed in float64 and kept for PROG_AD; Rhat^{-1} in the given precision
-    const int dt = prec == PV_BF16P ? DT_BF16 : (prec == PV_F32P ? DT_F32 : DT_F64);
+    // P_I with D z1 formed once and kept for PROG_AD: in float64, or in float32 for PV_F32ALL;
+    // Rhat^{-1} in the given precision
+    const int dt = prec == PV_BF16P ? DT_BF16
+                                    : ((prec == PV_F32P || prec == PV_F32ALL) ? DT_F32 : DT_F64);
+    const int dd = prec == PV_F32ALL ? DT_F32 : DT_F64;
     P.aux_elems = total_len(h, nrhs, SP_STATE);
     SVAR_TRY(add_sweep(B, OUT_SAD_ETA, 1, k, IN_SAD_X));  // c1 = Lhat^{-T} v3
     if (h->net) SVAR_TRY(add_net(B, OUT_SAD_ETA));
     std::vector<GemmProb> pd, pr;
-    add_cov(B, pd, MS_D, DT_F64, OUT_SAD_ETA, DZ1, NONE_REF, true, 1.0, 0.0);
-    if (!diag) add_cov(B, dt == DT_F64 ? pd : pr, MS_RHAT, dt, IN_SAD_NU, OUT_SAD_NU, NONE_REF,
+    add_cov(B, pd, MS_D, dd, OUT_SAD_ETA, DZ1, NONE_REF, true, 1.0, 0.0);
+    if (!diag) add_cov(B, dt == dd ? pd : pr, MS_RHAT, dt, IN_SAD_NU, OUT_SAD_NU, NONE_REF,
                        false, 1.0, 0.0);
-    SVAR_TRY(add_gemm(B, pd, DT_F64));
+    SVAR_TRY(add_gemm(B, pd, dd));
     if (!pr.empty()) SVAR_TRY(add_gemm(B, pr, dt));
     if (diag) SVAR_TRY(add_copy_obs(B, IN_SAD_NU, OUT_SAD_NU, true));
     SVAR_TRY(add_sweep(B, OUT_SAD_X, 0, k, IN_SAD_ETA, DZ1));  // Lhat^{-1} (v1 - D z1)

@@ -68,19 +68,21 @@ struct ProgKey {
 // A that adds that buffer instead of forming D z1 again (A is applied to z = P u right after)
 enum { PROG_A = 100, PROG_P = 101, PROG_HARVEST = 102, PROG_PD = 103, PROG_AD = 104 };
 // precision variants of a program
-enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2, PV_F32P = 3 };
+// launch-program precisions: PV_F32 float32 covariances in A; PV_BF16P / PV_F32P bfloat16 /
+// float32 covariances in P (D z1 of P_I stays float64); PV_F32ALL float32 everywhere in P
+enum { PV_F64 = 0, PV_F32 = 1, PV_BF16P = 2, PV_F32P = 3, PV_F32ALL = 4 };
 // program variants of the inner A and P of a SVAR_PRECISION_* setting
 inline bool prec_valid(int p) {
-  return p >= SVAR_PRECISION_FP64 && p <= SVAR_PRECISION_FP64_BF16P;
+  return p >= SVAR_PRECISION_FP64 && p <= SVAR_PRECISION_MIXED_F32;
 }
 inline bool prec_a64(int p) {
   return p == SVAR_PRECISION_FP64 || p == SVAR_PRECISION_FP64_F32P ||
          p == SVAR_PRECISION_FP64_BF16P;
 }
 inline int prec_pv_p(int p) {
-  return (p == SVAR_PRECISION_MIXED_BF16P || p == SVAR_PRECISION_FP64_BF16P)
-             ? PV_BF16P
-             : (p == SVAR_PRECISION_FP64_F32P ? PV_F32P : PV_F64);
+  if (p == SVAR_PRECISION_MIXED_BF16P || p == SVAR_PRECISION_FP64_BF16P) return PV_BF16P;
+  if (p == SVAR_PRECISION_FP64_F32P || p == SVAR_PRECISION_MIXED_F32) return PV_F32P;
+  return PV_F64;
 }
 
 struct Timer {

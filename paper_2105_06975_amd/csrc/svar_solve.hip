@@ -533,7 +533,7 @@ static int ensure_br(svar_handle* h, hipStream_t st) {
 // V[0..m], Z[0..m-1], each holding the whole batch): QR of the residual block, then per step
 // Z_j = P^{-1} V_j, W = A Z_j, two block Gram-Schmidt passes, two Cholesky QR rounds and the
 // Hessenberg step; the host reads the all-done flag every GRAPH_STEPS steps, one check late.
-static int br_cycle(svar_handle* h, int m, const Program& PA, const Program& PP,
+static int br_cycle(svar_handle* h, int m, int npass, const Program& PA, const Program& PP,
                     const std::vector<double>& tol_rel, double* x, std::vector<KState>& out,
                     double drop, int patience, HistArg hist, hipStream_t st) {
   int* net_off = h->net_off ? h->kry.net_off : nullptr;
@@ -568,7 +568,7 @@ static int br_cycle(svar_handle* h, int m, const Program& PA, const Program& PP,
     SVAR_TRY(run_program(h, PP, Vj, Zj, st, skip, K.flags));
     SVAR_TRY(run_program(h, PA, Zj, Wn, st, skip, K.flags));
     double* C[2] = {K.br_c1, K.br_c2};
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < npass; ++pass) {
       hipEvent_t e0, e1;
       timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
       bkr_dot(P, B, K.br_wins, K.V, K.ldv, j + 1, Wn, K.br_part, SLP, st);
@@ -579,7 +579,8 @@ static int br_cycle(svar_handle* h, int m, const Program& PA, const Program& PP,
       timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
     }
     qr(Wn, 0);
-    bkr_hess(P, B, K.br_wins, K.br_hs, K.st, K.br_c1, K.br_c2, SLS, j, m, net_off, drop,
+    bkr_hess(P, B, K.br_wins, K.br_hs, K.st, K.br_c1, npass > 1 ? K.br_c2 : nullptr, SLS, j, m,
+             net_off, drop,
              patience, hist, st);
     bkr_flags(P, B, K.br_wins, K.gl, K.flags, net_off, st);
     if ((j + 1) % GRAPH_STEPS == 0 && j + 1 < m) {
@@ -635,10 +636,11 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
   const int pv_p = prec_pv_p(o->precision);
   Program *A64 = nullptr, *Ain = nullptr, *Pin = nullptr;
   SVAR_TRY(get_program(h, PROG_A, nrhs, PV_F64, &A64, st));
-  if (h->popts.type == SVAR_PREC_PI && a64) {
-    // every inner A z follows z = P_I u at once: P keeps D z1 (float64) and A reuses it
-    SVAR_TRY(get_program(h, PROG_AD, nrhs, PV_F64, &Ain, st));
-    SVAR_TRY(get_program(h, PROG_PD, nrhs, pv_p, &Pin, st));
+  if (h->popts.type == SVAR_PREC_PI && (a64 || o->precision == SVAR_PRECISION_MIXED_F32)) {
+    // every inner A z follows z = P_I u at once: P keeps D z1 (float64, or float32 for
+    // MIXED_F32) and A reuses it
+    SVAR_TRY(get_program(h, PROG_AD, nrhs, a64 ? PV_F64 : PV_F32, &Ain, st));
+    SVAR_TRY(get_program(h, PROG_PD, nrhs, a64 ? pv_p : PV_F32ALL, &Pin, st));
   } else {
     SVAR_TRY(get_program(h, PROG_A, nrhs, pv_a, &Ain, st));
     SVAR_TRY(get_program(h, PROG_P, nrhs, pv_p, &Pin, st));
@@ -714,8 +716,8 @@ static int solve_fgmres(svar_handle* h, const svar_solve_opts* o, int nrhs, cons
     if (hist.h)
       SVAR_HIP(hipMemcpyAsync(K.it0, iters.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
     {
-      const int rc = brhs  ? br_cycle(h, m, *Ain, *Pin, tol, x, ks, drop, o->fallback_patience,
-                                      hist, st)
+      const int rc = brhs  ? br_cycle(h, m, o->block_rhs == 2 ? 1 : 2, *Ain, *Pin, tol, x, ks,
+                                      drop, o->fallback_patience, hist, st)
                      : blk ? block_cycle(h, m, blk, *Ain, *Pin, tol, x, ks, drop,
                                          o->fallback_patience, hv, hist, st)
                            : fgmres_cycle(h, nrhs, m, *Ain, *Pin, tol, x, ks, drop,
@@ -940,6 +942,7 @@ extern "C" int svar_solve(svar_handle* h, const svar_solve_opts* o, int32_t nrhs
   hipStream_t st = (hipStream_t)stream;
   if (o->wave_len < 0) return inval_msg("wave_len must be >= 0");
   if (o->block_rhs != 0) {
+    if (o->block_rhs < 0 || o->block_rhs > 2) return inval_msg("block_rhs must be 0, 1 or 2");
     if (o->method != SVAR_METHOD_FGMRES) return inval_msg("block_rhs needs FGMRES");
     if (nrhs > KBR_MAX) return inval_msg("block_rhs takes at most 8 right-hand sides");
     if (o->block >= 2) return inval_msg("block_rhs and block (s-step) exclude each other");

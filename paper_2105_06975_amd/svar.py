@@ -24,7 +24,8 @@ MODEL = {"dense": 0, "band": 1, "tridiag_inv": 2, "l96": 3, "band_dirichlet": 4}
 PREC = {"NONE": 0, "PD": 1, "PI": 2}
 RHAT = {"DIAG": 0, "RR": 1, "ME": 2, "EXACT": 3, "BLOCK": 4}
 METHOD = {"FGMRES": 0, "MINRES": 1}
-PRECISION = {"FP64": 0, "MIXED_FP32": 1, "MIXED_BF16P": 2, "FP64_F32P": 3, "FP64_BF16P": 4}
+PRECISION = {"FP64": 0, "MIXED_FP32": 1, "MIXED_BF16P": 2, "FP64_F32P": 3, "FP64_BF16P": 4,
+             "MIXED_F32": 5}
 OPS = {"L": 0, "LT": 1, "LHAT_INV": 2, "LHAT_INVT": 3, "D": 4, "DHAT_INV": 5, "R": 6,
        "RHAT_INV": 7, "H": 8, "HT": 9}
 OP_SPACES = {"L": ("state", "state"), "LT": ("state", "state"), "LHAT_INV": ("state", "state"),
@@ -342,7 +343,8 @@ class Handle:
         history: optional float64 device tensor (nsys, len): residual-norm estimate per iteration.
         wave_len: FGMRES over windows in contiguous waves of at most this packed length (0: from
         the free device memory).
-        block_rhs: block FGMRES over the nrhs (<= 8) right-hand sides of each window.
+        block_rhs: block FGMRES over the nrhs (<= 8) right-hand sides of each window (True or
+        1: two Gram-Schmidt passes per step; 2: one pass).
         """
         import torch
         x = torch.empty_like(rhs) if x is None else x
@@ -354,7 +356,7 @@ class Handle:
                       float(inner_rtol), int(max_outer), float(fallback_drop), hv, cap,
                       int(fallback_patience), 1 if graph else 0, int(block),
                       {"2": 0, "P": 1}[minres_norm], hp, hl, int(wave_len),
-                      1 if block_rhs else 0)
+                      int(block_rhs))
         ninfo = len(self.windows) * nrhs
         infos = (SolveInfo * ninfo)()
         rc = lib().svar_solve(self._h, C.byref(o), nrhs, _vp(rhs), _vp(x), infos, _stream(stream))

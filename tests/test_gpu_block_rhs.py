@@ -79,10 +79,11 @@ def test_first_cycle_matches_oracle_block_fgmres(sv, prec, nrhs, rtol):
 SHAPES = [(24, 3, 9), (40, 6, 15), (17, 2, 6), (64, 5, 30), (33, 7, 11)]
 
 
-@pytest.mark.parametrize("restart", [15, 25])
-def test_restarted_uneven_batch(sv, restart):
-    """Uneven windows in one call with restarts: every system meets rtol in the float64 true
-    residual; a window stops as a whole when all its columns are below their tolerances."""
+@pytest.mark.parametrize("restart,mode", [(15, 1), (25, 1), (25, 2)])
+def test_restarted_uneven_batch(sv, restart, mode):
+    """Uneven windows in one call with restarts (mode 2: one Gram-Schmidt pass per step):
+    every system meets rtol in the float64 true residual; a window stops as a whole when all
+    its columns are below their tolerances."""
     nrhs = 5
     wins = [wl.make_small_window(s=s, N=N, p=p, seed=120 + i, nrhs=nrhs)
             for i, (s, N, p) in enumerate(SHAPES)]
@@ -90,7 +91,7 @@ def test_restarted_uneven_batch(sv, restart):
     h = sv.Handle(wins, sv.Precond(type="PI", k=2, rhat="RR"))
     off = h.offsets(nrhs)
     x, info, rc = h.solve(dev(rhs), nrhs, rtol=1e-9, maxit=3000, restart=restart,
-                          max_outer=3000, block_rhs=True)
+                          max_outer=3000, block_rhs=mode)
     assert rc == sv.OK, [i for i in info if i["status"]][:3]
     xs = host(x)
     for w, win in enumerate(wins):
@@ -107,7 +108,7 @@ def test_restarted_uneven_batch(sv, restart):
     x1, info1, rc1 = h.solve(dev(rhs), nrhs, rtol=1e-9, maxit=3000, restart=restart,
                              max_outer=3000)
     d = np.linalg.norm(host(x1) - xs) / np.linalg.norm(xs)
-    print(f"restart {restart}: block steps per window "
+    print(f"restart {restart}, mode {mode}: block steps per window "
           f"{[info[w * nrhs]['iters'] for w in range(len(wins))]}, one at a time "
           f"{[max(info1[w * nrhs + r]['iters'] for r in range(nrhs)) for w in range(len(wins))]}"
           f", solution difference {d:.2e} (one at a time: status {rc1})", flush=True)

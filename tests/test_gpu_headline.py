@@ -4,8 +4,10 @@
   autotuned wide-panel GEMM plans (520 columns per covariance product) against the oracle,
   element by element per block.
 * The batched learned path of the headline batch (windows of the uneven batch, 8 rhs,
-  FP64 A with float32 Rhat^{-1} products, bfloat16 network inference, FGMRES(20), two
-  waves) against reference solutions: float64 FGMRES solves at rtol 1e-12 whose residual
+  bfloat16 network inference, FGMRES(20), two waves): the benchmark's path (one block Krylov
+  space per window over its 8 rhs with one Gram-Schmidt pass per step, every covariance product
+  float32 inside the float64 restart loop) and the one-column path (FP64 A, float32
+  Rhat^{-1}) against reference solutions: float64 FGMRES solves at rtol 1e-12 whose residual
   the oracle's A confirms.  The solution error of every system is reported and bounded.
 """
 import numpy as np
@@ -65,7 +67,8 @@ def test_c2_eight_rhs_wide_plans(sv):
     h.close()
 
 
-def test_headline_batched_learned_path_solution_error(sv):
+@pytest.mark.parametrize("block_rhs,precision", [(0, "FP64_F32P"), (2, "MIXED_F32")])
+def test_headline_batched_learned_path_solution_error(sv, block_rhs, precision):
     nrhs = 8
     wins = [wl.make_c4_window(w, nrhs=nrhs) for w in (5, 11, 2, 29)]
     print("windows (s, N, p):", [(w.s, w.N, int(w.p[0])) for w in wins], flush=True)
@@ -86,8 +89,8 @@ def test_headline_batched_learned_path_solution_error(sv):
     lens = [nrhs * w.n for w in wins]
     wave_len = max(lens[0] + lens[1], lens[2] + lens[3])
     x, inf, rc = h.solve(dev(rhs), nrhs, rtol=HEADLINE_RTOL, maxit=20000,
-                         restart=HEADLINE_RESTART, max_outer=20000, precision="FP64_F32P",
-                         fallback_patience=20, wave_len=wave_len)
+                         restart=HEADLINE_RESTART, max_outer=20000, precision=precision,
+                         fallback_patience=20, wave_len=wave_len, block_rhs=block_rhs)
     assert rc == sv.OK
     X = host(x)
     worst = 0.0

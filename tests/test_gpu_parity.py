@@ -311,7 +311,7 @@ def test_batched_systems_and_restarts(sv):
             assert info[i * nrhs + r]["outer"] >= 1
 
 
-@pytest.mark.parametrize("precision", ["MIXED_FP32", "MIXED_BF16P"])
+@pytest.mark.parametrize("precision", ["MIXED_FP32", "MIXED_BF16P", "MIXED_F32"])
 def test_mixed_precision_refinement(sv, precision):
     win = wl.make_config_window("c1", seed=2)
     orc = so.SaddleOracle(win, k=3, rhat="RR")
