@@ -27,6 +27,7 @@
 // columns of slot j.  A task is a range of rows of one window; its threads keep their rows of
 // all P columns in registers.
 #include "krylov.h"
+#include "lanes.h"
 #include "svar_impl.h"
 
 namespace svar {
@@ -35,27 +36,7 @@ static constexpr int NT = 256;
 static constexpr int BR_EPT = KBR_TASK / NT;  // rows per thread of a task
 static_assert(BR_EPT * NT == KBR_TASK, "a task is NT threads x BR_EPT rows");
 
-// 16 values per lane summed over the wave by halving exchanges; lane l ends with the sum of
-// value (l >> 2) & 15
-__device__ __forceinline__ double bwave_sum16(double (&v)[16]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int step = 0; step < 4; ++step) {
-    const int o = 32 >> step;
-    const int K = 16 >> step;
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int i = 0; i < K / 2; ++i) {
-      const double send = up ? v[i] : v[i + K / 2];
-      const double keep = up ? v[i + K / 2] : v[i];
-      v[i] = keep + __shfl_xor(send, o, 64);
-    }
-  }
-  double r = v[0];
-  r += __shfl_xor(r, 2, 64);
-  r += __shfl_xor(r, 1, 64);
-  return r;
-}
+using lanes::wave_sum16;
 
 // packed address of column c, row e (inside the window) of task t's window
 __device__ __forceinline__ int64_t bcol(const KBRTask& t, int c, int64_t e) {
@@ -131,7 +112,7 @@ __global__ __launch_bounds__(NT) void k_bkr_dot(const KBRTask* __restrict__ task
         }
         acc[u] = x;
       }
-      const double sm = bwave_sum16(acc);
+      const double sm = wave_sum16(acc);
       if ((ln & 3) == 0) L[wv][bt * 16 + (ln >> 2)] = sm;
     }
     __syncthreads();

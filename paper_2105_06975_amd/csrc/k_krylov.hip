@@ -16,40 +16,16 @@
 // iteration instead of four for two-pass classical Gram-Schmidt.
 #include "svar_impl.h"
 #include "krylov.h"
+#include "lanes.h"
 
 namespace svar {
 
 static constexpr int NT = 256;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sums 16 values per lane over the 64 lanes of a wave with a halving exchange: at each of
-// four steps a lane keeps half of its values and adds its partner's copy of that half, then
-// two plain butterfly steps finish.  On return lane l holds the wave total of value
-// index (l >> 2) & 15.  17 double shuffles instead of 16 x 6.
-__device__ __forceinline__ double wave_sum16(double (&v)[16]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int step = 0; step < 4; ++step) {
-    const int o = 32 >> step;          // partner distance
-    const int K = 16 >> step;          // live values
-    const bool up = (lane & o) != 0;   // keeps the upper half
-#pragma unroll
-    for (int i = 0; i < K / 2; ++i) {
-      const double send = up ? v[i] : v[i + K / 2];
-      const double keep = up ? v[i + K / 2] : v[i];
-      v[i] = keep + __shfl_xor(send, o, 64);
-    }
-  }
-  double r = v[0];
-  r += __shfl_xor(r, 2, 64);
-  r += __shfl_xor(r, 1, 64);
-  return r;
-}
+// wave sums without the LDS crossbar (lanes.h); wave_sum16 leaves the wave total of value
+// (l >> 2) & 15 in lane l
+using lanes::wave_sum;
+using lanes::wave_sum16;
 
 // block-wide sum of one value per thread; every thread gets the result
 __device__ double block_sum(double v, double* red) {
