@@ -765,7 +765,7 @@ def bench_c5(args):
             its1.append(inf1[0]["iters"])
         hw.close()
     h = svar.Handle(wins, prec)
-    kwb = dict(kw1, precision=args.precision)
+    kwb = dict(kw1, precision=args.precision, block_rhs=args.block_rhs)
     out = {}
     for name, attach in (("learned_batched", net), ("plain_batched", None)):
         h.set_net(attach)
@@ -782,7 +782,8 @@ def bench_c5(args):
                      "relres_max": float(max(i["relres_true"] for i in infb))}
         log(name, out[name])
     res = {"workload": f"c5: {args.c5} held-out windows (s={s}, N={N}, p=s/2) x {nrhs} rhs, "
-                       f"FGMRES({args.restart}) on every path",
+                       f"FGMRES({args.restart}) on every path; batched paths {args.precision}, "
+                       f"block_rhs {args.block_rhs}",
            "training": {"windows": args.train_windows, "epochs": args.epochs,
                         "loss_first": hist[0], "loss_last": hist[-1], "seconds": t_train},
            "plain_fp64_one_at_a_time": {"systems": len(its1), "solves_per_s": len(its1) / one_t,

@@ -125,17 +125,29 @@ __global__ __launch_bounds__(NT) void k_bkr_dot(const KBRTask* __restrict__ task
   }
 }
 
-// sums[w][v] = sum over the window's tasks of part[task][v], v < nv (fixed order)
+// sums[w][v] = sum over the window's tasks of part[task][v], v < nv (fixed order): a workgroup
+// takes 32 values of one window, its 8 waves-of-32 sum every 8th task each (coalesced 256-byte
+// reads of one task's 32 values), and the 8 partial sums are added in order through LDS
+static constexpr int RV = 32, RG = NT / RV;
 __global__ __launch_bounds__(NT) void k_bkr_reduce(const KBRWin* __restrict__ wins,
                                                    const double* __restrict__ part, int SLP,
                                                    int nv, double* __restrict__ sums, int SLS) {
+  __shared__ double red[RG][RV];
   const int w = blockIdx.x;
   if (wins[w].done) return;
   const int task0 = wins[w].task0, ntask = wins[w].ntask;
-  for (int v = blockIdx.y * NT + threadIdx.x; v < nv; v += gridDim.y * NT) {
-    double x = 0.0;
-    for (int k = 0; k < ntask; ++k) x += part[(int64_t)(task0 + k) * SLP + v];
-    sums[(int64_t)w * SLS + v] = x;
+  const int vl = threadIdx.x % RV, g = threadIdx.x / RV;
+  const int v = blockIdx.y * RV + vl;
+  double x = 0.0;
+  if (v < nv)
+    for (int k = g; k < ntask; k += RG) x += part[(int64_t)(task0 + k) * SLP + v];
+  red[g][vl] = x;
+  __syncthreads();
+  if (g == 0 && v < nv) {
+    double t = red[0][vl];
+#pragma unroll
+    for (int q = 1; q < RG; ++q) t += red[q][vl];
+    sums[(int64_t)w * SLS + v] = t;
   }
 }
 
@@ -550,7 +562,7 @@ void bkr_dot(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64
 }
 void bkr_reduce(const KBRPlan& p, const KBRWin* wins, const double* part, int SLP, int nv,
                 double* sums, int SLS, hipStream_t st) {
-  const int gy = (nv + NT - 1) / NT;
+  const int gy = (nv + RV - 1) / RV;
   hipLaunchKernelGGL(k_bkr_reduce, dim3(p.nwin, gy), dim3(NT), 0, st, wins, part, SLP, nv, sums,
                      SLS);
 }

@@ -442,6 +442,26 @@ def test_c2_operator_parity(sv, c2):
     assert abs(h.rhat_params(0)["gamma"][0] - lam[0]) <= 1e-9 * lam[0]
 
 
+def test_c2_pd_parity(sv, c2):
+    """C2 shape: P_D^{-1} v (k = 3, R_RR) and its D-hat^{-1} block against the oracle, element by
+    element per block (D-hat = B + 0.01 I, Q + 0.01 I: explicit inverses on the GPU, Cholesky
+    solves in the oracle)."""
+    win = c2
+    orc = so.SaddleOracle(win, k=3, rhat="RR")
+    h = sv.Handle([win], sv.Precond(type="PD", k=3, rhat="RR"))
+    V = wl.random_vectors(win, 1, seed=43)[0]
+    yp = host(h.apply_P(dev(V)))
+    rp = orc.apply_P_inv(V, "PD")
+    print(f"C2 P_D: relative error {rel(yp, rp):.2e}", flush=True)
+    assert rel(yp, rp) < 1e-10
+    assert_blocks(win, yp, rp, 1e-9, what="C2 P_D v")
+    xs = V[:win.nb * win.s]
+    yd = host(h.apply_op("DHAT_INV", dev(xs)))
+    rd = orc.Dhat_inv(xs.reshape(win.nb, win.s)).ravel()
+    assert rel(yd, rd) < 1e-10
+    assert_blocks(win, yd, rd, 1e-9, space="state", what="C2 Dhat^-1")
+
+
 def test_c2_solve_true_residual(sv, c2):
     """The metric's solve at full size: the oracle's own A confirms ||rhs - A x|| <= 1e-6 ||rhs||."""
     win = c2
@@ -548,6 +568,44 @@ def test_lhat_LI(sv, prec):
 
 
 # ------------------------------------------------------------------ heat equation (§7.2)
+def test_periodic_user_band_model(sv):
+    """SVAR_MODEL_CIRC_BAND (user offsets and weights, periodic): the model products, the
+    L_M(k) sweeps, A v and P^{-1} v against the oracle's band branch, with an asymmetric band
+    of 6 taps (offsets -4..2 without 0's neighbour -1) on an uneven two-window batch."""
+    rng = np.random.default_rng(21)
+    offs = [-4, -3, -2, 0, 1, 2]
+    wts = list(0.3 * rng.standard_normal(len(offs)))
+    wins = []
+    for i, (s_, N_, p_) in enumerate(((37, 4, 12), (64, 6, 20))):
+        w = wl.make_small_window(s=s_, N=N_, p=p_, seed=210 + i)
+        w.model = {"kind": "band", "offsets": np.asarray(offs, np.int32),
+                   "weights": np.asarray(wts, np.float64)}
+        wins.append(w)
+    for prec, k in (("PI", 3), ("PD", 2)):
+        h = sv.Handle(wins, sv.Precond(type=prec, k=k, rhat="RR"))
+        off = h.offsets(1)
+        for w, win in enumerate(wins):
+            orc = so.SaddleOracle(win, k=k, rhat="RR")
+            hw = sv.Handle([win], sv.Precond(type=prec, k=k, rhat="RR"))
+            X = np.random.default_rng(22 + w).standard_normal(win.nb * win.s)
+            for op, fn in {"L": orc.L_apply, "LT": orc.LT_apply, "LHAT_INV": orc.LM_inv,
+                           "LHAT_INVT": orc.LM_invT}.items():
+                out = host(hw.apply_op(op, dev(X)))
+                ref = fn(X.reshape(win.nb, win.s)).ravel()
+                assert rel(out, ref) < 1e-13, op
+                assert_blocks(win, out, ref, 1e-12, space="state", what=op)
+            hw.close()
+        V = np.concatenate([wl.random_vectors(win, 1, seed=30 + w)[0]
+                            for w, win in enumerate(wins)])
+        ya, yp = host(h.apply_A(dev(V))), host(h.apply_P(dev(V)))
+        for w, win in enumerate(wins):
+            orc = so.SaddleOracle(win, k=k, rhat="RR")
+            v = V[off[w]:off[w] + win.n]
+            assert rel(ya[off[w]:off[w] + win.n], orc.apply_A(v)) < 1e-12
+            assert rel(yp[off[w]:off[w] + win.n], orc.apply_P_inv(v, prec)) < 1e-10
+        h.close()
+
+
 def test_dirichlet_band_model(sv):
     """The explicit heat-equation step with Dirichlet boundaries (a non-periodic band): the
     model products, the L_M(k) sweeps, A v, P^{-1} v and the forecast against the oracle's
