@@ -152,7 +152,9 @@ __global__ __launch_bounds__(NT) void k_bkr_reduce(const KBRWin* __restrict__ wi
 }
 
 // Wb[col c] += sgn sum_{s < na} sum_r A_s[col r] C[w][s P^2 + r P + c] over the task's rows.
-// final_x: the solution update after the cycle (every window, na limited to its steps).
+// final_x: the solution update after the cycle (every window, na limited to its steps).  C is
+// the same for the whole workgroup, so its entries come through scalar loads; a slot's P x 4
+// basis values are loaded together before their FMAs.
 template <int P>
 __global__ __launch_bounds__(NT) void k_bkr_update(const KBRTask* __restrict__ tasks,
                                                    const KBRWin* __restrict__ wins,
@@ -161,7 +163,6 @@ __global__ __launch_bounds__(NT) void k_bkr_update(const KBRTask* __restrict__ t
                                                    const double* __restrict__ C, int SLS,
                                                    double sgn, int final_x) {
   constexpr int PP = P * P;
-  extern __shared__ double lc[];  // na P^2
   const KBRTask t = tasks[blockIdx.x];
   if (final_x) {
     na = min(na, wins[t.win].steps);
@@ -169,35 +170,36 @@ __global__ __launch_bounds__(NT) void k_bkr_update(const KBRTask* __restrict__ t
   } else if (wins[t.win].done) {
     return;
   }
-  for (int v = threadIdx.x; v < na * PP; v += NT) lc[v] = C[(int64_t)t.win * SLS + v];
-  __syncthreads();
+  const double* __restrict__ Cw = C + (int64_t)t.win * SLS;
   const BRows R(t);
+  // the block's own rows are loaded first, so that their latency overlaps the basis stream
   double acc[P][BR_EPT];
 #pragma unroll
   for (int c = 0; c < P; ++c)
 #pragma unroll
-    for (int q = 0; q < BR_EPT; ++q) acc[c][q] = 0.0;
+    for (int q = 0; q < BR_EPT; ++q) acc[c][q] = R.ok[q] ? Wb[bcol(t, c, R.e[q])] : 0.0;
   for (int s = 0; s < na; ++s) {
     const double* As = A + (int64_t)s * lda;
-    const double* Cs = lc + s * PP;
+    const double* Cs = Cw + s * PP;
+    double a[P][BR_EPT];
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      double a[BR_EPT];
+    for (int r = 0; r < P; ++r)
 #pragma unroll
-      for (int q = 0; q < BR_EPT; ++q) a[q] = __builtin_nontemporal_load(As + bcol(t, r, R.e[q]));
+      for (int q = 0; q < BR_EPT; ++q) a[r][q] = __builtin_nontemporal_load(As + bcol(t, r, R.e[q]));
+#pragma unroll
+    for (int r = 0; r < P; ++r)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double cv = Cs[r * P + c];
+        const double cv = sgn * Cs[r * P + c];
 #pragma unroll
-        for (int q = 0; q < BR_EPT; ++q) acc[c][q] += a[q] * cv;
+        for (int q = 0; q < BR_EPT; ++q) acc[c][q] += a[r][q] * cv;
       }
-    }
   }
 #pragma unroll
   for (int c = 0; c < P; ++c)
 #pragma unroll
     for (int q = 0; q < BR_EPT; ++q)
-      if (R.ok[q]) Wb[bcol(t, c, R.e[q])] += sgn * acc[c][q];
+      if (R.ok[q]) Wb[bcol(t, c, R.e[q])] = acc[c][q];
 }
 
 // One Cholesky QR round of every active window's block from its Gram matrix G = W^T W:
@@ -569,8 +571,7 @@ void bkr_reduce(const KBRPlan& p, const KBRWin* wins, const double* part, int SL
 void bkr_update(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64_t lda,
                 int na, double* Wb, const double* C, int SLS, double sgn, int final_x,
                 hipStream_t st) {
-  const size_t sh = (size_t)na * P * P * sizeof(double);
-  BKR_DISPATCH(P, hipLaunchKernelGGL(k_bkr_update<PT>, dim3(p.ntask), dim3(NT), sh, st, p.tasks,
+  BKR_DISPATCH(P, hipLaunchKernelGGL(k_bkr_update<PT>, dim3(p.ntask), dim3(NT), 0, st, p.tasks,
                                      wins, A, lda, na, Wb, C, SLS, sgn, final_x));
 }
 void bkr_chol(int P, const KBRPlan& p, KBRWin* wins, const double* G, int SLS, int round,

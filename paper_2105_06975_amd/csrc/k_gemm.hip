@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmProb* __restrict__ probs
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int row = rbase + rt * 16 + r16;
-    A[rt] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
+    A[rt] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.ld : (const CS*)P.zeros);
   }
   const double* X = opnd(b, P.X);
   gdp xp[CT];
@@ -291,10 +291,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled(const GemmProb* __restric
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt) {
     const int row = t.row0 + wave * 32 + rt * 16 + r16;
-    arow[rt] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
+    arow[rt] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.ld : (const CS*)P.zeros);
   }
   // 4-element loads need 4-aligned rows; the k-ranges start on multiples of 64
-  const bool avec = (P.n & 3) == 0 && ((uintptr_t)P.C & (4 * sizeof(CS) - 1)) == 0;
+  const bool avec = (P.ld & 3) == 0 && ((uintptr_t)P.C & (4 * sizeof(CS) - 1)) == 0;
   const double* X = opnd(b, P.X);
   gdp xcol[CT];
 #pragma unroll
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tiled_lds(const GemmProb* __res
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int row = t.row0 + rsub + 16 * j;
-    arow[j] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.n : (const CS*)P.zeros);
+    arow[j] = (cptr)(row < P.n ? (const CS*)P.C + (size_t)row * P.ld : (const CS*)P.zeros);
   }
   const double* X = opnd(b, P.X);
   gdp xcol[CT];

@@ -183,6 +183,15 @@ __device__ __forceinline__ unsigned short f2bf_rne(float f) {
 __global__ __launch_bounds__(NT) void k_to_f32(const double* src, float* dst, int64_t len) {
   GRID_LOOP(e, len) dst[e] = (float)src[e];
 }
+// dst[r ld + c] = src[r n + c] for c < n, 0 for n <= c < ld
+__global__ __launch_bounds__(NT) void k_to_f32_pad(const double* src, float* dst, int n, int ld) {
+  const int64_t len = (int64_t)n * ld;
+  GRID_LOOP(e, len) {
+    const int64_t r = e / ld;
+    const int c = (int)(e - r * ld);
+    dst[e] = c < n ? (float)src[r * n + c] : 0.0f;
+  }
+}
 __global__ __launch_bounds__(NT) void k_to_bf16(const double* src, unsigned short* dst, int64_t len) {
   GRID_LOOP(e, len) dst[e] = f2bf_rne((float)src[e]);
 }
@@ -266,6 +275,10 @@ void su_tridiag_inv_col(double a, double b, double c, int s, double* g, double* 
 }
 void su_to_f32(const double* src, void* dst, int64_t len, hipStream_t st) {
   hipLaunchKernelGGL(k_to_f32, dim3(gsz(len)), dim3(NT), 0, st, src, (float*)dst, len);
+}
+void su_to_f32_pad(const double* src, void* dst, int n, int ld, hipStream_t st) {
+  const int64_t len = (int64_t)n * ld;
+  hipLaunchKernelGGL(k_to_f32_pad, dim3(gsz(len)), dim3(NT), 0, st, src, (float*)dst, n, ld);
 }
 void su_to_bf16(const double* src, void* dst, int64_t len, hipStream_t st) {
   hipLaunchKernelGGL(k_to_bf16, dim3(gsz(len)), dim3(NT), 0, st, src, (unsigned short*)dst, len);

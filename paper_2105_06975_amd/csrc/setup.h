@@ -19,6 +19,8 @@ void su_tridiag_inv_col(double a, double b, double c, int s, double* g, double* 
                         hipStream_t st);
 void su_to_f32(const double* src, void* dst, int64_t len, hipStream_t st);
 void su_to_bf16(const double* src, void* dst, int64_t len, hipStream_t st);
+// float32 copy of an n x n matrix with rows padded to ld >= n elements (zeros)
+void su_to_f32_pad(const double* src, void* dst, int n, int ld, hipStream_t st);
 // scaled Frobenius norms of the super-diagonal blocks of R (block starts pst, device)
 void su_superdiag_norms(const double* R, int n, const int* pst, int npairs, double* out,
                         hipStream_t st);

@@ -245,6 +245,7 @@ static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector
   for (auto& p : probs) {
     p.dtype = dtype;
     p.zeros = h->zeros;
+    if (p.ld <= 0) p.ld = p.n;
   }
   int maxcols = 1;
   for (auto& p : probs) maxcols = std::max(maxcols, p.ncols);
@@ -265,7 +266,7 @@ static int make_gemm_plan(svar_handle* h, std::vector<void*>& owner, std::vector
   g.direct = 1;
   const size_t esz = dtype == DT_F64 ? 8 : (dtype == DT_F32 ? 4 : 2);
   for (auto& p : probs)
-    if ((p.n & 3) != 0 || ((uintptr_t)p.C & (4 * esz - 1)) != 0) g.direct = 0;
+    if ((p.ld & 3) != 0 || ((uintptr_t)p.C & (4 * esz - 1)) != 0) g.direct = 0;
   g.hprobs = probs;
   if (g.tiled)
     plan_gemm_tiled(probs, tasks, ws, maxct, target);
@@ -978,14 +979,33 @@ static int setup_lowprec(svar_handle* h, WinDev& W, hipStream_t st) {
     }
     return SVAR_OK;
   };
+  // float32 copies of whole n x n matrices with rows padded to pad4(n) elements (zeros past
+  // n), so that the GEMM kernels read every row with aligned 4-element loads
+  auto conv_pad = [&](const std::vector<double*>& src, std::vector<void*>& dst, int n_all,
+                      const std::vector<int>* sizes) -> int {
+    dst.assign(src.size(), nullptr);
+    for (size_t m = 0; m < src.size(); ++m) {
+      if (!src[m]) continue;
+      const int n = sizes ? (*sizes)[m] : n_all;
+      if (n <= 0) continue;
+      float* q = nullptr;
+      SVAR_TRY(dalloc(h->allocs, &q, (size_t)n * pad4(n)));
+      su_to_f32_pad(src[m], q, n, pad4(n), st);
+      dst[m] = q;
+    }
+    return SVAR_OK;
+  };
   const int64_t ss = (int64_t)W.s * W.s;
-  SVAR_TRY(conv(W.dmats, W.dmats_f32, ss, false, nullptr));
-  SVAR_TRY(conv(W.rmats, W.rmats_f32, 0, false, &W.rmat_p));
+  SVAR_TRY(conv_pad(W.dmats, W.dmats_f32, W.s, nullptr));
+  SVAR_TRY(conv_pad(W.rmats, W.rmats_f32, 0, &W.rmat_p));
   SVAR_TRY(conv(W.dmats, W.dmats_bf16, ss, true, nullptr));
   SVAR_TRY(conv_n(W.rhat_inv, W.rhat_inv_bf16, W.rhat_inv_elems, true));
   SVAR_TRY(conv(W.dhat_inv, W.dhat_inv_bf16, ss, true, nullptr));
-  SVAR_TRY(conv_n(W.rhat_inv, W.rhat_inv_f32, W.rhat_inv_elems, false));
-  SVAR_TRY(conv(W.dhat_inv, W.dhat_inv_f32, ss, false, nullptr));
+  if (h->popts.rhat == SVAR_RHAT_BLOCK)  // group inverses stored one after another
+    SVAR_TRY(conv_n(W.rhat_inv, W.rhat_inv_f32, W.rhat_inv_elems, false));
+  else
+    SVAR_TRY(conv_pad(W.rhat_inv, W.rhat_inv_f32, 0, &W.rmat_p));
+  SVAR_TRY(conv_pad(W.dhat_inv, W.dhat_inv_f32, W.s, nullptr));
   SVAR_HIP(hipStreamSynchronize(st));
   return SVAR_OK;
 }
@@ -1473,6 +1493,10 @@ static void add_cov(Builder& B, std::vector<GemmProb>& probs, MatSel sel, int dt
         GemmProb p{};
         p.C = mat_ptr(W, sel, key(i), dtype);
         p.n = n;
+        // the float32 copies of whole matrices have rows padded to 4 elements (set-up)
+        p.ld = (dtype == DT_F32 && !(sel == MS_RHAT && B.h->popts.rhat == SVAR_RHAT_BLOCK))
+                   ? pad4(n)
+                   : n;
         p.per = j - i;
         p.ncols = (j - i) * B.nrhs;
         p.X = blk(B.h, w, 0, B.nrhs, X, i);
@@ -1494,6 +1518,7 @@ static void add_cov(Builder& B, std::vector<GemmProb>& probs, MatSel sel, int dt
             GemmProb q = p;
             q.C = (const char*)p.C + g[2] * es;
             q.n = (int)(g[1] - g[0]);
+            q.ld = q.n;
             q.X.off += g[0];
             q.Y.off += g[0];
             if (q.Z.base >= 0) q.Z.off += g[0];
@@ -1764,7 +1789,7 @@ static int validate_program(const svar_handle* h, const Program& P, int64_t in_l
                               hipMemcpyDeviceToHost, st));
       SVAR_HIP(hipStreamSynchronize(st));
       for (auto& g : G) {
-        if (g.ncols < 1 || g.per < 1 || g.n < 1) return fail("gemm shape");
+        if (g.ncols < 1 || g.per < 1 || g.n < 1 || g.ld < g.n) return fail("gemm shape");
         const int co = (g.ncols - 1) / g.per, ci = std::min(g.per - 1, g.ncols - 1);
         spans.push_back({g.X.base, g.X.off, g.X.off + co * g.xo + ci * g.xi + g.n});
         spans.push_back({g.Y.base, g.Y.off, g.Y.off + co * g.yo + ci * g.yi + g.n});

@@ -58,6 +58,9 @@ struct Operand {
 // Y[:, c] = beta * Z[:, c] + alpha0 * alpha[c % per] * (C X)[:, c], C an n x n matrix
 // stored row-major (lda = n).  Column c of X lives at X.off + (c / per) * xo + (c % per) * xi.
 enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+// n rounded up to a multiple of 4 (row stride of the padded float32 matrix copies)
+inline int pad4(int n) { return (n + 3) & ~3; }
+
 struct GemmProb {
   const void* C;
   int32_t n, ncols, per, splits;
@@ -67,6 +70,7 @@ struct GemmProb {
   double alpha0, beta;
   int64_t ws_off;       // element offset of the split-K partials (splits > 1)
   int32_t dtype, flag;  // flag: skip flag index (see Bases)
+  int32_t ld, pad_ld;   // row stride of C in elements (>= n; 0 = n)
   const double* zeros;  // >= n zeros: stands in for rows / columns past the edge
 };
 struct GemmTask {
