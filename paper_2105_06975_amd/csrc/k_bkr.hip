@@ -68,6 +68,41 @@ struct BRows {
   }
 };
 
+// Gram matrix partials of the task's rows: out[r P + c] = sum over the workgroup's rows of
+// y[r] y[c] (rows outside the task hold zeros); wave sums, then the four waves in order
+template <int P>
+__device__ __forceinline__ void block_gram_part(const double (&y)[P][BR_EPT],
+                                                double* __restrict__ out) {
+  constexpr int PP = P * P;
+  constexpr int NB = (PP + 15) / 16;
+  __shared__ double lg[NT / 64][NB * 16];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int bt = 0; bt < NB; ++bt) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int v = bt * 16 + u;
+      double x = 0.0;
+      if (v < PP) {
+        const int r = v / P, c = v % P;
+#pragma unroll
+        for (int q = 0; q < BR_EPT; ++q) x += y[r][q] * y[c][q];
+      }
+      acc[u] = x;
+    }
+    const double sm = wave_sum16(acc);
+    if ((ln & 3) == 0) lg[wv][bt * 16 + (ln >> 2)] = sm;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < PP) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) x += lg[k][threadIdx.x];
+    out[threadIdx.x] = x;
+  }
+}
+
 // Inner products of the P columns of na consecutive slots of A (slot s at A + s lda) with the
 // P columns of the block at Wb: part[task][s P^2 + r P + c] = sum over the task's rows of
 // A_s[col r] . W[col c].  V^T W of the Gram-Schmidt passes (A = V) and W^T W (A = Wb, na = 1).
@@ -161,7 +196,8 @@ __global__ __launch_bounds__(NT) void k_bkr_update(const KBRTask* __restrict__ t
                                                    const double* __restrict__ A, int64_t lda,
                                                    int na, double* __restrict__ Wb,
                                                    const double* __restrict__ C, int SLS,
-                                                   double sgn, int final_x) {
+                                                   double sgn, int final_x,
+                                                   double* __restrict__ gpart, int SLP) {
   constexpr int PP = P * P;
   const KBRTask t = tasks[blockIdx.x];
   if (final_x) {
@@ -198,8 +234,12 @@ __global__ __launch_bounds__(NT) void k_bkr_update(const KBRTask* __restrict__ t
 #pragma unroll
   for (int c = 0; c < P; ++c)
 #pragma unroll
-    for (int q = 0; q < BR_EPT; ++q)
+    for (int q = 0; q < BR_EPT; ++q) {
       if (R.ok[q]) Wb[bcol(t, c, R.e[q])] = acc[c][q];
+      else acc[c][q] = 0.0;
+    }
+  // the Gram matrix of the updated block for the first Cholesky QR round
+  if (gpart) block_gram_part<P>(acc, gpart + (int64_t)blockIdx.x * SLP);
 }
 
 // One Cholesky QR round of every active window's block from its Gram matrix G = W^T W:
@@ -272,11 +312,12 @@ __global__ void k_bkr_chol(KBRWin* __restrict__ wins, int nwin, const double* __
 }
 
 // W <- W F^{-1} row by row (F upper triangular); deflated columns become zero, or random
-// (rmask)
+// (rmask).  gpart: also the Gram matrix partials of the result (the next Cholesky QR round).
 template <int P>
 __global__ __launch_bounds__(NT) void k_bkr_trsm(const KBRTask* __restrict__ tasks,
                                                  const KBRWin* __restrict__ wins,
-                                                 double* __restrict__ Wb) {
+                                                 double* __restrict__ Wb,
+                                                 double* __restrict__ gpart, int SLP) {
   const KBRTask t = tasks[blockIdx.x];
   const KBRWin& W = wins[t.win];
   if (W.done || W.bad) return;
@@ -284,18 +325,27 @@ __global__ __launch_bounds__(NT) void k_bkr_trsm(const KBRTask* __restrict__ tas
   if ((int)threadIdx.x < P * P) f[threadIdx.x] = W.Fr[threadIdx.x];
   const int zm = W.zmask, rm = W.rmask;
   __syncthreads();
-  for (int64_t e = t.e0 + threadIdx.x; e < t.e1; e += NT) {
-    double y[P];
+  const BRows R(t);
+  double y[P][BR_EPT];
+#pragma unroll
+  for (int q = 0; q < BR_EPT; ++q) {
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-      double v = Wb[bcol(t, c, e)];
+      double v = Wb[bcol(t, c, R.e[q])];
 #pragma unroll
-      for (int r = 0; r < c; ++r) v -= y[r] * f[r * P + c];
-      y[c] = (zm >> c & 1) ? ((rm >> c & 1) ? bkr_rand(t.win, c, e) : 0.0) : v / f[c * P + c];
+      for (int r = 0; r < c; ++r) v -= y[r][q] * f[r * P + c];
+      y[c][q] = (zm >> c & 1) ? ((rm >> c & 1) ? bkr_rand(t.win, c, R.e[q]) : 0.0)
+                              : v / f[c * P + c];
     }
-#pragma unroll
-    for (int c = 0; c < P; ++c) Wb[bcol(t, c, e)] = y[c];
   }
+#pragma unroll
+  for (int q = 0; q < BR_EPT; ++q)
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      if (R.ok[q]) Wb[bcol(t, c, R.e[q])] = y[c][q];
+      else y[c][q] = 0.0;
+    }
+  if (gpart) block_gram_part<P>(y, gpart + (int64_t)blockIdx.x * SLP);
 }
 
 // every window's cycle state cleared before the QR of the starting block
@@ -570,18 +620,19 @@ void bkr_reduce(const KBRPlan& p, const KBRWin* wins, const double* part, int SL
 }
 void bkr_update(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64_t lda,
                 int na, double* Wb, const double* C, int SLS, double sgn, int final_x,
-                hipStream_t st) {
+                double* gpart, int SLP, hipStream_t st) {
   BKR_DISPATCH(P, hipLaunchKernelGGL(k_bkr_update<PT>, dim3(p.ntask), dim3(NT), 0, st, p.tasks,
-                                     wins, A, lda, na, Wb, C, SLS, sgn, final_x));
+                                     wins, A, lda, na, Wb, C, SLS, sgn, final_x, gpart, SLP));
 }
 void bkr_chol(int P, const KBRPlan& p, KBRWin* wins, const double* G, int SLS, int round,
               int start, hipStream_t st) {
   BKR_DISPATCH(P, hipLaunchKernelGGL(k_bkr_chol<PT>, dim3((p.nwin + 63) / 64), dim3(64), 0, st,
                                      wins, p.nwin, G, SLS, round, start));
 }
-void bkr_trsm(int P, const KBRPlan& p, const KBRWin* wins, double* Wb, hipStream_t st) {
+void bkr_trsm(int P, const KBRPlan& p, const KBRWin* wins, double* Wb, double* gpart, int SLP,
+              hipStream_t st) {
   BKR_DISPATCH(P, hipLaunchKernelGGL(k_bkr_trsm<PT>, dim3(p.ntask), dim3(NT), 0, st, p.tasks,
-                                     wins, Wb));
+                                     wins, Wb, gpart, SLP));
 }
 void bkr_start(int P, const KBRPlan& p, KBRWin* wins, KBRHess* hs, KState* stt,
                const double* tol_rel, const double* G0, int SLS, int m, KGlobal* gl,

@@ -145,12 +145,14 @@ void bkr_dot(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64
              const double* Wb, double* part, int SLP, hipStream_t st);
 void bkr_reduce(const KBRPlan& p, const KBRWin* wins, const double* part, int SLP, int nv,
                 double* sums, int SLS, hipStream_t st);
+// gpart (nullable): also the per-task Gram partials of the updated block (stride SLP)
 void bkr_update(int P, const KBRPlan& p, const KBRWin* wins, const double* A, int64_t lda,
                 int na, double* Wb, const double* C, int SLS, double sgn, int final_x,
-                hipStream_t st);
+                double* gpart, int SLP, hipStream_t st);
 void bkr_chol(int P, const KBRPlan& p, KBRWin* wins, const double* G, int SLS, int round,
               int start, hipStream_t st);
-void bkr_trsm(int P, const KBRPlan& p, const KBRWin* wins, double* Wb, hipStream_t st);
+void bkr_trsm(int P, const KBRPlan& p, const KBRWin* wins, double* Wb, double* gpart, int SLP,
+              hipStream_t st);
 void bkr_start(int P, const KBRPlan& p, KBRWin* wins, KBRHess* hs, KState* stt,
                const double* tol_rel, const double* G0, int SLS, int m, KGlobal* gl,
                hipStream_t st);

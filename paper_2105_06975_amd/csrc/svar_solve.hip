@@ -549,15 +549,19 @@ static int br_cycle(svar_handle* h, int m, int npass, const Program& PA, const P
   double* V0 = K.V;
   SVAR_HIP(hipMemcpyAsync(V0, K.r, K.ntot * sizeof(double), hipMemcpyDeviceToDevice, st));
   double* gram[2] = {K.br_g0, K.br_g1};
-  auto qr = [&](double* Wb, int start) {
-    for (int round = 0; round < 2; ++round) {
-      bkr_dot(P, B, K.br_wins, Wb, K.ldv, 1, Wb, K.br_part, SLP, st);
-      bkr_reduce(B, K.br_wins, K.br_part, SLP, P * P, gram[round], SLS, st);
-      bkr_chol(P, B, K.br_wins, gram[round], SLS, round, start, st);
-      bkr_trsm(P, B, K.br_wins, Wb, st);
-    }
+  // two Cholesky QR rounds; the Gram partials of round 0 come from the kernel that wrote the
+  // block (the last Gram-Schmidt update) unless have_g0 is false, those of round 1 from the
+  // first triangular solve
+  auto qr = [&](double* Wb, int start, bool have_g0) {
+    if (!have_g0) bkr_dot(P, B, K.br_wins, Wb, K.ldv, 1, Wb, K.br_part, SLP, st);
+    bkr_reduce(B, K.br_wins, K.br_part, SLP, P * P, gram[0], SLS, st);
+    bkr_chol(P, B, K.br_wins, gram[0], SLS, 0, start, st);
+    bkr_trsm(P, B, K.br_wins, Wb, K.br_part, SLP, st);
+    bkr_reduce(B, K.br_wins, K.br_part, SLP, P * P, gram[1], SLS, st);
+    bkr_chol(P, B, K.br_wins, gram[1], SLS, 1, start, st);
+    bkr_trsm(P, B, K.br_wins, Wb, nullptr, 0, st);
   };
-  qr(V0, 1);
+  qr(V0, 1, false);
   bkr_start(P, B, K.br_wins, K.br_hs, K.st, K.tol_rel, K.br_g0, SLS, m, K.gl, st);
   bkr_flags(P, B, K.br_wins, K.gl, K.flags, net_off, st);
   int pend = -1, slot = 0;
@@ -575,10 +579,11 @@ static int br_cycle(svar_handle* h, int m, int npass, const Program& PA, const P
       timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
       bkr_reduce(B, K.br_wins, K.br_part, SLP, (j + 1) * P * P, C[pass], SLS, st);
       timed_begin(h, SVAR_KCLASS_ORTHO, st, &e0, &e1);
-      bkr_update(P, B, K.br_wins, K.V, K.ldv, j + 1, Wn, C[pass], SLS, -1.0, 0, st);
+      bkr_update(P, B, K.br_wins, K.V, K.ldv, j + 1, Wn, C[pass], SLS, -1.0, 0,
+                 pass + 1 == npass ? K.br_part : nullptr, SLP, st);
       timed_end(h, SVAR_KCLASS_ORTHO, st, e0, e1);
     }
-    qr(Wn, 0);
+    qr(Wn, 0, true);
     bkr_hess(P, B, K.br_wins, K.br_hs, K.st, K.br_c1, npass > 1 ? K.br_c2 : nullptr, SLS, j, m,
              net_off, drop,
              patience, hist, st);
@@ -597,7 +602,7 @@ static int br_cycle(svar_handle* h, int m, int npass, const Program& PA, const P
     }
   }
   bkr_solve_y(P, B, K.br_wins, K.br_hs, m, K.br_yl, SLS, st);
-  bkr_update(P, B, K.br_wins, K.Z, K.ldv, m, x, K.br_yl, SLS, 1.0, 1, st);
+  bkr_update(P, B, K.br_wins, K.Z, K.ldv, m, x, K.br_yl, SLS, 1.0, 1, nullptr, 0, st);
   out.resize(K.plan.nsys);
   SVAR_HIP(hipMemcpyAsync(out.data(), K.st, K.plan.nsys * sizeof(KState), hipMemcpyDeviceToHost,
                           st));
