@@ -544,6 +544,17 @@ def bench_headline(args):
     res["kernel_time_ms"] = {k.lower(): kt[k] for k in classes}
     res["kernel_time_ms"].update(timed_region=1e3 * el, launches={k.lower(): tm[k][1]
                                                                   for k in classes})
+    # every class against its own roof (the one with the largest time is `roofline` below)
+    t_gpeak = (wk["gemm_f64"] / (FP64_PEAK_TFLOPS * 1e12) +
+               wk["gemm_f32"] / (FP32_PEAK_TFLOPS * 1e12))
+    gfl = wk["gemm_f64"] + wk["gemm_f32"]
+    res["class_rates"] = {
+        "gemm_tflops": gfl / max(kt["GEMM"] * 1e-3, 1e-12) / 1e12,
+        "gemm_frac": (t_gpeak / max(kt["GEMM"] * 1e-3, 1e-12)) if gfl > 0 else None,
+        "ortho_gbs": wk["ortho_bytes"] / max(kt["ORTHO"] * 1e-3, 1e-12) / 1e9,
+        "ortho_frac": wk["ortho_bytes"] / max(kt["ORTHO"] * 1e-3, 1e-12) / 1e9 / HBM_PEAK_GBS,
+        "net_tflops": wk["net_flops"] / max(kt["NET"] * 1e-3, 1e-12) / 1e12,
+        "net_frac": wk["net_flops"] / max(kt["NET"] * 1e-3, 1e-12) / 1e12 / BF16_PEAK_TFLOPS}
     top = max(("GEMM", "ORTHO", "NET"), key=lambda k: kt[k])
     if top == "ORTHO":
         ach = wk["ortho_bytes"] / (kt["ORTHO"] * 1e-3) / 1e9
