@@ -75,6 +75,9 @@ def parse():
                          "N=15, dt=1e-4), B = heat equation (s=10000, N=5); iterations for "
                          "P_D (MINRES) and P_I (FGMRES) over k and Rhat (one JSON object)")
     ap.add_argument("--replay-s", type=int, default=0, help="--replay: state size override")
+    ap.add_argument("--replay-subset", default="",
+                    help="--replay: comma-separated preconditioners / Rhat kinds / k values to "
+                         "run, e.g. PI,BLOCK,DIAG,1,3,4,16 (default: all)")
     ap.add_argument("--grid", action="store_true",
                     help="the C2 window with R lengths 0.01, 0.05, 0.2: iterations and time of "
                          "P_D (MINRES, float64) and P_I (FGMRES, float64 and bfloat16 P "
@@ -653,8 +656,14 @@ def bench_replay(args):
     rhs = torch.from_numpy(np.ascontiguousarray(win.rhs[0])).cuda()
     pvec = win.meta["pvec"]
     rows = []
-    for ptype in ("PD", "PI"):
-        for rh in ("DIAG", "BLOCK", "RR", "ME", "EXACT"):
+    sub = [t for t in args.replay_subset.split(",") if t]
+    ptypes = [t for t in ("PD", "PI") if not sub or t in sub or not {"PD", "PI"} & set(sub)]
+    rhats = [t for t in ("DIAG", "BLOCK", "RR", "ME", "EXACT")
+             if not sub or t in sub or not {"DIAG", "BLOCK", "RR", "ME", "EXACT"} & set(sub)]
+    kk = [int(t) for t in sub if t.isdigit()]
+    ks = [k for k in ks if not kk or k in kk]
+    for ptype in ptypes:
+        for rh in rhats:
             for k in ks:
                 prec = svar.Precond(type=ptype, k=k, rhat=rh, rb_pvec=pvec, rb_tol=0.05)
                 h = svar.Handle([win], prec)

@@ -110,12 +110,18 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
       for (int U = maxst; U >= umin; --U) {
         int64_t ntask = 0;
         int longest = 0, maxS = 1;
+        double wsb = 0.0;  // split-K partials (bytes)
         for (auto& p : probs) {
           const int st = (p.n + 15) / 16, S = (st + U - 1) / U, ch = (st + S - 1) / S;
           ntask += (int64_t)((p.n + rows - 1) / rows) * ((p.ncols + cwt - 1) / cwt) * S;
           longest = std::max(longest, ch);
           maxS = std::max(maxS, S);
+          if (S > 1) wsb += 8.0 * S * p.ncols * (double)p.n;
         }
+        // products with very wide panels (set-up inverses of large matrices) have tasks enough
+        // without splits: keep their partials within 2 GiB (a 40,000^2 x 40,000 product would
+        // otherwise ask for 20 splits' partials, 256 GB)
+        if (wsb > 2147483648.0 && U < maxst) continue;
         const double cost =
             ((double)((ntask + target - 1) / target) * longest + maxS) * (ct + 2);
         if (cost < bestcost) {
@@ -180,6 +186,12 @@ static void plan_gemm_tiled(std::vector<GemmProb>& probs, std::vector<GemmTask>&
         groups.push_back(std::move(grp));
       }
   }
+  // longest k-ranges first, so that the short tasks of small problems fill the last round of
+  // resident workgroups instead of leaving long ones running alone at the end
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const std::vector<GemmTask>& a, const std::vector<GemmTask>& b) {
+                     return (a[0].k1 - a[0].k0) > (b[0].k1 - b[0].k0);
+                   });
   // deal the groups to 8 XCD queues (largest queue-balance first fit), then interleave
   const int NX = 8;
   std::vector<std::vector<GemmTask>> q(NX);
