@@ -15,6 +15,7 @@
 // points of the workgroup's tiles; partial sums per workgroup are reduced in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include "lanes.h"
 #include "net.h"
 
 namespace svar {
@@ -493,13 +494,18 @@ namespace fz {
 constexpr int ROWS = NET_FTILE + 16;    // computed rows per layer
 constexpr int PADR = NET_HALO;          // zero rows above and below (taps past both ends)
 constexpr int LROWS = ROWS + 2 * PADR;  // LDS rows per buffer
-constexpr int SX = NET_CIN1 + 8;        // row strides (elements): 16-byte aligned rows, and the
-constexpr int SA = NET_C + 8;           // 8 rows of one 16-byte read phase in distinct banks
+// Row strides (elements).  A 16-byte LDS read serves 32 lanes at a time and is free of bank
+// conflicts when their 16-byte slots differ modulo 32.  An MFMA operand read puts rows
+// r16 = 0..15 and two consecutive slots (q = 0, 1 or 2, 3) in each half-wave: a stride of
+// 2 x odd slots makes stride * r16 run over the 16 even residues and the +1 over the odd ones.
+constexpr int SX = NET_CIN1 + 16;       // 6 slots
+constexpr int SA = NET_C + 16;          // 10 slots
 constexpr int RT = ROWS / 16;           // MFMA row tiles per layer
 constexpr int FRG = 3;                  // row tiles accumulated together
 }  // namespace fz
 static_assert(fz::ROWS % 16 == 0 && 2 * NET_FTILE == 256, "fused tile shape");
 static_assert(NET_CIN1 % 32 == 0, "the fused layer 1 contracts 32 channels per instruction");
+static_assert((fz::SX / 8) % 4 == 2 && (fz::SA / 8) % 4 == 2, "row strides of 2 x odd slots");
 
 // one convolution of the fused kernel: out rows PADR.. = relu(conv(in) + bias) for this
 // lane's output channel co; the RT row tiles in groups of RG independent accumulation chains
@@ -525,12 +531,28 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in,
         acc[j] = NetMma32::mma(*(const bf8*)(in + ((g + j) * 16 + r16 + t) * STR + ci), bw[ks],
                                acc[j]);
     }
+    // lane (q, r16) holds rows 4q..4q+3 of channel co.  Neighbouring lanes trade two values
+    // so that the even lane writes rows 4q, 4q+1 and the odd lane rows 4q+2, 4q+3, each as
+    // channel pairs (co & ~1, co | 1) in one dword: one write instruction covers the rows
+    // 0, 2, .., 14 of the tile (or 1, 3, .., 15), 8 dwords each, which the 40-dword row
+    // stride puts in distinct banks.
+    const bool odd = r16 & 1;
 #pragma unroll
-    for (int j = 0; j < RG; ++j)
+    for (int j = 0; j < RG; ++j) {
+      uint32_t v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        out[((g + j) * 16 + 4 * q + e + fz::PADR) * fz::SA + co] =
-            f2bf(fmaxf(acc[j][e] + bias, 0.0f));
+      for (int e = 0; e < 4; ++e) v[e] = f2bf(fmaxf(acc[j][e] + bias, 0.0f));
+      const uint32_t t0 = (uint32_t)__builtin_amdgcn_update_dpp(
+          0, (int)(odd ? v[0] : v[2]), lanes::DPP_XOR1, 0xf, 0xf, false);
+      const uint32_t t1 = (uint32_t)__builtin_amdgcn_update_dpp(
+          0, (int)(odd ? v[1] : v[3]), lanes::DPP_XOR1, 0xf, 0xf, false);
+      const uint32_t w0 = odd ? (t0 | (v[2] << 16)) : (v[0] | (t0 << 16));
+      const uint32_t w1 = odd ? (t1 | (v[3] << 16)) : (v[1] | (t1 << 16));
+      uint32_t* o = (uint32_t*)(out + ((g + j) * 16 + 4 * q + (odd ? 2 : 0) + fz::PADR) * fz::SA +
+                                (co & ~1));
+      o[0] = w0;
+      o[fz::SA / 2] = w1;
+    }
   }
 }
 
@@ -579,16 +601,24 @@ __global__ __launch_bounds__(256, 2) void k_net_fused(
     const int hot = 1 + S + (e - P.blk);
     // features, channel 0: own block, 1..S: later segment starts (zero past the last block),
     // then the one-hot of e - blk.  The block values are loaded with consecutive threads on
-    // consecutive grid points (coalesced), the constant channels in a second pass.
+    // consecutive grid points (coalesced), all of a thread's loads issued before the first
+    // is used, and the constant channels are written in a second pass.
+    constexpr int JM = (NET_CIN1 * ROWS + 255) / 256;
     const int nval = (1 + S) * ROWS;
-#pragma unroll 4
-    for (int it = threadIdx.x; it < nval; it += 256) {
+    double v[JM];
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+      const int it = threadIdx.x + 256 * j;
       const int m = it / ROWS, r = it - m * ROWS;
       const int b = m == 0 ? P.blk : e + 1 + (m - 1) * k;
       const int pos = wrap(T.pos0 - 4 * NET_HALO + r, P.s);
-      float x = 0.0f;
-      if (b < P.nb) x = (float)(src[P.src + (int64_t)b * P.s + pos] * isg);
-      X[(r + PADR) * SX + m] = f2bf(x);
+      v[j] = (it < nval && b < P.nb) ? src[P.src + (int64_t)b * P.s + pos] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+      const int it = threadIdx.x + 256 * j;
+      const int m = it / ROWS, r = it - m * ROWS;
+      if (it < nval) X[(r + PADR) * SX + m] = f2bf((float)(v[j] * isg));
     }
     for (int it = threadIdx.x; it < ROWS * NET_CIN1; it += 256) {
       const int r = it / NET_CIN1, c = it - r * NET_CIN1;
@@ -602,26 +632,33 @@ __global__ __launch_bounds__(256, 2) void k_net_fused(
     fused_layer<NET_C, SA, FRG>(A2, A1, bw3, c3, q, r16, co);
     __syncthreads();
     // output layer (64 -> 1, float32 weights): point p at row 8 + p, two threads per point
-    // with 32 channels each.  A1 is next written by the following tile's layer 1, after the
-    // barrier that follows its features, so no barrier is needed here.
+    // with 32 channels each, lanes l and l ^ 16 of one wave.  A half-wave holds 16 points of
+    // both halves; the upper half reads its four 8-channel pieces in the order 1, 2, 3, 0, so
+    // that its slots are odd where the lower half's are even (10-slot rows).  A1 is next
+    // written by the following tile's layer 1, after the barrier that follows its features.
     {
-      const int p = threadIdx.x >> 1, h = threadIdx.x & 1;
+      const int l = threadIdx.x & 63, h = (l >> 4) & 1;
+      const int p = (threadIdx.x >> 6) * 32 + (l >> 5) * 16 + (l & 15);
       float acc = 0.0f;
 #pragma unroll
       for (int t = 0; t < NET_W; ++t) {
         const uint16_t* row = A1 + (4 * NET_HALO + p + t) * SA + h * 32;
         const float* wt = w4s + t * NET_C + h * 32;
 #pragma unroll
-        for (int c8 = 0; c8 < 4; ++c8) {
+        for (int c = 0; c < 4; ++c) {
+          const int c8 = (c + h) & 3;
           const uint4 vv = *(const uint4*)(row + c8 * 8);
           const uint16_t* ev = (const uint16_t*)&vv;
 #pragma unroll
           for (int i = 0; i < 8; ++i) acc += wt[c8 * 8 + i] * bf2f(ev[i]);
         }
       }
-      acc += __shfl_xor(acc, 1);
+      // own value plus that of lane l ^ 16 (the other channel half of the point)
+      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc),
+                                                       __float_as_uint(acc), false, false);
+      const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
       const int pos = T.pos0 + p;
-      if (h == 0 && pos < P.s) corr[P.row0 - row_base + pos] = acc + c4;
+      if (h == 0 && pos < P.s) corr[P.row0 - row_base + pos] = tot + c4;
     }
   }
 }
