@@ -485,8 +485,10 @@ __global__ __launch_bounds__(64) void k_net_out(const E* __restrict__ a3,
 // rows are the periodic extension of the sample (positions mod s), which makes this the same
 // as applying each periodic layer to the whole sample, for any s.  Wave w keeps the weights of
 // output channels 16w..16w+15 of the three convolutions in registers for the whole launch
-// (persistent workgroups loop over the tiles); hidden activations are rounded to bfloat16 as in
-// the layer-by-layer kernels, accumulation is float32.  The output (the normalised correction,
+// (persistent workgroups, three per CU, loop over the tiles); hidden activations are rounded to
+// bfloat16 as in the layer-by-layer kernels, accumulation is float32; the 64 -> 1 output layer
+// runs on the MFMA too, with its float32 weights split into two bfloat16 parts.  The feature
+// rows share LDS with the second hidden layer's buffer.  The output (the normalised correction,
 // float32) goes to a workspace row per grid point and k_net_apply adds sigma times it to the
 // sweep output afterwards: adding it in place here would race with tiles that still read the
 // vector (halo rows, later segment starts).
@@ -503,9 +505,24 @@ constexpr int SA = NET_C + 16;          // 10 slots
 constexpr int RT = ROWS / 16;           // MFMA row tiles per layer
 constexpr int FRG = 3;                  // row tiles accumulated together
 }  // namespace fz
-static_assert(fz::ROWS % 16 == 0 && 2 * NET_FTILE == 256, "fused tile shape");
+static_assert(fz::ROWS % 16 == 0 && NET_FTILE == 8 * 16, "two output row tiles per wave");
 static_assert(NET_CIN1 % 32 == 0, "the fused layer 1 contracts 32 channels per instruction");
 static_assert((fz::SX / 8) % 4 == 2 && (fz::SA / 8) % 4 == 2, "row strides of 2 x odd slots");
+
+// two floats to bfloat16 (round to nearest even) in one dword, a in the low half
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// ReLU of two packed bfloat16 values: as 16-bit integers every negative value (sign bit set,
+// -0 included) is below 0 and the non-negative ones keep their order (v_pk_max_i16)
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t u) {
+  typedef short s2 __attribute__((ext_vector_type(2)));
+  const s2 z = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s2, u), z));
+}
 
 // one convolution of the fused kernel: out rows PADR.. = relu(conv(in) + bias) for this
 // lane's output channel co; the RT row tiles in groups of RG independent accumulation chains
@@ -520,7 +537,7 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in,
   for (int g = 0; g < fz::RT; g += RG) {
     v4f acc[RG];
 #pragma unroll
-    for (int j = 0; j < RG; ++j) acc[j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < RG; ++j) acc[j] = v4f{bias, bias, bias, bias};  // bias summed first
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int kl = ks * 32 + q * 8;
@@ -531,32 +548,30 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in,
         acc[j] = NetMma32::mma(*(const bf8*)(in + ((g + j) * 16 + r16 + t) * STR + ci), bw[ks],
                                acc[j]);
     }
-    // lane (q, r16) holds rows 4q..4q+3 of channel co.  Neighbouring lanes trade two values
-    // so that the even lane writes rows 4q, 4q+1 and the odd lane rows 4q+2, 4q+3, each as
-    // channel pairs (co & ~1, co | 1) in one dword: one write instruction covers the rows
+    // lane (q, r16) holds rows 4q..4q+3 of channel co.  Neighbouring lanes trade one packed
+    // pair so that the even lane writes rows 4q, 4q+1 and the odd lane rows 4q+2, 4q+3, each
+    // as channel pairs (co & ~1, co | 1) in one dword: one write instruction covers the rows
     // 0, 2, .., 14 of the tile (or 1, 3, .., 15), 8 dwords each, which the 40-dword row
-    // stride puts in distinct banks.
+    // stride puts in distinct banks.  Round to nearest even (v_cvt_pk_bf16_f32), then ReLU on
+    // the packed pair.
     const bool odd = r16 & 1;
 #pragma unroll
     for (int j = 0; j < RG; ++j) {
-      uint32_t v[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = f2bf(fmaxf(acc[j][e] + bias, 0.0f));
-      const uint32_t t0 = (uint32_t)__builtin_amdgcn_update_dpp(
-          0, (int)(odd ? v[0] : v[2]), lanes::DPP_XOR1, 0xf, 0xf, false);
-      const uint32_t t1 = (uint32_t)__builtin_amdgcn_update_dpp(
-          0, (int)(odd ? v[1] : v[3]), lanes::DPP_XOR1, 0xf, 0xf, false);
-      const uint32_t w0 = odd ? (t0 | (v[2] << 16)) : (v[0] | (t0 << 16));
-      const uint32_t w1 = odd ? (t1 | (v[3] << 16)) : (v[1] | (t1 << 16));
+      const uint32_t u01 = relu_bf16x2(pack_bf16(acc[j][0], acc[j][1]));
+      const uint32_t u23 = relu_bf16x2(pack_bf16(acc[j][2], acc[j][3]));
+      const uint32_t own = odd ? u23 : u01;
+      const uint32_t oth = (uint32_t)__builtin_amdgcn_update_dpp(
+          0, (int)(odd ? u01 : u23), lanes::DPP_XOR1, 0xf, 0xf, false);
+      const uint32_t lo = odd ? oth : own, hi = odd ? own : oth;  // channels co & ~1, co | 1
       uint32_t* o = (uint32_t*)(out + ((g + j) * 16 + 4 * q + (odd ? 2 : 0) + fz::PADR) * fz::SA +
                                 (co & ~1));
-      o[0] = w0;
-      o[fz::SA / 2] = w1;
+      o[0] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);          // low halves: first row
+      o[fz::SA / 2] = __builtin_amdgcn_perm(hi, lo, 0x07060302u);  // high halves: second row
     }
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_net_fused(
+__global__ __launch_bounds__(256, 3) void k_net_fused(
     const double* __restrict__ src, const double* __restrict__ inv_sigma,
     const NetSample* __restrict__ smp, const NetTile* __restrict__ tiles, int ntiles,
     int64_t row_base, int k, int S, const uint16_t* __restrict__ W1,
@@ -565,10 +580,16 @@ __global__ __launch_bounds__(256, 2) void k_net_fused(
     const float* __restrict__ w4, const float* __restrict__ b4, float* __restrict__ corr,
     const int* __restrict__ skip, const int* __restrict__ off) {
   using namespace fz;
-  __shared__ __align__(16) uint16_t X[LROWS * SX];
   __shared__ __align__(16) uint16_t A1[LROWS * SA];
   __shared__ __align__(16) uint16_t A2[LROWS * SA];
-  __shared__ float w4s[NET_W * NET_C];
+  // output-layer weights split into bfloat16 high and low parts (w = hi + lo to 2^-16
+  // relative), the two nonzero columns of the output layer's MFMA operand
+  __shared__ __align__(16) uint16_t w4hl[2][NET_W * NET_C];
+  // the features live inside A2's computed rows: layer 1 reads them before layer 2 writes A2,
+  // and A2's zero pad rows stay clear of them.  Layer 2 overwrites X's pad rows, so every tile
+  // clears them again.
+  uint16_t* const X = A2 + PADR * SA;
+  static_assert(LROWS * SX <= ROWS * SA, "features fit in A2's computed rows");
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -585,12 +606,16 @@ __global__ __launch_bounds__(256, 2) void k_net_fused(
   const float c1 = b1[co], c2 = b2[co], c3 = b3[co], c4 = b4[0];
   // zero the buffers once: the pad rows are never written again
   const uint4 z4 = {0u, 0u, 0u, 0u};
-  for (int i = threadIdx.x; i < LROWS * SX / 8; i += 256) ((uint4*)X)[i] = z4;
   for (int i = threadIdx.x; i < LROWS * SA / 8; i += 256) {
     ((uint4*)A1)[i] = z4;
     ((uint4*)A2)[i] = z4;
   }
-  for (int i = threadIdx.x; i < NET_W * NET_C; i += 256) w4s[i] = w4[i];
+  for (int i = threadIdx.x; i < NET_W * NET_C; i += 256) {
+    const float w = w4[i];
+    const __bf16 hi = (__bf16)w;
+    w4hl[0][i] = __builtin_bit_cast(uint16_t, hi);
+    w4hl[1][i] = __builtin_bit_cast(uint16_t, (__bf16)(w - (float)hi));
+  }
   __syncthreads();
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const NetTile T = tiles[ti];
@@ -601,28 +626,39 @@ __global__ __launch_bounds__(256, 2) void k_net_fused(
     const int hot = 1 + S + (e - P.blk);
     // features, channel 0: own block, 1..S: later segment starts (zero past the last block),
     // then the one-hot of e - blk.  The block values are loaded with consecutive threads on
-    // consecutive grid points (coalesced), all of a thread's loads issued before the first
-    // is used, and the constant channels are written in a second pass.
-    constexpr int JM = (NET_CIN1 * ROWS + 255) / 256;
+    // consecutive grid points (coalesced), in batches of FB loads issued before the first is
+    // used (more would exceed the 168 registers of three workgroups per CU), and the constant
+    // channels are written in a second pass.
+    constexpr int FB = 2;
+    constexpr int JM = ((NET_CIN1 * ROWS + 255) / 256 + FB - 1) / FB * FB;
     const int nval = (1 + S) * ROWS;
-    double v[JM];
 #pragma unroll
-    for (int j = 0; j < JM; ++j) {
-      const int it = threadIdx.x + 256 * j;
-      const int m = it / ROWS, r = it - m * ROWS;
-      const int b = m == 0 ? P.blk : e + 1 + (m - 1) * k;
-      const int pos = wrap(T.pos0 - 4 * NET_HALO + r, P.s);
-      v[j] = (it < nval && b < P.nb) ? src[P.src + (int64_t)b * P.s + pos] : 0.0;
-    }
+    for (int j0 = 0; j0 < JM; j0 += FB) {
+      if (j0 * 256 >= nval) break;  // uniform
+      double v[FB];
 #pragma unroll
-    for (int j = 0; j < JM; ++j) {
-      const int it = threadIdx.x + 256 * j;
-      const int m = it / ROWS, r = it - m * ROWS;
-      if (it < nval) X[(r + PADR) * SX + m] = f2bf((float)(v[j] * isg));
+      for (int j = 0; j < FB; ++j) {
+        const int it = threadIdx.x + 256 * (j0 + j);
+        const int m = it / ROWS, r = it - m * ROWS;
+        const int b = m == 0 ? P.blk : e + 1 + (m - 1) * k;
+        const int pos = wrap(T.pos0 - 4 * NET_HALO + r, P.s);
+        v[j] = (it < nval && b < P.nb) ? src[P.src + (int64_t)b * P.s + pos] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < FB; ++j) {
+        const int it = threadIdx.x + 256 * (j0 + j);
+        const int m = it / ROWS, r = it - m * ROWS;
+        if (it < nval) X[(r + PADR) * SX + m] = (uint16_t)pack_bf16((float)(v[j] * isg), 0.0f);
+      }
     }
     for (int it = threadIdx.x; it < ROWS * NET_CIN1; it += 256) {
       const int r = it / NET_CIN1, c = it - r * NET_CIN1;
       if (c > S) X[(r + PADR) * SX + c] = c == hot ? (uint16_t)0x3f80u : (uint16_t)0;
+    }
+    if (threadIdx.x < 2 * PADR * (NET_CIN1 / 8)) {  // pad rows 0, 1, LROWS - 2, LROWS - 1
+      const int pr = threadIdx.x / (NET_CIN1 / 8), pc = threadIdx.x - pr * (NET_CIN1 / 8);
+      const int row = pr < PADR ? pr : LROWS - 2 * PADR + pr;
+      *(uint4*)(X + row * SX + pc * 8) = z4;
     }
     __syncthreads();
     fused_layer<NET_CIN1, SX, FRG>(X, A1, bw1, c1, q, r16, co);
@@ -631,34 +667,39 @@ __global__ __launch_bounds__(256, 2) void k_net_fused(
     __syncthreads();
     fused_layer<NET_C, SA, FRG>(A2, A1, bw3, c3, q, r16, co);
     __syncthreads();
-    // output layer (64 -> 1, float32 weights): point p at row 8 + p, two threads per point
-    // with 32 channels each, lanes l and l ^ 16 of one wave.  A half-wave holds 16 points of
-    // both halves; the upper half reads its four 8-channel pieces in the order 1, 2, 3, 0, so
-    // that its slots are odd where the lower half's are even (10-slot rows).  A1 is next
-    // written by the following tile's layer 1, after the barrier that follows its features.
+    // output layer (64 -> 1) on the MFMA: points 16 g .. 16 g + 15 (output row tiles 2w, 2w + 1
+    // of wave w) against a 320 x 16 weight operand whose columns 0 and 1 hold the high and
+    // low bfloat16 parts of the float32 weights (the other columns zero); their sum is the
+    // output.  Point p sits at row 8 + p.  A1 is next written by the following tile's layer 1,
+    // after the barrier that follows its features.
     {
-      const int l = threadIdx.x & 63, h = (l >> 4) & 1;
-      const int p = (threadIdx.x >> 6) * 32 + (l >> 5) * 16 + (l & 15);
-      float acc = 0.0f;
+      v4f oacc[2];
 #pragma unroll
-      for (int t = 0; t < NET_W; ++t) {
-        const uint16_t* row = A1 + (4 * NET_HALO + p + t) * SA + h * 32;
-        const float* wt = w4s + t * NET_C + h * 32;
+      for (int j = 0; j < 2; ++j) oacc[j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int c8 = (c + h) & 3;
-          const uint4 vv = *(const uint4*)(row + c8 * 8);
-          const uint16_t* ev = (const uint16_t*)&vv;
+      for (int ks = 0; ks < NET_W * NET_C / 32; ++ks) {
+        const int kl = ks * 32 + q * 8;
+        const int t = kl / NET_C, ci = kl - t * NET_C;
+        bf8 b = {};
+        if (r16 < 2) b = *(const bf8*)(&w4hl[r16][kl]);
 #pragma unroll
-          for (int i = 0; i < 8; ++i) acc += wt[c8 * 8 + i] * bf2f(ev[i]);
+        for (int j = 0; j < 2; ++j) {
+          const int g = 2 * wave + j;
+          const bf8 a = *(const bf8*)(A1 + (4 * NET_HALO + g * 16 + r16 + t) * SA + ci);
+          oacc[j] = NetMma32::mma(a, b, oacc[j]);
         }
       }
-      // own value plus that of lane l ^ 16 (the other channel half of the point)
-      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc),
-                                                       __float_as_uint(acc), false, false);
-      const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
-      const int pos = T.pos0 + p;
-      if (h == 0 && pos < P.s) corr[P.row0 - row_base + pos] = tot + c4;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          // column 0 (lane r16 = 0) plus column 1 (lane r16 = 1)
+          const float tot = oacc[j][e] + __int_as_float(__builtin_amdgcn_update_dpp(
+                                             0, __float_as_int(oacc[j][e]), lanes::DPP_XOR1,
+                                             0xf, 0xf, false));
+          const int pos = T.pos0 + (2 * wave + j) * 16 + 4 * q + e;
+          if (r16 == 0 && pos < P.s) corr[P.row0 - row_base + pos] = tot + c4;
+        }
     }
   }
 }
@@ -989,7 +1030,7 @@ void net_fused(const double* src, const double* inv_sigma, const NetSample* smp,
                const NetWeights& W, const float* theta, const NetLayout& L, float* corr,
                const int* skip, const int* off, hipStream_t st) {
   if (nftiles <= 0) return;
-  static int resident = 0;  // workgroups resident on the device at once (2 per CU by design)
+  static int resident = 0;  // workgroups resident on the device at once (3 per CU by design)
   if (resident == 0) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
