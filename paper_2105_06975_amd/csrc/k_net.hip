@@ -641,7 +641,13 @@ __global__ __launch_bounds__(256, 3) void k_net_fused(
         const int it = threadIdx.x + 256 * (j0 + j);
         const int m = it / ROWS, r = it - m * ROWS;
         const int b = m == 0 ? P.blk : e + 1 + (m - 1) * k;
-        const int pos = wrap(T.pos0 - 4 * NET_HALO + r, P.s);
+        // T.pos0 - 8 + r lies in [-8, s + 136): one correction when s >= 144 (uniform)
+        int pos = T.pos0 - 4 * NET_HALO + r;
+        if (P.s >= ROWS) {
+          pos = pos < 0 ? pos + P.s : (pos >= P.s ? pos - P.s : pos);
+        } else {
+          pos = wrap(pos, P.s);
+        }
         v[j] = (it < nval && b < P.nb) ? src[P.src + (int64_t)b * P.s + pos] : 0.0;
       }
 #pragma unroll
@@ -651,9 +657,28 @@ __global__ __launch_bounds__(256, 3) void k_net_fused(
         if (it < nval) X[(r + PADR) * SX + m] = (uint16_t)pack_bf16((float)(v[j] * isg), 0.0f);
       }
     }
-    for (int it = threadIdx.x; it < ROWS * NET_CIN1; it += 256) {
-      const int r = it / NET_CIN1, c = it - r * NET_CIN1;
-      if (c > S) X[(r + PADR) * SX + c] = c == hot ? (uint16_t)0x3f80u : (uint16_t)0;
+    // channels S+1..31 (zeros and the one-hot) are the same in every row: thread r < ROWS
+    // writes the 8-channel pieces of row r that hold no block value whole and the constant
+    // channels of the piece that holds both one by one (the value stores above write its other
+    // channels; the two sets of bytes are disjoint)
+    if (threadIdx.x < ROWS) {
+      uint16_t* xr = X + (threadIdx.x + PADR) * SX;
+      const int gm = (S + 1) / 8;  // the first piece with a constant channel (uniform)
+#pragma unroll
+      for (int g = 0; g < NET_CIN1 / 8; ++g) {
+        if (g < gm) continue;
+        if (8 * g > S) {
+          uint32_t wv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = 8 * g + 2 * i;
+            wv[i] = (c == hot ? 0x3f80u : 0u) | (c + 1 == hot ? 0x3f800000u : 0u);
+          }
+          *(uint4*)(xr + 8 * g) = uint4{wv[0], wv[1], wv[2], wv[3]};
+        } else {
+          for (int c = S + 1; c < 8 * g + 8; ++c) xr[c] = c == hot ? (uint16_t)0x3f80u : 0;
+        }
+      }
     }
     if (threadIdx.x < 2 * PADR * (NET_CIN1 / 8)) {  // pad rows 0, 1, LROWS - 2, LROWS - 1
       const int pr = threadIdx.x / (NET_CIN1 / 8), pc = threadIdx.x - pr * (NET_CIN1 / 8);
