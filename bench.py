@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--harvest", type=int, default=300, help="pairs harvested per window")
     ap.add_argument("--plain-only", action="store_true",
                     help="--c2: time only the plain FP64 path (no training)")
-    ap.add_argument("--n-bound", type=int, default=20,
+    ap.add_argument("--n-bound", type=int, default=8,
                     help="later segment starts the network sees (1 + n_bound + k <= 32)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="--c2: skip the GEMM autotuning of the batched path")
