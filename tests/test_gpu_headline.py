@@ -81,9 +81,9 @@ def test_headline_batched_learned_path_solution_error(sv, block_rhs, precision):
                             max_outer=20000)
     assert rcr == sv.OK
     XR = host(xr)
-    # the network of the benchmark (bfloat16 inference, n_bound = 20); its weights here are
+    # the network of the benchmark (bfloat16 inference, n_bound = 8); its weights here are
     # the seeded initial ones: the test is about the path's arithmetic, not the gain
-    net = sv.Net(3, 20, "BF16")
+    net = sv.Net(3, 8, "BF16")
     net.set_params(wl.net_init(net.cin, 64, seed=0))
     h.set_net(net)
     lens = [nrhs * w.n for w in wins]
