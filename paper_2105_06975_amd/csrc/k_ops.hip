@@ -20,7 +20,7 @@ __device__ __forceinline__ double job_out(const MJob& J, const Bases& b, int j, 
 }
 
 
-static constexpr int TS = 256;  // outputs per workgroup
+static constexpr int TS = JOB_TS;  // outputs per workgroup
 static constexpr int YMAX = 65535;
 
 __device__ __forceinline__ int job_id() { return blockIdx.y + YMAX * blockIdx.z; }
@@ -34,14 +34,16 @@ __device__ __forceinline__ double* opnd(const Bases& b, const Operand& o) {
 
 __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs,
                                                    const ModelDev* __restrict__ models, Bases b,
-                                                   const int* __restrict__ skip, int njobs) {
+                                                   const int* __restrict__ skip, int njobs,
+                                                   const JTile* __restrict__ tl) {
   if (skip && *skip) return;
   extern __shared__ double lds[];
-  if (job_id() >= njobs) return;
-  const MJob J = jobs[job_id()];
+  const int jid = tl ? tl[blockIdx.x].job : job_id();
+  if (jid >= njobs) return;
+  const MJob J = jobs[jid];
   if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
-  const int j0 = blockIdx.x * TS;
+  const int j0 = tl ? tl[blockIdx.x].first : blockIdx.x * TS;
   if (j0 >= s) return;
   const double* in = opnd(b, J.in);
   double* out = opnd(b, J.out);
@@ -78,15 +80,17 @@ __global__ __launch_bounds__(TS) void k_mstep_band(const MJob* __restrict__ jobs
 template <int H>
 __global__ __launch_bounds__(TS) void k_mstep_win(const MJob* __restrict__ jobs,
                                                   const ModelDev* __restrict__ models, Bases b,
-                                                  const int* __restrict__ skip, int njobs) {
+                                                  const int* __restrict__ skip, int njobs,
+                                                  const JTile* __restrict__ tl) {
   __shared__ double lw[H + 1];
   __shared__ double lx[TS + H];
   if (skip && *skip) return;
-  if (job_id() >= njobs) return;
-  const MJob J = jobs[job_id()];
+  const int jid = tl ? tl[blockIdx.x].job : job_id();
+  if (jid >= njobs) return;
+  const MJob J = jobs[jid];
   if (SVAR_JOB_SKIPPED(b, J)) return;
   const int s = J.s;
-  const int j0 = blockIdx.x * TS;
+  const int j0 = tl ? tl[blockIdx.x].first : blockIdx.x * TS;
   if (j0 >= s) return;
   const double* in = opnd(b, J.in);
   double* out = opnd(b, J.out);
@@ -222,12 +226,14 @@ __global__ __launch_bounds__(TS) void k_mstep_dense(const MJob* __restrict__ job
 }
 
 __global__ __launch_bounds__(TS) void k_gather(const HJob* __restrict__ jobs, Bases b,
-                                               const int* __restrict__ skip, int njobs) {
+                                               const int* __restrict__ skip, int njobs,
+                                               const JTile* __restrict__ tl) {
   if (skip && *skip) return;
-  if (job_id() >= njobs) return;
-  const HJob J = jobs[job_id()];
+  const int jid = tl ? tl[blockIdx.x].job : job_id();
+  if (jid >= njobs) return;
+  const HJob J = jobs[jid];
   if (SVAR_JOB_SKIPPED(b, J)) return;
-  const int r = blockIdx.x * TS + threadIdx.x;
+  const int r = (tl ? tl[blockIdx.x].first : blockIdx.x * TS) + threadIdx.x;
   if (r >= J.rows) return;
   const double* x = opnd(b, J.x);
   double acc = 0.0;
@@ -237,12 +243,14 @@ __global__ __launch_bounds__(TS) void k_gather(const HJob* __restrict__ jobs, Ba
 }
 
 __global__ __launch_bounds__(TS) void k_scatter(const HTJob* __restrict__ jobs, Bases b,
-                                                const int* __restrict__ skip, int njobs) {
+                                                const int* __restrict__ skip, int njobs,
+                                                const JTile* __restrict__ tl) {
   if (skip && *skip) return;
-  if (job_id() >= njobs) return;
-  const HTJob J = jobs[job_id()];
+  const int jid = tl ? tl[blockIdx.x].job : job_id();
+  if (jid >= njobs) return;
+  const HTJob J = jobs[jid];
   if (SVAR_JOB_SKIPPED(b, J)) return;
-  const int j = blockIdx.x * TS + threadIdx.x;
+  const int j = (tl ? tl[blockIdx.x].first : blockIdx.x * TS) + threadIdx.x;
   if (j >= J.s) return;
   const double* y = opnd(b, J.y);
   double acc = 0.0;
@@ -303,18 +311,24 @@ __global__ void k_axpby(double* y, const double* x, int64_t n, double a, double 
 
 static unsigned tiles(int64_t n) { return (unsigned)((n + TS - 1) / TS); }
 
+// tiles (nullable): the launch's flat tile list, one workgroup each; else a workgroup per
+// (job, 256-output tile of the longest job), the shorter jobs' extra workgroups exiting at once
+static dim3 tgrid(const JTile* tl, int ntiles, int max_len, int njobs) {
+  return tl ? dim3((unsigned)ntiles) : jgrid(tiles(max_len), njobs);
+}
 void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
                        const ModelDev* models, Bases b, const int* skip, hipStream_t st,
-                       bool windowed) {
-  if (njobs == 0) return;
+                       bool windowed, const JTile* tl, int ntiles) {
+  if (njobs == 0 || (tl && ntiles == 0)) return;
+  const dim3 g = tgrid(tl, ntiles, max_s, njobs);
   if (windowed) {  // every band model has a dense tap window (s >= SWEEP_H + 1)
-    hipLaunchKernelGGL((k_mstep_win<SWEEP_H>), jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs,
-                       models, b, skip, njobs);
+    hipLaunchKernelGGL((k_mstep_win<SWEEP_H>), g, dim3(TS), 0, st, jobs, models, b, skip, njobs,
+                       tl);
     return;
   }
   // LDS: the output tile plus the widest halo of any band model (checked at set-up)
-  hipLaunchKernelGGL(k_mstep_band, jgrid(tiles(max_s), njobs), dim3(TS),
-                     (size_t)(TS + max_halo) * sizeof(double), st, jobs, models, b, skip, njobs);
+  hipLaunchKernelGGL(k_mstep_band, g, dim3(TS), (size_t)(TS + max_halo) * sizeof(double), st,
+                     jobs, models, b, skip, njobs, tl);
 }
 void launch_sweep_band(const SJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
                        const int* skip, hipStream_t st) {
@@ -342,14 +356,16 @@ void launch_prefix(const SJob* jobs, int njobs, int max_s, Bases b, const int* s
   hipLaunchKernelGGL(k_prefix, jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
 }
 void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
-                   hipStream_t st) {
-  if (njobs == 0 || max_rows == 0) return;
-  hipLaunchKernelGGL(k_gather, jgrid(tiles(max_rows), njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
+                   hipStream_t st, const JTile* tl, int ntiles) {
+  if (njobs == 0 || max_rows == 0 || (tl && ntiles == 0)) return;
+  hipLaunchKernelGGL(k_gather, tgrid(tl, ntiles, max_rows, njobs), dim3(TS), 0, st, jobs, b, skip,
+                     njobs, tl);
 }
 void launch_scatter(const HTJob* jobs, int njobs, int max_s, Bases b, const int* skip,
-                    hipStream_t st) {
-  if (njobs == 0) return;
-  hipLaunchKernelGGL(k_scatter, jgrid(tiles(max_s), njobs), dim3(TS), 0, st, jobs, b, skip, njobs);
+                    hipStream_t st, const JTile* tl, int ntiles) {
+  if (njobs == 0 || (tl && ntiles == 0)) return;
+  hipLaunchKernelGGL(k_scatter, tgrid(tl, ntiles, max_s, njobs), dim3(TS), 0, st, jobs, b, skip,
+                     njobs, tl);
 }
 void launch_vec(const VJob* jobs, int njobs, int64_t max_len, Bases b, const int* skip,
                 hipStream_t st) {

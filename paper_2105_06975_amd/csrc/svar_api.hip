@@ -1068,6 +1068,19 @@ static int winflag(const Builder& B, int w) {
   return B.global_flag ? 0 : 1 + (int)B.h->wins.size() * B.nrhs + w;
 }
 
+// the flat tile list of a job-table launch: lens[j] outputs of job j in tiles of JOB_TS
+static int add_tiles(Builder& B, Launch& L, const std::vector<int>& lens) {
+  std::vector<JTile> t;
+  for (int j = 0; j < (int)lens.size(); ++j)
+    for (int f = 0; f < lens[j]; f += JOB_TS) t.push_back(JTile{j, f});
+  if (t.size() > (size_t)INT32_MAX) return SVAR_OK;  // keep the two-dimensional grid
+  JTile* d = nullptr;
+  SVAR_TRY(upload(B.h->allocs, &d, t.data(), t.size(), B.st));
+  L.tiles = d;
+  L.ntiles = (int)t.size();
+  return SVAR_OK;
+}
+
 static int add_mjobs(Builder& B, std::vector<MJob> jobs[3]) {
   const LaunchKind kinds[3] = {LK_MSTEP_BAND, LK_MSTEP_DENSE, LK_MSTEP_L96};
   for (int k = 0; k < 3; ++k) {
@@ -1080,6 +1093,11 @@ static int add_mjobs(Builder& B, std::vector<MJob> jobs[3]) {
     MJob* d = nullptr;
     SVAR_TRY(upload(B.h->allocs, &d, jobs[k].data(), jobs[k].size(), B.st));
     L.jobs = d;
+    if (kinds[k] == LK_MSTEP_BAND) {
+      std::vector<int> lens;
+      for (auto& j : jobs[k]) lens.push_back(j.s);
+      SVAR_TRY(add_tiles(B, L, lens));
+    }
     B.P->launches.push_back(L);
   }
   return SVAR_OK;
@@ -1429,6 +1447,9 @@ static int add_gather(Builder& B, VRef x, VRef out) {
   HJob* d = nullptr;
   SVAR_TRY(upload(B.h->allocs, &d, jobs.data(), jobs.size(), B.st));
   L.jobs = d;
+  std::vector<int> lens;
+  for (auto& j : jobs) lens.push_back(j.rows);
+  SVAR_TRY(add_tiles(B, L, lens));
   B.P->launches.push_back(L);
   return SVAR_OK;
 }
@@ -1461,6 +1482,9 @@ static int add_scatter(Builder& B, VRef y, VRef out) {
   HTJob* d = nullptr;
   SVAR_TRY(upload(B.h->allocs, &d, jobs.data(), jobs.size(), B.st));
   L.jobs = d;
+  std::vector<int> lens;
+  for (auto& j : jobs) lens.push_back(j.s);
+  SVAR_TRY(add_tiles(B, L, lens));
   B.P->launches.push_back(L);
   return SVAR_OK;
 }
@@ -1917,7 +1941,7 @@ static int exec_program(svar_handle* h, const Program& P, double* in, double* ou
     switch (L.kind) {
       case LK_MSTEP_BAND:
         launch_mstep_band((const MJob*)L.jobs, L.njobs, L.max_s, h->max_halo, h->models_dev, b,
-                          skip, st, h->band_window);
+                          skip, st, h->band_window, L.tiles, L.ntiles);
         break;
       case LK_MSTEP_DENSE:
         launch_mstep_dense((const MJob*)L.jobs, L.njobs, L.max_s, h->models_dev, b, skip, st);
@@ -1933,10 +1957,10 @@ static int exec_program(svar_handle* h, const Program& P, double* in, double* ou
                          b, skip, st);
         break;
       case LK_GATHER:
-        launch_gather((const HJob*)L.jobs, L.njobs, L.max_s, b, skip, st);
+        launch_gather((const HJob*)L.jobs, L.njobs, L.max_s, b, skip, st, L.tiles, L.ntiles);
         break;
       case LK_SCATTER:
-        launch_scatter((const HTJob*)L.jobs, L.njobs, L.max_s, b, skip, st);
+        launch_scatter((const HTJob*)L.jobs, L.njobs, L.max_s, b, skip, st, L.tiles, L.ntiles);
         break;
       case LK_VEC:
         launch_vec((const VJob*)L.jobs, L.njobs, L.max_s, b, skip, st);

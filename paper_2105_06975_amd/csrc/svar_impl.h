@@ -162,10 +162,19 @@ struct GemmPlanDev {
   std::vector<GemmProb> hprobs;   // host copy of the problems (autotuning re-plans them)
   std::string key;                // shape key of the launch (autotuning cache)
 };
+// one workgroup's share of a job-table launch: outputs first .. first + JOB_TS - 1 of job
+// `job` (a flat list of the tiles that exist, so jobs of different lengths share a launch
+// without empty workgroups)
+constexpr int JOB_TS = 256;
+struct JTile {
+  int32_t job, first;
+};
 struct Launch {
   LaunchKind kind;
   void* jobs = nullptr;   // device job table
   int njobs = 0;
+  const JTile* tiles = nullptr;  // model products, H and H^T: the workgroups' tiles
+  int ntiles = 0;
   int grid_x = 0;
   int max_s = 0;
   GemmPlanDev gemm;
@@ -182,7 +191,7 @@ struct Program {
 // kernel launchers (defined in the .hip files)
 void launch_mstep_band(const MJob* jobs, int njobs, int max_s, int max_halo,
                        const ModelDev* models, Bases b, const int* skip, hipStream_t st,
-                       bool windowed = false);
+                       bool windowed = false, const JTile* tiles = nullptr, int ntiles = 0);
 void launch_mstep_dense(const MJob* jobs, int njobs, int max_s, const ModelDev* models,
                         Bases b, const int* skip, hipStream_t st);
 void launch_sweep_band(const SJob* jobs, int njobs, int max_s, const ModelDev* models, Bases b,
@@ -194,9 +203,9 @@ void launch_prefix(const SJob* jobs, int njobs, int max_s, Bases b, const int* s
 void launch_mstep_l96(const MJob* jobs, int njobs, int max_s, int max_steps,
                       const ModelDev* models, Bases b, const int* skip, hipStream_t st);
 void launch_gather(const HJob* jobs, int njobs, int max_rows, Bases b, const int* skip,
-                   hipStream_t st);
+                   hipStream_t st, const JTile* tiles = nullptr, int ntiles = 0);
 void launch_scatter(const HTJob* jobs, int njobs, int max_s, Bases b, const int* skip,
-                    hipStream_t st);
+                    hipStream_t st, const JTile* tiles = nullptr, int ntiles = 0);
 void launch_vec(const VJob* jobs, int njobs, int64_t max_len, Bases b, const int* skip,
                 hipStream_t st);
 void launch_gemm(const GemmPlanDev& g, Bases b, double* ws, const int* skip, hipStream_t st);
